@@ -1,0 +1,166 @@
+"""Benchmark: exhaustive evaluation of every launch ordering of one task group.
+
+Workload: one group of N=12 tasks (6 dominant-kernel: K log-uniform 1-20 ms,
+HtD/DtH 0.1-2 ms; 6 dominant-transfer: ranges swapped), int64 ns, seed 1;
+overlap rates 3/4.  One step = all 12! = 479,001,600 orderings evaluated and
+reduced to best / worst / mean (one exhaustive call) plus the ordering
+heuristic for the same group.  Inputs are resident in HBM before timing.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line.  Only one GPU is used; --gpus above 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "orderings evaluated/sec at N=12 (exact); groups/sec + p99 latency, N≤16"
+N = 12
+SEED = 1
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 32-bit VALU lane-ops/s.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+# VALU instructions issued per ordering by the exhaustive kernel on this
+# workload (SQ_INSTS_VALU per launch / 12!, from the rocprofv3 counter run
+# recorded in profiles/exhaustive_n12_counters.txt); x64 lanes = lane-ops.
+VALU_INSTS_PER_ORDERING = None
+# HBM bytes per launch from FETCH_SIZE + WRITE_SIZE (same profile), scaled by
+# the copy-kernel calibration; None until measured for the current kernel.
+TRAFFIC_BYTES_PER_LAUNCH = None
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--cpu-seconds", type=float, default=15.0,
+                   help="target duration of the CPU-oracle baseline sample")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="also run a 256 MiB device copy (for HBM counter calibration)")
+    return p.parse_args()
+
+
+def cpu_baseline(tasks, seconds: float):
+    """The C oracle on a bounded prefix of the rank range, all host threads."""
+    from oracle import cmodel
+    from oracle import model as M
+    threads = cmodel.default_threads()
+    # calibrate on a short run, then size the sample to ~`seconds`
+    probe = 200_000 * threads
+    t0 = time.perf_counter()
+    cmodel.exhaustive(tasks, M.DEFAULT, lo=0, hi=probe, threads=threads)
+    dt = time.perf_counter() - t0
+    rate = probe / max(dt, 1e-9)
+    count = int(min(math.factorial(N), max(probe, rate * seconds)))
+    t0 = time.perf_counter()
+    cmodel.exhaustive(tasks, M.DEFAULT, lo=0, hi=count, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": count / dt, "unit": "orderings/s", "cores": threads, "kind": "oracle",
+            "sample": f"ranks 0..{count - 1} of the N=12 group ({count / math.factorial(N):.2%} "
+                      f"of 12!), plain C event simulator, {threads} threads, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: the path is measured on a single MI355X "
+              "(a multi-GPU run would shard the rank range; not part of this build)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1806_10113_amd import tgo, workloads as W
+
+    dev = torch.device("cuda:0")
+    tasks_np = W.single_group_mixed(N, SEED)
+    tasks = torch.as_tensor(tasks_np).to(dev)
+    offs = torch.tensor([0, N], dtype=torch.int32, device=dev)
+    model = tgo.DEFAULT
+    stream = torch.cuda.current_stream()
+    summary = torch.empty(tgo.SUMMARY_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+
+    if args.calibrate_copy:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    def step(ev_pair=None):
+        if ev_pair is not None:
+            ev_pair[0].record(stream)
+        tgo.exhaustive(tasks, model, summary=summary, stream=stream)
+        if ev_pair is not None:
+            ev_pair[1].record(stream)
+        tgo.heuristic(tasks, offs, model, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    k = args.steps
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for i in range(k):
+        step(evs[i])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    launch_ms = [a.elapsed_time(b) for a, b in evs]
+    avg_launch_ms = sum(launch_ms) / k
+
+    # the answer must be the oracle's (stored full enumeration)
+    s = tgo.read_summary(summary)
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "single_group_summaries.json")))["mixed_n12_seed1"]
+    ok = (s["status"] == 0 and s["min_ns"] == gold["min_ns"] and s["argmin_rank"] == gold["argmin_rank"]
+          and s["max_ns"] == gold["max_ns"] and s["sum"] == int(gold["sum"])
+          and s["fingerprint"] == int(gold["fingerprint"]))
+    if not ok:
+        print(json.dumps({"error": "result differs from the oracle", "got": s}), file=sys.stderr)
+        sys.exit(1)
+
+    orderings = math.factorial(N)
+    ms_per_step = total_ms / k
+    value = orderings * k / (total_ms / 1e3)
+
+    roof = {"bound": "alu", "unit": "TOP/s", "peak": VALU_PEAK_TOPS}
+    if VALU_INSTS_PER_ORDERING is not None:
+        achieved = VALU_INSTS_PER_ORDERING * 64 * orderings / (avg_launch_ms / 1e3) / 1e12
+        roof.update({"achieved": achieved, "frac": achieved / VALU_PEAK_TOPS})
+    else:
+        roof.update({"achieved": None, "frac": None})
+    roof["traffic"] = TRAFFIC_BYTES_PER_LAUNCH
+    roof["launch_ms"] = avg_launch_ms
+    roof["kernel"] = "exhaustive_kernel<u32, M=5> (+ finalize)"
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "orderings/s", "n_gpus": 1, "steps": k,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "exhaustive N=12 (6 DK + 6 DT, log-uniform, seed 1), all 479,001,600 "
+                               "orderings -> min/argmin/max/argmax/mean, plus Algorithm-1 heuristic",
+                   "group_size": N, "orderings_per_step": orderings, "overlap_rates": "3/4, 3/4",
+                   "time_path": "32-bit (bound checked on device; identical to int64)"},
+        "roofline": roof,
+        "min_ns": s["min_ns"], "mean_ns": s["mean_ns"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(tasks_np, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

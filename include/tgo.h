@@ -1,0 +1,144 @@
+/*
+ * tgo -- task-group ordering on MI355X (gfx950).
+ *
+ * C ABI of the library libtgo.so.  It evaluates the temporal execution model of
+ * Lazaro-Munoz et al., "Improving tasks throughput on accelerators using OpenCL
+ * command concurrency" (Section 4), over launch orderings of a task group, and
+ * runs the paper's ordering heuristic (Section 5.1, Algorithm 1).
+ *
+ * The model.  A task is an HtD transfer, a kernel K and a DtH transfer executed
+ * in that order (Section 3; any stage may be empty, i.e. zero).  Commands are
+ * issued in launch order through one FIFO queue per engine (Section 3.2, two-DMA
+ * launch scheme; Section 4.1 FIFO simulator): the HtD engine runs the HtDs
+ * back to back, K_j starts once HtD_j and K_{j-1} are done, DtH_j once K_j and
+ * DtH_{j-1} are done.  Kernels never overlap each other and always take their
+ * solo time (Section 4.1, last paragraph).  While an HtD and a DtH are both
+ * moving data they are slowed down (Section 4.2.1); the paper gives no formula,
+ * and this library's reading is that they then advance at p_htd/q and p_dth/q of
+ * solo speed.  Time is integer nanoseconds: remaining transfer work is exact in
+ * units of 1/q solo-ns and a completion estimate is rounded up to a whole ns.
+ * T(ordering) is the completion time of the last DtH.
+ *
+ * Orderings are ranked lexicographically (rank 0 = identity 0,1,...,n-1).  Ties
+ * for the best or worst ordering go to the lowest rank.
+ *
+ * Conventions for every call:
+ *   - Pointers named d_* are device pointers (HBM); h_* are host pointers.  The
+ *     caller owns every buffer.  Calls are asynchronous on `stream` (a
+ *     hipStream_t; NULL = the default stream); buffers must stay alive until the
+ *     stream is synchronized.
+ *   - Return value: TGO_OK (0) or a negative TGO_E* code; nothing aborts and no
+ *     exception crosses the ABI.  tgo_last_error() gives a thread-local detail
+ *     string for the last failing call.  Argument errors the host can see are
+ *     returned at once; errors in device-resident data (negative durations,
+ *     overflow of the integer bounds, an index that is not a permutation) are
+ *     reported through the status fields of the outputs.
+ *   - Functions are reentrant; a handle (plan, surrogate, server) must not be
+ *     used from two threads at once.
+ */
+#ifndef TGO_H
+#define TGO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TGO_MAX_N 16            /* largest group for evaluate / heuristic      */
+#define TGO_MAX_EXHAUSTIVE_N 13 /* largest group enumerated in full (13! ranks) */
+
+enum {
+    TGO_OK = 0,
+    TGO_EINVAL = -1,  /* bad argument: n out of range, NULL, bad model, not a permutation */
+    TGO_ERANGE = -2,  /* a duration is negative or the integer bounds would overflow      */
+    TGO_ENOMEM = -3,  /* allocation failed                                                 */
+    TGO_EDEVICE = -4, /* a HIP runtime error; tgo_last_error() has the HIP message        */
+};
+
+typedef void *tgo_stream; /* hipStream_t */
+
+/* Solo durations of one task, ns, each >= 0 (Section 3: HtD, K, DtH). */
+typedef struct {
+    int64_t htd_ns, kern_ns, dth_ns;
+} tgo_task;
+
+/* Device model.  dma_engines: 2 = separate HtD and DtH engines (the launch
+ * scheme of Section 3.2 with three command queues).  q = 1 << q_log2
+ * (q_log2 in 0..10); overlapped transfers advance at p_htd/q and p_dth/q of
+ * solo speed, 1 <= p <= q.  (q_log2 = 2, p = 3, 3) is the benchmark default;
+ * (3, 3, 3) reproduces the worked timeline of Section 4.1. */
+typedef struct {
+    int32_t dma_engines;
+    int32_t q_log2;
+    int32_t p_htd, p_dth;
+} tgo_model;
+
+/* Result of an enumeration over all n! orderings (the paper's best, worst and
+ * average over every ordering: Section 6, speedups against the worst). */
+typedef struct {
+    int64_t min_ns, max_ns;
+    uint64_t argmin_rank, argmax_rank; /* lowest rank among ties                  */
+    uint64_t sum_lo, sum_hi;           /* exact 128-bit sum of T over the ranks   */
+    uint64_t count;                    /* number of orderings (n!)                */
+    uint64_t fingerprint;              /* sum over ranks r of (2r+1)*T_r mod 2^64 */
+    double mean_ns;                    /* sum / count, rounded to nearest         */
+    int32_t status;                    /* TGO_OK or the TGO_E* found on the device */
+    int32_t n;
+    uint8_t best[16], worst[16];       /* orderings at argmin / argmax            */
+} tgo_summary;
+
+const char *tgo_strerror(int code);
+const char *tgo_last_error(void);
+int tgo_version(void);
+
+/* ---------------------------------------------------------------------------
+ * tgo_evaluate -- predicted total time of given orderings (Section 4: "given a
+ * specific ordering ... predict the total execution time").
+ *   d_tasks : n tasks (1 <= n <= TGO_MAX_N).
+ *   d_orders: m orderings, row-major m x n bytes, each a permutation of 0..n-1.
+ *   d_out   : m int64; T in ns, or a negative TGO_E* for a row that is not a
+ *             permutation (TGO_EINVAL) or tasks out of range (TGO_ERANGE).
+ * One GPU lane per ordering.
+ */
+int tgo_evaluate(const tgo_model *model, const tgo_task *d_tasks, int n, const uint8_t *d_orders,
+                 int64_t m, int64_t *d_out, tgo_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * tgo_exhaustive -- every ordering of one group (the brute force that Section 1
+ * and Section 5.1 call infeasible at runtime), reduced to best / worst / mean.
+ *   d_tasks     : n tasks, 1 <= n <= TGO_MAX_EXHAUSTIVE_N.
+ *   d_per_order : NULL, or n! int64 receiving T at index = rank (n <= 12).
+ *   d_summary   : one tgo_summary, written by the call (status set on error).
+ */
+int tgo_exhaustive(const tgo_model *model, const tgo_task *d_tasks, int n, int64_t *d_per_order,
+                   tgo_summary *d_summary, tgo_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * tgo_heuristic -- Algorithm 1 (Section 5.1) for a batch of groups.
+ *   d_tasks/d_offs: CSR batch, group g = d_tasks[d_offs[g] .. d_offs[g+1]),
+ *                   sizes 1..TGO_MAX_N.
+ *   d_orders      : n_groups x 16 bytes; the first n entries of row g are the
+ *                   heuristic ordering of group g (task indices local to g).
+ *   d_ns          : n_groups int64; T of that ordering, or a negative TGO_E*.
+ * Readings of the selection functions (the paper describes them in words):
+ *   first : largest K - HtD; ties to the longer DtH, then the lower index.
+ *   next  : smallest |h_c - (t_K - t_HtD)| + |k_c - (t_DtH - max(t_HtD + h_c, t_K))|
+ *           with t_* the completion times of the last HtD, K, DtH when the
+ *           ordered set is simulated alone; ties to the lower index.
+ *   last  : both orders (x, y) of the final two tasks scored
+ *           fit(x | OT) + fit(y | OT + x) + d_y; ties to the shorter d_y, then
+ *           to the order whose x has the lower index.
+ */
+int tgo_heuristic(const tgo_model *model, const tgo_task *d_tasks, const int32_t *d_offs,
+                  int n_groups, uint8_t *d_orders, int64_t *d_ns, tgo_stream stream);
+
+/* Host helpers: lexicographic rank <-> ordering (index arithmetic only). */
+int tgo_rank(int n, const uint8_t *h_order, uint64_t *rank);
+int tgo_unrank(int n, uint64_t rank, uint8_t *h_order);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TGO_H */

@@ -1,0 +1,162 @@
+// C ABI entry points: argument validation, model constants, launches.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "tgo_internal.h"
+
+namespace tgo {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return TGO_EDEVICE;
+}
+
+int make_rates(const tgo_model *m, Rates *r) {
+    if (!m) return fail(TGO_EINVAL, "model is NULL");
+    if (m->dma_engines != 2) return fail(TGO_EINVAL, "dma_engines must be 2");
+    if (m->q_log2 < 0 || m->q_log2 > 10) return fail(TGO_EINVAL, "q_log2 must be in 0..10");
+    const int q = 1 << m->q_log2;
+    if (m->p_htd < 1 || m->p_htd > q || m->p_dth < 1 || m->p_dth > q)
+        return fail(TGO_EINVAL, "overlap rates must satisfy 1 <= p <= q");
+    r->q_log2 = m->q_log2;
+    r->p_h = (uint32_t)m->p_htd;
+    r->p_d = (uint32_t)m->p_dth;
+    r->inv_ph = 1.0 / (double)m->p_htd;
+    r->c_ph = ((double)m->p_htd - 0.5) * r->inv_ph;
+    r->inv_pd = 1.0 / (double)m->p_dth;
+    r->c_pd = ((double)m->p_dth - 0.5) * r->inv_pd;
+    return TGO_OK;
+}
+
+struct DevWs {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+static std::mutex g_ws_mu;
+static std::vector<DevWs> g_ws;
+
+int workspace(size_t bytes, void **ptr) {
+    int dev = 0;
+    TGO_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
+    DevWs &w = g_ws[dev];
+    if (w.bytes < bytes) {
+        // Wait for work that may still use the old buffer before freeing it.
+        if (w.ptr) {
+            TGO_HIP(hipDeviceSynchronize());
+            TGO_HIP(hipFree(w.ptr));
+            w.ptr = nullptr;
+            w.bytes = 0;
+        }
+        size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) return fail(TGO_ENOMEM, std::string("workspace: ") + hipGetErrorString(e));
+        w.ptr = p;
+        w.bytes = want;
+    }
+    *ptr = w.ptr;
+    return TGO_OK;
+}
+
+}  // namespace tgo
+
+using namespace tgo;
+
+extern "C" {
+
+const char *tgo_strerror(int code) {
+    switch (code) {
+        case TGO_OK: return "ok";
+        case TGO_EINVAL: return "invalid argument";
+        case TGO_ERANGE: return "value out of range";
+        case TGO_ENOMEM: return "out of memory";
+        case TGO_EDEVICE: return "device error";
+        default: return "unknown error";
+    }
+}
+
+const char *tgo_last_error(void) { return g_err.c_str(); }
+
+int tgo_version(void) { return 1; }
+
+int tgo_evaluate(const tgo_model *model, const tgo_task *d_tasks, int n, const uint8_t *d_orders,
+                 int64_t m, int64_t *d_out, tgo_stream stream) {
+    Rates r;
+    int rc = make_rates(model, &r);
+    if (rc) return rc;
+    if (n < 1 || n > TGO_MAX_N) return fail(TGO_EINVAL, "n must be in 1..16");
+    if (m < 0) return fail(TGO_EINVAL, "m must be >= 0");
+    if (m > 0 && (!d_tasks || !d_orders || !d_out)) return fail(TGO_EINVAL, "NULL buffer");
+    return launch_evaluate(r, d_tasks, n, d_orders, m, d_out, (hipStream_t)stream);
+}
+
+int tgo_exhaustive(const tgo_model *model, const tgo_task *d_tasks, int n, int64_t *d_per_order,
+                   tgo_summary *d_summary, tgo_stream stream) {
+    Rates r;
+    int rc = make_rates(model, &r);
+    if (rc) return rc;
+    if (n < 1 || n > TGO_MAX_EXHAUSTIVE_N) return fail(TGO_EINVAL, "n must be in 1..13");
+    if (d_per_order && n > 12) return fail(TGO_EINVAL, "per-ordering output needs n <= 12");
+    if (!d_tasks || !d_summary) return fail(TGO_EINVAL, "NULL buffer");
+    return launch_exhaustive(r, d_tasks, n, d_per_order, d_summary, (hipStream_t)stream);
+}
+
+int tgo_heuristic(const tgo_model *model, const tgo_task *d_tasks, const int32_t *d_offs,
+                  int n_groups, uint8_t *d_orders, int64_t *d_ns, tgo_stream stream) {
+    Rates r;
+    int rc = make_rates(model, &r);
+    if (rc) return rc;
+    if (n_groups < 0) return fail(TGO_EINVAL, "n_groups must be >= 0");
+    if (n_groups > 0 && (!d_tasks || !d_offs || !d_orders || !d_ns)) return fail(TGO_EINVAL, "NULL buffer");
+    return launch_heuristic(r, d_tasks, d_offs, n_groups, d_orders, d_ns, (hipStream_t)stream);
+}
+
+int tgo_rank(int n, const uint8_t *h_order, uint64_t *rank) {
+    if (n < 1 || n > TGO_MAX_N || !h_order || !rank) return fail(TGO_EINVAL, "bad argument");
+    uint32_t seen = 0;
+    for (int i = 0; i < n; ++i) {
+        if (h_order[i] >= n || ((seen >> h_order[i]) & 1u)) return fail(TGO_EINVAL, "not a permutation");
+        seen |= 1u << h_order[i];
+    }
+    uint64_t r = 0;
+    for (int i = 0; i < n; ++i) {
+        uint64_t c = 0;
+        for (int j = i + 1; j < n; ++j) c += h_order[j] < h_order[i];
+        r = r * (uint64_t)(n - i) + c;
+    }
+    *rank = r;
+    return TGO_OK;
+}
+
+int tgo_unrank(int n, uint64_t rank, uint8_t *h_order) {
+    if (n < 1 || n > TGO_MAX_N || !h_order) return fail(TGO_EINVAL, "bad argument");
+    if (rank >= factorial(n)) return fail(TGO_ERANGE, "rank >= n!");
+    uint8_t rest[16];
+    for (int i = 0; i < n; ++i) rest[i] = (uint8_t)i;
+    int left = n;
+    for (int i = 0; i < n; ++i) {
+        const uint64_t f = factorial(n - 1 - i);
+        const int c = (int)(rank / f);
+        rank %= f;
+        h_order[i] = rest[c];
+        for (int j = c; j < left - 1; ++j) rest[j] = rest[j + 1];
+        --left;
+    }
+    return TGO_OK;
+}
+
+}  // extern "C"

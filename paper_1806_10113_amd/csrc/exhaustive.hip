@@ -1,0 +1,362 @@
+// Exhaustive evaluation of every launch ordering of one task group.
+//
+// Brute force over all n! orderings (the search that Section 1 and
+// Section 5.1 rule out at runtime on a CPU), reduced to the best, worst and
+// average ordering (the quantities plotted in Section 6).
+//
+// Work decomposition: ranks are lexicographic, so the orderings sharing a
+// prefix of length n - M form a contiguous block of M! ranks.  One lane owns
+// such a block ("subtree"): it decodes the prefix from the block index,
+// simulates the prefix windows once, then walks the last M positions depth
+// first in lexicographic order, re-simulating only the windows below the
+// position that changed.  Per ordering this costs about 1.72 windows plus the
+// tail instead of n windows.  The reduction keeps the lowest rank on ties
+// because each lane meets its ranks in increasing order.
+#include <hip/hip_runtime.h>
+
+#include "tables_dev.h"
+#include "tgo_internal.h"
+
+namespace tgo {
+
+constexpr int EX_THREADS = 256;
+constexpr int EX_MAX_BLOCKS_PER_PASS = 4096;
+
+template <typename TT>
+struct Acc {
+    TT min_t;        // smallest T seen
+    TT max_t1;       // largest T seen, plus one (0 = none yet)
+    uint64_t min_r, max_r;
+    uint64_t sum_lo, sum_hi;
+    uint64_t fp;
+};
+
+template <typename TT>
+__device__ __forceinline__ void acc_init(Acc<TT> &a) {
+    a.min_t = inf_time<TT>();
+    a.max_t1 = 0;
+    a.min_r = ~0ull;
+    a.max_r = ~0ull;
+    a.sum_lo = 0;
+    a.sum_hi = 0;
+    a.fp = 0;
+}
+
+template <typename TT, bool STORE>
+__device__ __forceinline__ void leaf(TT T, uint64_t rank, Acc<TT> &a, int64_t *out) {
+    if (T < a.min_t) { a.min_t = T; a.min_r = rank; }
+    if (T >= a.max_t1) { a.max_t1 = T + 1; a.max_r = rank; }
+    if constexpr (sizeof(TT) == 8) {
+        a.sum_lo += (uint64_t)T;
+        a.sum_hi += (a.sum_lo < (uint64_t)T) ? 1ull : 0ull;
+    } else {
+        a.sum_lo += (uint64_t)T;
+    }
+    a.fp += (2ull * rank + 1ull) * (uint64_t)T;
+    if constexpr (STORE) out[rank] = (int64_t)T;
+}
+
+struct Ctx {
+    int n;
+    Rates r;
+    int64_t *out;
+};
+
+// Level with L positions left (position n - L is being chosen).
+template <typename TT, int L, bool STORE>
+__device__ __forceinline__ void level(const Ctx &c, const View<TT> &v, const Lane<TT> &s,
+                                      uint64_t list, uint64_t rank, Acc<TT> &a) {
+    const int j = c.n - L;
+#pragma unroll 1
+    for (int ci = 0; ci < L; ++ci) {
+        const uint32_t x = (uint32_t)(list >> (4 * ci)) & 15u;
+        Lane<TT> s2 = s;
+        window(s2, j, x, v, c.r);
+        const uint64_t r2 = rank + (uint64_t)ci * factorial(L - 1);
+        if constexpr (L == 1) {
+            leaf<TT, STORE>(tail(s2, c.n, v, c.r), r2, a, c.out);
+        } else {
+            const uint64_t lo = list & ((1ull << (4 * ci)) - 1ull);
+            const uint64_t hi = (list >> (4 * ci + 4)) << (4 * ci);
+            level<TT, L - 1, STORE>(c, v, s2, lo | hi, r2, a);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_xor64(T v, int m) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = __shfl_xor((uint32_t)u, m);
+    const uint32_t hi = __shfl_xor((uint32_t)(u >> 32), m);
+    return (T)(((uint64_t)hi << 32) | lo);
+}
+
+// (t, r) pairs: smaller t wins, ties to smaller r.
+__device__ __forceinline__ void merge_min(uint64_t &t, uint64_t &r, uint64_t t2, uint64_t r2) {
+    if (t2 < t || (t2 == t && r2 < r)) { t = t2; r = r2; }
+}
+// larger t wins (t is max+1, 0 = none), ties to smaller r.
+__device__ __forceinline__ void merge_max(uint64_t &t, uint64_t &r, uint64_t t2, uint64_t r2) {
+    if (t2 > t || (t2 == t && r2 < r)) { t = t2; r = r2; }
+}
+
+__device__ __forceinline__ void add128(uint64_t &lo, uint64_t &hi, uint64_t lo2, uint64_t hi2) {
+    const uint64_t s = lo + lo2;
+    hi += hi2 + (s < lo ? 1ull : 0ull);
+    lo = s;
+}
+
+// Reduce a block's lane accumulators into one Partial (thread 0 writes it).
+__device__ void block_reduce_write(Partial p, Partial *dst) {
+    __shared__ Partial wsum[EX_THREADS / 64];
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t mt = shfl_xor64(p.min_t, m), mr = shfl_xor64(p.min_r, m);
+        const uint64_t xt = shfl_xor64(p.max_t, m), xr = shfl_xor64(p.max_r, m);
+        const uint64_t sl = shfl_xor64(p.sum_lo, m), sh = shfl_xor64(p.sum_hi, m);
+        const uint64_t f = shfl_xor64(p.fp, m);
+        merge_min(p.min_t, p.min_r, mt, mr);
+        merge_max(p.max_t, p.max_r, xt, xr);
+        add128(p.sum_lo, p.sum_hi, sl, sh);
+        p.fp += f;
+    }
+    const int w = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0) wsum[w] = p;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Partial o = wsum[0];
+        for (int i = 1; i < (int)(blockDim.x / 64); ++i) {
+            merge_min(o.min_t, o.min_r, wsum[i].min_t, wsum[i].min_r);
+            merge_max(o.max_t, o.max_r, wsum[i].max_t, wsum[i].max_r);
+            add128(o.sum_lo, o.sum_hi, wsum[i].sum_lo, wsum[i].sum_hi);
+            o.fp += wsum[i].fp;
+        }
+        o.status = 0;
+        o.pad = 0;
+        *dst = o;
+    }
+}
+
+// MODE: 0 = 32-bit time path, 1 = 64-bit.  Both instantiations are launched;
+// a block whose group does not belong to its mode returns at once.
+template <typename TT, int M, bool STORE>
+__global__ __launch_bounds__(EX_THREADS) void exhaustive_kernel(const tgo_task *__restrict__ tasks,
+                                                                int n, Rates r, uint32_t n_sub,
+                                                                int64_t *out, Partial *partials) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int MODE = sizeof(TT) == 4 ? 0 : 1;
+    __shared__ Pair<TT> Ht[MAXN];
+    __shared__ TT Kt[MAXN];
+    __shared__ Pair<TT> Dt[MAXN];
+    __shared__ int mode;
+    if (threadIdx.x == 0) mode = classify_group(tasks, n, r);
+    if ((int)threadIdx.x < n) table_entry<TT>(tasks[threadIdx.x], r, &Ht[threadIdx.x], &Kt[threadIdx.x], &Dt[threadIdx.x]);
+    __syncthreads();
+    if (mode < 0) {
+        if (MODE == 0 && threadIdx.x == 0) {
+            Partial p = {};
+            p.status = mode;
+            partials[blockIdx.x] = p;
+        }
+        return;
+    }
+    if (mode != MODE) return;
+
+    View<TT> v;
+    v.H = Ht;
+    v.K = Kt;
+    v.D = Dt;
+    v.Q = reinterpret_cast<Slot<TT> *>(smem) + threadIdx.x;
+    v.tstride = 1;
+    v.qstride = blockDim.x;
+    Ctx c;
+    c.n = n;
+    c.r = r;
+    c.out = out;
+
+    Acc<TT> a;
+    acc_init(a);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_sub; s += stride) {
+        // Decode the prefix: digit i of rank s*M! in the factorial base.
+        uint64_t list = 0;
+        for (int i = n - 1; i >= 0; --i) list = (list << 4) | (uint64_t)i;
+        Lane<TT> st = lane_init<TT>();
+        const int plen = n - M;
+        uint32_t rem = s;
+        // block size of position i in subtree units: (n-1-i)!/M!
+        uint32_t blk = 1;
+        for (int i = M + 1; i <= n - 1; ++i) blk *= (uint32_t)i;
+        for (int i = 0; i < plen; ++i) {
+            const uint32_t cdig = rem / blk;
+            rem -= cdig * blk;
+            if (i + 1 < plen) blk /= (uint32_t)(n - 1 - i);
+            const uint32_t x = (uint32_t)(list >> (4 * cdig)) & 15u;
+            const uint64_t lo = list & ((1ull << (4 * cdig)) - 1ull);
+            const uint64_t hi = (list >> (4 * cdig + 4)) << (4 * cdig);
+            list = lo | hi;
+            window(st, i, x, v, r);
+        }
+        level<TT, M, STORE>(c, v, st, list, (uint64_t)s * factorial(M), a);
+    }
+    Partial p;
+    p.min_t = (uint64_t)a.min_t;
+    p.min_r = a.min_r;
+    if constexpr (sizeof(TT) == 4) {
+        p.min_t = a.min_t == inf_time<TT>() ? ~0ull : (uint64_t)a.min_t;
+    }
+    p.max_t = (uint64_t)a.max_t1;
+    p.max_r = a.max_r;
+    p.sum_lo = a.sum_lo;
+    p.sum_hi = a.sum_hi;
+    p.fp = a.fp;
+    p.status = 0;
+    p.pad = 0;
+    block_reduce_write(p, &partials[blockIdx.x]);
+}
+
+__device__ inline void unrank_dev(int n, uint64_t r, uint8_t *out) {
+    uint64_t list = 0;
+    for (int i = n - 1; i >= 0; --i) list = (list << 4) | (uint64_t)i;
+    uint64_t f = 1;
+    for (int i = 2; i <= n - 1; ++i) f *= (uint64_t)i;
+    for (int i = 0; i < n; ++i) {
+        const uint64_t cd = f ? r / f : 0;
+        r -= cd * f;
+        if (n - 1 - i > 0) f /= (uint64_t)(n - 1 - i);
+        out[i] = (uint8_t)((list >> (4 * cd)) & 15u);
+        const uint64_t lo = list & ((1ull << (4 * cd)) - 1ull);
+        const uint64_t hi = (list >> (4 * cd + 4)) << (4 * cd);
+        list = lo | hi;
+    }
+    for (int i = n; i < 16; ++i) out[i] = 0xff;
+}
+
+__global__ __launch_bounds__(256) void exhaustive_finalize(const Partial *__restrict__ parts,
+                                                           int nparts, int n, uint64_t count,
+                                                           tgo_summary *out) {
+    __shared__ Partial red[256];
+    __shared__ int status;
+    if (threadIdx.x == 0) status = 0;
+    __syncthreads();
+    Partial p;
+    p.min_t = ~0ull; p.min_r = ~0ull; p.max_t = 0; p.max_r = ~0ull;
+    p.sum_lo = 0; p.sum_hi = 0; p.fp = 0; p.status = 0; p.pad = 0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
+        const Partial q = parts[i];
+        if (q.status != 0) atomicMin(&status, q.status);
+        merge_min(p.min_t, p.min_r, q.min_t, q.min_r);
+        merge_max(p.max_t, p.max_r, q.max_t, q.max_r);
+        add128(p.sum_lo, p.sum_hi, q.sum_lo, q.sum_hi);
+        p.fp += q.fp;
+    }
+    red[threadIdx.x] = p;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            Partial q = red[threadIdx.x + s];
+            Partial &o = red[threadIdx.x];
+            merge_min(o.min_t, o.min_r, q.min_t, q.min_r);
+            merge_max(o.max_t, o.max_r, q.max_t, q.max_r);
+            add128(o.sum_lo, o.sum_hi, q.sum_lo, q.sum_hi);
+            o.fp += q.fp;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        tgo_summary s;
+        const Partial &o = red[0];
+        s.n = n;
+        s.status = status;
+        s.count = count;
+        for (int i = 0; i < 16; ++i) { s.best[i] = 0xff; s.worst[i] = 0xff; }
+        if (status != 0) {
+            s.min_ns = s.max_ns = 0;
+            s.argmin_rank = s.argmax_rank = 0;
+            s.sum_lo = s.sum_hi = 0;
+            s.fingerprint = 0;
+            s.mean_ns = 0.0;
+        } else {
+            s.min_ns = (int64_t)o.min_t;
+            s.argmin_rank = o.min_r;
+            s.max_ns = (int64_t)(o.max_t - 1);
+            s.argmax_rank = o.max_r;
+            s.sum_lo = o.sum_lo;
+            s.sum_hi = o.sum_hi;
+            s.fingerprint = o.fp;
+            // mean = sum / count: whole part exactly, then the fraction
+            double mean;
+            if (o.sum_hi == 0) {
+                const uint64_t qt = o.sum_lo / count, rm = o.sum_lo % count;
+                mean = (double)qt + (double)rm / (double)count;
+            } else {
+                mean = ((double)o.sum_hi * 18446744073709551616.0 + (double)o.sum_lo) / (double)count;
+            }
+            s.mean_ns = mean;
+            unrank_dev(n, o.min_r, s.best);
+            unrank_dev(n, o.max_r, s.worst);
+        }
+        *out = s;
+    }
+}
+
+// Positions enumerated depth-first per lane: enough subtrees to fill the GPU.
+static int choose_m(int n) {
+    int m = 1;
+    for (int c = 5; c >= 1; --c) {
+        if (c > n) continue;
+        const uint64_t sub = factorial(n) / factorial(c);
+        if (sub >= 32768 || c == 1) { m = c; break; }
+    }
+    if (n <= 5) m = n < 1 ? 1 : n;
+    return m;
+}
+
+template <int M, bool STORE>
+static void launch_pair(dim3 grid, size_t shm32, size_t shm64, hipStream_t st, const tgo_task *t,
+                        int n, const Rates &r, uint32_t n_sub, int64_t *out, Partial *parts) {
+    hipLaunchKernelGGL((exhaustive_kernel<uint32_t, M, STORE>), grid, dim3(EX_THREADS), shm32, st,
+                       t, n, r, n_sub, out, parts);
+    hipLaunchKernelGGL((exhaustive_kernel<uint64_t, M, STORE>), grid, dim3(EX_THREADS), shm64, st,
+                       t, n, r, n_sub, out, parts);
+}
+
+template <bool STORE>
+static void launch_m(int m, dim3 grid, size_t shm32, size_t shm64, hipStream_t st,
+                     const tgo_task *t, int n, const Rates &r, uint32_t n_sub, int64_t *out,
+                     Partial *parts) {
+    switch (m) {
+        case 1: launch_pair<1, STORE>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
+        case 2: launch_pair<2, STORE>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
+        case 3: launch_pair<3, STORE>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
+        case 4: launch_pair<4, STORE>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
+        default: launch_pair<5, STORE>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
+    }
+}
+
+int launch_exhaustive(const Rates &r, const tgo_task *d_tasks, int n, int64_t *d_per_order,
+                      tgo_summary *d_out, hipStream_t st) {
+    const int m = choose_m(n);
+    const uint64_t n_sub64 = factorial(n) / factorial(m);
+    if (n_sub64 >= (1ull << 32)) return fail(TGO_EINVAL, "group too large to enumerate");
+    const uint32_t n_sub = (uint32_t)n_sub64;
+    const uint64_t lanes_per_pass = (uint64_t)EX_THREADS * EX_MAX_BLOCKS_PER_PASS;
+    const uint64_t passes = (n_sub64 + lanes_per_pass - 1) / lanes_per_pass;
+    const uint64_t per_block = (uint64_t)EX_THREADS * passes;
+    const uint32_t blocks = (uint32_t)((n_sub64 + per_block - 1) / per_block);
+    Partial *parts = nullptr;
+    int rc = workspace(sizeof(Partial) * blocks, (void **)&parts);
+    if (rc) return rc;
+    const size_t shm32 = sizeof(Slot<uint32_t>) * EX_THREADS * n;
+    const size_t shm64 = sizeof(Slot<uint64_t>) * EX_THREADS * n;
+    if (d_per_order)
+        launch_m<true>(m, dim3(blocks), shm32, shm64, st, d_tasks, n, r, n_sub, d_per_order, parts);
+    else
+        launch_m<false>(m, dim3(blocks), shm32, shm64, st, d_tasks, n, r, n_sub, nullptr, parts);
+    TGO_HIP(hipGetLastError());
+    hipLaunchKernelGGL(exhaustive_finalize, dim3(1), dim3(256), 0, st, parts, (int)blocks, n,
+                       factorial(n), d_out);
+    TGO_HIP(hipGetLastError());
+    return TGO_OK;
+}
+
+}  // namespace tgo

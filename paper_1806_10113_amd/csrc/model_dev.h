@@ -1,0 +1,184 @@
+// Device-side temporal execution model (gfx950).
+//
+// The model is the FIFO simulator of Section 4.1 for a two-DMA device
+// (launch scheme of Section 3.2 with three command queues), with the
+// overlapped-transfer slowdown of Section 4.2.1 read as constant rates p/q.
+// Integer nanoseconds; remaining transfer work exact in 1/q solo-ns units; a
+// completion estimate is rounded up to a whole nanosecond.
+//
+// GPU formulation (same results as stepping every event):
+//   * The HtD engine is busy without a gap from t = 0 until the last HtD
+//     completes, so the DtH rate is p_dth/q for every DtH that starts before
+//     that instant and q/q afterwards.  The HtD rate changes only when the
+//     DtH engine goes idle or starts from idle.
+//   * Between rate changes an end estimate stays valid, because
+//     ceil((U - r*D)/r) = ceil(U/r) - D for a whole number of ns D.  So each
+//     running transfer carries its absolute end time, and the remaining work is
+//     recomputed (one multiply) only when its rate changes.
+//   * The kernel engine needs no events of its own: K_j = max(HtD_j end,
+//     K_{j-1} end) + k.  A kernel completion matters only to the DtH engine,
+//     which reads it from a per-lane queue in LDS (slot j = K_j end, task).
+//   * The simulation is cut into "windows": window j runs from the start to
+//     the end of HtD at position j and processes the DtH events inside it.
+//     The state at the start of window j depends only on positions < j, which
+//     lets an enumeration share the windows of a common prefix.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tgo {
+
+constexpr int MAXN = 16;
+
+// Host-prepared model constants.
+struct Rates {
+    int32_t q_log2;
+    uint32_t p_h, p_d;
+    // ceil(u / p) for u < 2^32 as trunc(fma(u, 1/p, (p - 1/2)/p)).  The exact
+    // value (u + p - 1/2)/p lies at least 1/(2p) away from the integers that
+    // bound ceil(u/p); the double rounding error is below 2^-19 for u < 2^32,
+    // so for p <= 1024 the truncation is exact.
+    double inv_ph, c_ph;
+    double inv_pd, c_pd;
+};
+
+template <typename TT>
+struct alignas(2 * sizeof(TT)) Pair {
+    TT a, b;  // (solo duration, duration when fully overlapped)
+};
+
+template <typename TT>
+struct alignas(2 * sizeof(TT)) Slot {
+    TT ck;       // completion time of the kernel at this position
+    uint32_t x;  // task at this position
+};
+
+template <typename TT>
+__device__ __forceinline__ TT ceil_q(TT u, int q_log2) {
+    return (u + ((TT(1) << q_log2) - 1)) >> q_log2;
+}
+
+__device__ __forceinline__ uint32_t ceil_p(uint32_t u, uint32_t, double inv, double c) {
+    return (uint32_t)__builtin_fma((double)u, inv, c);
+}
+__device__ __forceinline__ uint64_t ceil_p(uint64_t u, uint32_t p, double, double) {
+    return (u + p - 1) / p;
+}
+
+template <typename TT>
+__device__ __forceinline__ TT tmax(TT a, TT b) { return a > b ? a : b; }
+
+template <typename TT>
+__device__ __forceinline__ TT inf_time() { return ~TT(0); }
+
+// Task tables and the per-lane kernel-completion queue.  Entry x of a table
+// is at [x * tstride], slot j of the queue at [j * qstride]; shared tables use
+// tstride 1, per-lane tables interleave lanes so that a wave's accesses fall
+// into distinct banks.
+template <typename TT>
+struct View {
+    const Pair<TT> *H;  // (h, ceil(q h / p_h))
+    const TT *K;        // k
+    const Pair<TT> *D;  // (d, ceil(q d / p_d))
+    Slot<TT> *Q;
+    int tstride, qstride;
+    __device__ __forceinline__ Pair<TT> h(uint32_t x) const { return H[x * tstride]; }
+    __device__ __forceinline__ TT k(uint32_t x) const { return K[x * tstride]; }
+    __device__ __forceinline__ Pair<TT> d(uint32_t x) const { return D[x * tstride]; }
+    __device__ __forceinline__ Slot<TT> q(int j) const { return Q[j * qstride]; }
+    __device__ __forceinline__ void put(int j, Slot<TT> s) const { Q[j * qstride] = s; }
+};
+
+// Simulation state at the start of a window (an HtD about to start).
+template <typename TT>
+struct Lane {
+    TT t;        // now: end of the previous HtD (0 before the first)
+    TT ck;       // end of the previous kernel
+    TT ed;       // running DtH: end estimate
+    TT td0;      // running DtH: start time
+    TT wait;     // idle DtH: end of the kernel it waits for (inf if unknown)
+    uint32_t xd; // running DtH: task
+    int i;       // DtH cursor (position of the running or next DtH)
+    bool drun;   // DtH engine busy
+};
+
+template <typename TT>
+__device__ __forceinline__ Lane<TT> lane_init() {
+    Lane<TT> s;
+    s.t = 0; s.ck = 0; s.ed = 0; s.td0 = 0; s.wait = inf_time<TT>();
+    s.xd = 0; s.i = 0; s.drun = false;
+    return s;
+}
+
+// Window j: HtD of task x starts at s.t; process DtH events until it ends,
+// then derive the kernel of position j and record it in the queue.
+template <typename TT>
+__device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const View<TT> &v,
+                                       const Rates &r) {
+    const TT q = TT(1) << r.q_log2;
+    const Pair<TT> hx = v.h(x);
+    // a DtH waiting for the previous position's kernel now knows its time
+    if (!s.drun && s.i == j - 1) s.wait = s.ck;
+    TT uh = hx.a << r.q_log2;  // remaining HtD work at th0
+    TT th0 = s.t;
+    TT eh = s.t + (s.drun ? hx.b : hx.a);
+    for (;;) {
+        const TT ev = s.drun ? s.ed : s.wait;
+        if (!(ev < eh)) break;
+        // DtH event at ev: a completion (running) or a start from idle.
+        const int inew = s.drun ? s.i + 1 : s.i;
+        Slot<TT> nx;
+        nx.ck = inf_time<TT>();
+        nx.x = 0;
+        if (inew < j) nx = v.q(inew);
+        const bool start = inew < j && nx.ck <= ev;
+        // HtD work left at ev under the rate that held since th0.
+        const TT rate_old = s.drun ? TT(r.p_h) : q;
+        uh = uh - rate_old * (ev - th0);
+        th0 = ev;
+        eh = ev + (start ? (TT)ceil_p(uh, r.p_h, r.inv_ph, r.c_ph) : ceil_q(uh, r.q_log2));
+        if (start) {
+            s.xd = nx.x;
+            s.ed = ev + v.d(nx.x).b;
+            s.td0 = ev;
+        }
+        s.wait = start ? inf_time<TT>() : nx.ck;
+        s.drun = start;
+        s.i = inew;
+    }
+    s.t = eh;
+    s.ck = tmax(eh, s.ck) + v.k(x);
+    Slot<TT> sl;
+    sl.ck = s.ck;
+    sl.x = x;
+    v.put(j, sl);
+}
+
+// After the last HtD (position n-1) has ended at s.t: the DtH engine runs at
+// full speed; finish the queue.  Returns the end of the last DtH.
+template <typename TT>
+__device__ __forceinline__ TT tail(const Lane<TT> &s, int n, const View<TT> &v, const Rates &r) {
+    TT dend = 0;
+    int i = s.i;
+    if (s.drun) {
+        const TT qd = v.d(s.xd).a << r.q_log2;
+        const TT done = TT(r.p_d) * (s.t - s.td0);
+        const TT ud = done >= qd ? TT(0) : qd - done;
+        dend = s.t + ceil_q(ud, r.q_log2);
+        ++i;
+    }
+    for (; i < n; ++i) {
+        const Slot<TT> sl = v.q(i);
+        dend = tmax(dend, sl.ck) + v.d(sl.x).a;
+    }
+    return dend;
+}
+
+// Host-side validity bound for the 32-bit time path (checked on the device
+// from the task table): every work amount fits 31 bits and every instant of
+// the simulation fits 31 bits.  T never exceeds the sum of each command's
+// slowest duration plus one ns of rounding per rate change per command.
+__host__ __device__ inline uint64_t time_bound_slack(int n) { return 3ull * n * (2ull * n + 2ull); }
+
+}  // namespace tgo

@@ -1,0 +1,52 @@
+// Internal host-side helpers shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/tgo.h"
+#include "model_dev.h"
+
+namespace tgo {
+
+// Thread-local error detail behind tgo_last_error().
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define TGO_HIP(call)                                      \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return ::tgo::hip_fail(e_, #call); \
+    } while (0)
+
+// Validate a model and derive the kernel constants.
+int make_rates(const tgo_model *m, Rates *r);
+
+// Per-device workspace owned by the library, grown on demand and kept until
+// the process ends.  Not safe for overlapping calls on different streams of
+// one device that both need it (each call serialises through a mutex and the
+// buffer is stream-ordered per call).
+int workspace(size_t bytes, void **ptr);
+
+constexpr uint64_t factorial(int n) { return n <= 1 ? 1ull : (uint64_t)n * factorial(n - 1); }
+
+// Device-side validity of a task table: 0 (32-bit time path), 1 (64-bit path)
+// or a negative TGO_E* code.  Durations must lie in [0, 2^40) ns.
+constexpr int64_t MAX_DURATION = int64_t(1) << 40;
+
+struct Partial {
+    uint64_t min_t, min_r, max_t, max_r, sum_lo, sum_hi, fp;
+    int32_t status, pad;
+};
+
+int launch_exhaustive(const Rates &r, const tgo_task *d_tasks, int n, int64_t *d_per_order,
+                      tgo_summary *d_out, hipStream_t st);
+int launch_evaluate(const Rates &r, const tgo_task *d_tasks, int n, const uint8_t *d_orders,
+                    int64_t m, int64_t *d_out, hipStream_t st);
+int launch_heuristic(const Rates &r, const tgo_task *d_tasks, const int32_t *d_offs, int n_groups,
+                     uint8_t *d_orders, int64_t *d_ns, hipStream_t st);
+
+}  // namespace tgo

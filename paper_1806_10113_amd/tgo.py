@@ -1,0 +1,185 @@
+"""Python binding of libtgo.so: argument marshalling only.
+
+Device memory and streams come from PyTorch (ROCm); every step of the model
+runs in the library's HIP kernels.  If the library is missing this module
+raises at the first call: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtgo.so")
+
+TGO_OK, TGO_EINVAL, TGO_ERANGE, TGO_ENOMEM, TGO_EDEVICE = 0, -1, -2, -3, -4
+MAX_N = 16
+MAX_EXHAUSTIVE_N = 13
+
+
+class TgoError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: error {code} ({detail})")
+        self.code = code
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [("dma_engines", ctypes.c_int32), ("q_log2", ctypes.c_int32),
+                ("p_htd", ctypes.c_int32), ("p_dth", ctypes.c_int32)]
+
+
+SUMMARY_DTYPE = np.dtype([
+    ("min_ns", "<i8"), ("max_ns", "<i8"), ("argmin_rank", "<u8"), ("argmax_rank", "<u8"),
+    ("sum_lo", "<u8"), ("sum_hi", "<u8"), ("count", "<u8"), ("fingerprint", "<u8"),
+    ("mean_ns", "<f8"), ("status", "<i4"), ("n", "<i4"), ("best", "u1", (16,)),
+    ("worst", "u1", (16,)),
+])
+assert SUMMARY_DTYPE.itemsize == 112
+
+
+@dataclass(frozen=True)
+class Model:
+    """Overlapped HtD/DtH advance at p_htd/q and p_dth/q of solo speed, q = 2**q_log2."""
+
+    q_log2: int = 2
+    p_htd: int = 3
+    p_dth: int = 3
+    dma_engines: int = 2
+
+    @property
+    def q(self) -> int:
+        return 1 << self.q_log2
+
+    def _c(self) -> _Model:
+        return _Model(self.dma_engines, self.q_log2, self.p_htd, self.p_dth)
+
+
+DEFAULT = Model(2, 3, 3)
+PAPER_EXAMPLE = Model(3, 3, 3)
+NO_SLOWDOWN = Model(0, 1, 1)
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_1806_10113_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+        M = ctypes.POINTER(_Model)
+        L.tgo_strerror.restype = ctypes.c_char_p
+        L.tgo_strerror.argtypes = [i32]
+        L.tgo_last_error.restype = ctypes.c_char_p
+        L.tgo_last_error.argtypes = []
+        L.tgo_version.restype = i32
+        L.tgo_evaluate.argtypes = [M, vp, i32, vp, i64, vp, vp]
+        L.tgo_exhaustive.argtypes = [M, vp, i32, vp, vp, vp]
+        L.tgo_heuristic.argtypes = [M, vp, vp, i32, vp, vp, vp]
+        L.tgo_rank.argtypes = [i32, vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.tgo_unrank.argtypes = [i32, ctypes.c_uint64, vp]
+        for f in (L.tgo_evaluate, L.tgo_exhaustive, L.tgo_heuristic, L.tgo_rank, L.tgo_unrank):
+            f.restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != TGO_OK:
+        L = lib()
+        raise TgoError(rc, where, f"{L.tgo_strerror(rc).decode()}: {L.tgo_last_error().decode()}")
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dev_tensor(x, dtype, shape_last=None, name="tensor"):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if x.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {x.dtype}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_last is not None and (x.dim() < 1 or x.shape[-1] != shape_last):
+        raise ValueError(f"{name} must have last dimension {shape_last}")
+    return x
+
+
+def evaluate(tasks, orders, model: Model = DEFAULT, out=None, stream=None):
+    """T (int64 ns) for each row of ``orders`` (uint8 [m, n]); tasks int64 [n, 3]."""
+    import torch
+    _dev_tensor(tasks, torch.int64, 3, "tasks")
+    _dev_tensor(orders, torch.uint8, None, "orders")
+    n = tasks.shape[0]
+    if orders.dim() != 2 or orders.shape[1] != n:
+        raise ValueError("orders must be [m, n]")
+    m = orders.shape[0]
+    if out is None:
+        out = torch.empty(m, dtype=torch.int64, device=tasks.device)
+    _dev_tensor(out, torch.int64, None, "out")
+    _check(lib().tgo_evaluate(ctypes.byref(model._c()), tasks.data_ptr(), n, orders.data_ptr(), m,
+                              out.data_ptr(), _stream(stream)), "tgo_evaluate")
+    return out
+
+
+def exhaustive(tasks, model: Model = DEFAULT, per_order: bool = False, summary=None, stream=None):
+    """Enumerate all n! orderings.  Returns (summary uint8[112] device tensor,
+    per-ordering int64[n!] device tensor or None)."""
+    import math
+    import torch
+    _dev_tensor(tasks, torch.int64, 3, "tasks")
+    n = tasks.shape[0]
+    po = None
+    if per_order:
+        po = torch.empty(math.factorial(n), dtype=torch.int64, device=tasks.device)
+    if summary is None:
+        summary = torch.empty(SUMMARY_DTYPE.itemsize, dtype=torch.uint8, device=tasks.device)
+    _check(lib().tgo_exhaustive(ctypes.byref(model._c()), tasks.data_ptr(), n,
+                                po.data_ptr() if po is not None else None, summary.data_ptr(),
+                                _stream(stream)), "tgo_exhaustive")
+    return summary, po
+
+
+def read_summary(summary) -> dict:
+    """Copy a device summary to the host and decode it."""
+    raw = summary.cpu().numpy().view(SUMMARY_DTYPE)[0]
+    n = int(raw["n"])
+    d = {k: raw[k].item() for k in SUMMARY_DTYPE.names if k not in ("best", "worst")}
+    d["sum"] = int(raw["sum_lo"]) | (int(raw["sum_hi"]) << 64)
+    d["best"] = [int(v) for v in raw["best"][:n]]
+    d["worst"] = [int(v) for v in raw["worst"][:n]]
+    return d
+
+
+def heuristic(tasks, offs, model: Model = DEFAULT, stream=None):
+    """Algorithm 1 on every group of a CSR batch.  Returns (orders uint8 [G, 16], T int64 [G])."""
+    import torch
+    _dev_tensor(tasks, torch.int64, 3, "tasks")
+    _dev_tensor(offs, torch.int32, None, "offs")
+    g = offs.shape[0] - 1
+    orders = torch.empty((max(g, 0), 16), dtype=torch.uint8, device=tasks.device)
+    ns = torch.empty(max(g, 0), dtype=torch.int64, device=tasks.device)
+    _check(lib().tgo_heuristic(ctypes.byref(model._c()), tasks.data_ptr(), offs.data_ptr(), g,
+                               orders.data_ptr(), ns.data_ptr(), _stream(stream)), "tgo_heuristic")
+    return orders, ns
+
+
+def rank(order) -> int:
+    o = np.ascontiguousarray(np.asarray(order, dtype=np.uint8))
+    r = ctypes.c_uint64()
+    _check(lib().tgo_rank(len(o), o.ctypes.data, ctypes.byref(r)), "tgo_rank")
+    return r.value
+
+
+def unrank(n: int, r: int):
+    o = np.zeros(16, dtype=np.uint8)
+    _check(lib().tgo_unrank(n, r, o.ctypes.data), "tgo_unrank")
+    return [int(v) for v in o[:n]]

@@ -1,0 +1,84 @@
+"""The C ABI library: loads, exports every declared symbol, rejects bad
+arguments on the host (no device call is made for these)."""
+import ctypes
+import itertools
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import model as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tgo.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(tgo_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1806_10113_amd import tgo
+    if not os.path.exists(tgo.LIB_PATH):
+        pytest.fail("libtgo.so is not built (python -m paper_1806_10113_amd.build)")
+    return tgo.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert "tgo_exhaustive" in names and "tgo_evaluate" in names and "tgo_heuristic" in names
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_strerror_and_version(L):
+    assert L.tgo_version() >= 1
+    for code in (0, -1, -2, -3, -4):
+        assert L.tgo_strerror(code)
+
+
+def test_host_argument_errors(L):
+    from paper_1806_10113_amd import tgo
+    bad_models = [tgo._Model(1, 2, 3, 3), tgo._Model(2, 11, 3, 3), tgo._Model(2, 2, 0, 3),
+                  tgo._Model(2, 2, 3, 5)]
+    fake = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    for m in bad_models:
+        assert L.tgo_exhaustive(ctypes.byref(m), fake, 4, None, fake, None) == tgo.TGO_EINVAL
+        assert L.tgo_evaluate(ctypes.byref(m), fake, 4, fake, 1, fake, None) == tgo.TGO_EINVAL
+        assert L.tgo_heuristic(ctypes.byref(m), fake, fake, 1, fake, fake, None) == tgo.TGO_EINVAL
+    good = tgo.DEFAULT._c()
+    assert L.tgo_exhaustive(None, fake, 4, None, fake, None) == tgo.TGO_EINVAL
+    assert L.tgo_exhaustive(ctypes.byref(good), fake, 0, None, fake, None) == tgo.TGO_EINVAL
+    assert L.tgo_exhaustive(ctypes.byref(good), fake, 14, None, fake, None) == tgo.TGO_EINVAL
+    assert L.tgo_exhaustive(ctypes.byref(good), fake, 13, fake, fake, None) == tgo.TGO_EINVAL
+    assert L.tgo_exhaustive(ctypes.byref(good), None, 4, None, fake, None) == tgo.TGO_EINVAL
+    assert L.tgo_evaluate(ctypes.byref(good), fake, 17, fake, 1, fake, None) == tgo.TGO_EINVAL
+    assert L.tgo_evaluate(ctypes.byref(good), fake, 4, fake, -1, fake, None) == tgo.TGO_EINVAL
+    assert L.tgo_evaluate(ctypes.byref(good), None, 4, fake, 3, fake, None) == tgo.TGO_EINVAL
+    assert L.tgo_heuristic(ctypes.byref(good), fake, fake, -1, fake, fake, None) == tgo.TGO_EINVAL
+    assert b"n must be" in L.tgo_last_error() or L.tgo_last_error()
+
+
+def test_rank_unrank_match_lexicographic_order():
+    from paper_1806_10113_amd import tgo
+    for n in range(1, 7):
+        for r, p in enumerate(itertools.permutations(range(n))):
+            assert tgo.rank(p) == r
+            assert tuple(tgo.unrank(n, r)) == p
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        n = int(rng.integers(7, 17))
+        p = list(rng.permutation(n))
+        r = tgo.rank(p)
+        assert r == M.lehmer_rank(p)
+        assert tgo.unrank(n, r) == p
+    with pytest.raises(tgo.TgoError):
+        tgo.unrank(5, math.factorial(5))
+    with pytest.raises(tgo.TgoError):
+        tgo.rank([0, 0, 1])
