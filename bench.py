@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # VALU instructions issued per ordering by the exhaustive kernel on this
 # workload (SQ_INSTS_VALU per launch / 12!, from the rocprofv3 counter run
 # recorded in profiles/exhaustive_n12_counters.txt); x64 lanes = lane-ops.
-VALU_INSTS_PER_ORDERING = None
+VALU_INSTS_PER_ORDERING = 327.18 / 64  # wave-instructions per ordering
 # HBM bytes per launch from FETCH_SIZE + WRITE_SIZE (same profile), scaled by
 # the copy-kernel calibration; None until measured for the current kernel.
 TRAFFIC_BYTES_PER_LAUNCH = None
