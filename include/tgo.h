@@ -87,6 +87,8 @@ typedef struct {
     int32_t status;                    /* TGO_OK or the TGO_E* found on the device */
     int32_t n;
     uint8_t best[16], worst[16];       /* orderings at argmin / argmax            */
+    uint8_t heur[16];                  /* Algorithm-1 ordering (tgo_batch only;    */
+    int64_t heur_ns;                   /*  0xff / -1 when not computed)           */
 } tgo_summary;
 
 const char *tgo_strerror(int code);
@@ -133,6 +135,37 @@ int tgo_exhaustive(const tgo_model *model, const tgo_task *d_tasks, int n, int64
  */
 int tgo_heuristic(const tgo_model *model, const tgo_task *d_tasks, const int32_t *d_offs,
                   int n_groups, uint8_t *d_orders, int64_t *d_ns, tgo_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched enumeration: many groups of uneven size in one persistent launch.
+ * The paper's runtime reorders the task group that its proxy thread finds
+ * waiting (Section 6.2); a batch holds many such groups.
+ *
+ * tgo_plan_create  -- device workspace for up to max_groups groups (allocated
+ *                     here, freed by tgo_plan_destroy) and a capture stream.
+ * tgo_plan_autotune-- times candidate work decompositions (positions
+ *                     enumerated per lane by group size, subtrees per lane per
+ *                     tile, persistent grid size) on the given batch and keeps
+ *                     the fastest.  Blocks until done; overwrites d_out.
+ * tgo_plan_describe-- the chosen decomposition as a JSON object.
+ * tgo_batch        -- for every group g of the CSR batch (tasks
+ *                     d_tasks[d_offs[g] .. d_offs[g+1])), writes d_out[g]: the
+ *                     full-enumeration summary plus the heuristic ordering
+ *                     (heur, heur_ns).  Group sizes 1..12; a group whose
+ *                     predicted times could reach 2^31 ns gets status
+ *                     TGO_ERANGE (use tgo_exhaustive for it).  The launch
+ *                     sequence is captured once into a HIP graph and replayed
+ *                     while (d_tasks, d_offs, n_groups, d_out) stay the same.
+ *                     Calls on one plan must not overlap on different streams.
+ */
+typedef struct tgo_plan tgo_plan;
+int tgo_plan_create(const tgo_model *model, int max_groups, tgo_plan **out);
+int tgo_plan_autotune(tgo_plan *plan, const tgo_task *d_tasks, const int32_t *d_offs, int n_groups,
+                      tgo_summary *d_out, tgo_stream stream);
+int tgo_plan_describe(const tgo_plan *plan, char *buf, size_t len);
+int tgo_batch(tgo_plan *plan, const tgo_task *d_tasks, const int32_t *d_offs, int n_groups,
+              tgo_summary *d_out, tgo_stream stream);
+void tgo_plan_destroy(tgo_plan *plan);
 
 /* Host helpers: lexicographic rank <-> ordering (index arithmetic only). */
 int tgo_rank(int n, const uint8_t *h_order, uint64_t *rank);

@@ -122,7 +122,7 @@ int tgo_heuristic(const tgo_model *model, const tgo_task *d_tasks, const int32_t
     if (rc) return rc;
     if (n_groups < 0) return fail(TGO_EINVAL, "n_groups must be >= 0");
     if (n_groups > 0 && (!d_tasks || !d_offs || !d_orders || !d_ns)) return fail(TGO_EINVAL, "NULL buffer");
-    return launch_heuristic(r, d_tasks, d_offs, n_groups, d_orders, d_ns, (hipStream_t)stream);
+    return launch_heuristic(r, d_tasks, d_offs, n_groups, d_orders, 16, d_ns, 1, (hipStream_t)stream);
 }
 
 int tgo_rank(int n, const uint8_t *h_order, uint64_t *rank) {

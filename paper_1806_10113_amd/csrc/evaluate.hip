@@ -31,13 +31,11 @@ __global__ __launch_bounds__(EV_THREADS) void evaluate_kernel(const tgo_task *__
         return;
     }
     if (mode != MODE) return;
-    View<TT> v;
+    View<TT, 1, EV_THREADS> v;
     v.H = Ht;
     v.K = Kt;
     v.D = Dt;
     v.Q = reinterpret_cast<Slot<TT> *>(smem) + threadIdx.x;
-    v.tstride = 1;
-    v.qstride = blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
         const uint8_t *o = orders + i * n;
         uint32_t seen = 0;
@@ -91,7 +89,8 @@ __device__ __forceinline__ int64_t fit(int64_t h, int64_t k, const Fit3 &u) {
 __global__ __launch_bounds__(HEU_THREADS) void heuristic_kernel(const tgo_task *__restrict__ tasks,
                                                                 const int32_t *__restrict__ offs,
                                                                 int n_groups, Rates r,
-                                                                uint8_t *orders, int64_t *ns) {
+                                                                uint8_t *orders, int order_stride,
+                                                                int64_t *ns, int ns_stride) {
     using TT = uint64_t;
     __shared__ Pair<TT> Ht[MAXN * HEU_THREADS];
     __shared__ TT Kt[MAXN * HEU_THREADS];
@@ -101,25 +100,24 @@ __global__ __launch_bounds__(HEU_THREADS) void heuristic_kernel(const tgo_task *
     if (g >= n_groups) return;
     const int base = offs[g];
     const int n = offs[g + 1] - base;
-    uint8_t *orow = orders + (size_t)g * 16;
+    uint8_t *orow = orders + (size_t)g * order_stride;
+    int64_t *nsg = ns + (size_t)g * ns_stride;
     for (int i = 0; i < 16; ++i) orow[i] = 0xff;
     if (n < 1 || n > MAXN) {
-        ns[g] = TGO_EINVAL;
+        *nsg = TGO_EINVAL;
         return;
     }
     const tgo_task *t = tasks + base;
     const int cls = classify_group(t, n, r);
     if (cls < 0) {
-        ns[g] = cls;
+        *nsg = cls;
         return;
     }
-    View<TT> v;
+    View<TT, HEU_THREADS, HEU_THREADS> v;
     v.H = Ht + threadIdx.x;
     v.K = Kt + threadIdx.x;
     v.D = Dt + threadIdx.x;
     v.Q = Qs + threadIdx.x;
-    v.tstride = blockDim.x;
-    v.qstride = blockDim.x;
     for (int x = 0; x < n; ++x)
         table_entry<TT>(t[x], r, &Ht[x * blockDim.x + threadIdx.x], &Kt[x * blockDim.x + threadIdx.x],
                         &Dt[x * blockDim.x + threadIdx.x]);
@@ -188,16 +186,17 @@ __global__ __launch_bounds__(HEU_THREADS) void heuristic_kernel(const tgo_task *
         window(st, pos, (uint32_t)x, v, r);
         ++pos;
     }
-    ns[g] = (int64_t)tail(st, n, v, r);
+    *nsg = (int64_t)tail(st, n, v, r);
     for (int i = 0; i < n; ++i) orow[i] = ord[i];
 }
 
 int launch_heuristic(const Rates &r, const tgo_task *d_tasks, const int32_t *d_offs, int n_groups,
-                     uint8_t *d_orders, int64_t *d_ns, hipStream_t st) {
+                     uint8_t *d_orders, int order_stride, int64_t *d_ns, int ns_stride,
+                     hipStream_t st) {
     if (n_groups == 0) return TGO_OK;
     const int blocks = (n_groups + HEU_THREADS - 1) / HEU_THREADS;
     hipLaunchKernelGGL(heuristic_kernel, dim3(blocks), dim3(HEU_THREADS), 0, st, d_tasks, d_offs,
-                       n_groups, r, d_orders, d_ns);
+                       n_groups, r, d_orders, order_stride, d_ns, ns_stride);
     TGO_HIP(hipGetLastError());
     return TGO_OK;
 }

@@ -4,16 +4,11 @@
 // Section 5.1 rule out at runtime on a CPU), reduced to the best, worst and
 // average ordering (the quantities plotted in Section 6).
 //
-// Work decomposition: ranks are lexicographic, so the orderings sharing a
-// prefix of length n - M form a contiguous block of M! ranks.  One lane owns
-// such a block ("subtree"): it decodes the prefix from the block index,
-// simulates the prefix windows once, then walks the last M positions depth
-// first in lexicographic order, re-simulating only the windows below the
-// position that changed.  Per ordering this costs about 1.72 windows plus the
-// tail instead of n windows.  The reduction keeps the lowest rank on ties
-// because each lane meets its ranks in increasing order.
+// One lane per subtree (see enum_dev.h); lanes meet their ranks in increasing
+// order, so the reduction keeps the lowest rank on ties.
 #include <hip/hip_runtime.h>
 
+#include "enum_dev.h"
 #include "tables_dev.h"
 #include "tgo_internal.h"
 
@@ -22,6 +17,7 @@ namespace tgo {
 constexpr int EX_THREADS = 256;
 constexpr int EX_MAX_BLOCKS_PER_PASS = 4096;
 
+// Per-lane accumulators over all ranks the lane owns.
 template <typename TT>
 struct Acc {
     TT min_t;        // smallest T seen
@@ -42,69 +38,22 @@ __device__ __forceinline__ void acc_init(Acc<TT> &a) {
     a.fp = 0;
 }
 
-template <typename TT, bool STORE>
-__device__ __forceinline__ void leaf(TT T, uint64_t rank, Acc<TT> &a, int64_t *out) {
-    if (T < a.min_t) { a.min_t = T; a.min_r = rank; }
-    if (T >= a.max_t1) { a.max_t1 = T + 1; a.max_r = rank; }
-    if constexpr (sizeof(TT) == 8) {
-        a.sum_lo += (uint64_t)T;
-        a.sum_hi += (a.sum_lo < (uint64_t)T) ? 1ull : 0ull;
-    } else {
-        a.sum_lo += (uint64_t)T;
-    }
-    a.fp += (2ull * rank + 1ull) * (uint64_t)T;
-    if constexpr (STORE) out[rank] = (int64_t)T;
+// Fold a finished subtree (first rank r0) into the lane accumulators.  The
+// lane meets its subtrees in increasing rank order, so strict comparisons
+// keep the lowest rank on ties.  fingerprint: sum of (2r+1) T with
+// r = r0 + l is 2 (r0 sum T + sum l T) + sum T.
+template <typename TT>
+__device__ __forceinline__ void fold(Acc<TT> &a, const Sub<TT> &u, uint64_t r0) {
+    if (u.min_t < a.min_t) { a.min_t = u.min_t; a.min_r = r0 + u.min_l; }
+    if (u.max_t1 > a.max_t1) { a.max_t1 = u.max_t1; a.max_r = r0 + u.max_l; }
+    const uint64_t lo = a.sum_lo + u.sum;
+    a.sum_hi += lo < a.sum_lo ? 1ull : 0ull;
+    a.sum_lo = lo;
+    a.fp += 2ull * (r0 * u.sum + u.s2) + u.sum;
 }
 
-struct Ctx {
-    int n;
-    Rates r;
-    int64_t *out;
-};
-
-// Level with L positions left (position n - L is being chosen).
-template <typename TT, int L, bool STORE>
-__device__ __forceinline__ void level(const Ctx &c, const View<TT> &v, const Lane<TT> &s,
-                                      uint64_t list, uint64_t rank, Acc<TT> &a) {
-    const int j = c.n - L;
-#pragma unroll 1
-    for (int ci = 0; ci < L; ++ci) {
-        const uint32_t x = (uint32_t)(list >> (4 * ci)) & 15u;
-        Lane<TT> s2 = s;
-        window(s2, j, x, v, c.r);
-        const uint64_t r2 = rank + (uint64_t)ci * factorial(L - 1);
-        if constexpr (L == 1) {
-            leaf<TT, STORE>(tail(s2, c.n, v, c.r), r2, a, c.out);
-        } else {
-            const uint64_t lo = list & ((1ull << (4 * ci)) - 1ull);
-            const uint64_t hi = (list >> (4 * ci + 4)) << (4 * ci);
-            level<TT, L - 1, STORE>(c, v, s2, lo | hi, r2, a);
-        }
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ T shfl_xor64(T v, int m) {
-    const uint64_t u = (uint64_t)v;
-    const uint32_t lo = __shfl_xor((uint32_t)u, m);
-    const uint32_t hi = __shfl_xor((uint32_t)(u >> 32), m);
-    return (T)(((uint64_t)hi << 32) | lo);
-}
-
-// (t, r) pairs: smaller t wins, ties to smaller r.
-__device__ __forceinline__ void merge_min(uint64_t &t, uint64_t &r, uint64_t t2, uint64_t r2) {
-    if (t2 < t || (t2 == t && r2 < r)) { t = t2; r = r2; }
-}
-// larger t wins (t is max+1, 0 = none), ties to smaller r.
-__device__ __forceinline__ void merge_max(uint64_t &t, uint64_t &r, uint64_t t2, uint64_t r2) {
-    if (t2 > t || (t2 == t && r2 < r)) { t = t2; r = r2; }
-}
-
-__device__ __forceinline__ void add128(uint64_t &lo, uint64_t &hi, uint64_t lo2, uint64_t hi2) {
-    const uint64_t s = lo + lo2;
-    hi += hi2 + (s < lo ? 1ull : 0ull);
-    lo = s;
-}
+template <typename TT>
+using ExView = View<TT, 1, EX_THREADS>;
 
 // Reduce a block's lane accumulators into one Partial (thread 0 writes it).
 __device__ void block_reduce_write(Partial p, Partial *dst) {
@@ -161,42 +110,28 @@ __global__ __launch_bounds__(EX_THREADS) void exhaustive_kernel(const tgo_task *
     }
     if (mode != MODE) return;
 
-    View<TT> v;
+    ExView<TT> v;
     v.H = Ht;
     v.K = Kt;
     v.D = Dt;
     v.Q = reinterpret_cast<Slot<TT> *>(smem) + threadIdx.x;
-    v.tstride = 1;
-    v.qstride = blockDim.x;
     Ctx c;
     c.n = n;
     c.r = r;
-    c.out = out;
+    c.out_sub = nullptr;
 
     Acc<TT> a;
     acc_init(a);
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_sub; s += stride) {
-        // Decode the prefix: digit i of rank s*M! in the factorial base.
-        uint64_t list = 0;
-        for (int i = n - 1; i >= 0; --i) list = (list << 4) | (uint64_t)i;
-        Lane<TT> st = lane_init<TT>();
-        const int plen = n - M;
-        uint32_t rem = s;
-        // block size of position i in subtree units: (n-1-i)!/M!
-        uint32_t blk = 1;
-        for (int i = M + 1; i <= n - 1; ++i) blk *= (uint32_t)i;
-        for (int i = 0; i < plen; ++i) {
-            const uint32_t cdig = rem / blk;
-            rem -= cdig * blk;
-            if (i + 1 < plen) blk /= (uint32_t)(n - 1 - i);
-            const uint32_t x = (uint32_t)(list >> (4 * cdig)) & 15u;
-            const uint64_t lo = list & ((1ull << (4 * cdig)) - 1ull);
-            const uint64_t hi = (list >> (4 * cdig + 4)) << (4 * cdig);
-            list = lo | hi;
-            window(st, i, x, v, r);
-        }
-        level<TT, M, STORE>(c, v, st, list, (uint64_t)s * factorial(M), a);
+        Lane<TT> st;
+        const uint64_t list = prefix(st, s, n, M, v, r);
+        const uint64_t r0 = (uint64_t)s * factorial(M);
+        if constexpr (STORE) c.out_sub = out + r0;
+        Sub<TT> u;
+        sub_init(u);
+        level<TT, M, STORE, 1, EX_THREADS>(c, v, st, (uint32_t)list, 0u, u);
+        fold(a, u, r0);
     }
     Partial p;
     p.min_t = (uint64_t)a.min_t;
@@ -268,7 +203,8 @@ __global__ __launch_bounds__(256) void exhaustive_finalize(const Partial *__rest
         s.n = n;
         s.status = status;
         s.count = count;
-        for (int i = 0; i < 16; ++i) { s.best[i] = 0xff; s.worst[i] = 0xff; }
+        for (int i = 0; i < 16; ++i) { s.best[i] = 0xff; s.worst[i] = 0xff; s.heur[i] = 0xff; }
+        s.heur_ns = -1;
         if (status != 0) {
             s.min_ns = s.max_ns = 0;
             s.argmin_rank = s.argmax_rank = 0;

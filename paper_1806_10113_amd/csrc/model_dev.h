@@ -73,21 +73,20 @@ template <typename TT>
 __device__ __forceinline__ TT inf_time() { return ~TT(0); }
 
 // Task tables and the per-lane kernel-completion queue.  Entry x of a table
-// is at [x * tstride], slot j of the queue at [j * qstride]; shared tables use
-// tstride 1, per-lane tables interleave lanes so that a wave's accesses fall
-// into distinct banks.
-template <typename TT>
+// is at [x * TS], slot j of the queue at [j * QS] (compile-time strides);
+// shared tables use TS = 1, per-lane tables interleave lanes so that a
+// wave's accesses fall into distinct banks.
+template <typename TT, int TS, int QS>
 struct View {
     const Pair<TT> *H;  // (h, ceil(q h / p_h))
     const TT *K;        // k
     const Pair<TT> *D;  // (d, ceil(q d / p_d))
     Slot<TT> *Q;
-    int tstride, qstride;
-    __device__ __forceinline__ Pair<TT> h(uint32_t x) const { return H[x * tstride]; }
-    __device__ __forceinline__ TT k(uint32_t x) const { return K[x * tstride]; }
-    __device__ __forceinline__ Pair<TT> d(uint32_t x) const { return D[x * tstride]; }
-    __device__ __forceinline__ Slot<TT> q(int j) const { return Q[j * qstride]; }
-    __device__ __forceinline__ void put(int j, Slot<TT> s) const { Q[j * qstride] = s; }
+    __device__ __forceinline__ Pair<TT> h(uint32_t x) const { return H[x * TS]; }
+    __device__ __forceinline__ TT k(uint32_t x) const { return K[x * TS]; }
+    __device__ __forceinline__ Pair<TT> d(uint32_t x) const { return D[x * TS]; }
+    __device__ __forceinline__ Slot<TT> q(int j) const { return Q[j * QS]; }
+    __device__ __forceinline__ void put(int j, Slot<TT> s) const { Q[j * QS] = s; }
 };
 
 // Simulation state at the start of a window (an HtD about to start).
@@ -95,9 +94,9 @@ template <typename TT>
 struct Lane {
     TT t;        // now: end of the previous HtD (0 before the first)
     TT ck;       // end of the previous kernel
-    TT ed;       // running DtH: end estimate
+    TT dev;      // next DtH event: end of the running DtH, or (idle) end of
+                 // the kernel it waits for; inf while that is not known yet
     TT td0;      // running DtH: start time
-    TT wait;     // idle DtH: end of the kernel it waits for (inf if unknown)
     uint32_t xd; // running DtH: task
     int i;       // DtH cursor (position of the running or next DtH)
     bool drun;   // DtH engine busy
@@ -106,44 +105,49 @@ struct Lane {
 template <typename TT>
 __device__ __forceinline__ Lane<TT> lane_init() {
     Lane<TT> s;
-    s.t = 0; s.ck = 0; s.ed = 0; s.td0 = 0; s.wait = inf_time<TT>();
+    s.t = 0; s.ck = 0; s.dev = inf_time<TT>(); s.td0 = 0;
     s.xd = 0; s.i = 0; s.drun = false;
     return s;
 }
 
 // Window j: HtD of task x starts at s.t; process DtH events until it ends,
 // then derive the kernel of position j and record it in the queue.
-template <typename TT>
-__device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const View<TT> &v,
+//
+// A DtH event is either a completion (engine busy) or a start from idle.  A
+// completion followed at once by the next DtH leaves both rates unchanged, so
+// the HtD end estimate stays valid; only a change of the DtH engine between
+// busy and idle changes the HtD rate and forces a new estimate from the exact
+// remaining work.
+template <typename TT, int TS, int QS>
+__device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const View<TT, TS, QS> &v,
                                        const Rates &r) {
     const TT q = TT(1) << r.q_log2;
     const Pair<TT> hx = v.h(x);
-    // a DtH waiting for the previous position's kernel now knows its time
-    if (!s.drun && s.i == j - 1) s.wait = s.ck;
+    // an idle DtH waiting for the previous position's kernel now knows its time
+    if (!s.drun && s.i == j - 1) s.dev = s.ck;
     TT uh = hx.a << r.q_log2;  // remaining HtD work at th0
     TT th0 = s.t;
     TT eh = s.t + (s.drun ? hx.b : hx.a);
     for (;;) {
-        const TT ev = s.drun ? s.ed : s.wait;
+        const TT ev = s.dev;
         if (!(ev < eh)) break;
-        // DtH event at ev: a completion (running) or a start from idle.
-        const int inew = s.drun ? s.i + 1 : s.i;
-        Slot<TT> nx;
-        nx.ck = inf_time<TT>();
-        nx.x = 0;
-        if (inew < j) nx = v.q(inew);
+        const int inew = s.i + (s.drun ? 1 : 0);
+        // slot inew is in bounds for every inew <= j; it is only used if inew < j
+        const Slot<TT> nx = v.q(inew);
         const bool start = inew < j && nx.ck <= ev;
-        // HtD work left at ev under the rate that held since th0.
-        const TT rate_old = s.drun ? TT(r.p_h) : q;
-        uh = uh - rate_old * (ev - th0);
-        th0 = ev;
-        eh = ev + (start ? (TT)ceil_p(uh, r.p_h, r.inv_ph, r.c_ph) : ceil_q(uh, r.q_log2));
+        if (start != s.drun) {
+            // the HtD rate changes at ev: exact remaining work, new estimate
+            uh -= (s.drun ? TT(r.p_h) : q) * (ev - th0);
+            th0 = ev;
+            eh = ev + (start ? (TT)ceil_p(uh, r.p_h, r.inv_ph, r.c_ph) : ceil_q(uh, r.q_log2));
+        }
         if (start) {
             s.xd = nx.x;
-            s.ed = ev + v.d(nx.x).b;
             s.td0 = ev;
+            s.dev = ev + v.d(nx.x).b;
+        } else {
+            s.dev = inew < j ? nx.ck : inf_time<TT>();
         }
-        s.wait = start ? inf_time<TT>() : nx.ck;
         s.drun = start;
         s.i = inew;
     }
@@ -157,8 +161,9 @@ __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const Vie
 
 // After the last HtD (position n-1) has ended at s.t: the DtH engine runs at
 // full speed; finish the queue.  Returns the end of the last DtH.
-template <typename TT>
-__device__ __forceinline__ TT tail(const Lane<TT> &s, int n, const View<TT> &v, const Rates &r) {
+template <typename TT, int TS, int QS>
+__device__ __forceinline__ TT tail(const Lane<TT> &s, int n, const View<TT, TS, QS> &v,
+                                   const Rates &r) {
     TT dend = 0;
     int i = s.i;
     if (s.drun) {

@@ -47,6 +47,7 @@ int launch_exhaustive(const Rates &r, const tgo_task *d_tasks, int n, int64_t *d
 int launch_evaluate(const Rates &r, const tgo_task *d_tasks, int n, const uint8_t *d_orders,
                     int64_t m, int64_t *d_out, hipStream_t st);
 int launch_heuristic(const Rates &r, const tgo_task *d_tasks, const int32_t *d_offs, int n_groups,
-                     uint8_t *d_orders, int64_t *d_ns, hipStream_t st);
+                     uint8_t *d_orders, int order_stride, int64_t *d_ns, int ns_stride,
+                     hipStream_t st);
 
 }  // namespace tgo

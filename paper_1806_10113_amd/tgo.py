@@ -35,9 +35,9 @@ SUMMARY_DTYPE = np.dtype([
     ("min_ns", "<i8"), ("max_ns", "<i8"), ("argmin_rank", "<u8"), ("argmax_rank", "<u8"),
     ("sum_lo", "<u8"), ("sum_hi", "<u8"), ("count", "<u8"), ("fingerprint", "<u8"),
     ("mean_ns", "<f8"), ("status", "<i4"), ("n", "<i4"), ("best", "u1", (16,)),
-    ("worst", "u1", (16,)),
+    ("worst", "u1", (16,)), ("heur", "u1", (16,)), ("heur_ns", "<i8"),
 ])
-assert SUMMARY_DTYPE.itemsize == 112
+assert SUMMARY_DTYPE.itemsize == 136
 
 
 @dataclass(frozen=True)
@@ -82,7 +82,14 @@ def lib():
         L.tgo_heuristic.argtypes = [M, vp, vp, i32, vp, vp, vp]
         L.tgo_rank.argtypes = [i32, vp, ctypes.POINTER(ctypes.c_uint64)]
         L.tgo_unrank.argtypes = [i32, ctypes.c_uint64, vp]
-        for f in (L.tgo_evaluate, L.tgo_exhaustive, L.tgo_heuristic, L.tgo_rank, L.tgo_unrank):
+        L.tgo_plan_create.argtypes = [M, i32, ctypes.POINTER(vp)]
+        L.tgo_plan_autotune.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.tgo_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+        L.tgo_batch.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.tgo_plan_destroy.argtypes = [vp]
+        L.tgo_plan_destroy.restype = None
+        for f in (L.tgo_evaluate, L.tgo_exhaustive, L.tgo_heuristic, L.tgo_rank, L.tgo_unrank,
+                  L.tgo_plan_create, L.tgo_plan_autotune, L.tgo_plan_describe, L.tgo_batch):
             f.restype = i32
         _lib = L
     return _lib
@@ -151,12 +158,23 @@ def exhaustive(tasks, model: Model = DEFAULT, per_order: bool = False, summary=N
 def read_summary(summary) -> dict:
     """Copy a device summary to the host and decode it."""
     raw = summary.cpu().numpy().view(SUMMARY_DTYPE)[0]
+    return _decode(raw)
+
+
+def _decode(raw) -> dict:
     n = int(raw["n"])
-    d = {k: raw[k].item() for k in SUMMARY_DTYPE.names if k not in ("best", "worst")}
+    d = {k: raw[k].item() for k in SUMMARY_DTYPE.names if k not in ("best", "worst", "heur")}
     d["sum"] = int(raw["sum_lo"]) | (int(raw["sum_hi"]) << 64)
     d["best"] = [int(v) for v in raw["best"][:n]]
     d["worst"] = [int(v) for v in raw["worst"][:n]]
+    d["heur"] = [int(v) for v in raw["heur"][:n]]
     return d
+
+
+def read_summaries(summaries) -> list:
+    """Decode a device array of summaries (uint8 [G, 136])."""
+    raw = summaries.cpu().numpy().reshape(-1).view(SUMMARY_DTYPE)
+    return [_decode(r) for r in raw]
 
 
 def heuristic(tasks, offs, model: Model = DEFAULT, stream=None):
@@ -170,6 +188,61 @@ def heuristic(tasks, offs, model: Model = DEFAULT, stream=None):
     _check(lib().tgo_heuristic(ctypes.byref(model._c()), tasks.data_ptr(), offs.data_ptr(), g,
                                orders.data_ptr(), ns.data_ptr(), _stream(stream)), "tgo_heuristic")
     return orders, ns
+
+
+class Plan:
+    """Batched enumeration plan (device workspace, captured graph, tuned decomposition)."""
+
+    def __init__(self, model: Model = DEFAULT, max_groups: int = 4096):
+        self._h = ctypes.c_void_p()
+        self.model = model
+        self.max_groups = max_groups
+        _check(lib().tgo_plan_create(ctypes.byref(model._c()), max_groups, ctypes.byref(self._h)),
+               "tgo_plan_create")
+
+    def close(self):
+        if self._h:
+            lib().tgo_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _out(self, offs, out):
+        import torch
+        g = offs.shape[0] - 1
+        if out is None:
+            out = torch.empty((g, SUMMARY_DTYPE.itemsize), dtype=torch.uint8, device=offs.device)
+        return g, out
+
+    def autotune(self, tasks, offs, out=None, stream=None):
+        import torch
+        _dev_tensor(tasks, torch.int64, 3, "tasks")
+        _dev_tensor(offs, torch.int32, None, "offs")
+        g, out = self._out(offs, out)
+        _check(lib().tgo_plan_autotune(self._h, tasks.data_ptr(), offs.data_ptr(), g, out.data_ptr(),
+                                       _stream(stream)), "tgo_plan_autotune")
+        return self.describe()
+
+    def describe(self) -> dict:
+        import json
+        buf = ctypes.create_string_buffer(1024)
+        _check(lib().tgo_plan_describe(self._h, buf, 1024), "tgo_plan_describe")
+        return json.loads(buf.value.decode())
+
+    def run(self, tasks, offs, out=None, stream=None):
+        """Summaries (uint8 [G, 136] device tensor) for every group of the batch."""
+        import torch
+        _dev_tensor(tasks, torch.int64, 3, "tasks")
+        _dev_tensor(offs, torch.int32, None, "offs")
+        g, out = self._out(offs, out)
+        _dev_tensor(out, torch.uint8, SUMMARY_DTYPE.itemsize, "out")
+        _check(lib().tgo_batch(self._h, tasks.data_ptr(), offs.data_ptr(), g, out.data_ptr(),
+                               _stream(stream)), "tgo_batch")
+        return out
 
 
 def rank(order) -> int:

@@ -1,0 +1,134 @@
+"""GPU parity of the batched persistent path (tgo_batch) against the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cmodel
+from oracle import model as M
+from paper_1806_10113_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_10113_amd import tgo
+    tgo.lib()
+    return torch.device("cuda:0")
+
+
+def to_dev(a, dev):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dev)
+
+
+def check_group(s, tasks, m, full=True):
+    n = len(tasks)
+    assert s["status"] == 0 and s["n"] == n
+    ref = cmodel.exhaustive(tasks, m)
+    for k in ("min_ns", "argmin_rank", "max_ns", "argmax_rank", "fingerprint"):
+        assert int(s[k]) == int(ref[k]), k
+    assert s["sum"] == ref["sum"]
+    assert s["count"] == math.factorial(n)
+    assert abs(s["mean_ns"] - ref["mean_ns"]) <= 2e-16 * ref["mean_ns"]
+    assert s["best"] == list(M.nth_permutation(n, ref["argmin_rank"]))
+    assert s["worst"] == list(M.nth_permutation(n, ref["argmax_rank"]))
+
+
+def check_heur(s, tasks, m):
+    h = M.heuristic(tasks, m)
+    assert s["heur"] == h
+    assert s["heur_ns"] == M.simulate(tasks, h, m)
+
+
+def test_batch_small_groups_all_checked(dev):
+    from paper_1806_10113_amd import tgo
+    b = W.batch_groups(240, 1, 8, seed=200, per_task_label=True)
+    for m, tm in ((M.DEFAULT, tgo.DEFAULT), (M.PAPER_EXAMPLE, tgo.PAPER_EXAMPLE)):
+        plan = tgo.Plan(tm, max_groups=b.n_groups)
+        out = plan.run(to_dev(b.tasks, dev), to_dev(b.offs, dev))
+        ss = tgo.read_summaries(out)
+        for g in range(b.n_groups):
+            check_group(ss[g], b.group(g), m)
+            check_heur(ss[g], b.group(g), m)
+        plan.close()
+
+
+def test_batch_uneven_4096_groups(dev):
+    """4,096 groups, N uniform in [4, 10], one DK/DT label per group, seed 2:
+    every group in one persistent launch (autotuned), checked against the
+    oracle on every group with N <= 8 and on a sample of the N = 9, 10 groups;
+    the heuristic on every group."""
+    from paper_1806_10113_amd import tgo
+    b = W.batch_groups(4096, 4, 10, seed=2)
+    tasks, offs = to_dev(b.tasks, dev), to_dev(b.offs, dev)
+    plan = tgo.Plan(tgo.DEFAULT, max_groups=4096)
+    desc = plan.autotune(tasks, offs)
+    assert desc["tuned"]
+    out = plan.run(tasks, offs)
+    ss = tgo.read_summaries(out)
+    sizes = b.sizes()
+    rng = np.random.default_rng(201)
+    big = [g for g in range(b.n_groups) if sizes[g] >= 9]
+    sample = set(rng.choice(big, size=16, replace=False).tolist())
+    for g in range(b.n_groups):
+        assert ss[g]["status"] == 0
+        assert ss[g]["count"] == math.factorial(int(sizes[g]))
+        if sizes[g] <= 8 or g in sample:
+            check_group(ss[g], b.group(g), M.DEFAULT)
+        check_heur(ss[g], b.group(g), M.DEFAULT)
+        assert ss[g]["min_ns"] <= ss[g]["heur_ns"] <= ss[g]["max_ns"]
+    # a fresh plan with the default decomposition gives identical bytes
+    plan2 = tgo.Plan(tgo.DEFAULT, max_groups=4096)
+    out2 = plan2.run(tasks, offs)
+    assert bool((out2 == out).all())
+    plan.close()
+    plan2.close()
+
+
+def test_batch_graph_replays(dev):
+    """Replays of the captured graph, with eager work in between, all equal."""
+    import torch
+    from paper_1806_10113_amd import tgo
+    b = W.batch_groups(500, 3, 9, seed=202)
+    tasks, offs = to_dev(b.tasks, dev), to_dev(b.offs, dev)
+    plan = tgo.Plan(tgo.DEFAULT, max_groups=600)
+    out = torch.empty((b.n_groups, tgo.SUMMARY_DTYPE.itemsize), dtype=torch.uint8, device=dev)
+    first = plan.run(tasks, offs, out).clone()
+    for i in range(4):
+        junk = torch.full((1 << 20,), i, dtype=torch.int64, device=dev).sum()  # eager work
+        tgo.exhaustive(to_dev(W.single_group_uniform(7, i), dev))
+        torch.cuda.synchronize()
+        out.fill_(0xAB)
+        plan.run(tasks, offs, out)
+        torch.cuda.synchronize()
+        assert bool((out == first).all()), f"replay {i} differs"
+        del junk
+    ss = tgo.read_summaries(first)
+    for g in range(0, b.n_groups, 37):
+        check_group(ss[g], b.group(g), M.DEFAULT)
+    plan.close()
+
+
+def test_batch_group_errors(dev):
+    from paper_1806_10113_amd import tgo
+    groups = [np.array([[1, 2, 3]] * 13, dtype=np.int64),          # n = 13: too large for a batch
+              np.array([[1, -2, 3], [4, 5, 6]], dtype=np.int64),   # negative duration
+              np.array([[1 << 38, 5, 6], [4, 5, 6]], dtype=np.int64),  # needs the 64-bit path
+              np.array([[3, 4, 5], [6, 7, 8], [1, 1, 1]], dtype=np.int64)]
+    tasks = np.concatenate(groups)
+    offs = np.cumsum([0] + [len(g) for g in groups]).astype(np.int32)
+    plan = tgo.Plan(tgo.DEFAULT, max_groups=8)
+    ss = tgo.read_summaries(plan.run(to_dev(tasks, dev), to_dev(offs, dev)))
+    assert ss[0]["status"] == tgo.TGO_EINVAL
+    assert ss[1]["status"] == tgo.TGO_ERANGE
+    assert ss[2]["status"] == tgo.TGO_ERANGE
+    check_group(ss[3], groups[3], M.DEFAULT)
+    with pytest.raises(tgo.TgoError):
+        plan.run(to_dev(np.concatenate([tasks] * 3), dev),
+                 to_dev(np.arange(0, 10 * 3, 3, dtype=np.int32), dev))  # 9 groups > max_groups
+    plan.close()
