@@ -5,7 +5,7 @@
 // heuristic of Section 5.1.
 //
 // Work decomposition.  Group g of size n is split into n!/m(n) subtrees
-// (enumeration.h), one lane per subtree; a wave-sized tile holds
+// (enum_dev.h), one lane per subtree; a wave-sized tile holds
 // 64 * lane_mult consecutive subtrees of one group, so the four waves of a
 // block work on up to four different groups, each with its own task table in
 // LDS.  Waves pull tiles from a device counter until the batch is drained (a
@@ -30,7 +30,7 @@ namespace tgo {
 constexpr int BT_THREADS = 256;
 constexpr int BT_WAVES = BT_THREADS / 64;
 constexpr int BT_MAX_N = 12;  // 12! < 2^29 keeps a rank in the low word of a key
-constexpr int BT_MAX_M = 6;
+constexpr int BT_MAX_M = 5;
 
 struct BatchCfg {
     int8_t m[BT_MAX_N + 1];  // positions enumerated per lane, by group size
@@ -140,14 +140,12 @@ __global__ __launch_bounds__(BT_THREADS) void batch_kernel(const tgo_task *__res
                                                            const uint32_t *__restrict__ tile_off,
                                                            BatchHdr *hdr) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ Pair<uint32_t> Ht[BT_WAVES][MAXN];
-    __shared__ uint32_t Kt[BT_WAVES][MAXN];
+    __shared__ Quad<uint32_t> Ht[BT_WAVES][MAXN];
     __shared__ Pair<uint32_t> Dt[BT_WAVES][MAXN];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     View<uint32_t, 1, BT_THREADS> v;
     v.H = Ht[w];
-    v.K = Kt[w];
     v.D = Dt[w];
     v.Q = reinterpret_cast<Slot<uint32_t> *>(smem) + threadIdx.x;
     const uint32_t total = hdr->total_tiles;
@@ -167,7 +165,7 @@ __global__ __launch_bounds__(BT_THREADS) void batch_kernel(const tgo_task *__res
         const int base = offs[g];
         const int n = offs[g + 1] - base;
         const int m = cfg.m[n];
-        if (lane < n) table_entry<uint32_t>(tasks[base + lane], r, &Ht[w][lane], &Kt[w][lane], &Dt[w][lane]);
+        if (lane < n) table_entry<uint32_t>(tasks[base + lane], r, &Ht[w][lane], &Dt[w][lane]);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -190,8 +188,7 @@ __global__ __launch_bounds__(BT_THREADS) void batch_kernel(const tgo_task *__res
                     case 2: run_subtree<2>(c, v, st, list, u); break;
                     case 3: run_subtree<3>(c, v, st, list, u); break;
                     case 4: run_subtree<4>(c, v, st, list, u); break;
-                    case 5: run_subtree<5>(c, v, st, list, u); break;
-                    default: run_subtree<6>(c, v, st, list, u); break;
+                    default: run_subtree<5>(c, v, st, list, u); break;
                 }
                 const uint64_t r0 = (uint64_t)s * fact_c(m);
                 const unsigned long long a = ((unsigned long long)u.min_t << 32) | (r0 + u.min_l);
@@ -437,7 +434,7 @@ int tgo_plan_autotune(tgo_plan *p, const tgo_task *d_tasks, const int32_t *d_off
     TGO_HIP(hipEventCreate(&e0));
     TGO_HIP(hipEventCreate(&e1));
     std::vector<BatchCfg> cands;
-    for (int mbig = 4; mbig <= 6; ++mbig)
+    for (int mbig = 3; mbig <= BT_MAX_M; ++mbig)
         for (int mult : {1, 2, 4})
             for (int bpc : {4, 8}) {
                 BatchCfg c = default_cfg(p->cus);

@@ -64,7 +64,7 @@ __device__ __forceinline__ void level(const Ctx &c, const View<TT, TS, QS> &v, c
         window(s2, j, x, v, c.r);
         const uint32_t l2 = l + (uint32_t)ci * (uint32_t)fact_c(L - 1);
         if constexpr (L == 1) {
-            leaf<TT, STORE>(tail(s2, c.n, v, c.r), l2, u, c.out_sub);
+            leaf<TT, STORE>(tail(s2, c.r), l2, u, c.out_sub);
         } else {
             const uint32_t lo = list & ((1u << (4 * ci)) - 1u);
             const uint32_t hi = (list >> (4 * ci + 4)) << (4 * ci);

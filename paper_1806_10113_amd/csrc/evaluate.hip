@@ -8,7 +8,7 @@
 namespace tgo {
 
 constexpr int EV_THREADS = 256;
-constexpr int HEU_THREADS = 64;
+constexpr int HEU_THREADS = 32;
 
 template <typename TT>
 __global__ __launch_bounds__(EV_THREADS) void evaluate_kernel(const tgo_task *__restrict__ tasks,
@@ -17,12 +17,11 @@ __global__ __launch_bounds__(EV_THREADS) void evaluate_kernel(const tgo_task *__
                                                               int64_t m, int64_t *out) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int MODE = sizeof(TT) == 4 ? 0 : 1;
-    __shared__ Pair<TT> Ht[MAXN];
-    __shared__ TT Kt[MAXN];
+    __shared__ Quad<TT> Ht[MAXN];
     __shared__ Pair<TT> Dt[MAXN];
     __shared__ int mode;
     if (threadIdx.x == 0) mode = classify_group(tasks, n, r);
-    if ((int)threadIdx.x < n) table_entry<TT>(tasks[threadIdx.x], r, &Ht[threadIdx.x], &Kt[threadIdx.x], &Dt[threadIdx.x]);
+    if ((int)threadIdx.x < n) table_entry<TT>(tasks[threadIdx.x], r, &Ht[threadIdx.x], &Dt[threadIdx.x]);
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if (mode < 0) {
@@ -33,7 +32,6 @@ __global__ __launch_bounds__(EV_THREADS) void evaluate_kernel(const tgo_task *__
     if (mode != MODE) return;
     View<TT, 1, EV_THREADS> v;
     v.H = Ht;
-    v.K = Kt;
     v.D = Dt;
     v.Q = reinterpret_cast<Slot<TT> *>(smem) + threadIdx.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
@@ -51,7 +49,7 @@ __global__ __launch_bounds__(EV_THREADS) void evaluate_kernel(const tgo_task *__
         }
         Lane<TT> st = lane_init<TT>();
         for (int j = 0; j < n; ++j) window(st, j, (uint32_t)o[j], v, r);
-        out[i] = (int64_t)tail(st, n, v, r);
+        out[i] = (int64_t)tail(st, r);
     }
 }
 
@@ -92,8 +90,7 @@ __global__ __launch_bounds__(HEU_THREADS) void heuristic_kernel(const tgo_task *
                                                                 uint8_t *orders, int order_stride,
                                                                 int64_t *ns, int ns_stride) {
     using TT = uint64_t;
-    __shared__ Pair<TT> Ht[MAXN * HEU_THREADS];
-    __shared__ TT Kt[MAXN * HEU_THREADS];
+    __shared__ Quad<TT> Ht[MAXN * HEU_THREADS];
     __shared__ Pair<TT> Dt[MAXN * HEU_THREADS];
     __shared__ Slot<TT> Qs[MAXN * HEU_THREADS];
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -115,12 +112,10 @@ __global__ __launch_bounds__(HEU_THREADS) void heuristic_kernel(const tgo_task *
     }
     View<TT, HEU_THREADS, HEU_THREADS> v;
     v.H = Ht + threadIdx.x;
-    v.K = Kt + threadIdx.x;
     v.D = Dt + threadIdx.x;
     v.Q = Qs + threadIdx.x;
     for (int x = 0; x < n; ++x)
-        table_entry<TT>(t[x], r, &Ht[x * blockDim.x + threadIdx.x], &Kt[x * blockDim.x + threadIdx.x],
-                        &Dt[x * blockDim.x + threadIdx.x]);
+        table_entry<TT>(t[x], r, &Ht[x * blockDim.x + threadIdx.x], &Dt[x * blockDim.x + threadIdx.x]);
 
     uint32_t rt = (n == 32) ? ~0u : ((1u << n) - 1u);
     // select_first: largest k - h; ties to larger d, then lower index
@@ -140,7 +135,7 @@ __global__ __launch_bounds__(HEU_THREADS) void heuristic_kernel(const tgo_task *
         Fit3 u;
         u.th = (int64_t)st.t;
         u.tk = (int64_t)st.ck;
-        u.td = (int64_t)tail(st, pos, v, r);
+        u.td = (int64_t)tail(st, r);
         int best = -1;
         int64_t bf = 0;
         for (int c = 0; c < n; ++c) {
@@ -159,7 +154,7 @@ __global__ __launch_bounds__(HEU_THREADS) void heuristic_kernel(const tgo_task *
         Fit3 u;
         u.th = (int64_t)st.t;
         u.tk = (int64_t)st.ck;
-        u.td = (int64_t)tail(st, pos, v, r);
+        u.td = (int64_t)tail(st, r);
         int bx = -1, by = -1;
         int64_t bs = 0, bdy = 0;
         for (int o = 0; o < 2; ++o) {
@@ -170,7 +165,7 @@ __global__ __launch_bounds__(HEU_THREADS) void heuristic_kernel(const tgo_task *
             Fit3 w;
             w.th = (int64_t)s2.t;
             w.tk = (int64_t)s2.ck;
-            w.td = (int64_t)tail(s2, pos + 1, v, r);
+            w.td = (int64_t)tail(s2, r);
             const int64_t sc = s1 + fit(t[y].htd_ns, t[y].kern_ns, w) + t[y].dth_ns;
             const int64_t dy = t[y].dth_ns;
             if (bx < 0 || sc < bs || (sc == bs && dy < bdy)) { bx = x; by = y; bs = sc; bdy = dy; }
@@ -186,7 +181,7 @@ __global__ __launch_bounds__(HEU_THREADS) void heuristic_kernel(const tgo_task *
         window(st, pos, (uint32_t)x, v, r);
         ++pos;
     }
-    *nsg = (int64_t)tail(st, n, v, r);
+    *nsg = (int64_t)tail(st, r);
     for (int i = 0; i < n; ++i) orow[i] = ord[i];
 }
 

@@ -8,6 +8,8 @@
 // order, so the reduction keeps the lowest rank on ties.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "enum_dev.h"
 #include "tables_dev.h"
 #include "tgo_internal.h"
@@ -93,12 +95,11 @@ __global__ __launch_bounds__(EX_THREADS) void exhaustive_kernel(const tgo_task *
                                                                 int64_t *out, Partial *partials) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int MODE = sizeof(TT) == 4 ? 0 : 1;
-    __shared__ Pair<TT> Ht[MAXN];
-    __shared__ TT Kt[MAXN];
+    __shared__ Quad<TT> Ht[MAXN];
     __shared__ Pair<TT> Dt[MAXN];
     __shared__ int mode;
     if (threadIdx.x == 0) mode = classify_group(tasks, n, r);
-    if ((int)threadIdx.x < n) table_entry<TT>(tasks[threadIdx.x], r, &Ht[threadIdx.x], &Kt[threadIdx.x], &Dt[threadIdx.x]);
+    if ((int)threadIdx.x < n) table_entry<TT>(tasks[threadIdx.x], r, &Ht[threadIdx.x], &Dt[threadIdx.x]);
     __syncthreads();
     if (mode < 0) {
         if (MODE == 0 && threadIdx.x == 0) {
@@ -112,7 +113,6 @@ __global__ __launch_bounds__(EX_THREADS) void exhaustive_kernel(const tgo_task *
 
     ExView<TT> v;
     v.H = Ht;
-    v.K = Kt;
     v.D = Dt;
     v.Q = reinterpret_cast<Slot<TT> *>(smem) + threadIdx.x;
     Ctx c;
@@ -236,7 +236,12 @@ __global__ __launch_bounds__(256) void exhaustive_finalize(const Partial *__rest
 }
 
 // Positions enumerated depth-first per lane: enough subtrees to fill the GPU.
+// TGO_EXHAUSTIVE_M (1..5) overrides the choice for tuning experiments.
 static int choose_m(int n) {
+    if (const char *e = std::getenv("TGO_EXHAUSTIVE_M")) {
+        const int m = std::atoi(e);
+        if (m >= 1 && m <= 5 && m <= n) return m;
+    }
     int m = 1;
     for (int c = 5; c >= 1; --c) {
         if (c > n) continue;

@@ -45,7 +45,12 @@ struct Rates {
 
 template <typename TT>
 struct alignas(2 * sizeof(TT)) Pair {
-    TT a, b;  // (solo duration, duration when fully overlapped)
+    TT a, b;  // DtH: (solo duration, duration when fully overlapped)
+};
+
+template <typename TT>
+struct alignas(4 * sizeof(TT)) Quad {
+    TT h, hp, k, d;  // HtD solo, HtD fully overlapped, kernel, DtH solo
 };
 
 template <typename TT>
@@ -53,6 +58,10 @@ struct alignas(2 * sizeof(TT)) Slot {
     TT ck;       // completion time of the kernel at this position
     uint32_t x;  // task at this position
 };
+
+template <typename TT> struct Signed;
+template <> struct Signed<uint32_t> { using type = int32_t; };
+template <> struct Signed<uint64_t> { using type = int64_t; };
 
 template <typename TT>
 __device__ __forceinline__ TT ceil_q(TT u, int q_log2) {
@@ -78,12 +87,10 @@ __device__ __forceinline__ TT inf_time() { return ~TT(0); }
 // wave's accesses fall into distinct banks.
 template <typename TT, int TS, int QS>
 struct View {
-    const Pair<TT> *H;  // (h, ceil(q h / p_h))
-    const TT *K;        // k
+    const Quad<TT> *H;  // (h, ceil(q h / p_h), k, d)
     const Pair<TT> *D;  // (d, ceil(q d / p_d))
     Slot<TT> *Q;
-    __device__ __forceinline__ Pair<TT> h(uint32_t x) const { return H[x * TS]; }
-    __device__ __forceinline__ TT k(uint32_t x) const { return K[x * TS]; }
+    __device__ __forceinline__ Quad<TT> task(uint32_t x) const { return H[x * TS]; }
     __device__ __forceinline__ Pair<TT> d(uint32_t x) const { return D[x * TS]; }
     __device__ __forceinline__ Slot<TT> q(int j) const { return Q[j * QS]; }
     __device__ __forceinline__ void put(int j, Slot<TT> s) const { Q[j * QS] = s; }
@@ -92,21 +99,28 @@ struct View {
 // Simulation state at the start of a window (an HtD about to start).
 template <typename TT>
 struct Lane {
+    using ST = typename Signed<TT>::type;
     TT t;        // now: end of the previous HtD (0 before the first)
     TT ck;       // end of the previous kernel
     TT dev;      // next DtH event: end of the running DtH, or (idle) end of
                  // the kernel it waits for; inf while that is not known yet
-    TT td0;      // running DtH: start time
-    uint32_t xd; // running DtH: task
+    TT ukey;     // running DtH: q d + p_dth t0 (mod 2^bits) for start t0, so
+                 // that its work left at time t is q d - p_dth (t - t0)
+    TT dpre;     // sum of solo DtH durations of the positions placed so far
+    TT dthru;    // sum of solo DtH durations up to the cursor (running included)
+    ST emax;     // max over placed positions p of (K_p end - sum_{s<p} d_s)
     int i;       // DtH cursor (position of the running or next DtH)
     bool drun;   // DtH engine busy
 };
 
 template <typename TT>
 __device__ __forceinline__ Lane<TT> lane_init() {
+    using ST = typename Signed<TT>::type;
     Lane<TT> s;
-    s.t = 0; s.ck = 0; s.dev = inf_time<TT>(); s.td0 = 0;
-    s.xd = 0; s.i = 0; s.drun = false;
+    s.t = 0; s.ck = 0; s.dev = inf_time<TT>(); s.ukey = 0;
+    s.dpre = 0; s.dthru = 0;
+    s.emax = (ST)(((TT)1) << (8 * sizeof(TT) - 1));  // most negative
+    s.i = 0; s.drun = false;
     return s;
 }
 
@@ -121,13 +135,14 @@ __device__ __forceinline__ Lane<TT> lane_init() {
 template <typename TT, int TS, int QS>
 __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const View<TT, TS, QS> &v,
                                        const Rates &r) {
+    using ST = typename Signed<TT>::type;
     const TT q = TT(1) << r.q_log2;
-    const Pair<TT> hx = v.h(x);
+    const Quad<TT> tx = v.task(x);
     // an idle DtH waiting for the previous position's kernel now knows its time
     if (!s.drun && s.i == j - 1) s.dev = s.ck;
-    TT uh = hx.a << r.q_log2;  // remaining HtD work at th0
+    TT uh = tx.h << r.q_log2;  // remaining HtD work at th0
     TT th0 = s.t;
-    TT eh = s.t + (s.drun ? hx.b : hx.a);
+    TT eh = s.t + (s.drun ? tx.hp : tx.h);
     for (;;) {
         const TT ev = s.dev;
         if (!(ev < eh)) break;
@@ -142,9 +157,10 @@ __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const Vie
             eh = ev + (start ? (TT)ceil_p(uh, r.p_h, r.inv_ph, r.c_ph) : ceil_q(uh, r.q_log2));
         }
         if (start) {
-            s.xd = nx.x;
-            s.td0 = ev;
-            s.dev = ev + v.d(nx.x).b;
+            const Pair<TT> dd = v.d(nx.x);
+            s.dthru += dd.a;
+            s.ukey = (dd.a << r.q_log2) + TT(r.p_d) * ev;
+            s.dev = ev + dd.b;
         } else {
             s.dev = inew < j ? nx.ck : inf_time<TT>();
         }
@@ -152,32 +168,37 @@ __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const Vie
         s.i = inew;
     }
     s.t = eh;
-    s.ck = tmax(eh, s.ck) + v.k(x);
+    s.ck = tmax(eh, s.ck) + tx.k;
+    const ST e = (ST)s.ck - (ST)s.dpre;
+    s.emax = e > s.emax ? e : s.emax;
+    s.dpre += tx.d;
     Slot<TT> sl;
     sl.ck = s.ck;
     sl.x = x;
     v.put(j, sl);
 }
 
-// After the last HtD (position n-1) has ended at s.t: the DtH engine runs at
-// full speed; finish the queue.  Returns the end of the last DtH.
-template <typename TT, int TS, int QS>
-__device__ __forceinline__ TT tail(const Lane<TT> &s, int n, const View<TT, TS, QS> &v,
-                                   const Rates &r) {
-    TT dend = 0;
-    int i = s.i;
+// Total time once the last placed HtD has ended at s.t (used for the whole
+// group, and for a prefix simulated on its own).  After that instant every
+// DtH runs at full speed, so the rest is the two-machine recurrence
+// D = max(D, K_p end) + d_p over the remaining positions, whose value is
+//   max(end of the running DtH + sum of the solo DtH left after it,
+//       max_p (K_p end + sum_{s >= p} d_s)).
+// Terms of positions whose DtH already started are lower bounds of the total
+// (every DtH takes at least its solo time after its kernel), so the second max
+// may run over every placed position: it is emax + dpre, kept per window.
+template <typename TT>
+__device__ __forceinline__ TT tail(const Lane<TT> &s, const Rates &r) {
+    using ST = typename Signed<TT>::type;
+    TT T = (TT)(s.emax + (ST)s.dpre);
     if (s.drun) {
-        const TT qd = v.d(s.xd).a << r.q_log2;
-        const TT done = TT(r.p_d) * (s.t - s.td0);
-        const TT ud = done >= qd ? TT(0) : qd - done;
-        dend = s.t + ceil_q(ud, r.q_log2);
-        ++i;
+        // work left on the running DtH; the true value lies in (-p_dth, q d],
+        // so the wrapped difference read as signed is exact
+        const ST ud = (ST)(s.ukey - TT(r.p_d) * s.t);
+        const TT dend = s.t + ceil_q(ud > 0 ? (TT)ud : TT(0), r.q_log2) + (s.dpre - s.dthru);
+        T = tmax(T, dend);
     }
-    for (; i < n; ++i) {
-        const Slot<TT> sl = v.q(i);
-        dend = tmax(dend, sl.ck) + v.d(sl.x).a;
-    }
-    return dend;
+    return T;
 }
 
 // Host-side validity bound for the 32-bit time path (checked on the device
