@@ -167,6 +167,82 @@ int tgo_batch(tgo_plan *plan, const tgo_task *d_tasks, const int32_t *d_offs, in
               tgo_summary *d_out, tgo_stream stream);
 void tgo_plan_destroy(tgo_plan *plan);
 
+/* ---------------------------------------------------------------------------
+ * Learned proposal for groups too large to enumerate (n <= 16).  Not in the
+ * paper, whose answer for large groups is the heuristic (Section 5.1); here
+ * the heuristic stays a candidate and the exact model (Section 4) decides.
+ *
+ * Network: per-position features of the ordering (for each of 16 positions
+ * the HtD, K, DtH of the task there as log1p(x / 1 us) / log1p(20 ms / 1 us),
+ * zero past the group) -> 256 -> 256 -> 256 -> 1, ReLU between layers,
+ * bfloat16 weights and activations with float32 accumulation on the matrix
+ * cores.  Trained with mean squared error against y = T / LB - 1 (LB: the
+ * largest machine lower bound of the group) and Adam on float32 masters.
+ * Parameter order (float32, TGO_SURROGATE_PARAMS values): W1[256][48], b1[256],
+ * W2[256][256], b2[256], W3[256][256], b3[256], W4[256], b4[1]; W[out][in].
+ *
+ * Sampled orderings: ordering s of group g under `seed` comes from one
+ * Philox4x32-10 call (counter (s lo, s hi, g, 0), key (seed lo, seed hi)) and a
+ * Fisher-Yates shuffle from the last position down, position i taking
+ * hi32(x (i + 1)) and keeping x = lo32(x (i + 1)), x reloaded from the next
+ * word every four draws.
+ *
+ * Search and pair generation use the 32-bit time path: a group whose times
+ * could reach 2^31 ns gets status TGO_ERANGE.  All buffers below are device
+ * memory; the surrogate owns max_rows rows of activations.
+ */
+#define TGO_SURROGATE_PARAMS 144385
+
+typedef struct {
+    int64_t best_ns;       /* best exact T found: candidates and heuristic     */
+    int64_t heur_ns;       /* T of the heuristic ordering                      */
+    int64_t cand_best_ns;  /* best exact T among the sampled candidates (-1: none) */
+    uint64_t best_sample;  /* sample index of that candidate                   */
+    int32_t status, n;
+    int32_t from_heuristic, pad;  /* 1 if the heuristic ordering is best_ns   */
+    uint8_t best[16];      /* the best ordering                                */
+} tgo_search_result;
+
+typedef struct tgo_surrogate tgo_surrogate;
+int tgo_surrogate_create(int64_t max_rows, int max_groups, tgo_surrogate **out);
+void tgo_surrogate_destroy(tgo_surrogate *s);
+int tgo_surrogate_param_count(void);
+/* He-uniform weights from Philox(seed, parameter index), zero biases, Adam reset. */
+int tgo_surrogate_init(tgo_surrogate *s, uint64_t seed, tgo_stream stream);
+/* Host float32 parameters in (set; resets Adam) and out (get); both synchronize. */
+int tgo_surrogate_set_params(tgo_surrogate *s, const float *h_params, tgo_stream stream);
+int tgo_surrogate_get_params(tgo_surrogate *s, float *h_params, tgo_stream stream);
+/* Training pairs: per_group (multiple of 64) sampled orderings of every group,
+ * d_orders [G*per_group][16] (0xff past n), d_gid, exact d_T (or the group's
+ * negative status). d_status [G]. */
+int tgo_surrogate_pairs(const tgo_model *model, const tgo_task *d_tasks, const int32_t *d_offs,
+                        int n_groups, int64_t per_group, uint64_t seed, int32_t *d_status,
+                        uint8_t *d_orders, int32_t *d_gid, int64_t *d_T, tgo_stream stream);
+/* Scores of given orderings (rows <= max_rows): d_orders [rows][16], d_gid [rows]. */
+int tgo_surrogate_score(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *d_offs, int n_groups,
+                        const uint8_t *d_orders, const int32_t *d_gid, int64_t rows, float *d_scores,
+                        tgo_stream stream);
+/* Loss and gradient (d_grad: TGO_SURROGATE_PARAMS floats, may be NULL) on a
+ * batch of pairs (rows a multiple of 64, <= max_rows). */
+int tgo_surrogate_grad(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *d_offs, int n_groups,
+                       const uint8_t *d_orders, const int32_t *d_gid, const int64_t *d_T, int rows,
+                       float *d_grad, float *d_loss, tgo_stream stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on a batch of pairs. */
+int tgo_surrogate_train_step(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *d_offs,
+                             int n_groups, const uint8_t *d_orders, const int32_t *d_gid,
+                             const int64_t *d_T, int rows, float lr, float *d_loss, tgo_stream stream);
+/* Surrogate-guided search: score `samples` sampled orderings per group, re-score
+ * the `topk` (<= 64) best-scored exactly, return the best of those and the
+ * heuristic ordering (ties to the heuristic). */
+int tgo_surrogate_search(tgo_surrogate *s, const tgo_model *model, const tgo_task *d_tasks,
+                         const int32_t *d_offs, int n_groups, int64_t samples, int topk, uint64_t seed,
+                         tgo_search_result *d_out, tgo_stream stream);
+/* Plain exact search: the heuristic plus `samples` sampled orderings per group
+ * scored exactly (rounded up to a multiple of 64). */
+int tgo_random_search(const tgo_model *model, const tgo_task *d_tasks, const int32_t *d_offs,
+                      int n_groups, int64_t samples, uint64_t seed, tgo_search_result *d_out,
+                      tgo_stream stream);
+
 /* Host helpers: lexicographic rank <-> ordering (index arithmetic only). */
 int tgo_rank(int n, const uint8_t *h_order, uint64_t *rank);
 int tgo_unrank(int n, uint64_t rank, uint8_t *h_order);

@@ -242,8 +242,10 @@ static int choose_m(int n) {
         const int m = std::atoi(e);
         if (m >= 1 && m <= 5 && m <= n) return m;
     }
+    // 4 levels beat 5 at n = 12 on MI355X (fewer live snapshots, one more
+    // wave per SIMD); deeper walks only pay when subtrees are scarce
     int m = 1;
-    for (int c = 5; c >= 1; --c) {
+    for (int c = 4; c >= 1; --c) {
         if (c > n) continue;
         const uint64_t sub = factorial(n) / factorial(c);
         if (sub >= 32768 || c == 1) { m = c; break; }

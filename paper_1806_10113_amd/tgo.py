@@ -86,6 +86,24 @@ def lib():
         L.tgo_plan_autotune.argtypes = [vp, vp, vp, i32, vp, vp]
         L.tgo_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
         L.tgo_batch.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.tgo_surrogate_create.argtypes = [i64, i32, ctypes.POINTER(vp)]
+        L.tgo_surrogate_destroy.argtypes = [vp]
+        L.tgo_surrogate_destroy.restype = None
+        L.tgo_surrogate_param_count.argtypes = []
+        L.tgo_surrogate_init.argtypes = [vp, ctypes.c_uint64, vp]
+        L.tgo_surrogate_set_params.argtypes = [vp, vp, vp]
+        L.tgo_surrogate_get_params.argtypes = [vp, vp, vp]
+        L.tgo_surrogate_pairs.argtypes = [M, vp, vp, i32, i64, ctypes.c_uint64, vp, vp, vp, vp, vp]
+        L.tgo_surrogate_score.argtypes = [vp, vp, vp, i32, vp, vp, i64, vp, vp]
+        L.tgo_surrogate_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp, i32, vp, vp, vp]
+        L.tgo_surrogate_train_step.argtypes = [vp, vp, vp, i32, vp, vp, vp, i32, ctypes.c_float, vp, vp]
+        L.tgo_surrogate_search.argtypes = [vp, M, vp, vp, i32, i64, i32, ctypes.c_uint64, vp, vp]
+        L.tgo_random_search.argtypes = [M, vp, vp, i32, i64, ctypes.c_uint64, vp, vp]
+        for f in (L.tgo_surrogate_create, L.tgo_surrogate_param_count, L.tgo_surrogate_init,
+                  L.tgo_surrogate_set_params, L.tgo_surrogate_get_params, L.tgo_surrogate_pairs,
+                  L.tgo_surrogate_score, L.tgo_surrogate_grad, L.tgo_surrogate_train_step,
+                  L.tgo_surrogate_search, L.tgo_random_search):
+            f.restype = i32
         L.tgo_plan_destroy.argtypes = [vp]
         L.tgo_plan_destroy.restype = None
         for f in (L.tgo_evaluate, L.tgo_exhaustive, L.tgo_heuristic, L.tgo_rank, L.tgo_unrank,
@@ -242,6 +260,138 @@ class Plan:
         _dev_tensor(out, torch.uint8, SUMMARY_DTYPE.itemsize, "out")
         _check(lib().tgo_batch(self._h, tasks.data_ptr(), offs.data_ptr(), g, out.data_ptr(),
                                _stream(stream)), "tgo_batch")
+        return out
+
+
+SEARCH_DTYPE = np.dtype([
+    ("best_ns", "<i8"), ("heur_ns", "<i8"), ("cand_best_ns", "<i8"), ("best_sample", "<u8"),
+    ("status", "<i4"), ("n", "<i4"), ("from_heuristic", "<i4"), ("pad", "<i4"), ("best", "u1", (16,)),
+])
+assert SEARCH_DTYPE.itemsize == 64
+SURROGATE_PARAMS = 144385
+
+
+def read_search(results) -> list:
+    raw = results.cpu().numpy().reshape(-1).view(SEARCH_DTYPE)
+    out = []
+    for r in raw:
+        n = int(r["n"])
+        d = {k: r[k].item() for k in SEARCH_DTYPE.names if k not in ("best", "pad")}
+        d["best"] = [int(v) for v in r["best"][:n]]
+        out.append(d)
+    return out
+
+
+def _groups(tasks, offs):
+    import torch
+    _dev_tensor(tasks, torch.int64, 3, "tasks")
+    _dev_tensor(offs, torch.int32, None, "offs")
+    return offs.shape[0] - 1
+
+
+def pairs(tasks, offs, per_group: int, seed: int, model: Model = DEFAULT, stream=None):
+    """Exact training pairs: (orders uint8 [P,16], gid int32 [P], T int64 [P], status int32 [G])."""
+    import torch
+    g = _groups(tasks, offs)
+    P = g * per_group
+    dev = tasks.device
+    orders = torch.empty((P, 16), dtype=torch.uint8, device=dev)
+    gid = torch.empty(P, dtype=torch.int32, device=dev)
+    T = torch.empty(P, dtype=torch.int64, device=dev)
+    status = torch.empty(g, dtype=torch.int32, device=dev)
+    _check(lib().tgo_surrogate_pairs(ctypes.byref(model._c()), tasks.data_ptr(), offs.data_ptr(), g,
+                                     per_group, seed, status.data_ptr(), orders.data_ptr(),
+                                     gid.data_ptr(), T.data_ptr(), _stream(stream)),
+           "tgo_surrogate_pairs")
+    return orders, gid, T, status
+
+
+def random_search(tasks, offs, samples: int, seed: int, model: Model = DEFAULT, stream=None):
+    """Plain exact search (heuristic + sampled orderings scored exactly); uint8 [G, 64] results."""
+    import torch
+    g = _groups(tasks, offs)
+    out = torch.empty((g, SEARCH_DTYPE.itemsize), dtype=torch.uint8, device=tasks.device)
+    _check(lib().tgo_random_search(ctypes.byref(model._c()), tasks.data_ptr(), offs.data_ptr(), g,
+                                   samples, seed, out.data_ptr(), _stream(stream)), "tgo_random_search")
+    return out
+
+
+class Surrogate:
+    """The learned proposal: bf16 MLP on the matrix cores, float32 masters, Adam."""
+
+    def __init__(self, max_rows: int = 1 << 18, max_groups: int = 4096):
+        self._h = ctypes.c_void_p()
+        self.max_rows = max_rows
+        _check(lib().tgo_surrogate_create(max_rows, max_groups, ctypes.byref(self._h)),
+               "tgo_surrogate_create")
+
+    def close(self):
+        if self._h:
+            lib().tgo_surrogate_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, seed: int, stream=None):
+        _check(lib().tgo_surrogate_init(self._h, seed, _stream(stream)), "tgo_surrogate_init")
+
+    def set_params(self, params: np.ndarray, stream=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == SURROGATE_PARAMS
+        _check(lib().tgo_surrogate_set_params(self._h, p.ctypes.data, _stream(stream)),
+               "tgo_surrogate_set_params")
+
+    def get_params(self, stream=None) -> np.ndarray:
+        p = np.empty(SURROGATE_PARAMS, dtype=np.float32)
+        _check(lib().tgo_surrogate_get_params(self._h, p.ctypes.data, _stream(stream)),
+               "tgo_surrogate_get_params")
+        return p
+
+    def score(self, tasks, offs, orders, gid, stream=None):
+        import torch
+        g = _groups(tasks, offs)
+        rows = orders.shape[0]
+        out = torch.empty(rows, dtype=torch.float32, device=tasks.device)
+        _check(lib().tgo_surrogate_score(self._h, tasks.data_ptr(), offs.data_ptr(), g,
+                                         orders.data_ptr(), gid.data_ptr(), rows, out.data_ptr(),
+                                         _stream(stream)), "tgo_surrogate_score")
+        return out
+
+    def grad(self, tasks, offs, orders, gid, T, stream=None):
+        import torch
+        g = _groups(tasks, offs)
+        rows = orders.shape[0]
+        grad = torch.empty(SURROGATE_PARAMS, dtype=torch.float32, device=tasks.device)
+        loss = torch.empty(1, dtype=torch.float32, device=tasks.device)
+        _check(lib().tgo_surrogate_grad(self._h, tasks.data_ptr(), offs.data_ptr(), g, orders.data_ptr(),
+                                        gid.data_ptr(), T.data_ptr(), rows, grad.data_ptr(),
+                                        loss.data_ptr(), _stream(stream)), "tgo_surrogate_grad")
+        return grad, loss
+
+    def train_step(self, tasks, offs, orders, gid, T, lr: float, loss=None, stream=None):
+        import torch
+        g = _groups(tasks, offs)
+        rows = orders.shape[0]
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=tasks.device)
+        _check(lib().tgo_surrogate_train_step(self._h, tasks.data_ptr(), offs.data_ptr(), g,
+                                              orders.data_ptr(), gid.data_ptr(), T.data_ptr(), rows,
+                                              lr, loss.data_ptr(), _stream(stream)),
+               "tgo_surrogate_train_step")
+        return loss
+
+    def search(self, tasks, offs, samples: int, topk: int, seed: int, model: Model = DEFAULT,
+               stream=None):
+        import torch
+        g = _groups(tasks, offs)
+        out = torch.empty((g, SEARCH_DTYPE.itemsize), dtype=torch.uint8, device=tasks.device)
+        _check(lib().tgo_surrogate_search(self._h, ctypes.byref(model._c()), tasks.data_ptr(),
+                                          offs.data_ptr(), g, samples, topk, seed, out.data_ptr(),
+                                          _stream(stream)), "tgo_surrogate_search")
         return out
 
 
