@@ -233,15 +233,79 @@ int tgo_surrogate_train_step(tgo_surrogate *s, const tgo_task *d_tasks, const in
                              const int64_t *d_T, int rows, float lr, float *d_loss, tgo_stream stream);
 /* Surrogate-guided search: score `samples` sampled orderings per group, re-score
  * the `topk` (<= 64) best-scored exactly, return the best of those and the
- * heuristic ordering (ties to the heuristic). */
+ * heuristic ordering (ties to the heuristic).  d_keys (NULL: the group index)
+ * names the sampling stream of each group, so a group gets the same result
+ * whatever batch it is in. */
 int tgo_surrogate_search(tgo_surrogate *s, const tgo_model *model, const tgo_task *d_tasks,
-                         const int32_t *d_offs, int n_groups, int64_t samples, int topk, uint64_t seed,
-                         tgo_search_result *d_out, tgo_stream stream);
+                         const int32_t *d_offs, const uint32_t *d_keys, int n_groups, int64_t samples,
+                         int topk, uint64_t seed, tgo_search_result *d_out, tgo_stream stream);
 /* Plain exact search: the heuristic plus `samples` sampled orderings per group
  * scored exactly (rounded up to a multiple of 64). */
 int tgo_random_search(const tgo_model *model, const tgo_task *d_tasks, const int32_t *d_offs,
                       int n_groups, int64_t samples, uint64_t seed, tgo_search_result *d_out,
                       tgo_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a continuous-batching request loop.  The paper's proxy thread polls
+ * a buffer of offloaded tasks, forms a task group, reorders and submits it
+ * (Section 6.2); here requests (one task group each) arrive at any time and a
+ * scheduler thread keeps up to `streams` batches in flight on their own HIP
+ * streams.  A free stream takes the waiting requests of one size class, oldest
+ * first, as far as the device-memory budget allows; requests that arrive
+ * while others run are admitted as soon as a stream and memory free up.
+ * Groups with n <= small_max_n are enumerated in full (tgo_batch; answer =
+ * the best ordering, with the heuristic's time beside it); larger groups use
+ * the learned proposal (tgo_surrogate_search with the request's key as its
+ * sampling key, so a request's answer is the same alone and in any mix).
+ */
+typedef struct {
+    int64_t budget_bytes;   /* device memory that admitted requests may hold   */
+    int32_t streams;        /* batches in flight (1..8)                        */
+    int32_t max_batch;      /* groups per exhaustive batch (1..4096)           */
+    int32_t max_batch_large;/* groups per surrogate batch (1..4096)            */
+    int32_t small_max_n;    /* exhaustive up to this size (1..12)              */
+    int32_t topk;           /* exact re-scores per large group (1..64)         */
+    int32_t pad;
+    int64_t samples;        /* scored samples per large group                  */
+    uint64_t seed;          /* sampling seed                                   */
+} tgo_server_config;
+
+typedef struct {
+    uint64_t id;
+    int64_t t_arrive_ns, t_admit_ns, t_done_ns; /* steady clock of the host      */
+    int32_t n, path;        /* path 0 = full enumeration, 1 = learned proposal   */
+    int32_t status, pad;
+    int64_t best_ns;        /* exact T of the returned ordering                */
+    int64_t heur_ns;        /* exact T of the heuristic ordering               */
+    uint8_t best[16];
+} tgo_server_result;
+
+typedef struct {
+    uint64_t submitted, completed, batches, rejected;
+    int64_t in_use_bytes, max_in_use_bytes, queued, max_queued;
+} tgo_server_stats;
+
+typedef struct tgo_server tgo_server;
+void tgo_server_config_default(tgo_server_config *cfg);
+/* sur may be NULL (then only groups with n <= small_max_n are accepted); its
+ * parameters are copied. */
+int tgo_server_create(const tgo_model *model, const tgo_server_config *cfg, tgo_surrogate *sur,
+                      tgo_server **out);
+/* Non-blocking, thread-safe; h_tasks is copied.  key names the sampling stream
+ * of a large group (0: the request id). */
+int tgo_server_submit(tgo_server *srv, const tgo_task *h_tasks, int n, uint32_t key, uint64_t *id);
+/* Completed results, in completion order; *count <= max. */
+int tgo_server_poll(tgo_server *srv, tgo_server_result *out, int max, int *count);
+/* Block until every submitted request has completed (TGO_ERANGE on timeout). */
+int tgo_server_drain(tgo_server *srv, int64_t timeout_ms);
+int tgo_server_get_stats(tgo_server *srv, tgo_server_stats *out);
+/* Replay an arrival trace in real time (request i submitted at
+ * h_arrival_ns[i] - h_arrival_ns[0] after the call starts), wait for all, and
+ * return the results in request order. */
+int tgo_server_replay(tgo_server *srv, const tgo_task *h_tasks, const int32_t *h_offs,
+                      const int64_t *h_arrival_ns, int n_requests, tgo_server_result *h_out,
+                      int64_t timeout_ms);
+void tgo_server_destroy(tgo_server *srv);
 
 /* Host helpers: lexicographic rank <-> ordering (index arithmetic only). */
 int tgo_rank(int n, const uint8_t *h_order, uint64_t *rank);

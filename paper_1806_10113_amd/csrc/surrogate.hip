@@ -142,6 +142,7 @@ __global__ __launch_bounds__(SG_THREADS) void rescore_kernel(const tgo_task *__r
                                                              const int32_t *__restrict__ offs, int G,
                                                              Rates r, int k, uint64_t seed,
                                                              const int32_t *__restrict__ status,
+                                                             const uint32_t *__restrict__ gkeys,
                                                              const unsigned long long *__restrict__ keys,
                                                              int key_stride,
                                                              unsigned long long *best) {
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(SG_THREADS) void rescore_kernel(const tgo_task *__r
         const unsigned long long kk = lane < k ? keys[(int64_t)g * key_stride + lane] : ~0ull;
         if (kk != ~0ull) {
             const uint64_t s = kk & 0xffffffffull;
-            const uint64_t perm = sample_ordering(n, (uint32_t)g, s, seed);
+            const uint64_t perm = sample_ordering(n, gkeys ? gkeys[g] : (uint32_t)g, s, seed);
             key = ((unsigned long long)eval_perm(perm, n, v, r) << 32) | s;
         }
         for (int m = 32; m >= 1; m >>= 1) {
@@ -197,6 +198,7 @@ __global__ void group_features_kernel(const tgo_task *__restrict__ tasks, const 
 // row0 + i is sample (row mod spad) of group (row div spad); samples >= S are
 // padding rows, flagged in `valid`).
 __global__ void features_kernel(const float *__restrict__ F, const int32_t *__restrict__ offs,
+                                const uint32_t *__restrict__ gkeys,
                                 const uint8_t *__restrict__ orders, const int32_t *__restrict__ gid,
                                 int64_t row0, int64_t rows, int64_t spad, int64_t S, uint64_t seed,
                                 uint16_t *X, uint16_t *Xt, int64_t xt_rows, uint8_t *valid) {
@@ -219,7 +221,7 @@ __global__ void features_kernel(const float *__restrict__ F, const int32_t *__re
         const int64_t s = row % spad;
         n = offs[g + 1] - offs[g];
         ok = s < S && n >= 1 && n <= SG_POS;
-        perm = ok ? sample_ordering(n, (uint32_t)g, (uint64_t)s, seed) : 0;
+        perm = ok ? sample_ordering(n, gkeys ? gkeys[g] : (uint32_t)g, (uint64_t)s, seed) : 0;
     }
     if (ok) {
         for (int p = 0; p < n && p < SG_POS; ++p) {
@@ -529,6 +531,7 @@ __global__ void fill_u64_kernel(unsigned long long *p, int64_t n, unsigned long 
 
 // results: best of candidates (exact) and the heuristic
 __global__ void search_finish_kernel(const int32_t *__restrict__ offs, int G, uint64_t seed,
+                                     const uint32_t *__restrict__ gkeys,
                                      const int32_t *__restrict__ status,
                                      const unsigned long long *__restrict__ best,
                                      const uint8_t *__restrict__ horders, const int64_t *__restrict__ hns,
@@ -563,7 +566,7 @@ __global__ void search_finish_kernel(const int32_t *__restrict__ offs, int G, ui
     } else {
         r.best_ns = cT;
         r.from_heuristic = 0;
-        const uint64_t perm = sample_ordering(n, (uint32_t)g, cs, seed);
+        const uint64_t perm = sample_ordering(n, gkeys ? gkeys[g] : (uint32_t)g, cs, seed);
         for (int i = 0; i < n; ++i) r.best[i] = (uint8_t)((perm >> (4 * i)) & 15u);
     }
     out[g] = r;
@@ -634,7 +637,7 @@ int tgo_surrogate_create(int64_t max_rows, int max_groups, tgo_surrogate **out) 
     if (!s) return fail(TGO_ENOMEM, "surrogate");
     s->max_rows = max_rows;
     s->max_groups = max_groups;
-    hipGetDevice(&s->device);
+    (void)hipGetDevice(&s->device);
     const size_t R = (size_t)max_rows;
     std::vector<std::pair<void **, size_t>> parts = {
         {(void **)&s->p, 4 * SG_NPARAM}, {(void **)&s->g, 4 * SG_NPARAM}, {(void **)&s->m, 4 * SG_NPARAM},
@@ -753,7 +756,8 @@ static int given_features(tgo_surrogate *s, const tgo_task *d_tasks, const int32
     const int64_t pad = (rows + 63) / 64 * 64;
     if (pad > rows) TGO_HIP(hipMemsetAsync(s->X + rows * SG_K0, 0, 2 * (pad - rows) * SG_K0, st));
     hipLaunchKernelGGL(features_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, s->F, d_offs,
-                       d_orders, d_gid, (int64_t)0, rows, (int64_t)1, (int64_t)1, (uint64_t)0, s->X,
+                       (const uint32_t *)nullptr, d_orders, d_gid, (int64_t)0, rows, (int64_t)1, (int64_t)1,
+                       (uint64_t)0, s->X,
                        with_t ? s->Xt : (uint16_t *)nullptr, rows, (uint8_t *)nullptr);
     TGO_HIP(hipGetLastError());
     return TGO_OK;
@@ -880,8 +884,8 @@ static int grow_cand(tgo_surrogate *s, size_t bytes) {
 }
 
 int tgo_surrogate_search(tgo_surrogate *s, const tgo_model *model, const tgo_task *d_tasks,
-                         const int32_t *d_offs, int G, int64_t samples, int topk, uint64_t seed,
-                         tgo_search_result *d_out, tgo_stream stream) {
+                         const int32_t *d_offs, const uint32_t *d_keys, int G, int64_t samples, int topk,
+                         uint64_t seed, tgo_search_result *d_out, tgo_stream stream) {
     if (!s) return fail(TGO_EINVAL, "surrogate is NULL");
     Rates r;
     int rc = make_rates(model, &r);
@@ -909,7 +913,7 @@ int tgo_surrogate_search(tgo_surrogate *s, const tgo_model *model, const tgo_tas
     for (int64_t row0 = 0; row0 < total; row0 += chunk) {
         const int64_t rows = std::min(chunk, total - row0);
         hipLaunchKernelGGL(features_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, s->F, d_offs,
-                           (const uint8_t *)nullptr, (const int32_t *)nullptr, row0, rows, spad, samples, seed,
+                           d_keys, (const uint8_t *)nullptr, (const int32_t *)nullptr, row0, rows, spad, samples, seed,
                            s->X, (uint16_t *)nullptr, rows, s->valid);
         rc = sur_forward(s, rows, false, st);
         if (rc) return rc;
@@ -933,9 +937,9 @@ int tgo_surrogate_search(tgo_surrogate *s, const tgo_model *model, const tgo_tas
     hipLaunchKernelGGL(fill_u64_kernel, dim3((G + 255) / 256), dim3(256), 0, st, s->best, (int64_t)G, ~0ull);
     const size_t shm = sizeof(Slot<uint32_t>) * SG_THREADS * SG_POS;
     hipLaunchKernelGGL(rescore_kernel, dim3((G + 3) / 4), dim3(SG_THREADS), shm, st, d_tasks, d_offs, G, r, topk,
-                       seed, s->status, s->cand[cur], (int)len, s->best);
-    hipLaunchKernelGGL(search_finish_kernel, dim3((G + 255) / 256), dim3(256), 0, st, d_offs, G, seed, s->status,
-                       s->best, s->horders, s->hns, d_out);
+                       seed, s->status, d_keys, s->cand[cur], (int)len, s->best);
+    hipLaunchKernelGGL(search_finish_kernel, dim3((G + 255) / 256), dim3(256), 0, st, d_offs, G, seed, d_keys,
+                       s->status, s->best, s->horders, s->hns, d_out);
     TGO_HIP(hipGetLastError());
     return TGO_OK;
 }
@@ -969,8 +973,8 @@ int tgo_random_search(const tgo_model *model, const tgo_task *d_tasks, const int
         hipLaunchKernelGGL(random_search_kernel, dim3(blocks), dim3(SG_THREADS), shm, st, d_tasks, d_offs, G, r,
                            per, seed, status, best);
     }
-    hipLaunchKernelGGL(search_finish_kernel, dim3((G + 255) / 256), dim3(256), 0, st, d_offs, G, seed, status,
-                       best, horders, hns, d_out);
+    hipLaunchKernelGGL(search_finish_kernel, dim3((G + 255) / 256), dim3(256), 0, st, d_offs, G, seed,
+                       (const uint32_t *)nullptr, status, best, horders, hns, d_out);
     TGO_HIP(hipGetLastError());
     return TGO_OK;
 }

@@ -97,12 +97,25 @@ def lib():
         L.tgo_surrogate_score.argtypes = [vp, vp, vp, i32, vp, vp, i64, vp, vp]
         L.tgo_surrogate_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp, i32, vp, vp, vp]
         L.tgo_surrogate_train_step.argtypes = [vp, vp, vp, i32, vp, vp, vp, i32, ctypes.c_float, vp, vp]
-        L.tgo_surrogate_search.argtypes = [vp, M, vp, vp, i32, i64, i32, ctypes.c_uint64, vp, vp]
+        L.tgo_surrogate_search.argtypes = [vp, M, vp, vp, vp, i32, i64, i32, ctypes.c_uint64, vp, vp]
         L.tgo_random_search.argtypes = [M, vp, vp, i32, i64, ctypes.c_uint64, vp, vp]
         for f in (L.tgo_surrogate_create, L.tgo_surrogate_param_count, L.tgo_surrogate_init,
                   L.tgo_surrogate_set_params, L.tgo_surrogate_get_params, L.tgo_surrogate_pairs,
                   L.tgo_surrogate_score, L.tgo_surrogate_grad, L.tgo_surrogate_train_step,
                   L.tgo_surrogate_search, L.tgo_random_search):
+            f.restype = i32
+        L.tgo_server_config_default.argtypes = [vp]
+        L.tgo_server_config_default.restype = None
+        L.tgo_server_create.argtypes = [M, vp, vp, ctypes.POINTER(vp)]
+        L.tgo_server_submit.argtypes = [vp, vp, i32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]
+        L.tgo_server_poll.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_int)]
+        L.tgo_server_drain.argtypes = [vp, i64]
+        L.tgo_server_get_stats.argtypes = [vp, vp]
+        L.tgo_server_replay.argtypes = [vp, vp, vp, vp, i32, vp, i64]
+        L.tgo_server_destroy.argtypes = [vp]
+        L.tgo_server_destroy.restype = None
+        for f in (L.tgo_server_create, L.tgo_server_submit, L.tgo_server_poll, L.tgo_server_drain,
+                  L.tgo_server_get_stats, L.tgo_server_replay):
             f.restype = i32
         L.tgo_plan_destroy.argtypes = [vp]
         L.tgo_plan_destroy.restype = None
@@ -385,13 +398,101 @@ class Surrogate:
         return loss
 
     def search(self, tasks, offs, samples: int, topk: int, seed: int, model: Model = DEFAULT,
-               stream=None):
+               keys=None, stream=None):
         import torch
         g = _groups(tasks, offs)
+        if keys is not None:
+            _dev_tensor(keys, torch.int32, None, "keys")
         out = torch.empty((g, SEARCH_DTYPE.itemsize), dtype=torch.uint8, device=tasks.device)
         _check(lib().tgo_surrogate_search(self._h, ctypes.byref(model._c()), tasks.data_ptr(),
-                                          offs.data_ptr(), g, samples, topk, seed, out.data_ptr(),
-                                          _stream(stream)), "tgo_surrogate_search")
+                                          offs.data_ptr(), keys.data_ptr() if keys is not None else None,
+                                          g, samples, topk, seed, out.data_ptr(), _stream(stream)),
+               "tgo_surrogate_search")
+        return out
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("max_batch_large", ctypes.c_int32),
+                ("small_max_n", ctypes.c_int32), ("topk", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("samples", ctypes.c_int64), ("seed", ctypes.c_uint64)]
+
+
+SERVER_RESULT_DTYPE = np.dtype([
+    ("id", "<u8"), ("t_arrive_ns", "<i8"), ("t_admit_ns", "<i8"), ("t_done_ns", "<i8"),
+    ("n", "<i4"), ("path", "<i4"), ("status", "<i4"), ("pad", "<i4"), ("best_ns", "<i8"),
+    ("heur_ns", "<i8"), ("best", "u1", (16,)),
+])
+assert SERVER_RESULT_DTYPE.itemsize == 80
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("in_use_bytes", ctypes.c_int64), ("max_in_use_bytes", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("max_queued", ctypes.c_int64)]
+
+
+def server_config(**kw) -> ServerConfig:
+    c = ServerConfig()
+    lib().tgo_server_config_default(ctypes.byref(c))
+    for k, v in kw.items():
+        setattr(c, k, v)
+    return c
+
+
+class Server:
+    """Continuous-batching request loop (host scheduler thread, HIP streams)."""
+
+    def __init__(self, model: Model = DEFAULT, config: ServerConfig | None = None,
+                 surrogate: "Surrogate | None" = None):
+        self._h = ctypes.c_void_p()
+        self.config = config or server_config()
+        _check(lib().tgo_server_create(ctypes.byref(model._c()), ctypes.byref(self.config),
+                                       surrogate._h if surrogate is not None else None,
+                                       ctypes.byref(self._h)), "tgo_server_create")
+
+    def close(self):
+        if self._h:
+            lib().tgo_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, tasks, key: int = 0) -> int:
+        t = np.ascontiguousarray(np.asarray(tasks, dtype=np.int64).reshape(-1, 3))
+        rid = ctypes.c_uint64()
+        _check(lib().tgo_server_submit(self._h, t.ctypes.data, len(t), key, ctypes.byref(rid)),
+               "tgo_server_submit")
+        return rid.value
+
+    def poll(self, max_results: int = 4096) -> np.ndarray:
+        out = np.zeros(max_results, dtype=SERVER_RESULT_DTYPE)
+        k = ctypes.c_int()
+        _check(lib().tgo_server_poll(self._h, out.ctypes.data, max_results, ctypes.byref(k)),
+               "tgo_server_poll")
+        return out[:k.value]
+
+    def drain(self, timeout_ms: int = 60_000):
+        _check(lib().tgo_server_drain(self._h, timeout_ms), "tgo_server_drain")
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().tgo_server_get_stats(self._h, ctypes.byref(s)), "tgo_server_get_stats")
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def replay(self, tasks, offs, arrival_ns, timeout_ms: int = 600_000) -> np.ndarray:
+        t = np.ascontiguousarray(np.asarray(tasks, dtype=np.int64).reshape(-1, 3))
+        o = np.ascontiguousarray(np.asarray(offs, dtype=np.int32))
+        a = np.ascontiguousarray(np.asarray(arrival_ns, dtype=np.int64))
+        n = len(o) - 1
+        out = np.zeros(n, dtype=SERVER_RESULT_DTYPE)
+        _check(lib().tgo_server_replay(self._h, t.ctypes.data, o.ctypes.data, a.ctypes.data, n,
+                                       out.ctypes.data, timeout_ms), "tgo_server_replay")
         return out
 
 

@@ -1,0 +1,132 @@
+"""GPU checks of the continuous-batching server: every answer exact against
+the oracle, the same alone and in a mix, admission within the memory budget,
+and a real-time replay of a Poisson trace."""
+import numpy as np
+import pytest
+
+from oracle import cmodel
+from oracle import model as M
+from paper_1806_10113_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_10113_amd import tgo
+    tgo.lib()
+    return torch.device("cuda:0")
+
+
+def check_small(r, grp):
+    n = len(grp)
+    assert r["status"] == 0 and r["path"] == 0 and r["n"] == n
+    s = cmodel.exhaustive(grp, M.DEFAULT)
+    assert r["best_ns"] == s["min_ns"]
+    best = [int(v) for v in r["best"][:n]]
+    assert best == list(M.nth_permutation(n, s["argmin_rank"]))
+    assert r["heur_ns"] == M.simulate(grp, M.heuristic(grp, M.DEFAULT), M.DEFAULT)
+    assert r["t_arrive_ns"] <= r["t_admit_ns"] <= r["t_done_ns"]
+
+
+def by_id(results):
+    return {int(r["id"]): r for r in results}
+
+
+def test_small_groups_exact(dev):
+    from paper_1806_10113_amd import tgo
+    b = W.batch_groups(300, 1, 9, seed=400, per_task_label=True)
+    srv = tgo.Server(tgo.DEFAULT, tgo.server_config(streams=3, max_batch=64))
+    ids = [srv.submit(b.group(g)) for g in range(b.n_groups)]
+    srv.drain()
+    res = by_id(srv.poll(1000))
+    assert len(res) == b.n_groups
+    for g, i in enumerate(ids):
+        check_small(res[i], b.group(g))
+    st = srv.stats()
+    assert st["completed"] == b.n_groups and st["batches"] >= b.n_groups // 64
+    srv.close()
+
+
+def test_same_alone_and_in_mix_small_and_large(dev):
+    """A request's answer does not depend on what else is in flight: the same
+    small and large probes (same sampling key) alone and inside a mix."""
+    from paper_1806_10113_amd import tgo
+    sur = tgo.Surrogate(max_rows=1 << 14, max_groups=64)
+    sur.init(9)
+    cfg = tgo.server_config(streams=2, max_batch=32, max_batch_large=8, samples=4096, topk=32)
+    probe_small = W.batch_groups(1, 8, 8, seed=401).group(0)
+    probe_large = W.fixed_size_groups(1, 14, seed=402).group(0)
+    mix = W.batch_groups(120, 4, 16, seed=403, per_task_label=True)
+
+    def run(with_mix):
+        srv = tgo.Server(tgo.DEFAULT, cfg, sur)
+        ids = []
+        if with_mix:
+            ids += [srv.submit(mix.group(g)) for g in range(60)]
+        a = srv.submit(probe_small, key=777)
+        c = srv.submit(probe_large, key=778)
+        if with_mix:
+            ids += [srv.submit(mix.group(g)) for g in range(60, 120)]
+        srv.drain()
+        res = by_id(srv.poll(1000))
+        srv.close()
+        return res, a, c, ids
+
+    alone, a1, c1, _ = run(False)
+    mixed, a2, c2, ids = run(True)
+    for x1, x2 in ((a1, a2), (c1, c2)):
+        for k in ("best_ns", "heur_ns", "status", "path", "n"):
+            assert alone[x1][k] == mixed[x2][k], k
+        assert bytes(alone[x1]["best"]) == bytes(mixed[x2]["best"])
+    check_small(alone[a1], probe_small)
+    L = mixed[c2]
+    assert L["path"] == 1 and L["status"] == 0
+    assert L["best_ns"] == cmodel.simulate(probe_large, [int(v) for v in L["best"][:14]], M.DEFAULT)
+    assert L["best_ns"] <= L["heur_ns"]
+    # every mixed request is answered exactly
+    for g, i in enumerate(ids):
+        r = mixed[i]
+        grp = mix.group(g)
+        n = len(grp)
+        assert r["status"] == 0
+        assert r["best_ns"] == cmodel.simulate(grp, [int(v) for v in r["best"][:n]], M.DEFAULT)
+        if n <= 10:
+            check_small(r, grp)
+        else:
+            assert r["path"] == 1 and r["best_ns"] <= r["heur_ns"]
+    sur.close()
+
+
+def test_budget_admission(dev):
+    from paper_1806_10113_amd import tgo
+    # a budget of about three small requests forces waiting for memory
+    cfg = tgo.server_config(streams=4, max_batch=16, budget_bytes=3 * 700)
+    b = W.batch_groups(40, 4, 8, seed=405)
+    srv = tgo.Server(tgo.DEFAULT, cfg)
+    ids = [srv.submit(b.group(g)) for g in range(b.n_groups)]
+    srv.drain()
+    res = by_id(srv.poll(100))
+    st = srv.stats()
+    assert st["max_in_use_bytes"] <= 3 * 700
+    assert st["batches"] >= b.n_groups // 3
+    for g, i in enumerate(ids):
+        check_small(res[i], b.group(g))
+    srv.close()
+
+
+def test_replay_poisson_trace(dev):
+    from paper_1806_10113_amd import tgo
+    arr = W.poisson_arrivals(20_000.0, 0.1, 4, 10, seed=406)
+    srv = tgo.Server(tgo.DEFAULT, tgo.server_config(streams=4, max_batch=128))
+    out = srv.replay(arr.batch.tasks, arr.batch.offs, arr.t_ns)
+    assert (out["status"] == 0).all()
+    lat = (out["t_done_ns"] - out["t_arrive_ns"]) / 1e3
+    assert (lat > 0).all()
+    rng = np.random.default_rng(0)
+    for g in rng.choice(arr.batch.n_groups, size=40, replace=False):
+        check_small(out[g], arr.batch.group(int(g)))
+    srv.close()
