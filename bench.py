@@ -47,7 +47,11 @@ def parse():
                    help="target duration of the CPU-oracle baseline sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extras", action="store_true",
-                   help="skip the batched-workload measurement")
+                   help="skip the batched, learned-proposal and serving measurements")
+    p.add_argument("--train-pairs", type=float, default=2e6,
+                   help="exact (ordering, time) pairs used to train the proposal network")
+    p.add_argument("--eval-groups", type=int, default=1024)
+    p.add_argument("--serve-seconds", type=float, default=2.0)
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a 256 MiB device copy (for HBM counter calibration)")
     return p.parse_args()
@@ -101,6 +105,135 @@ def batch_extra(dev, reps: int = 5):
             "ms_per_batch": ms, "groups_per_s": b.n_groups / (ms / 1e3),
             "orderings_per_s": orderings / (ms / 1e3), "orderings": orderings,
             "bad_status": bad, "plan": desc}
+
+
+def train_surrogate(dev, pairs_total: float, seed: int = 1003, batch: int = 8192, lr: float = 1e-3):
+    """Train the proposal network on exact pairs from groups of N in [8, 16]."""
+    import torch
+    from paper_1806_10113_amd import tgo, workloads as W
+    per = 1024
+    groups = max(64, int(pairs_total // per))
+    b = W.batch_groups(groups, 8, 16, seed=seed, per_task_label=True)
+    tasks, offs = torch.as_tensor(b.tasks).to(dev), torch.as_tensor(b.offs).to(dev)
+    t0 = time.perf_counter()
+    orders, gid, T, status = tgo.pairs(tasks, offs, per, seed=seed)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    sur = tgo.Surrogate(max_rows=1 << 18, max_groups=4096)
+    sur.init(seed)
+    P = orders.shape[0]
+    steps = P // batch
+    perm = torch.randperm(P, generator=torch.Generator().manual_seed(seed)).to(dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    first = None
+    t0 = time.perf_counter()
+    for i in range(steps):
+        idx = perm[i * batch:(i + 1) * batch]
+        rate = lr if i < steps * 2 // 3 else lr / 4
+        sur.train_step(tasks, offs, orders[idx].contiguous(), gid[idx].contiguous(), T[idx].contiguous(),
+                       rate, loss=loss)
+        if i == 0:
+            first = float(loss.cpu()[0])
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    return sur, {"pairs": int(P), "train_groups": groups, "steps": steps, "batch": batch,
+                 "pairs_s": t_pairs, "train_s": t_train, "loss_first": first,
+                 "loss_last": float(loss.cpu()[0]),
+                 "train_flop_per_s": 3 * 2 * 143616 * P / t_train}
+
+
+def surrogate_extra(dev, sur, n_groups: int):
+    """1,024 groups of N=16 (per-task DK/DT, seed 3): learned proposal vs the
+    plain exact-evaluation search (heuristic + uniformly sampled orderings)."""
+    import torch
+    from paper_1806_10113_amd import tgo, workloads as W
+    ev = W.fixed_size_groups(n_groups, 16, seed=3)
+    tasks, offs = torch.as_tensor(ev.tasks).to(dev), torch.as_tensor(ev.offs).to(dev)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    res = {}
+    sur_runs = {}
+    for S in (1 << 14, 1 << 16, 1 << 18):
+        r, t = timed(lambda: sur.search(tasks, offs, samples=S, topk=64, seed=31))
+        sur_runs[S] = (tgo.read_search(r), t)
+    plain_runs = {}
+    for B in (1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20):
+        r, t = timed(lambda: tgo.random_search(tasks, offs, samples=B, seed=32))
+        plain_runs[B] = (tgo.read_search(r), t)
+    ablation, _ = timed(lambda: tgo.random_search(tasks, offs, samples=64, seed=33))
+    ablation = tgo.read_search(ablation)
+
+    def mean_best(rs):
+        return sum(x["best_ns"] for x in rs) / len(rs)
+
+    def gap(a, b):  # mean over groups of (T_a - T_b) / T_b, percent
+        return 100.0 * sum((x["best_ns"] - y["best_ns"]) / y["best_ns"] for x, y in zip(a, b)) / len(a)
+
+    res["surrogate"] = {str(S): {"s": t, "groups_per_s": n_groups / t, "mean_best_ns": mean_best(r),
+                                 "from_heuristic": sum(x["from_heuristic"] for x in r)}
+                        for S, (r, t) in sur_runs.items()}
+    res["plain"] = {str(B): {"s": t, "groups_per_s": n_groups / t, "mean_best_ns": mean_best(r)}
+                    for B, (r, t) in plain_runs.items()}
+    # equal wall time: the plain budget whose time is closest to each surrogate run
+    eq = {}
+    for S, (r, t) in sur_runs.items():
+        B = min(plain_runs, key=lambda b: abs(math.log(plain_runs[b][1] / t)))
+        eq[str(S)] = {"plain_samples": B, "time_ratio": plain_runs[B][1] / t,
+                      "gap_pct_vs_plain": gap(r, plain_runs[B][0])}
+    res["equal_time"] = eq
+    # the plain search at its largest budget vs every surrogate run
+    Bmax = max(plain_runs)
+    res["vs_plain_max"] = {str(S): {"gap_pct": gap(r, plain_runs[Bmax][0]),
+                                    "speedup_groups_per_s": plain_runs[Bmax][1] / t}
+                           for S, (r, t) in sur_runs.items()}
+    res["plain_max_samples"] = Bmax
+    # ablation: the network's 64 candidates vs 64 uniformly sampled ones
+    r16 = sur_runs[1 << 16][0]
+    res["ablation_candidates"] = {
+        "network_better": sum(x["cand_best_ns"] < y["cand_best_ns"] for x, y in zip(r16, ablation)),
+        "random_better": sum(x["cand_best_ns"] > y["cand_best_ns"] for x, y in zip(r16, ablation)),
+        "gap_pct_network_vs_random": 100.0 * sum((x["cand_best_ns"] - y["cand_best_ns"]) / y["cand_best_ns"]
+                                                 for x, y in zip(r16, ablation)) / n_groups}
+    res["heuristic_mean_ns"] = sum(x["heur_ns"] for x in r16) / n_groups
+    return res
+
+
+def serving_extra(dev, sur, seconds: float):
+    """Poisson arrivals at 20,000 groups/s, N ~ U{4..16}, per-task DK/DT, seed 4."""
+    import numpy as np
+    from paper_1806_10113_amd import tgo, workloads as W
+    arr = W.poisson_arrivals(20_000.0, seconds, 4, 16, seed=4)
+    cfg = tgo.server_config(streams=4, max_batch=256, max_batch_large=64, samples=4096, topk=64,
+                            budget_bytes=8 << 30)
+    srv = tgo.Server(tgo.DEFAULT, cfg, sur)
+    t0 = time.perf_counter()
+    out = srv.replay(arr.batch.tasks, arr.batch.offs, arr.t_ns)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    warm = arr.t_ns[0] + int(0.25 * seconds * 1e9)
+    keep = arr.t_ns >= warm
+    lat = (out["t_done_ns"] - out["t_arrive_ns"])[keep] / 1e3
+    small = (out["path"] == 0)[keep]
+    span = (out["t_done_ns"].max() - out["t_arrive_ns"].min()) / 1e9
+    return {"offered_groups_per_s": 20_000.0, "requests": int(len(out)),
+            "achieved_groups_per_s": len(out) / span, "wall_s": wall,
+            "p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
+            "p50_us_exhaustive": float(np.percentile(lat[small], 50)),
+            "p99_us_exhaustive": float(np.percentile(lat[small], 99)),
+            "p50_us_proposal": float(np.percentile(lat[~small], 50)) if (~small).any() else None,
+            "p99_us_proposal": float(np.percentile(lat[~small], 99)) if (~small).any() else None,
+            "bad_status": int((out["status"] != 0).sum()), "batches": st["batches"],
+            "max_queued": st["max_queued"], "max_in_use_bytes": st["max_in_use_bytes"],
+            "latency_window": "arrivals after the first quarter of the trace",
+            "config": {"streams": 4, "max_batch": 256, "max_batch_large": 64, "samples": 4096,
+                       "topk": 64, "budget_bytes": 8 << 30}}
 
 
 def main():
@@ -190,7 +323,13 @@ def main():
         "min_ns": s["min_ns"], "mean_ns": s["mean_ns"],
     }
     if not args.no_extras:
-        out["extras"] = {"batch": batch_extra(dev)}
+        extras = {"batch": batch_extra(dev)}
+        sur, tr = train_surrogate(dev, args.train_pairs)
+        extras["proposal_training"] = tr
+        extras["proposal_n16"] = surrogate_extra(dev, sur, args.eval_groups)
+        extras["serving"] = serving_extra(dev, sur, args.serve_seconds)
+        sur.close()
+        out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(tasks_np, args.cpu_seconds)
     print(json.dumps(out), flush=True)
