@@ -317,10 +317,94 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const uint16_t *__restrict
     }
 }
 
+// Large-M variant for the forward passes: block tile 128 x 128, wave w owns
+// the 64 x 64 quadrant (w/2, w%2) as 4 x 4 MFMA tiles, so every K step issues
+// 16 MFMAs per wave between two barriers; the next K slice is fetched into
+// registers while the current one is multiplied.  M, N multiples of 128.
+constexpr int BT2 = 128;
+
+__device__ __forceinline__ void epilogue_store(const GemmOut &out, int EPI, int M, int N, int row0, int col,
+                                               const f32x4 &acc) {
+    const float bb = (EPI & EPI_BIAS) ? out.bias[col] : 0.f;
+    uint16_t yv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = row0 + i;
+        float vv = acc[i] + bb;
+        if (EPI & EPI_RELU) vv = vv > 0.f ? vv : 0.f;
+        if (EPI & EPI_MASK) vv = bf2f(out.mask[(int64_t)row * N + col]) > 0.f ? vv : 0.f;
+        if (out.Cf) out.Cf[(int64_t)row * N + col] = vv;
+        yv[i] = f2bf(vv);
+        if (out.Y) out.Y[(int64_t)row * N + col] = yv[i];
+    }
+    if (out.Yt) {
+        uint2 q;
+        q.x = yv[0] | ((uint32_t)yv[1] << 16);
+        q.y = yv[2] | ((uint32_t)yv[3] << 16);
+        *reinterpret_cast<uint2 *>(out.Yt + (int64_t)col * M + row0) = q;
+    }
+}
+
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_nt_big_kernel(const uint16_t *__restrict__ A,
+                                                          const uint16_t *__restrict__ B, int M, int N, int K,
+                                                          GemmOut out) {
+    __shared__ __align__(16) uint16_t As[BT2][GK + GPAD];
+    __shared__ __align__(16) uint16_t Bs[BT2][GK + GPAD];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int m0 = blockIdx.y * BT2, n0 = blockIdx.x * BT2;
+    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // each thread moves rows (tid / 4) and (tid / 4 + 64), 8 bf16 at column (tid % 4) * 8
+    const int lr = tid >> 2, lk = (tid & 3) * 8;
+    const uint16_t *a0 = A + (int64_t)(m0 + lr) * K + lk, *a1 = a0 + (int64_t)64 * K;
+    const uint16_t *b0 = B + (int64_t)(n0 + lr) * K + lk, *b1 = b0 + (int64_t)64 * K;
+    uint4 ra0 = *reinterpret_cast<const uint4 *>(a0), ra1 = *reinterpret_cast<const uint4 *>(a1);
+    uint4 rb0 = *reinterpret_cast<const uint4 *>(b0), rb1 = *reinterpret_cast<const uint4 *>(b1);
+    for (int k0 = 0; k0 < K; k0 += GK) {
+        __syncthreads();
+        *reinterpret_cast<uint4 *>(&As[lr][lk]) = ra0;
+        *reinterpret_cast<uint4 *>(&As[lr + 64][lk]) = ra1;
+        *reinterpret_cast<uint4 *>(&Bs[lr][lk]) = rb0;
+        *reinterpret_cast<uint4 *>(&Bs[lr + 64][lk]) = rb1;
+        __syncthreads();
+        if (k0 + GK < K) {
+            ra0 = *reinterpret_cast<const uint4 *>(a0 + k0 + GK);
+            ra1 = *reinterpret_cast<const uint4 *>(a1 + k0 + GK);
+            rb0 = *reinterpret_cast<const uint4 *>(b0 + k0 + GK);
+            rb1 = *reinterpret_cast<const uint4 *>(b1 + k0 + GK);
+        }
+        bf16x8 fa[4], fb[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            fa[t] = *reinterpret_cast<const bf16x8 *>(&As[wr + t * 16 + (l & 15)][(l >> 4) * 8]);
+            fb[t] = *reinterpret_cast<const bf16x8 *>(&Bs[wc + t * 16 + (l & 15)][(l >> 4) * 8]);
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            epilogue_store(out, EPI, M, N, m0 + wr + a * 16 + (l >> 4) * 4, n0 + wc + b * 16 + (l & 15),
+                           acc[a][b]);
+}
+
 template <int EPI>
 static void gemm(const uint16_t *A, const uint16_t *B, int M, int N, int K, const GemmOut &o,
                  hipStream_t st) {
-    hipLaunchKernelGGL(gemm_nt_kernel<EPI>, dim3(N / GT, M / GT), dim3(256), 0, st, A, B, M, N, K, o);
+    if (M % BT2 == 0 && N % BT2 == 0 && M >= 4096)
+        hipLaunchKernelGGL(gemm_nt_big_kernel<EPI>, dim3(N / BT2, M / BT2), dim3(256), 0, st, A, B, M, N, K, o);
+    else
+        hipLaunchKernelGGL(gemm_nt_kernel<EPI>, dim3(N / GT, M / GT), dim3(256), 0, st, A, B, M, N, K, o);
 }
 
 // ----------------------------------------------------------- head, loss
