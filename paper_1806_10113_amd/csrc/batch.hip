@@ -141,7 +141,7 @@ __global__ __launch_bounds__(BT_THREADS) void batch_kernel(const tgo_task *__res
                                                            BatchHdr *hdr) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ Quad<uint32_t> Ht[BT_WAVES][MAXN];
-    __shared__ Pair<uint32_t> Dt[BT_WAVES][MAXN];
+    __shared__ DRec<uint32_t> Dt[BT_WAVES][MAXN];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     View<uint32_t, 1, BT_THREADS> v;

@@ -18,7 +18,7 @@ __global__ __launch_bounds__(EV_THREADS) void evaluate_kernel(const tgo_task *__
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int MODE = sizeof(TT) == 4 ? 0 : 1;
     __shared__ Quad<TT> Ht[MAXN];
-    __shared__ Pair<TT> Dt[MAXN];
+    __shared__ DRec<TT> Dt[MAXN];
     __shared__ int mode;
     if (threadIdx.x == 0) mode = classify_group(tasks, n, r);
     if ((int)threadIdx.x < n) table_entry<TT>(tasks[threadIdx.x], r, &Ht[threadIdx.x], &Dt[threadIdx.x]);
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(HEU_THREADS) void heuristic_kernel(const tgo_task *
                                                                 int64_t *ns, int ns_stride) {
     using TT = uint64_t;
     __shared__ Quad<TT> Ht[MAXN * HEU_THREADS];
-    __shared__ Pair<TT> Dt[MAXN * HEU_THREADS];
+    __shared__ DRec<TT> Dt[MAXN * HEU_THREADS];
     __shared__ Slot<TT> Qs[MAXN * HEU_THREADS];
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n_groups) return;

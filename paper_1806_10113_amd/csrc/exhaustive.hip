@@ -96,7 +96,7 @@ __global__ __launch_bounds__(EX_THREADS) void exhaustive_kernel(const tgo_task *
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int MODE = sizeof(TT) == 4 ? 0 : 1;
     __shared__ Quad<TT> Ht[MAXN];
-    __shared__ Pair<TT> Dt[MAXN];
+    __shared__ DRec<TT> Dt[MAXN];
     __shared__ int mode;
     if (threadIdx.x == 0) mode = classify_group(tasks, n, r);
     if ((int)threadIdx.x < n) table_entry<TT>(tasks[threadIdx.x], r, &Ht[threadIdx.x], &Dt[threadIdx.x]);

@@ -44,8 +44,11 @@ struct Rates {
 };
 
 template <typename TT>
-struct alignas(2 * sizeof(TT)) Pair {
-    TT a, b;  // DtH: (solo duration, duration when fully overlapped)
+struct alignas(4 * sizeof(TT)) DRec {
+    TT d;      // DtH solo duration
+    TT dp;     // duration when fully overlapped: ceil(q d / p_dth)
+    TT slack;  // p_dth dp - q d, in [0, p_dth)
+    TT pad;
 };
 
 template <typename TT>
@@ -88,10 +91,10 @@ __device__ __forceinline__ TT inf_time() { return ~TT(0); }
 template <typename TT, int TS, int QS>
 struct View {
     const Quad<TT> *H;  // (h, ceil(q h / p_h), k, d)
-    const Pair<TT> *D;  // (d, ceil(q d / p_d))
+    const DRec<TT> *D;  // (d, ceil(q d / p_d), slack)
     Slot<TT> *Q;
     __device__ __forceinline__ Quad<TT> task(uint32_t x) const { return H[x * TS]; }
-    __device__ __forceinline__ Pair<TT> d(uint32_t x) const { return D[x * TS]; }
+    __device__ __forceinline__ DRec<TT> d(uint32_t x) const { return D[x * TS]; }
     __device__ __forceinline__ Slot<TT> q(int j) const { return Q[j * QS]; }
     __device__ __forceinline__ void put(int j, Slot<TT> s) const { Q[j * QS] = s; }
 };
@@ -104,8 +107,8 @@ struct Lane {
     TT ck;       // end of the previous kernel
     TT dev;      // next DtH event: end of the running DtH, or (idle) end of
                  // the kernel it waits for; inf while that is not known yet
-    TT ukey;     // running DtH: q d + p_dth t0 (mod 2^bits) for start t0, so
-                 // that its work left at time t is q d - p_dth (t - t0)
+    TT slack;    // running DtH: p_dth dp - q d of its task; with end estimate
+                 // dev its work left at time t <= dev is p_dth (dev - t) - slack
     TT dpre;     // sum of solo DtH durations of the positions placed so far
     TT dthru;    // sum of solo DtH durations up to the cursor (running included)
     ST emax;     // max over placed positions p of (K_p end - sum_{s<p} d_s)
@@ -117,7 +120,7 @@ template <typename TT>
 __device__ __forceinline__ Lane<TT> lane_init() {
     using ST = typename Signed<TT>::type;
     Lane<TT> s;
-    s.t = 0; s.ck = 0; s.dev = inf_time<TT>(); s.ukey = 0;
+    s.t = 0; s.ck = 0; s.dev = inf_time<TT>(); s.slack = 0;
     s.dpre = 0; s.dthru = 0;
     s.emax = (ST)(((TT)1) << (8 * sizeof(TT) - 1));  // most negative
     s.i = 0; s.drun = false;
@@ -157,10 +160,10 @@ __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const Vie
             eh = ev + (start ? (TT)ceil_p(uh, r.p_h, r.inv_ph, r.c_ph) : ceil_q(uh, r.q_log2));
         }
         if (start) {
-            const Pair<TT> dd = v.d(nx.x);
-            s.dthru += dd.a;
-            s.ukey = (dd.a << r.q_log2) + TT(r.p_d) * ev;
-            s.dev = ev + dd.b;
+            const DRec<TT> dd = v.d(nx.x);
+            s.dthru += dd.d;
+            s.slack = dd.slack;
+            s.dev = ev + dd.dp;
         } else {
             s.dev = inew < j ? nx.ck : inf_time<TT>();
         }
@@ -192,10 +195,11 @@ __device__ __forceinline__ TT tail(const Lane<TT> &s, const Rates &r) {
     using ST = typename Signed<TT>::type;
     TT T = (TT)(s.emax + (ST)s.dpre);
     if (s.drun) {
-        // work left on the running DtH; the true value lies in (-p_dth, q d],
-        // so the wrapped difference read as signed is exact
-        const ST ud = (ST)(s.ukey - TT(r.p_d) * s.t);
-        const TT dend = s.t + ceil_q(ud > 0 ? (TT)ud : TT(0), r.q_log2) + (s.dpre - s.dthru);
+        // work left on the running DtH (it ran at p_dth since its start;
+        // s.dev >= s.t): q d - p_dth (t - start) = p_dth (dev - t) - slack
+        const TT pw = TT(r.p_d) * (s.dev - s.t);
+        const TT ud = pw > s.slack ? pw - s.slack : TT(0);
+        const TT dend = s.t + ceil_q(ud, r.q_log2) + (s.dpre - s.dthru);
         T = tmax(T, dend);
     }
     return T;

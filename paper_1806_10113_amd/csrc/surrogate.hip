@@ -33,7 +33,7 @@ constexpr int SG_THREADS = 256;
 
 struct WaveTables {
     Quad<uint32_t> H[4][MAXN];
-    Pair<uint32_t> D[4][MAXN];
+    DRec<uint32_t> D[4][MAXN];
 };
 
 __device__ __forceinline__ uint32_t eval_perm(uint64_t perm, int n, const View<uint32_t, 1, SG_THREADS> &v,

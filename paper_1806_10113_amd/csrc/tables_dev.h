@@ -24,9 +24,10 @@ __device__ inline int classify_group(const tgo_task *t, int n, const Rates &r) {
     return (mx < lim32 && sum + time_bound_slack(n) < lim32) ? 0 : 1;
 }
 
-// Entry x of the tables from task t: (h, ceil(q h/p_h), k, d) and (d, ceil(q d/p_d)).
+// Entry x of the tables from task t: (h, ceil(q h/p_h), k, d) and
+// (d, ceil(q d/p_d), p_d ceil(q d/p_d) - q d).
 template <typename TT>
-__device__ inline void table_entry(const tgo_task &t, const Rates &r, Quad<TT> *H, Pair<TT> *D) {
+__device__ inline void table_entry(const tgo_task &t, const Rates &r, Quad<TT> *H, DRec<TT> *D) {
     const uint64_t q = 1ull << r.q_log2;
     const uint64_t h = (uint64_t)t.htd_ns, k = (uint64_t)t.kern_ns, d = (uint64_t)t.dth_ns;
     Quad<TT> e;
@@ -34,9 +35,12 @@ __device__ inline void table_entry(const tgo_task &t, const Rates &r, Quad<TT> *
     e.hp = (TT)((q * h + r.p_h - 1) / r.p_h);
     e.k = (TT)k;
     e.d = (TT)d;
-    Pair<TT> pd;
-    pd.a = (TT)d;
-    pd.b = (TT)((q * d + r.p_d - 1) / r.p_d);
+    DRec<TT> pd;
+    const uint64_t dp = (q * d + r.p_d - 1) / r.p_d;
+    pd.d = (TT)d;
+    pd.dp = (TT)dp;
+    pd.slack = (TT)(r.p_d * dp - q * d);
+    pd.pad = 0;
     *H = e;
     *D = pd;
 }
