@@ -48,7 +48,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the batched, learned-proposal and serving measurements")
-    p.add_argument("--train-pairs", type=float, default=2e6,
+    p.add_argument("--train-pairs", type=float, default=2e7,
                    help="exact (ordering, time) pairs used to train the proposal network")
     p.add_argument("--eval-groups", type=int, default=1024)
     p.add_argument("--serve-seconds", type=float, default=2.0)

@@ -204,8 +204,6 @@ __global__ void features_kernel(const float *__restrict__ F, const int32_t *__re
                                 uint16_t *X, uint16_t *Xt, int64_t xt_rows, uint8_t *valid) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rows) return;
-    uint16_t x[SG_K0];
-    for (int c = 0; c < SG_K0; ++c) x[c] = 0;
     int g;
     uint64_t perm;
     int n;
@@ -223,26 +221,44 @@ __global__ void features_kernel(const float *__restrict__ F, const int32_t *__re
         ok = s < S && n >= 1 && n <= SG_POS;
         perm = ok ? sample_ordering(n, gkeys ? gkeys[g] : (uint32_t)g, (uint64_t)s, seed) : 0;
     }
-    if (ok) {
-        for (int p = 0; p < n && p < SG_POS; ++p) {
+    // 48 features + 16 zeros as 32 packed bf16 pairs; every index static
+    uint32_t w[SG_K0 / 2];
+#pragma unroll
+    for (int c = 0; c < SG_K0 / 2; ++c) w[c] = 0;
+    const float *Fg = F + (int64_t)g * SG_POS * 3;
+#pragma unroll
+    for (int p = 0; p < SG_POS; ++p) {
+        if (ok && p < n) {
             const int t = (int)((perm >> (4 * p)) & 15u);
-            const float *f = F + ((int64_t)g * SG_POS + t) * 3;
-            x[3 * p] = f2bf(f[0]);
-            x[3 * p + 1] = f2bf(f[1]);
-            x[3 * p + 2] = f2bf(f[2]);
+            const uint32_t f0 = f2bf(Fg[t * 3]), f1 = f2bf(Fg[t * 3 + 1]), f2 = f2bf(Fg[t * 3 + 2]);
+            // features 3p, 3p+1, 3p+2 -> halves of words (3p)/2 ...
+            const int c0 = 3 * p;
+            if ((c0 & 1) == 0) {
+                w[c0 / 2] = f0 | (f1 << 16);
+                w[c0 / 2 + 1] |= f2;
+            } else {
+                w[c0 / 2] |= f0 << 16;
+                w[c0 / 2 + 1] = f1 | (f2 << 16);
+            }
         }
     }
     uint4 *dst = reinterpret_cast<uint4 *>(X + i * SG_K0);
+#pragma unroll
     for (int c = 0; c < SG_K0 / 8; ++c) {
         uint4 q;
-        q.x = x[8 * c] | ((uint32_t)x[8 * c + 1] << 16);
-        q.y = x[8 * c + 2] | ((uint32_t)x[8 * c + 3] << 16);
-        q.z = x[8 * c + 4] | ((uint32_t)x[8 * c + 5] << 16);
-        q.w = x[8 * c + 6] | ((uint32_t)x[8 * c + 7] << 16);
+        q.x = w[4 * c];
+        q.y = w[4 * c + 1];
+        q.z = w[4 * c + 2];
+        q.w = w[4 * c + 3];
         dst[c] = q;
     }
-    if (Xt)
-        for (int c = 0; c < SG_K0; ++c) Xt[(int64_t)c * xt_rows + i] = x[c];
+    if (Xt) {
+#pragma unroll
+        for (int c = 0; c < SG_K0 / 2; ++c) {
+            Xt[(int64_t)(2 * c) * xt_rows + i] = (uint16_t)w[c];
+            Xt[(int64_t)(2 * c + 1) * xt_rows + i] = (uint16_t)(w[c] >> 16);
+        }
+    }
     if (valid) valid[i] = ok ? 1 : 0;
 }
 
@@ -462,11 +478,9 @@ __global__ void loss_kernel(const float *__restrict__ score, const float *__rest
     if ((threadIdx.x & 63) == 0) atomicAdd(loss, e);
 }
 
-// dh3 = dscore w4 * (h3 > 0), bf16 [rows][256] and [256][rows];
-// grad w4 += sum_i dscore_i h3_i; grad b4 += sum dscore (one wave per row)
+// dh3 = dscore w4 * (h3 > 0), bf16 [rows][256] and [256][rows] (one wave per row)
 __global__ void head_bwd_kernel(const uint16_t *__restrict__ H3, const float *__restrict__ w4,
-                                const float *__restrict__ dscore, int rows, uint16_t *dH, uint16_t *dHt,
-                                float *gw4, float *gb4) {
+                                const float *__restrict__ dscore, int rows, uint16_t *dH, uint16_t *dHt) {
     const int row = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int l = threadIdx.x & 63;
     if (row >= rows) return;
@@ -477,9 +491,26 @@ __global__ void head_bwd_kernel(const uint16_t *__restrict__ H3, const float *__
         const uint16_t g = f2bf(h > 0.f ? ds * w4[c] : 0.f);
         dH[(int64_t)row * SG_H + c] = g;
         dHt[(int64_t)c * rows + row] = g;
-        atomicAdd(&gw4[c], ds * h);
     }
-    if (l == 0) atomicAdd(gb4, ds);
+}
+
+// grad w4[c] = sum_i dscore_i h3[i][c] from the transposed activations (block
+// c < 256), grad b4 = sum_i dscore_i (block 256)
+__global__ void head_wgrad_kernel(const uint16_t *__restrict__ H3t, const float *__restrict__ dscore, int rows,
+                                  float *gw4, float *gb4) {
+    const int c = blockIdx.x;
+    float acc = 0.f;
+    for (int i = threadIdx.x; i < rows; i += blockDim.x)
+        acc += dscore[i] * (c < SG_H ? bf2f(H3t[(int64_t)c * rows + i]) : 1.f);
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
+    __shared__ float red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float t = red[0] + red[1] + red[2] + red[3];
+        if (c < SG_H) gw4[c] = t;
+        else gb4[0] = t;
+    }
 }
 
 // bias gradient: gb[c] = sum_i Gt[c][i] (rows of the transposed gradient)
@@ -884,7 +915,9 @@ static int sur_grad(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *d_
     hipLaunchKernelGGL(loss_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, s->score, s->y, rows, s->dscore,
                        d_loss);
     hipLaunchKernelGGL(head_bwd_kernel, dim3((unsigned)((rows * 64 + 255) / 256)), dim3(256), 0, st, s->H3,
-                       s->p + SG_OFF_W4, s->dscore, rows, s->D3, s->D3t, s->g + SG_OFF_W4, s->g + SG_OFF_B4);
+                       s->p + SG_OFF_W4, s->dscore, rows, s->D3, s->D3t);
+    hipLaunchKernelGGL(head_wgrad_kernel, dim3(SG_H + 1), dim3(256), 0, st, s->H3t, s->dscore, rows,
+                       s->g + SG_OFF_W4, s->g + SG_OFF_B4);
     // layer 3: grad W3 = D3^T H2 ; grad b3 = colsum ; D2 = (D3 W3) * (H2 > 0)
     GemmOut o{};
     o.Cf = s->g + SG_OFF_W3;
