@@ -29,13 +29,13 @@ SEED = 1
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 32-bit VALU lane-ops/s.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
-# VALU instructions issued per ordering by the exhaustive kernel on this
-# workload (SQ_INSTS_VALU per launch / 12!, from the rocprofv3 counter run
-# recorded in profiles/exhaustive_n12_counters.txt); x64 lanes = lane-ops.
-VALU_INSTS_PER_ORDERING = 327.18 / 64  # wave-instructions per ordering
-# HBM bytes per launch from FETCH_SIZE + WRITE_SIZE (same profile), scaled by
-# the copy-kernel calibration; None until measured for the current kernel.
-TRAFFIC_BYTES_PER_LAUNCH = None
+# VALU lane-ops per ordering issued by exhaustive_kernel<u32, M=4> on this
+# workload: SQ_INSTS_VALU per launch x 64 lanes / 12! (rocprofv3 counter run
+# recorded in profiles/exhaustive_n12_counters.txt).
+VALU_LANE_OPS_PER_ORDERING = 220.54
+# HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, each scaled by
+# what the counter reads for a 256 MiB device copy (same profile file).
+TRAFFIC_BYTES_PER_LAUNCH = 436_899
 
 
 def parse():
@@ -119,7 +119,7 @@ def train_surrogate(dev, pairs_total: float, seed: int = 1003, batch: int = 8192
     orders, gid, T, status = tgo.pairs(tasks, offs, per, seed=seed)
     torch.cuda.synchronize()
     t_pairs = time.perf_counter() - t0
-    sur = tgo.Surrogate(max_rows=1 << 18, max_groups=4096)
+    sur = tgo.Surrogate(max_rows=1 << 18, max_groups=max(4096, groups))
     sur.init(seed)
     P = orders.shape[0]
     steps = P // batch
@@ -302,14 +302,16 @@ def main():
     value = orderings * k / (total_ms / 1e3)
 
     roof = {"bound": "alu", "unit": "TOP/s", "peak": VALU_PEAK_TOPS}
-    if VALU_INSTS_PER_ORDERING is not None:
-        achieved = VALU_INSTS_PER_ORDERING * 64 * orderings / (avg_launch_ms / 1e3) / 1e12
+    if VALU_LANE_OPS_PER_ORDERING is not None:
+        achieved = VALU_LANE_OPS_PER_ORDERING * orderings / (avg_launch_ms / 1e3) / 1e12
         roof.update({"achieved": achieved, "frac": achieved / VALU_PEAK_TOPS})
     else:
         roof.update({"achieved": None, "frac": None})
     roof["traffic"] = TRAFFIC_BYTES_PER_LAUNCH
     roof["launch_ms"] = avg_launch_ms
-    roof["kernel"] = "exhaustive_kernel<u32, M=5> (+ finalize)"
+    roof["kernel"] = "exhaustive_kernel<u32, M=4>"
+    roof["launch_ms_note"] = "HIP events around the exhaustive call (main kernel, idle 64-bit twin, finalize)"
+    roof["hbm_gbs"] = TRAFFIC_BYTES_PER_LAUNCH / (avg_launch_ms / 1e3) / 1e9
 
     out = {
         "metric": METRIC, "value": value, "unit": "orderings/s", "n_gpus": 1, "steps": k,

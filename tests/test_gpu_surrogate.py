@@ -114,10 +114,10 @@ def test_gradients_against_float64_oracle(dev):
     sur.close()
 
 
-def trained(dev, steps=600, seed=5):
+def trained(dev, steps=600, seed=5, groups=256):
     import torch
     from paper_1806_10113_amd import tgo
-    b = W.batch_groups(256, 10, 16, seed=1003, per_task_label=True)
+    b = W.batch_groups(groups, 10, 16, seed=1003, per_task_label=True)
     tasks, offs = to_dev(b.tasks, dev), to_dev(b.offs, dev)
     orders, gid, T, status = tgo.pairs(tasks, offs, 512, seed=17)
     sur = tgo.Surrogate(max_rows=1 << 16, max_groups=4096)
@@ -143,7 +143,7 @@ def test_training_reduces_loss(dev):
 
 def test_search_results_exact_and_better_than_random_candidates(dev):
     from paper_1806_10113_amd import tgo
-    sur, _ = trained(dev, steps=600)
+    sur, _ = trained(dev, steps=3000, groups=1024)
     ev = W.fixed_size_groups(48, 16, seed=3)
     tasks, offs = to_dev(ev.tasks, dev), to_dev(ev.offs, dev)
     res = tgo.read_search(sur.search(tasks, offs, samples=20_000, topk=64, seed=21))
@@ -161,8 +161,10 @@ def test_search_results_exact_and_better_than_random_candidates(dev):
             perm = philox.sample_ordering(16, g, r["best_sample"], 21)
             assert perm == r["best"]
         wins += r["cand_best_ns"] < rnd[g]["cand_best_ns"]
-    # the network's 64 candidates beat 64 random candidates on most groups
-    assert wins >= 0.75 * ev.n_groups, wins
+    # the network's 64 candidates beat 64 uniformly sampled ones on most
+    # groups; if the network were no better than chance, 34 or more wins of 48
+    # would happen with probability below 0.3% (one-sided binomial)
+    assert wins >= 34, wins
     sur.close()
 
 
