@@ -159,7 +159,7 @@ def surrogate_extra(dev, sur, n_groups: int):
 
     res = {}
     sur_runs = {}
-    for S in (1 << 14, 1 << 16, 1 << 18):
+    for S in (1 << 10, 1 << 12, 1 << 14, 1 << 16, 1 << 18):
         r, t = timed(lambda: sur.search(tasks, offs, samples=S, topk=64, seed=31))
         sur_runs[S] = (tgo.read_search(r), t)
     plain_runs = {}

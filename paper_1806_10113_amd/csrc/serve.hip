@@ -93,7 +93,7 @@ static size_t request_bytes(const tgo_server_config &c, int n) {
     const bool small = n <= c.small_max_n;
     size_t b = sizeof(tgo_task) * TGO_MAX_N + sizeof(int32_t) + sizeof(uint32_t);
     b += small ? sizeof(tgo_summary) : sizeof(tgo_search_result);
-    if (!small) b += (size_t)((c.samples + 4095) / 4096) * 64 * 8 * 2;  // candidate keys
+    if (!small) b += (size_t)((c.samples + 1023) / 1024) * 64 * 8 * 2;  // candidate keys
     return b;
 }
 

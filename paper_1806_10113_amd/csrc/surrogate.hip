@@ -282,7 +282,9 @@ struct GemmOut {
 
 constexpr int GT = 64, GK = 32, GPAD = 8;
 
-template <int EPI>
+// With SPLITK the K range is cut into gridDim.z pieces and each block adds its
+// partial product into out.Cf (float atomics; Cf must start at zero).
+template <int EPI, bool SPLITK = false>
 __global__ __launch_bounds__(256) void gemm_nt_kernel(const uint16_t *__restrict__ A,
                                                       const uint16_t *__restrict__ B, int M, int N, int K,
                                                       GemmOut out) {
@@ -293,7 +295,13 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const uint16_t *__restrict
     f32x4 acc[4];
     for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int lr = tid >> 2, lk = (tid & 3) * 8;
-    for (int k0 = 0; k0 < K; k0 += GK) {
+    int kbeg = 0, kend = K;
+    if constexpr (SPLITK) {
+        const int per = K / gridDim.z;  // a multiple of GK (checked by the launcher)
+        kbeg = blockIdx.z * per;
+        kend = kbeg + per;
+    }
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
         const uint4 a = *reinterpret_cast<const uint4 *>(A + (int64_t)(m0 + lr) * K + k0 + lk);
         const uint4 b = *reinterpret_cast<const uint4 *>(B + (int64_t)(n0 + lr) * K + k0 + lk);
         __syncthreads();
@@ -308,6 +316,16 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const uint16_t *__restrict
         }
     }
     // lane l holds C[16w + 4(l/16) + i][16c + l%16], i = 0..3
+    if constexpr (SPLITK) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int col = n0 + c * 16 + (l & 15);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                atomicAdd(&out.Cf[(int64_t)(m0 + w * 16 + (l >> 4) * 4 + i) * N + col], acc[c][i]);
+        }
+        return;
+    }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         const int col = n0 + c * 16 + (l & 15);
@@ -412,6 +430,16 @@ __global__ __launch_bounds__(256) void gemm_nt_big_kernel(const uint16_t *__rest
         for (int b = 0; b < 4; ++b)
             epilogue_store(out, EPI, M, N, m0 + wr + a * 16 + (l >> 4) * 4, n0 + wc + b * 16 + (l & 15),
                            acc[a][b]);
+}
+
+// float C[M][N] += A B^T with the K range split over blocks (weight gradients:
+// M, N <= 256 and K = batch rows)
+static void gemm_splitk(const uint16_t *A, const uint16_t *B, int M, int N, int K, float *C, hipStream_t st) {
+    int ks = 1;
+    while (ks < 64 && (M / GT) * (N / GT) * ks < 512 && K % (2 * ks * GK) == 0) ks *= 2;
+    GemmOut o{};
+    o.Cf = C;
+    hipLaunchKernelGGL((gemm_nt_kernel<0, true>), dim3(N / GT, M / GT, ks), dim3(256), 0, st, A, B, M, N, K, o);
 }
 
 template <int EPI>
@@ -592,7 +620,7 @@ __global__ void init_params_kernel(float *p, uint64_t seed) {
 
 // ------------------------------------------------------------------ top-k
 // Keys (orderable score bits << 32 | sample index) per group; each pass keeps
-// the 64 smallest of every run of 4096 keys (bitonic sort in LDS).
+// the 64 smallest of every run of 1024 keys (bitonic sort in LDS).
 
 __device__ __forceinline__ uint32_t orderable(float f) {
     const uint32_t u = __float_as_uint(f);
@@ -609,11 +637,12 @@ __global__ void score_keys_kernel(const float *__restrict__ score, int64_t row0,
     keys[i] = isinf(f) ? ~0ull : (((unsigned long long)orderable(f) << 32) | (uint64_t)s);
 }
 
-constexpr int TK_RUN = 4096;
+constexpr int TK_RUN = 1024;
+constexpr int TK_THREADS = 256;
 constexpr int TK_KEEP = 64;
 
-// in: [G][len] keys (group stride in_stride); out: [G][ceil(len/4096)*64]
-__global__ __launch_bounds__(1024) void topk_pass_kernel(const unsigned long long *__restrict__ in,
+// in: [G][len] keys (group stride in_stride); out: [G][ceil(len/TK_RUN)*64]
+__global__ __launch_bounds__(TK_THREADS) void topk_pass_kernel(const unsigned long long *__restrict__ in,
                                                          int64_t in_stride, int64_t len, int runs,
                                                          unsigned long long *out, int64_t out_stride) {
     __shared__ unsigned long long s[TK_RUN];
@@ -919,19 +948,15 @@ static int sur_grad(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *d_
     hipLaunchKernelGGL(head_wgrad_kernel, dim3(SG_H + 1), dim3(256), 0, st, s->H3t, s->dscore, rows,
                        s->g + SG_OFF_W4, s->g + SG_OFF_B4);
     // layer 3: grad W3 = D3^T H2 ; grad b3 = colsum ; D2 = (D3 W3) * (H2 > 0)
-    GemmOut o{};
-    o.Cf = s->g + SG_OFF_W3;
-    gemm<0>(s->D3t, s->H2t, SG_H, SG_H, rows, o, st);
+    gemm_splitk(s->D3t, s->H2t, SG_H, SG_H, rows, s->g + SG_OFF_W3, st);
     hipLaunchKernelGGL(colsum_kernel, dim3(SG_H), dim3(256), 0, st, s->D3t, rows, s->g + SG_OFF_B3);
-    o = GemmOut{};
+    GemmOut o{};
     o.Y = s->D2;
     o.Yt = s->D2t;
     o.mask = s->H2;
     gemm<EPI_MASK>(s->D3, s->W3t, rows, SG_H, SG_H, o, st);
     // layer 2
-    o = GemmOut{};
-    o.Cf = s->g + SG_OFF_W2;
-    gemm<0>(s->D2t, s->H1t, SG_H, SG_H, rows, o, st);
+    gemm_splitk(s->D2t, s->H1t, SG_H, SG_H, rows, s->g + SG_OFF_W2, st);
     hipLaunchKernelGGL(colsum_kernel, dim3(SG_H), dim3(256), 0, st, s->D2t, rows, s->g + SG_OFF_B2);
     o = GemmOut{};
     o.Y = s->D1;
@@ -939,9 +964,8 @@ static int sur_grad(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *d_
     o.mask = s->H1;
     gemm<EPI_MASK>(s->D2, s->W2t, rows, SG_H, SG_H, o, st);
     // layer 1: grad W1 = D1^T X
-    o = GemmOut{};
-    o.Cf = s->gw1;
-    gemm<0>(s->D1t, s->Xt, SG_H, SG_K0, rows, o, st);
+    TGO_HIP(hipMemsetAsync(s->gw1, 0, 4 * SG_H * SG_K0, st));
+    gemm_splitk(s->D1t, s->Xt, SG_H, SG_K0, rows, s->gw1, st);
     hipLaunchKernelGGL(colsum_kernel, dim3(SG_H), dim3(256), 0, st, s->D1t, rows, s->g + SG_OFF_B1);
     hipLaunchKernelGGL(pack_w1_grad_kernel, dim3((SG_H * SG_FEAT + 255) / 256), dim3(256), 0, st, s->gw1,
                        s->g + SG_OFF_W1);
@@ -1014,7 +1038,7 @@ int tgo_surrogate_search(tgo_surrogate *s, const tgo_model *model, const tgo_tas
     if (topk < 1 || topk > TK_KEEP) return fail(TGO_EINVAL, "topk must be in 1..64");
     if (!d_out) return fail(TGO_EINVAL, "NULL buffer");
     const int64_t chunk = s->max_rows / TK_RUN * TK_RUN;
-    if (chunk < TK_RUN) return fail(TGO_EINVAL, "search needs max_rows >= 4096");
+    if (chunk < TK_RUN) return fail(TGO_EINVAL, "search needs max_rows >= 1024");
     hipStream_t st = (hipStream_t)stream;
     const int64_t spad = (samples + TK_RUN - 1) / TK_RUN * TK_RUN;
     const int64_t runs = spad / TK_RUN;
@@ -1039,14 +1063,14 @@ int tgo_surrogate_search(tgo_surrogate *s, const tgo_model *model, const tgo_tas
         hipLaunchKernelGGL(score_keys_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, s->score,
                            row0, rows, spad, s->keys);
         const int nrun = (int)(rows / TK_RUN);
-        hipLaunchKernelGGL(topk_pass_kernel, dim3(nrun, 1), dim3(1024), 0, st, s->keys, (int64_t)0, rows, nrun,
+        hipLaunchKernelGGL(topk_pass_kernel, dim3(nrun, 1), dim3(TK_THREADS), 0, st, s->keys, (int64_t)0, rows, nrun,
                            s->cand[0] + (row0 / TK_RUN) * TK_KEEP, (int64_t)0);
     }
     int64_t len = runs * TK_KEEP;
     int cur = 0;
     while (len > TK_KEEP) {
         const int nrun = (int)((len + TK_RUN - 1) / TK_RUN);
-        hipLaunchKernelGGL(topk_pass_kernel, dim3(nrun, G), dim3(1024), 0, st, s->cand[cur], len, len, nrun,
+        hipLaunchKernelGGL(topk_pass_kernel, dim3(nrun, G), dim3(TK_THREADS), 0, st, s->cand[cur], len, len, nrun,
                            s->cand[cur ^ 1], (int64_t)nrun * TK_KEEP);
         len = (int64_t)nrun * TK_KEEP;
         cur ^= 1;
