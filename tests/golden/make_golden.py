@@ -2,7 +2,7 @@
 
 Calls only the CPU oracle (oracle/) and the seeded input generators.  Run from
 the repository root:  python tests/golden/make_golden.py
-The N=12 enumeration (479,001,600 orderings) takes about a minute on 8 cores.
+Each N=12 enumeration (479,001,600 orderings) takes about a minute on 8 cores.
 """
 import json
 import os
@@ -43,6 +43,10 @@ def main():
     out["uniform_n8_seed0"] = summary(W.single_group_uniform(8, 0), M.DEFAULT)
     out["uniform_n8_seed0_paper_rates"] = summary(W.single_group_uniform(8, 0), M.PAPER_EXAMPLE)
     out["mixed_n12_seed1"] = summary(W.single_group_mixed(12, 1), M.DEFAULT)
+    # one DMA engine (Section 3.2, launch scheme for such devices)
+    one = M.Model(4, 3, 3, 1)
+    out["uniform_n8_seed0_one_dma"] = summary(W.single_group_uniform(8, 0), one)
+    out["mixed_n12_seed1_one_dma"] = summary(W.single_group_mixed(12, 1), one)
     with open(os.path.join(HERE, "single_group_summaries.json"), "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps({k: {kk: v[kk] for kk in ("min_ns", "max_ns", "mean_ns", "oracle_wall_s")}

@@ -357,3 +357,99 @@ def test_heuristic_beats_average_on_paper_benchmarks_mostly():
         T = M.simulate(bk, M.heuristic(bk, M.DEFAULT), M.DEFAULT)
         wins += T <= s["mean_ns"]
     assert wins >= 4
+
+
+# ------------------------------------------------------ one DMA engine
+# Section 3.2 (launch scheme for devices with one DMA engine): all HtDs go
+# to the one transfer queue before any DtH; kernels use the other queue.
+
+ONE_DMA = M.Model(4, 3, 3, 1)
+
+
+def one_dma_recurrence(tasks, order):
+    """Textbook recurrence for that scheme: the transfer engine is busy with
+    the HtDs back to back until their sum, then serves the DtHs in order, each
+    after its kernel; the kernel engine serves kernels in order, each after
+    its HtD."""
+    H = K = 0
+    ks = []
+    for x in order:
+        h, k, _ = tasks[x]
+        H += h
+        K = max(H, K) + k
+        ks.append(K)
+    D = H
+    for x, kend in zip(order, ks):
+        D = max(D, kend) + tasks[x][2]
+    return D
+
+
+def test_one_dma_hand_worked_timelines():
+    g = load("one_dma_hand.json")
+    for case in g["cases"]:
+        T, ev = M.simulate(case["tasks_ns"], case["order"], ONE_DMA, trace=True)
+        assert T == case["T"]
+        for name, (a, b) in case["events"].items():
+            kind, x = name.split("_")
+            assert ev[(kind, int(x))] == [a, b], name
+
+
+def test_one_dma_closed_form_recurrence():
+    rng = np.random.default_rng(31)
+    for _ in range(60):
+        n = int(rng.integers(1, 6))
+        tasks = rand_group(rng, n, 0, 40)
+        for p in itertools.permutations(range(n)):
+            assert M.simulate(tasks, p, ONE_DMA) == one_dma_recurrence(tasks, p)
+
+
+def test_one_dma_rates_do_not_matter():
+    # one engine never moves data both ways at once, so no slowdown applies
+    rng = np.random.default_rng(32)
+    for _ in range(40):
+        n = int(rng.integers(1, 6))
+        tasks = rand_group(rng, n)
+        p = list(rng.permutation(n))
+        ts = {M.simulate(tasks, p, M.Model(q, ph, pd, 1), exact=ex)
+              for q, ph, pd in ((4, 3, 3), (8, 3, 3), (1, 1, 1), (16, 9, 13)) for ex in (False, True)}
+        assert len(ts) == 1
+
+
+def test_one_dma_special_cases():
+    rng = np.random.default_rng(33)
+    for _ in range(25):
+        n = int(rng.integers(2, 7))
+        h = [int(v) for v in rng.integers(0, 40, n)]
+        k = [int(v) for v in rng.integers(0, 40, n)]
+        d = [int(v) for v in rng.integers(0, 40, n)]
+        # no HtD work: two-machine flow shop (K, DtH), optimum by Johnson's rule
+        no_h = [(0, k[i], d[i]) for i in range(n)]
+        assert M.exhaustive(no_h, ONE_DMA)["min_ns"] == johnson_makespan(k, d)
+        # no DtH work: two-machine flow shop (HtD, K)
+        no_d = [(h[i], k[i], 0) for i in range(n)]
+        assert M.exhaustive(no_d, ONE_DMA)["min_ns"] == johnson_makespan(h, k)
+        # no kernel work: the transfer engine alone decides, for every ordering
+        no_k = [(h[i], 0, d[i]) for i in range(n)]
+        assert set(M.all_times(no_k, ONE_DMA)) == {sum(h) + sum(d)}
+
+
+def test_one_dma_lower_bounds_and_serial_upper_bound():
+    rng = np.random.default_rng(34)
+    for _ in range(150):
+        n = int(rng.integers(1, 7))
+        tasks = rand_group(rng, n)
+        h = [t[0] for t in tasks]; k = [t[1] for t in tasks]; d = [t[2] for t in tasks]
+        p = list(rng.permutation(n))
+        T = M.simulate(tasks, p, ONE_DMA)
+        assert sum(h) + sum(d) <= T <= sum(h) + sum(k) + sum(d)
+        assert T >= min(h) + sum(k) + min(d)
+        # one engine is never faster than two at full speed
+        assert T >= M.simulate(tasks, p, M.NO_SLOWDOWN)
+
+
+def test_one_dma_heuristic_is_a_valid_ordering():
+    for seed in range(6):
+        tasks = W.single_group_uniform(7, seed)
+        h = M.heuristic(tasks, ONE_DMA)
+        assert sorted(h) == list(range(7))
+        assert M.exhaustive(tasks, ONE_DMA)["min_ns"] <= M.simulate(tasks, h, ONE_DMA)
