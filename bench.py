@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 VALU_LANE_OPS_PER_ORDERING = 220.54
 # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, each scaled by
 # what the counter reads for a 256 MiB device copy (same profile file).
-TRAFFIC_BYTES_PER_LAUNCH = 436_899
+TRAFFIC_BYTES_PER_LAUNCH = 420_518
 
 
 def parse():
@@ -105,6 +105,59 @@ def batch_extra(dev, reps: int = 5):
             "ms_per_batch": ms, "groups_per_s": b.n_groups / (ms / 1e3),
             "orderings_per_s": orderings / (ms / 1e3), "orderings": orderings,
             "bad_status": bad, "plan": desc}
+
+
+def one_dma_extra(dev, reps: int = 10):
+    """The one-DMA launch scheme (HtDs before DtHs on one transfer engine):
+    N=12 mixed group (checked against the oracle's stored enumeration), an
+    N=13 group, and the 4,096-group batch."""
+    import torch
+    from paper_1806_10113_amd import tgo, workloads as W
+    model = tgo.Model(2, 3, 3, dma_engines=1)
+    stream = torch.cuda.current_stream()
+    out = {}
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "single_group_summaries.json")))
+    for n in (12, 13):
+        t = torch.as_tensor(W.single_group_mixed(n, SEED)).to(dev)
+        summ, _ = tgo.exhaustive(t, model, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            tgo.exhaustive(t, model, summary=summ, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        s = tgo.read_summary(summ)
+        rec = {"ms": ms, "orderings_per_s": math.factorial(n) / (ms / 1e3), "min_ns": s["min_ns"],
+               "max_ns": s["max_ns"], "mean_ns": s["mean_ns"], "status": s["status"]}
+        if n == 12:
+            g = gold["mixed_n12_seed1_one_dma"]
+            rec["matches_oracle"] = bool(s["min_ns"] == g["min_ns"] and s["argmin_rank"] == g["argmin_rank"]
+                                         and s["sum"] == int(g["sum"])
+                                         and s["fingerprint"] == int(g["fingerprint"]))
+        out[f"exhaustive_n{n}"] = rec
+    b = W.batch_groups(4096, 4, 10, seed=2)
+    tasks, offs = torch.as_tensor(b.tasks).to(dev), torch.as_tensor(b.offs).to(dev)
+    plan = tgo.Plan(model, max_groups=b.n_groups)
+    desc = plan.autotune(tasks, offs)
+    res = plan.run(tasks, offs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        plan.run(tasks, offs, res)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    orderings = int(sum(math.factorial(int(n)) for n in b.sizes()))
+    bad = sum(1 for x in tgo.read_summaries(res) if x["status"] != 0)
+    plan.close()
+    out["batch"] = {"ms_per_batch": ms, "groups_per_s": b.n_groups / (ms / 1e3),
+                    "orderings_per_s": orderings / (ms / 1e3), "bad_status": bad,
+                    "plan": {"m_by_n": desc.get("m_by_n"), "lane_mult": desc.get("lane_mult"),
+                             "blocks": desc.get("blocks")}}
+    return out
 
 
 def train_surrogate(dev, pairs_total: float, seed: int = 1003, batch: int = 8192, lr: float = 1e-3):
@@ -322,10 +375,12 @@ def main():
                    "group_size": N, "orderings_per_step": orderings, "overlap_rates": "3/4, 3/4",
                    "time_path": "32-bit (bound checked on device; identical to int64)"},
         "roofline": roof,
+        # the model's own work unit: 3N command completions per ordering
+        "event_steps_per_s": value * 3 * N,
         "min_ns": s["min_ns"], "mean_ns": s["mean_ns"],
     }
     if not args.no_extras:
-        extras = {"batch": batch_extra(dev)}
+        extras = {"batch": batch_extra(dev), "one_dma": one_dma_extra(dev)}
         sur, tr = train_surrogate(dev, args.train_pairs)
         extras["proposal_training"] = tr
         extras["proposal_n16"] = surrogate_extra(dev, sur, args.eval_groups)

@@ -65,10 +65,14 @@ typedef struct {
 } tgo_task;
 
 /* Device model.  dma_engines: 2 = separate HtD and DtH engines (the launch
- * scheme of Section 3.2 with three command queues).  q = 1 << q_log2
- * (q_log2 in 0..10); overlapped transfers advance at p_htd/q and p_dth/q of
- * solo speed, 1 <= p <= q.  (q_log2 = 2, p = 3, 3) is the benchmark default;
- * (3, 3, 3) reproduces the worked timeline of Section 4.1. */
+ * scheme of Section 3.2 with three command queues); 1 = one engine for both
+ * directions (the Section 3.2 scheme with two command queues: every HtD is
+ * queued before every DtH, so transfers never overlap and run at solo speed;
+ * the rates below are validated but have no effect).  Any other value is
+ * TGO_EINVAL.  q = 1 << q_log2 (q_log2 in 0..10); overlapped transfers advance
+ * at p_htd/q and p_dth/q of solo speed, 1 <= p <= q.  (q_log2 = 2, p = 3, 3)
+ * is the benchmark default; (3, 3, 3) reproduces the worked timeline of
+ * Section 4.1.  Every entry point below takes either scheme. */
 typedef struct {
     int32_t dma_engines;
     int32_t q_log2;

@@ -25,12 +25,13 @@ int hip_fail(hipError_t e, const char *what) {
 
 int make_rates(const tgo_model *m, Rates *r) {
     if (!m) return fail(TGO_EINVAL, "model is NULL");
-    if (m->dma_engines != 2) return fail(TGO_EINVAL, "dma_engines must be 2");
+    if (m->dma_engines != 1 && m->dma_engines != 2) return fail(TGO_EINVAL, "dma_engines must be 1 or 2");
     if (m->q_log2 < 0 || m->q_log2 > 10) return fail(TGO_EINVAL, "q_log2 must be in 0..10");
     const int q = 1 << m->q_log2;
     if (m->p_htd < 1 || m->p_htd > q || m->p_dth < 1 || m->p_dth > q)
         return fail(TGO_EINVAL, "overlap rates must satisfy 1 <= p <= q");
     r->q_log2 = m->q_log2;
+    r->one_dma = m->dma_engines == 1 ? 1 : 0;
     r->p_h = (uint32_t)m->p_htd;
     r->p_d = (uint32_t)m->p_dth;
     r->inv_ph = 1.0 / (double)m->p_htd;

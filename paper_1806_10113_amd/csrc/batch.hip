@@ -108,11 +108,11 @@ __global__ __launch_bounds__(1024) void batch_prepare(const tgo_task *__restrict
     }
 }
 
-template <int M>
+template <int M, int DMA>
 __device__ __forceinline__ void run_subtree(const Ctx &c, const View<uint32_t, 1, BT_THREADS> &v,
                                             const Lane<uint32_t> &st, uint32_t list,
                                             Sub<uint32_t> &u) {
-    level<uint32_t, M, false, 1, BT_THREADS>(c, v, st, list, 0u, u);
+    level<uint32_t, M, false, 1, BT_THREADS, false, DMA>(c, v, st, list, 0u, u);
 }
 
 __device__ __forceinline__ unsigned long long wave_min(unsigned long long x) {
@@ -134,6 +134,7 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
     return x;
 }
 
+template <int DMA>
 __global__ __launch_bounds__(BT_THREADS) void batch_kernel(const tgo_task *__restrict__ tasks,
                                                            const int32_t *__restrict__ offs, int G,
                                                            Rates r, BatchCfg cfg, GroupAcc *acc,
@@ -180,15 +181,15 @@ __global__ __launch_bounds__(BT_THREADS) void batch_kernel(const tgo_task *__res
             const uint32_t s = s0 + (uint32_t)k * 64u + (uint32_t)lane;
             if (s < S) {
                 Lane<uint32_t> st;
-                const uint32_t list = (uint32_t)prefix(st, s, n, m, v, r);
+                const uint32_t list = (uint32_t)prefix<DMA>(st, s, n, m, v, r);
                 Sub<uint32_t> u;
                 sub_init(u);
                 switch (m) {
-                    case 1: run_subtree<1>(c, v, st, list, u); break;
-                    case 2: run_subtree<2>(c, v, st, list, u); break;
-                    case 3: run_subtree<3>(c, v, st, list, u); break;
-                    case 4: run_subtree<4>(c, v, st, list, u); break;
-                    default: run_subtree<5>(c, v, st, list, u); break;
+                    case 1: run_subtree<1, DMA>(c, v, st, list, u); break;
+                    case 2: run_subtree<2, DMA>(c, v, st, list, u); break;
+                    case 3: run_subtree<3, DMA>(c, v, st, list, u); break;
+                    case 4: run_subtree<4, DMA>(c, v, st, list, u); break;
+                    default: run_subtree<5, DMA>(c, v, st, list, u); break;
                 }
                 const uint64_t r0 = (uint64_t)s * fact_c(m);
                 const unsigned long long a = ((unsigned long long)u.min_t << 32) | (r0 + u.min_l);
@@ -312,9 +313,15 @@ static int enqueue_batch(tgo_plan *p, const BatchCfg &cfg, const tgo_task *d_tas
                          const int32_t *d_offs, int G, tgo_summary *d_out, hipStream_t st) {
     hipLaunchKernelGGL(batch_prepare, dim3(1), dim3(1024), 0, st, d_tasks, d_offs, G, p->r, cfg,
                        p->acc, p->tile_off, p->hdr);
-    const size_t shm = sizeof(Slot<uint32_t>) * BT_THREADS * BT_MAX_N;
-    hipLaunchKernelGGL(batch_kernel, dim3(cfg.blocks), dim3(BT_THREADS), shm, st, d_tasks, d_offs, G,
-                       p->r, cfg, p->acc, p->tile_off, p->hdr);
+    if (p->r.one_dma) {
+        // no kernel-completion queue with one DMA engine
+        hipLaunchKernelGGL(batch_kernel<DMA_ONE>, dim3(cfg.blocks), dim3(BT_THREADS), 0, st, d_tasks,
+                           d_offs, G, p->r, cfg, p->acc, p->tile_off, p->hdr);
+    } else {
+        const size_t shm = sizeof(Slot<uint32_t>) * BT_THREADS * BT_MAX_N;
+        hipLaunchKernelGGL(batch_kernel<DMA_TWO>, dim3(cfg.blocks), dim3(BT_THREADS), shm, st, d_tasks,
+                           d_offs, G, p->r, cfg, p->acc, p->tile_off, p->hdr);
+    }
     hipLaunchKernelGGL(batch_finalize, dim3((G + 255) / 256), dim3(256), 0, st, p->acc, G, d_out);
     int rc = launch_heuristic(p->r, d_tasks, d_offs, G, &d_out[0].heur[0], (int)sizeof(tgo_summary),
                               &d_out[0].heur_ns, (int)(sizeof(tgo_summary) / sizeof(int64_t)), st);

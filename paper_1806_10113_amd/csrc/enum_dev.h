@@ -53,7 +53,7 @@ struct Ctx {
 
 // Level with L positions left (position n - L is being chosen).  list holds
 // the remaining tasks in increasing order, one per nibble.
-template <typename TT, int L, bool STORE, int TS, int QS, bool SELECT = false>
+template <typename TT, int L, bool STORE, int TS, int QS, bool SELECT, int DMA>
 __device__ __forceinline__ void level(const Ctx &c, const View<TT, TS, QS> &v, const Lane<TT> &s,
                                       uint32_t list, uint32_t l, Sub<TT> &u) {
     const int j = c.n - L;
@@ -61,21 +61,21 @@ __device__ __forceinline__ void level(const Ctx &c, const View<TT, TS, QS> &v, c
     for (int ci = 0; ci < L; ++ci) {
         const uint32_t x = (list >> (4 * ci)) & 15u;
         Lane<TT> s2 = s;
-        window<TT, TS, QS, SELECT>(s2, j, x, v, c.r);
+        window<DMA, SELECT>(s2, j, x, v, c.r);
         const uint32_t l2 = l + (uint32_t)ci * (uint32_t)fact_c(L - 1);
         if constexpr (L == 1) {
-            leaf<TT, STORE>(tail(s2, c.r), l2, u, c.out_sub);
+            leaf<TT, STORE>(tail<DMA>(s2, c.r), l2, u, c.out_sub);
         } else {
             const uint32_t lo = list & ((1u << (4 * ci)) - 1u);
             const uint32_t hi = (list >> (4 * ci + 4)) << (4 * ci);
-            level<TT, L - 1, STORE, TS, QS, SELECT>(c, v, s2, lo | hi, l2, u);
+            level<TT, L - 1, STORE, TS, QS, SELECT, DMA>(c, v, s2, lo | hi, l2, u);
         }
     }
 }
 
 // Decode the prefix of subtree s (positions 0 .. n-M-1 of rank s*M!) and
 // simulate its windows.  Returns the remaining tasks, ascending, one per nibble.
-template <typename TT, int TS, int QS>
+template <int DMA, typename TT, int TS, int QS>
 __device__ __forceinline__ uint64_t prefix(Lane<TT> &st, uint32_t s, int n, int m,
                                            const View<TT, TS, QS> &v, const Rates &r) {
     uint64_t list = 0;
@@ -94,7 +94,7 @@ __device__ __forceinline__ uint64_t prefix(Lane<TT> &st, uint32_t s, int n, int 
         const uint64_t lo = list & ((1ull << (4 * cdig)) - 1ull);
         const uint64_t hi = (list >> (4 * cdig + 4)) << (4 * cdig);
         list = lo | hi;
-        window(st, i, x, v, r);
+        window<DMA>(st, i, x, v, r);
     }
     return list;
 }

@@ -88,8 +88,9 @@ __device__ void block_reduce_write(Partial p, Partial *dst) {
 }
 
 // MODE: 0 = 32-bit time path, 1 = 64-bit.  Both instantiations are launched;
-// a block whose group does not belong to its mode returns at once.
-template <typename TT, int M, bool STORE, bool SELECT = false>
+// a block whose group does not belong to its mode returns at once.  DMA is
+// the launch scheme (DMA_TWO or DMA_ONE, fixed per instantiation).
+template <typename TT, int M, bool STORE, bool SELECT, int DMA>
 __global__ __launch_bounds__(EX_THREADS) void exhaustive_kernel(const tgo_task *__restrict__ tasks,
                                                                 int n, Rates r, uint32_t n_sub,
                                                                 int64_t *out, Partial *partials) {
@@ -125,12 +126,12 @@ __global__ __launch_bounds__(EX_THREADS) void exhaustive_kernel(const tgo_task *
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_sub; s += stride) {
         Lane<TT> st;
-        const uint64_t list = prefix(st, s, n, M, v, r);
+        const uint64_t list = prefix<DMA>(st, s, n, M, v, r);
         const uint64_t r0 = (uint64_t)s * factorial(M);
         if constexpr (STORE) c.out_sub = out + r0;
         Sub<TT> u;
         sub_init(u);
-        level<TT, M, STORE, 1, EX_THREADS, SELECT>(c, v, st, (uint32_t)list, 0u, u);
+        level<TT, M, STORE, 1, EX_THREADS, SELECT, DMA>(c, v, st, (uint32_t)list, 0u, u);
         fold(a, u, r0);
     }
     Partial p;
@@ -236,16 +237,21 @@ __global__ __launch_bounds__(256) void exhaustive_finalize(const Partial *__rest
 }
 
 // Positions enumerated depth-first per lane: enough subtrees to fill the GPU.
-// TGO_EXHAUSTIVE_M (1..5) overrides the choice for tuning experiments.
-static int choose_m(int n) {
+// TGO_EXHAUSTIVE_M overrides the choice for tuning experiments (1..5, or
+// 1..6 with one DMA engine).
+static int choose_m(int n, bool one_dma) {
+    const int cap = one_dma ? 6 : 5;
     if (const char *e = std::getenv("TGO_EXHAUSTIVE_M")) {
         const int m = std::atoi(e);
-        if (m >= 1 && m <= 5 && m <= n) return m;
+        if (m >= 1 && m <= cap && m <= n) return m;
     }
-    // 4 levels beat 5 at n = 12 on MI355X (fewer live snapshots, one more
-    // wave per SIMD); deeper walks only pay when subtrees are scarce
+    // two engines: 4 levels beat 5 at n = 12 on MI355X (fewer live
+    // snapshots, one more wave per SIMD); deeper walks only pay when
+    // subtrees are scarce.  One engine: a window is a handful of operations,
+    // so the per-subtree prefix decode is worth amortising over 6 levels.
+    const int top = one_dma ? 6 : 4;
     int m = 1;
-    for (int c = 4; c >= 1; --c) {
+    for (int c = top; c >= 1; --c) {
         if (c > n) continue;
         const uint64_t sub = factorial(n) / factorial(c);
         if (sub >= 32768 || c == 1) { m = c; break; }
@@ -264,35 +270,42 @@ static bool use_select() {
     return v;
 }
 
-template <int M, bool STORE>
+template <int M, bool STORE, int DMA>
 static void launch_pair(dim3 grid, size_t shm32, size_t shm64, hipStream_t st, const tgo_task *t,
                         int n, const Rates &r, uint32_t n_sub, int64_t *out, Partial *parts) {
-    if (!STORE && use_select())
-        hipLaunchKernelGGL((exhaustive_kernel<uint32_t, M, STORE, true>), grid, dim3(EX_THREADS), shm32, st,
-                           t, n, r, n_sub, out, parts);
+    if (DMA == DMA_TWO && !STORE && use_select())
+        hipLaunchKernelGGL((exhaustive_kernel<uint32_t, M, STORE, true, DMA>), grid, dim3(EX_THREADS),
+                           shm32, st, t, n, r, n_sub, out, parts);
     else
-        hipLaunchKernelGGL((exhaustive_kernel<uint32_t, M, STORE>), grid, dim3(EX_THREADS), shm32, st,
-                           t, n, r, n_sub, out, parts);
-    hipLaunchKernelGGL((exhaustive_kernel<uint64_t, M, STORE>), grid, dim3(EX_THREADS), shm64, st,
-                       t, n, r, n_sub, out, parts);
+        hipLaunchKernelGGL((exhaustive_kernel<uint32_t, M, STORE, false, DMA>), grid, dim3(EX_THREADS),
+                           shm32, st, t, n, r, n_sub, out, parts);
+    hipLaunchKernelGGL((exhaustive_kernel<uint64_t, M, STORE, false, DMA>), grid, dim3(EX_THREADS), shm64,
+                       st, t, n, r, n_sub, out, parts);
 }
 
-template <bool STORE>
+template <bool STORE, int DMA>
 static void launch_m(int m, dim3 grid, size_t shm32, size_t shm64, hipStream_t st,
                      const tgo_task *t, int n, const Rates &r, uint32_t n_sub, int64_t *out,
                      Partial *parts) {
     switch (m) {
-        case 1: launch_pair<1, STORE>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
-        case 2: launch_pair<2, STORE>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
-        case 3: launch_pair<3, STORE>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
-        case 4: launch_pair<4, STORE>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
-        default: launch_pair<5, STORE>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
+        case 1: launch_pair<1, STORE, DMA>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
+        case 2: launch_pair<2, STORE, DMA>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
+        case 3: launch_pair<3, STORE, DMA>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
+        case 4: launch_pair<4, STORE, DMA>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
+        case 5: launch_pair<5, STORE, DMA>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
+        default:
+            if constexpr (DMA == DMA_ONE)
+                launch_pair<6, STORE, DMA>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts);
+            else
+                launch_pair<5, STORE, DMA>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts);
+            break;
     }
 }
 
 int launch_exhaustive(const Rates &r, const tgo_task *d_tasks, int n, int64_t *d_per_order,
                       tgo_summary *d_out, hipStream_t st) {
-    const int m = choose_m(n);
+    const bool one = r.one_dma != 0;
+    const int m = choose_m(n, one);
     const uint64_t n_sub64 = factorial(n) / factorial(m);
     if (n_sub64 >= (1ull << 32)) return fail(TGO_EINVAL, "group too large to enumerate");
     const uint32_t n_sub = (uint32_t)n_sub64;
@@ -303,12 +316,21 @@ int launch_exhaustive(const Rates &r, const tgo_task *d_tasks, int n, int64_t *d
     Partial *parts = nullptr;
     int rc = workspace(sizeof(Partial) * blocks, (void **)&parts);
     if (rc) return rc;
-    const size_t shm32 = sizeof(Slot<uint32_t>) * EX_THREADS * n;
-    const size_t shm64 = sizeof(Slot<uint64_t>) * EX_THREADS * n;
-    if (d_per_order)
-        launch_m<true>(m, dim3(blocks), shm32, shm64, st, d_tasks, n, r, n_sub, d_per_order, parts);
-    else
-        launch_m<false>(m, dim3(blocks), shm32, shm64, st, d_tasks, n, r, n_sub, nullptr, parts);
+    // the kernel-completion queue is read only by the two-engine DtH events
+    const size_t shm32 = one ? 0 : sizeof(Slot<uint32_t>) * EX_THREADS * n;
+    const size_t shm64 = one ? 0 : sizeof(Slot<uint64_t>) * EX_THREADS * n;
+    const dim3 g(blocks);
+    if (one) {
+        if (d_per_order)
+            launch_m<true, DMA_ONE>(m, g, shm32, shm64, st, d_tasks, n, r, n_sub, d_per_order, parts);
+        else
+            launch_m<false, DMA_ONE>(m, g, shm32, shm64, st, d_tasks, n, r, n_sub, nullptr, parts);
+    } else {
+        if (d_per_order)
+            launch_m<true, DMA_TWO>(m, g, shm32, shm64, st, d_tasks, n, r, n_sub, d_per_order, parts);
+        else
+            launch_m<false, DMA_TWO>(m, g, shm32, shm64, st, d_tasks, n, r, n_sub, nullptr, parts);
+    }
     TGO_HIP(hipGetLastError());
     hipLaunchKernelGGL(exhaustive_finalize, dim3(1), dim3(256), 0, st, parts, (int)blocks, n,
                        factorial(n), d_out);

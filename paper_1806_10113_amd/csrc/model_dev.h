@@ -35,6 +35,7 @@ constexpr int MAXN = 16;
 struct Rates {
     int32_t q_log2;
     uint32_t p_h, p_d;
+    int32_t one_dma;  // 1: device with one DMA engine (launch scheme of Section 3.2)
     // ceil(u / p) for u < 2^32 as trunc(fma(u, 1/p, (p - 1/2)/p)).  The exact
     // value (u + p - 1/2)/p lies at least 1/(2p) away from the integers that
     // bound ceil(u/p); the double rounding error is below 2^-19 for u < 2^32,
@@ -84,6 +85,17 @@ __device__ __forceinline__ TT tmax(TT a, TT b) { return a > b ? a : b; }
 template <typename TT>
 __device__ __forceinline__ TT inf_time() { return ~TT(0); }
 
+// Launch scheme a function is compiled for: read from Rates at run time, or
+// fixed at compile time (kernels specialised for one scheme).
+enum DmaMode : int { DMA_RUNTIME = 0, DMA_ONE = 1, DMA_TWO = 2 };
+
+template <int DMA>
+__device__ __forceinline__ bool is_one_dma(const Rates &r) {
+    if constexpr (DMA == DMA_ONE) return true;
+    else if constexpr (DMA == DMA_TWO) return false;
+    else return r.one_dma != 0;
+}
+
 // Task tables and the per-lane kernel-completion queue.  Entry x of a table
 // is at [x * TS], slot j of the queue at [j * QS] (compile-time strides);
 // shared tables use TS = 1, per-lane tables interleave lanes so that a
@@ -127,6 +139,22 @@ __device__ __forceinline__ Lane<TT> lane_init() {
     return s;
 }
 
+// One DMA engine (Section 3.2, scheme for such devices): every HtD is queued
+// on the one transfer engine before every DtH, so the HtDs run back to back
+// at solo speed (two transfers never move data at the same time), kernels
+// follow K_j = max(HtD_j end, K_{j-1} end) + k, and every DtH waits for the
+// last HtD.  A window is the HtD alone; the DtHs are left to the tail.
+template <typename TT, int TS, int QS>
+__device__ __forceinline__ void window_one(Lane<TT> &s, uint32_t x, const View<TT, TS, QS> &v) {
+    using ST = typename Signed<TT>::type;
+    const Quad<TT> tx = v.task(x);
+    s.t += tx.h;
+    s.ck = tmax(s.t, s.ck) + tx.k;
+    const ST e = (ST)s.ck - (ST)s.dpre;
+    s.emax = e > s.emax ? e : s.emax;
+    s.dpre += tx.d;
+}
+
 // Window j: HtD of task x starts at s.t; process DtH events until it ends,
 // then derive the kernel of position j and record it in the queue.
 //
@@ -135,10 +163,14 @@ __device__ __forceinline__ Lane<TT> lane_init() {
 // the HtD end estimate stays valid; only a change of the DtH engine between
 // busy and idle changes the HtD rate and forces a new estimate from the exact
 // remaining work.
-template <typename TT, int TS, int QS, bool SELECT = false>
+template <int DMA = DMA_RUNTIME, bool SELECT = false, typename TT, int TS, int QS>
 __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const View<TT, TS, QS> &v,
                                        const Rates &r) {
     using ST = typename Signed<TT>::type;
+    if (is_one_dma<DMA>(r)) {
+        window_one(s, x, v);
+        return;
+    }
     const TT q = TT(1) << r.q_log2;
     const Quad<TT> tx = v.task(x);
     // an idle DtH waiting for the previous position's kernel now knows its time
@@ -204,9 +236,17 @@ __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const Vie
 // Terms of positions whose DtH already started are lower bounds of the total
 // (every DtH takes at least its solo time after its kernel), so the second max
 // may run over every placed position: it is emax + dpre, kept per window.
-template <typename TT>
+//
+// With one DMA engine the DtH recurrence starts when the last HtD ends (the
+// engine is busy with HtDs until s.t), so the total is
+// max(s.t + sum d, max_p (K_p end + sum_{s >= p} d_s)) = max(s.t, emax) + dpre.
+template <int DMA = DMA_RUNTIME, typename TT>
 __device__ __forceinline__ TT tail(const Lane<TT> &s, const Rates &r) {
     using ST = typename Signed<TT>::type;
+    if (is_one_dma<DMA>(r)) {
+        const ST e = (ST)s.t > s.emax ? (ST)s.t : s.emax;
+        return (TT)(e + (ST)s.dpre);
+    }
     TT T = (TT)(s.emax + (ST)s.dpre);
     if (s.drun) {
         // work left on the running DtH (it ran at p_dth since its start;

@@ -45,8 +45,9 @@ def test_strerror_and_version(L):
 
 def test_host_argument_errors(L):
     from paper_1806_10113_amd import tgo
-    bad_models = [tgo._Model(1, 2, 3, 3), tgo._Model(2, 11, 3, 3), tgo._Model(2, 2, 0, 3),
-                  tgo._Model(2, 2, 3, 5)]
+    bad_models = [tgo._Model(0, 2, 3, 3), tgo._Model(3, 2, 3, 3), tgo._Model(2, 11, 3, 3),
+                  tgo._Model(2, 2, 0, 3), tgo._Model(2, 2, 3, 5), tgo._Model(1, 2, 0, 3),
+                  tgo._Model(1, -1, 1, 1)]
     fake = ctypes.c_void_p(16)  # never dereferenced: validation fails first
     for m in bad_models:
         assert L.tgo_exhaustive(ctypes.byref(m), fake, 4, None, fake, None) == tgo.TGO_EINVAL
