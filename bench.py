@@ -160,6 +160,45 @@ def one_dma_extra(dev, reps: int = 10):
     return out
 
 
+def rounds_extra(dev, seed: int = 11):
+    """Section 6.2 in the model: T workers x R dependent tasks drawn from each
+    BK benchmark; NoReorder over every ordering vs the Heuristic setup.
+    Speedups are against the worst NoReorder ordering, as in the paper's
+    figures (best, median, geometric mean, heuristic)."""
+    import numpy as np
+    import torch
+    from paper_1806_10113_amd import tgo, workloads as W
+    stream = torch.cuda.current_stream()
+    out = {}
+    total_orderings, total_ms = 0, 0.0
+    for T, R in ((4, 1), (4, 2), (4, 4), (6, 1), (6, 2), (8, 1)):
+        for bi, bk in enumerate(W.PAPER_BENCHMARKS):
+            tasks = torch.as_tensor(W.rounds_experiment(bk, T, R, seed + 100 * bi + 10 * T + R)).to(dev)
+            summ, po, groups = tgo.rounds(tasks, T, R, tgo.DEFAULT, per_order=True, stream=stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            tgo.rounds(tasks, T, R, tgo.DEFAULT, summary=summ, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            s = tgo.read_summary(summ)
+            times = po.cpu().numpy().astype(np.float64)
+            worst = float(s["max_ns"])
+            count = math.factorial(T) ** R
+            total_orderings += count
+            total_ms += ms
+            out[f"T{T}_R{R}_{bk}"] = {
+                "orderings": count, "ms": ms, "status": s["status"],
+                "speedup_best": worst / s["min_ns"], "speedup_median": worst / float(np.median(times)),
+                "speedup_geomean": worst / float(np.exp(np.log(times).mean())),
+                "speedup_heuristic": worst / s["heur_ns"],
+                "heuristic_groups": len(tgo.read_groups(groups)),
+            }
+    return {"cases": out, "orderings": total_orderings, "ms": total_ms,
+            "orderings_per_s": total_orderings / (total_ms / 1e3)}
+
+
 def train_surrogate(dev, pairs_total: float, seed: int = 1003, batch: int = 8192, lr: float = 1e-3):
     """Train the proposal network on exact pairs from groups of N in [8, 16]."""
     import torch
@@ -380,7 +419,7 @@ def main():
         "min_ns": s["min_ns"], "mean_ns": s["mean_ns"],
     }
     if not args.no_extras:
-        extras = {"batch": batch_extra(dev), "one_dma": one_dma_extra(dev)}
+        extras = {"batch": batch_extra(dev), "one_dma": one_dma_extra(dev), "rounds": rounds_extra(dev)}
         sur, tr = train_surrogate(dev, args.train_pairs)
         extras["proposal_training"] = tr
         extras["proposal_n16"] = surrogate_extra(dev, sur, args.eval_groups)

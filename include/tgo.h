@@ -48,6 +48,7 @@ extern "C" {
 
 #define TGO_MAX_N 16            /* largest group for evaluate / heuristic      */
 #define TGO_MAX_EXHAUSTIVE_N 13 /* largest group enumerated in full (13! ranks) */
+#define TGO_ROUNDS_MAX_PER_ORDER 479001600ull /* per-ordering output limit of tgo_rounds */
 
 enum {
     TGO_OK = 0,
@@ -310,6 +311,39 @@ int tgo_server_replay(tgo_server *srv, const tgo_task *h_tasks, const int32_t *h
                       const int64_t *h_arrival_ns, int n_requests, tgo_server_result *h_out,
                       int64_t timeout_ms);
 void tgo_server_destroy(tgo_server *srv);
+
+/* ---------------------------------------------------------------------------
+ * tgo_rounds -- several workers offloading dependent tasks (Section 6.2: T
+ * workers, each with a batch of dependent tasks; a worker hands over its next
+ * task only when the previous one has completely finished).
+ *   d_tasks : workers * rounds tasks; task (w, r) -- worker w's r-th task -- at
+ *             index w * rounds + r.  1 <= workers, 1 <= rounds,
+ *             workers * rounds <= 16, (workers!)^rounds < 2^32.
+ *   NoReorder setup (Section 6.2): every task queued at t = 0, round by round,
+ *     round r in a worker order pi_r; the HtD of (w, r) waits for the DtH of
+ *     (w, r - 1) and the in-order queue waits behind it.  All
+ *     (workers!)^rounds orderings are evaluated; rank = mixed radix workers!
+ *     with pi_0 most significant, each pi_r ranked lexicographically.
+ *     d_summary receives min / argmin / max / argmax / sum / mean /
+ *     fingerprint over them (fingerprint = sum of (2 rank + 1) T mod 2^64);
+ *     best[] and worst[] are launch sequences (task index per position,
+ *     0xff-padded); n = workers * rounds; count = (workers!)^rounds.
+ *   Heuristic setup (Section 6.2): a proxy takes every waiting task as a task
+ *     group, orders it with Algorithm 1 and queues it, and looks for the next
+ *     group when the HtD of the group's last task starts (or at the next
+ *     arrival if none is waiting then).  d_summary->heur[] receives its launch
+ *     sequence and heur_ns its total time (or a negative TGO_E*).
+ *   d_per_order : NULL, or (workers!)^rounds int64 (at most
+ *                 TGO_ROUNDS_MAX_PER_ORDER) receiving T at index = rank.
+ *   d_groups    : NULL, or one uint16: bit j set if launch position j ends a
+ *                 task group formed by the proxy.
+ * Both launch schemes (model->dma_engines 1 or 2); the model has one kernel
+ * queue (no concurrent kernels).  Durations must lie in [0, 2^40) ns, else
+ * status = TGO_ERANGE.  Device buffers belong to the caller; the call
+ * enqueues on `stream` and returns at once.
+ */
+int tgo_rounds(const tgo_model *model, const tgo_task *d_tasks, int workers, int rounds,
+               int64_t *d_per_order, tgo_summary *d_summary, uint16_t *d_groups, tgo_stream stream);
 
 /* Host helpers: lexicographic rank <-> ordering (index arithmetic only). */
 int tgo_rank(int n, const uint8_t *h_order, uint64_t *rank);

@@ -126,6 +126,25 @@ int tgo_heuristic(const tgo_model *model, const tgo_task *d_tasks, const int32_t
     return launch_heuristic(r, d_tasks, d_offs, n_groups, d_orders, 16, d_ns, 1, (hipStream_t)stream);
 }
 
+int tgo_rounds(const tgo_model *model, const tgo_task *d_tasks, int workers, int rounds,
+               int64_t *d_per_order, tgo_summary *d_summary, uint16_t *d_groups, tgo_stream stream) {
+    Rates r;
+    int rc = make_rates(model, &r);
+    if (rc) return rc;
+    if (workers < 1 || rounds < 1 || workers * rounds > TGO_MAX_N)
+        return fail(TGO_EINVAL, "need workers >= 1, rounds >= 1, workers * rounds <= 16");
+    uint64_t count = 1;
+    for (int i = 0; i < rounds; ++i) {
+        count *= factorial(workers);
+        if (count > 0xffffffffull) return fail(TGO_EINVAL, "(workers!)^rounds must be below 2^32");
+    }
+    if (d_per_order && count > TGO_ROUNDS_MAX_PER_ORDER)
+        return fail(TGO_EINVAL, "per-ordering output needs (workers!)^rounds <= 479001600");
+    if (!d_tasks || !d_summary) return fail(TGO_EINVAL, "NULL buffer");
+    return launch_rounds(r, d_tasks, workers, rounds, d_per_order, d_summary, d_groups,
+                         (hipStream_t)stream);
+}
+
 int tgo_rank(int n, const uint8_t *h_order, uint64_t *rank) {
     if (n < 1 || n > TGO_MAX_N || !h_order || !rank) return fail(TGO_EINVAL, "bad argument");
     uint32_t seen = 0;

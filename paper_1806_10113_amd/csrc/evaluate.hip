@@ -2,6 +2,7 @@
 // heuristic of Section 5.1 (Algorithm 1, one lane per group).
 #include <hip/hip_runtime.h>
 
+#include "heur_dev.h"
 #include "tables_dev.h"
 #include "tgo_internal.h"
 
@@ -70,18 +71,6 @@ int launch_evaluate(const Rates &r, const tgo_task *d_tasks, int n, const uint8_
 
 // ---------------------------------------------------------------- heuristic
 
-struct Fit3 {
-    int64_t th, tk, td;
-};
-
-// |h_c - (t_K - t_HtD)| + |k_c - (t_DtH - max(t_HtD + h_c, t_K))|
-__device__ __forceinline__ int64_t fit(int64_t h, int64_t k, const Fit3 &u) {
-    const int64_t a = h - (u.tk - u.th);
-    const int64_t kstart = (u.th + h) > u.tk ? (u.th + h) : u.tk;
-    const int64_t b = k - (u.td - kstart);
-    return (a < 0 ? -a : a) + (b < 0 ? -b : b);
-}
-
 // One lane per group; the group's tables and the lane's queue live in LDS,
 // interleaved by lane.  Always runs the 64-bit time path.
 __global__ __launch_bounds__(HEU_THREADS) void heuristic_kernel(const tgo_task *__restrict__ tasks,
@@ -117,71 +106,8 @@ __global__ __launch_bounds__(HEU_THREADS) void heuristic_kernel(const tgo_task *
     for (int x = 0; x < n; ++x)
         table_entry<TT>(t[x], r, &Ht[x * blockDim.x + threadIdx.x], &Dt[x * blockDim.x + threadIdx.x]);
 
-    uint32_t rt = (n == 32) ? ~0u : ((1u << n) - 1u);
-    // select_first: largest k - h; ties to larger d, then lower index
-    int first = -1;
-    int64_t bkh = 0, bd = 0;
-    for (int x = 0; x < n; ++x) {
-        const int64_t kh = t[x].kern_ns - t[x].htd_ns, d = t[x].dth_ns;
-        if (first < 0 || kh > bkh || (kh == bkh && d > bd)) { first = x; bkh = kh; bd = d; }
-    }
     uint8_t ord[MAXN];
-    ord[0] = (uint8_t)first;
-    rt &= ~(1u << first);
-    Lane<TT> st = lane_init<TT>();
-    window(st, 0, (uint32_t)first, v, r);
-    int pos = 1;
-    while (__popc(rt) > 2) {
-        Fit3 u;
-        u.th = (int64_t)st.t;
-        u.tk = (int64_t)st.ck;
-        u.td = (int64_t)tail(st, r);
-        int best = -1;
-        int64_t bf = 0;
-        for (int c = 0; c < n; ++c) {
-            if (!((rt >> c) & 1u)) continue;
-            const int64_t f = fit(t[c].htd_ns, t[c].kern_ns, u);
-            if (best < 0 || f < bf) { best = c; bf = f; }
-        }
-        ord[pos] = (uint8_t)best;
-        rt &= ~(1u << best);
-        window(st, pos, (uint32_t)best, v, r);
-        ++pos;
-    }
-    if (__popc(rt) == 2) {
-        const int a = __ffs(rt) - 1;
-        const int b = 31 - __clz(rt);
-        Fit3 u;
-        u.th = (int64_t)st.t;
-        u.tk = (int64_t)st.ck;
-        u.td = (int64_t)tail(st, r);
-        int bx = -1, by = -1;
-        int64_t bs = 0, bdy = 0;
-        for (int o = 0; o < 2; ++o) {
-            const int x = o == 0 ? a : b, y = o == 0 ? b : a;
-            const int64_t s1 = fit(t[x].htd_ns, t[x].kern_ns, u);
-            Lane<TT> s2 = st;
-            window(s2, pos, (uint32_t)x, v, r);
-            Fit3 w;
-            w.th = (int64_t)s2.t;
-            w.tk = (int64_t)s2.ck;
-            w.td = (int64_t)tail(s2, r);
-            const int64_t sc = s1 + fit(t[y].htd_ns, t[y].kern_ns, w) + t[y].dth_ns;
-            const int64_t dy = t[y].dth_ns;
-            if (bx < 0 || sc < bs || (sc == bs && dy < bdy)) { bx = x; by = y; bs = sc; bdy = dy; }
-        }
-        ord[pos] = (uint8_t)bx;
-        ord[pos + 1] = (uint8_t)by;
-        window(st, pos, (uint32_t)bx, v, r);
-        window(st, pos + 1, (uint32_t)by, v, r);
-        pos += 2;
-    } else if (__popc(rt) == 1) {
-        const int x = __ffs(rt) - 1;
-        ord[pos] = (uint8_t)x;
-        window(st, pos, (uint32_t)x, v, r);
-        ++pos;
-    }
-    *nsg = (int64_t)tail(st, r);
+    *nsg = heuristic_order([t](int x) { return t[x]; }, n, v, r, ord);
     for (int i = 0; i < n; ++i) orow[i] = ord[i];
 }
 

@@ -80,6 +80,7 @@ def lib():
         L.tgo_evaluate.argtypes = [M, vp, i32, vp, i64, vp, vp]
         L.tgo_exhaustive.argtypes = [M, vp, i32, vp, vp, vp]
         L.tgo_heuristic.argtypes = [M, vp, vp, i32, vp, vp, vp]
+        L.tgo_rounds.argtypes = [M, vp, i32, i32, vp, vp, vp, vp]
         L.tgo_rank.argtypes = [i32, vp, ctypes.POINTER(ctypes.c_uint64)]
         L.tgo_unrank.argtypes = [i32, ctypes.c_uint64, vp]
         L.tgo_plan_create.argtypes = [M, i32, ctypes.POINTER(vp)]
@@ -119,7 +120,7 @@ def lib():
             f.restype = i32
         L.tgo_plan_destroy.argtypes = [vp]
         L.tgo_plan_destroy.restype = None
-        for f in (L.tgo_evaluate, L.tgo_exhaustive, L.tgo_heuristic, L.tgo_rank, L.tgo_unrank,
+        for f in (L.tgo_evaluate, L.tgo_exhaustive, L.tgo_heuristic, L.tgo_rounds, L.tgo_rank, L.tgo_unrank,
                   L.tgo_plan_create, L.tgo_plan_autotune, L.tgo_plan_describe, L.tgo_batch):
             f.restype = i32
         _lib = L
@@ -184,6 +185,36 @@ def exhaustive(tasks, model: Model = DEFAULT, per_order: bool = False, summary=N
                                 po.data_ptr() if po is not None else None, summary.data_ptr(),
                                 _stream(stream)), "tgo_exhaustive")
     return summary, po
+
+
+def rounds(tasks, workers: int, rounds: int, model: Model = DEFAULT, per_order: bool = False,
+           summary=None, stream=None):
+    """Several workers offloading dependent tasks: task (w, r) at row
+    w * rounds + r of ``tasks`` (int64 [workers * rounds, 3]).  Returns
+    (summary uint8[136] device tensor -- NoReorder over all (workers!)^rounds
+    orderings, plus the Heuristic setup in heur / heur_ns --, per-ordering
+    int64 device tensor or None, uint16 group-end mask device tensor)."""
+    import math
+    import torch
+    _dev_tensor(tasks, torch.int64, 3, "tasks")
+    if tasks.shape[0] != workers * rounds:
+        raise ValueError("tasks must have workers * rounds rows")
+    po = None
+    if per_order:
+        po = torch.empty(math.factorial(workers) ** rounds, dtype=torch.int64, device=tasks.device)
+    if summary is None:
+        summary = torch.empty(SUMMARY_DTYPE.itemsize, dtype=torch.uint8, device=tasks.device)
+    groups = torch.zeros(1, dtype=torch.int16, device=tasks.device)
+    _check(lib().tgo_rounds(ctypes.byref(model._c()), tasks.data_ptr(), workers, rounds,
+                            po.data_ptr() if po is not None else None, summary.data_ptr(),
+                            groups.data_ptr(), _stream(stream)), "tgo_rounds")
+    return summary, po, groups
+
+
+def read_groups(groups) -> list:
+    """Positions that end a proxy task group, from the uint16 mask."""
+    m = int(groups.cpu().numpy().view("<u2")[0])
+    return [j for j in range(16) if (m >> j) & 1]
 
 
 def read_summary(summary) -> dict:

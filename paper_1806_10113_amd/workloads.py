@@ -158,3 +158,13 @@ def paper_benchmark(name: str) -> np.ndarray:
     for t in PAPER_BENCHMARKS[name]:
         rows.append([int(round(f * PAPER_UNIT_NS)) for f in PAPER_TASKS_UNITS[t]])
     return np.asarray(rows, dtype=np.int64)
+
+
+def rounds_experiment(benchmark: str, workers: int, rounds: int, seed: int) -> np.ndarray:
+    """Section 6.2 experiment: workers x rounds tasks drawn uniformly (with
+    replacement) from the four tasks of a BK benchmark; task (w, r) at row
+    w * rounds + r."""
+    base = paper_benchmark(benchmark)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    idx = rng.integers(0, len(base), size=workers * rounds)
+    return np.ascontiguousarray(base[idx])

@@ -64,6 +64,14 @@ def test_host_argument_errors(L):
     assert L.tgo_evaluate(ctypes.byref(good), None, 4, fake, 3, fake, None) == tgo.TGO_EINVAL
     assert L.tgo_heuristic(ctypes.byref(good), fake, fake, -1, fake, fake, None) == tgo.TGO_EINVAL
     assert b"n must be" in L.tgo_last_error() or L.tgo_last_error()
+    # multi-round shapes: workers * rounds <= 16, (workers!)^rounds < 2^32,
+    # per-ordering output only up to 12! orderings
+    for T, R, po in ((0, 2, None), (2, 0, None), (9, 2, None), (13, 1, None), (7, 3, None),
+                     (8, 2, fake)):
+        assert L.tgo_rounds(ctypes.byref(good), fake, T, R, po, fake, None, None) == tgo.TGO_EINVAL
+    assert L.tgo_rounds(ctypes.byref(good), None, 2, 2, None, fake, None, None) == tgo.TGO_EINVAL
+    assert L.tgo_rounds(ctypes.byref(tgo._Model(3, 2, 3, 3)), fake, 2, 2, None, fake, None,
+                        None) == tgo.TGO_EINVAL
 
 
 def test_rank_unrank_match_lexicographic_order():
