@@ -52,6 +52,8 @@ def parse():
                    help="exact (ordering, time) pairs used to train the proposal network")
     p.add_argument("--eval-groups", type=int, default=1024)
     p.add_argument("--serve-seconds", type=float, default=2.0)
+    p.add_argument("--hw-unit-ms", type=float, default=10.0,
+                   help="time unit of the synthetic tasks run on the device (0: skip that validation)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a 256 MiB device copy (for HBM counter calibration)")
     return p.parse_args()
@@ -197,6 +199,22 @@ def rounds_extra(dev, seed: int = 11):
             }
     return {"cases": out, "orderings": total_orderings, "ms": total_ms,
             "orderings_per_s": total_orderings / (total_ms / 1e3)}
+
+
+def hw_validation_extra(dev, unit_ms: float):
+    """The model against real HtD / kernel / DtH tasks on this device
+    (Sections 4.2, 4.3): fitted rates, overlap-model errors, and the mean
+    prediction error over every ordering of each BK benchmark."""
+    from paper_1806_10113_amd import validate
+    r = validate.run(dev, unit_ms=unit_ms, reps=3)
+    out = {"unit_ms": unit_ms, "transfers": r["transfers"], "kernel": r["kernel"], "overlap": r["overlap"]}
+    for sc in ("two_dma", "one_dma_scheme"):
+        out[sc] = {"geomean_err_pct": r[sc]["geomean_err_pct"],
+                   "benchmarks": {b: {k: v[k] for k in ("mean_err_pct", "max_err_pct", "measured_speedup_best",
+                                                          "measured_speedup_heuristic",
+                                                          "measured_time_of_predicted_best_vs_best_pct")}
+                                  for b, v in r[sc]["benchmarks"].items()}}
+    return out
 
 
 def train_surrogate(dev, pairs_total: float, seed: int = 1003, batch: int = 8192, lr: float = 1e-3):
@@ -424,6 +442,8 @@ def main():
         extras["proposal_training"] = tr
         extras["proposal_n16"] = surrogate_extra(dev, sur, args.eval_groups)
         extras["serving"] = serving_extra(dev, sur, args.serve_seconds)
+        if args.hw_unit_ms > 0:
+            extras["hw_validation"] = hw_validation_extra(dev, args.hw_unit_ms)
         sur.close()
         out["extras"] = extras
     if not args.no_cpu_baseline:

@@ -345,6 +345,55 @@ void tgo_server_destroy(tgo_server *srv);
 int tgo_rounds(const tgo_model *model, const tgo_task *d_tasks, int workers, int rounds,
                int64_t *d_per_order, tgo_summary *d_summary, uint16_t *d_groups, tgo_stream stream);
 
+/* ---------------------------------------------------------------------------
+ * Real execution on the device, to validate the model (Sections 4.2, 4.3):
+ * each task is an HtD copy from pinned host memory, a kernel, and a DtH copy,
+ * launched with a scheme of Section 3.2 on HIP streams (one stream per command
+ * queue, events for the dependencies inside a task) and timed with events.
+ */
+typedef struct tgo_hw tgo_hw;
+
+typedef struct {
+    int64_t htd_bytes;   /* bytes copied host -> device (0: no HtD)           */
+    int64_t dth_bytes;   /* bytes copied device -> host (0: no DtH)           */
+    int64_t kern_elems;  /* floats the kernel scales per pass                 */
+    int32_t kern_iters;  /* passes (0: no kernel); the duration is linear in   */
+    int32_t pad;         /* kern_elems * kern_iters (Eq. 1)                   */
+} tgo_hw_task;
+
+typedef struct {
+    int64_t start_ns[3], end_ns[3]; /* HtD, K, DtH; ns after the group's start */
+} tgo_hw_times;
+
+/* Pinned host buffers, device buffers and three non-blocking streams for up
+ * to max_tasks tasks of at most max_bytes per copy and max_kern_elems floats
+ * per kernel, on the current device.  Owned by the handle. */
+int tgo_hw_create(int max_tasks, int64_t max_bytes, int64_t max_kern_elems, tgo_hw **out);
+void tgo_hw_destroy(tgo_hw *hw);
+/* Run n tasks (h_tasks on the host) in h_order with the one- or two-DMA scheme
+ * (dma_engines 1: one transfer stream holding every HtD then every DtH; 2: an
+ * HtD stream, a kernel stream, a DtH stream), wait for them, and return the
+ * makespan and, if h_cmds is not NULL, each task's command times (indexed by
+ * task).  The streams are held for 2 ms first so that enqueueing on the host
+ * does not delay the device.  Blocking. */
+int tgo_hw_run(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *h_order, int dma_engines,
+               int64_t *h_total_ns, tgo_hw_times *h_cmds);
+/* An HtD of htd_bytes and, on another stream, a DtH of dth_bytes issued
+ * dth_delay_ns after it (a device-side wait), as in the overlap experiment of
+ * Section 4.2.1.  h_times[4] = HtD start, HtD end, DtH start, DtH end (ns).
+ * Blocking. */
+int tgo_hw_overlap(tgo_hw *hw, int64_t htd_bytes, int64_t dth_bytes, int64_t dth_delay_ns, int64_t *h_times);
+/* Least-squares line y = slope * x + intercept over n >= 2 points (host); the
+ * kernel model T = eta * m + gamma of Eq. 1, and transfer time against size. */
+int tgo_fit_line(const double *h_x, const double *h_y, int n, double *slope, double *intercept);
+/* Overlap rates from n overlap experiments (Section 4.2.1): h_times as
+ * returned by tgo_hw_overlap (4 per experiment), h_solo the solo HtD and DtH
+ * durations (2 per experiment).  With L the overlapped time of an experiment,
+ * a transfer's solo work = its time outside the overlap + rho * L; rho is
+ * fitted over all experiments as sum(solo - outside) / sum(L).  Experiments
+ * without overlap are skipped (TGO_EINVAL if none overlaps). */
+int tgo_fit_overlap(const int64_t *h_times, const int64_t *h_solo, int n, double *rho_htd, double *rho_dth);
+
 /* Host helpers: lexicographic rank <-> ordering (index arithmetic only). */
 int tgo_rank(int n, const uint8_t *h_order, uint64_t *rank);
 int tgo_unrank(int n, uint64_t rank, uint8_t *h_order);

@@ -1,0 +1,306 @@
+// Real task execution on the device, for validating the model (Sections 4.2
+// and 4.3): each task is an HtD copy from pinned host memory, a kernel and a
+// DtH copy back, launched with the schemes of Section 3.2 on HIP streams
+// (one stream per command queue, events for the dependencies inside a task),
+// and timed with events.  Also the two calibration fits the model needs: the
+// linear kernel model T = eta * m + gamma (Eq. 1), the same line for
+// transfer time against size, and the overlapped-transfer rates (Section
+// 4.2.1) from measured overlapping copies.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "tgo_internal.h"
+
+// Synthetic kernel (the paper's synthetic tasks scale a vector; the
+// iteration count sets the duration): iters passes of x = x * s + b over
+// n floats.
+__global__ __launch_bounds__(256) void tgo_hw_scale_kernel(float *x, int64_t n, int iters, float s, float b) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int it = 0; it < iters; ++it)
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+            x[i] = x[i] * s + b;
+}
+
+// One thread waits until `ticks` of the constant-rate wall clock have passed
+// (bounded by max_polls reads of the clock).
+__global__ void tgo_hw_delay_kernel(int64_t ticks, int64_t max_polls) {
+    if (threadIdx.x != 0) return;
+    const int64_t t0 = wall_clock64();
+    for (int64_t i = 0; i < max_polls; ++i) {
+        if (wall_clock64() - t0 >= ticks) break;
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+namespace {
+
+constexpr int64_t GATE_NS = 2000000;  // streams held back while the host enqueues
+
+struct TaskBufs {
+    void *host_in = nullptr, *host_out = nullptr;
+    void *dev_in = nullptr, *dev_out = nullptr;
+    float *dev_k = nullptr;
+};
+
+}  // namespace
+
+struct tgo_hw {
+    int device = 0;
+    int max_tasks = 0;
+    int64_t max_bytes = 0, max_elems = 0;
+    int64_t clock_khz = 0;
+    int blocks = 1024;
+    hipStream_t sh = nullptr, sk = nullptr, sd = nullptr;
+    std::vector<TaskBufs> bufs;
+    hipEvent_t t0 = nullptr;
+    std::vector<hipEvent_t> ev;  // 6 per task slot: HtD, K, DtH start and end
+};
+
+namespace tgo {
+
+static void hw_free(tgo_hw *hw) {
+    for (auto &b : hw->bufs) {
+        if (b.host_in) (void)hipHostFree(b.host_in);
+        if (b.host_out) (void)hipHostFree(b.host_out);
+        if (b.dev_in) (void)hipFree(b.dev_in);
+        if (b.dev_out) (void)hipFree(b.dev_out);
+        if (b.dev_k) (void)hipFree(b.dev_k);
+    }
+    for (auto e : hw->ev) (void)hipEventDestroy(e);
+    if (hw->t0) (void)hipEventDestroy(hw->t0);
+    if (hw->sh) (void)hipStreamDestroy(hw->sh);
+    if (hw->sk) (void)hipStreamDestroy(hw->sk);
+    if (hw->sd) (void)hipStreamDestroy(hw->sd);
+    delete hw;
+}
+
+static int64_t ns_between(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1;
+    return (int64_t)llround((double)ms * 1e6);
+}
+
+static void delay(tgo_hw *hw, hipStream_t st, int64_t ns) {
+    const int64_t ticks = ns * hw->clock_khz / 1000000;
+    // each poll sleeps ~128 cycles; the bound is far above the wait asked for
+    const int64_t polls = 64 + ticks * 64;
+    hipLaunchKernelGGL(tgo_hw_delay_kernel, dim3(1), dim3(64), 0, st, ticks, polls);
+}
+
+}  // namespace tgo
+
+using namespace tgo;
+
+extern "C" {
+
+int tgo_hw_create(int max_tasks, int64_t max_bytes, int64_t max_kern_elems, tgo_hw **out) {
+    if (!out) return fail(TGO_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_tasks < 1 || max_tasks > TGO_MAX_N) return fail(TGO_EINVAL, "max_tasks must be in 1..16");
+    if (max_bytes < 0 || max_kern_elems < 0) return fail(TGO_EINVAL, "sizes must be >= 0");
+    tgo_hw *hw = new tgo_hw();
+    hw->max_tasks = max_tasks;
+    hw->max_bytes = max_bytes;
+    hw->max_elems = max_kern_elems;
+    auto bail = [&](hipError_t e, const char *what) {
+        hw_free(hw);
+        return hip_fail(e, what);
+    };
+    hipError_t e = hipGetDevice(&hw->device);
+    if (e != hipSuccess) return bail(e, "hipGetDevice");
+    int khz = 0;
+    e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, hw->device);
+    if (e != hipSuccess || khz <= 0) return bail(e == hipSuccess ? hipErrorInvalidValue : e, "wall clock rate");
+    hw->clock_khz = khz;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hw->device) == hipSuccess && cus > 0)
+        hw->blocks = cus * 4;
+    if ((e = hipStreamCreateWithFlags(&hw->sh, hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
+    if ((e = hipStreamCreateWithFlags(&hw->sk, hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
+    if ((e = hipStreamCreateWithFlags(&hw->sd, hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
+    if ((e = hipEventCreate(&hw->t0)) != hipSuccess) return bail(e, "event");
+    hw->ev.resize(6 * max_tasks, nullptr);
+    for (auto &ev : hw->ev)
+        if ((e = hipEventCreate(&ev)) != hipSuccess) return bail(e, "event");
+    hw->bufs.resize(max_tasks);
+    const size_t nb = (size_t)std::max<int64_t>(max_bytes, 4);
+    const size_t kb = sizeof(float) * (size_t)std::max<int64_t>(max_kern_elems, 1);
+    for (auto &b : hw->bufs) {
+        if ((e = hipHostMalloc(&b.host_in, nb, hipHostMallocDefault)) != hipSuccess) return bail(e, "hipHostMalloc");
+        if ((e = hipHostMalloc(&b.host_out, nb, hipHostMallocDefault)) != hipSuccess) return bail(e, "hipHostMalloc");
+        if ((e = hipMalloc(&b.dev_in, nb)) != hipSuccess) return bail(e, "hipMalloc");
+        if ((e = hipMalloc(&b.dev_out, nb)) != hipSuccess) return bail(e, "hipMalloc");
+        if ((e = hipMalloc((void **)&b.dev_k, kb)) != hipSuccess) return bail(e, "hipMalloc");
+        std::fill((unsigned char *)b.host_in, (unsigned char *)b.host_in + nb, (unsigned char)1);
+        if ((e = hipMemset(b.dev_out, 0, nb)) != hipSuccess) return bail(e, "hipMemset");
+        if ((e = hipMemset(b.dev_k, 0, kb)) != hipSuccess) return bail(e, "hipMemset");
+    }
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return bail(e, "hipDeviceSynchronize");
+    *out = hw;
+    return TGO_OK;
+}
+
+void tgo_hw_destroy(tgo_hw *hw) {
+    if (!hw) return;
+    (void)hipSetDevice(hw->device);
+    (void)hipDeviceSynchronize();
+    hw_free(hw);
+}
+
+int tgo_hw_run(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *h_order, int dma_engines,
+               int64_t *h_total_ns, tgo_hw_times *h_cmds) {
+    if (!hw || !h_tasks || !h_order || !h_total_ns) return fail(TGO_EINVAL, "NULL argument");
+    if (n < 1 || n > hw->max_tasks) return fail(TGO_EINVAL, "n must be in 1..max_tasks");
+    if (dma_engines != 1 && dma_engines != 2) return fail(TGO_EINVAL, "dma_engines must be 1 or 2");
+    uint32_t seen = 0;
+    for (int i = 0; i < n; ++i) {
+        if (h_order[i] >= n || ((seen >> h_order[i]) & 1u)) return fail(TGO_EINVAL, "not a permutation");
+        seen |= 1u << h_order[i];
+        const tgo_hw_task &t = h_tasks[i];
+        if (t.htd_bytes < 0 || t.htd_bytes > hw->max_bytes || t.dth_bytes < 0 || t.dth_bytes > hw->max_bytes ||
+            t.kern_elems < 0 || t.kern_elems > hw->max_elems || t.kern_iters < 0)
+            return fail(TGO_EINVAL, "task exceeds the runner's buffers");
+    }
+    TGO_HIP(hipSetDevice(hw->device));
+    hipStream_t sx = hw->sh;                            // transfer queue(s)
+    hipStream_t sd = dma_engines == 2 ? hw->sd : hw->sh;
+    // hold every stream until the host has enqueued the whole group
+    delay(hw, hw->sh, GATE_NS);
+    TGO_HIP(hipEventRecord(hw->t0, hw->sh));
+    TGO_HIP(hipStreamWaitEvent(hw->sk, hw->t0, 0));
+    if (sd != sx) TGO_HIP(hipStreamWaitEvent(sd, hw->t0, 0));
+    auto E = [&](int x, int c) { return hw->ev[6 * x + c]; };
+    auto htd = [&](int x) -> int {
+        const tgo_hw_task &t = h_tasks[x];
+        TGO_HIP(hipEventRecord(E(x, 0), sx));
+        if (t.htd_bytes > 0)
+            TGO_HIP(hipMemcpyAsync(hw->bufs[x].dev_in, hw->bufs[x].host_in, (size_t)t.htd_bytes,
+                                   hipMemcpyHostToDevice, sx));
+        TGO_HIP(hipEventRecord(E(x, 1), sx));
+        return TGO_OK;
+    };
+    auto kern = [&](int x) -> int {
+        const tgo_hw_task &t = h_tasks[x];
+        TGO_HIP(hipStreamWaitEvent(hw->sk, E(x, 1), 0));
+        TGO_HIP(hipEventRecord(E(x, 2), hw->sk));
+        if (t.kern_iters > 0 && t.kern_elems > 0) {
+            const int64_t want = (t.kern_elems + 255) / 256;
+            const int blocks = (int)std::min<int64_t>(want, hw->blocks);
+            hipLaunchKernelGGL(tgo_hw_scale_kernel, dim3(blocks), dim3(256), 0, hw->sk, hw->bufs[x].dev_k,
+                               t.kern_elems, t.kern_iters, 0.999f, 0.001f);
+            TGO_HIP(hipGetLastError());
+        }
+        TGO_HIP(hipEventRecord(E(x, 3), hw->sk));
+        return TGO_OK;
+    };
+    auto dth = [&](int x) -> int {
+        const tgo_hw_task &t = h_tasks[x];
+        TGO_HIP(hipStreamWaitEvent(sd, E(x, 3), 0));
+        TGO_HIP(hipEventRecord(E(x, 4), sd));
+        if (t.dth_bytes > 0)
+            TGO_HIP(hipMemcpyAsync(hw->bufs[x].host_out, hw->bufs[x].dev_out, (size_t)t.dth_bytes,
+                                   hipMemcpyDeviceToHost, sd));
+        TGO_HIP(hipEventRecord(E(x, 5), sd));
+        return TGO_OK;
+    };
+    int rc;
+    if (dma_engines == 2) {
+        // three queues, commands in launch order (Section 3.2, two DMA engines)
+        for (int i = 0; i < n; ++i) {
+            const int x = h_order[i];
+            if ((rc = htd(x)) || (rc = kern(x)) || (rc = dth(x))) return rc;
+        }
+    } else {
+        // one transfer queue: every HtD, then every DtH; kernels on their own queue
+        for (int i = 0; i < n; ++i)
+            if ((rc = htd(h_order[i])) || (rc = kern(h_order[i]))) return rc;
+        for (int i = 0; i < n; ++i)
+            if ((rc = dth(h_order[i]))) return rc;
+    }
+    TGO_HIP(hipStreamSynchronize(hw->sh));
+    TGO_HIP(hipStreamSynchronize(hw->sk));
+    TGO_HIP(hipStreamSynchronize(hw->sd));
+    int64_t total = 0;
+    for (int x = 0; x < n; ++x) {
+        tgo_hw_times c;
+        for (int k = 0; k < 3; ++k) {
+            c.start_ns[k] = ns_between(hw->t0, E(x, 2 * k));
+            c.end_ns[k] = ns_between(hw->t0, E(x, 2 * k + 1));
+            total = std::max(total, c.end_ns[k]);
+        }
+        if (h_cmds) h_cmds[x] = c;
+    }
+    *h_total_ns = total;
+    return TGO_OK;
+}
+
+int tgo_hw_overlap(tgo_hw *hw, int64_t htd_bytes, int64_t dth_bytes, int64_t dth_delay_ns, int64_t *h_times) {
+    if (!hw || !h_times) return fail(TGO_EINVAL, "NULL argument");
+    if (htd_bytes < 0 || htd_bytes > hw->max_bytes || dth_bytes < 0 || dth_bytes > hw->max_bytes ||
+        dth_delay_ns < 0 || dth_delay_ns > 10000000000ll)
+        return fail(TGO_EINVAL, "sizes out of range");
+    TGO_HIP(hipSetDevice(hw->device));
+    delay(hw, hw->sh, GATE_NS);
+    TGO_HIP(hipEventRecord(hw->t0, hw->sh));
+    TGO_HIP(hipStreamWaitEvent(hw->sd, hw->t0, 0));
+    TGO_HIP(hipEventRecord(hw->ev[0], hw->sh));
+    if (htd_bytes > 0)
+        TGO_HIP(hipMemcpyAsync(hw->bufs[0].dev_in, hw->bufs[0].host_in, (size_t)htd_bytes,
+                               hipMemcpyHostToDevice, hw->sh));
+    TGO_HIP(hipEventRecord(hw->ev[1], hw->sh));
+    if (dth_delay_ns > 0) delay(hw, hw->sd, dth_delay_ns);
+    TGO_HIP(hipEventRecord(hw->ev[4], hw->sd));
+    if (dth_bytes > 0)
+        TGO_HIP(hipMemcpyAsync(hw->bufs[0].host_out, hw->bufs[0].dev_out, (size_t)dth_bytes,
+                               hipMemcpyDeviceToHost, hw->sd));
+    TGO_HIP(hipEventRecord(hw->ev[5], hw->sd));
+    TGO_HIP(hipStreamSynchronize(hw->sh));
+    TGO_HIP(hipStreamSynchronize(hw->sd));
+    h_times[0] = ns_between(hw->t0, hw->ev[0]);
+    h_times[1] = ns_between(hw->t0, hw->ev[1]);
+    h_times[2] = ns_between(hw->t0, hw->ev[4]);
+    h_times[3] = ns_between(hw->t0, hw->ev[5]);
+    return TGO_OK;
+}
+
+int tgo_fit_line(const double *h_x, const double *h_y, int n, double *slope, double *intercept) {
+    if (!h_x || !h_y || !slope || !intercept || n < 2) return fail(TGO_EINVAL, "need n >= 2 points");
+    double mx = 0, my = 0;
+    for (int i = 0; i < n; ++i) { mx += h_x[i]; my += h_y[i]; }
+    mx /= n;
+    my /= n;
+    double sxx = 0, sxy = 0;
+    for (int i = 0; i < n; ++i) {
+        sxx += (h_x[i] - mx) * (h_x[i] - mx);
+        sxy += (h_x[i] - mx) * (h_y[i] - my);
+    }
+    if (!(sxx > 0)) return fail(TGO_EINVAL, "x values are all equal");
+    *slope = sxy / sxx;
+    *intercept = my - *slope * mx;
+    return TGO_OK;
+}
+
+int tgo_fit_overlap(const int64_t *h_times, const int64_t *h_solo, int n, double *rho_htd, double *rho_dth) {
+    if (!h_times || !h_solo || !rho_htd || !rho_dth || n < 1) return fail(TGO_EINVAL, "bad argument");
+    double wh = 0, sh = 0, wd = 0, sd = 0;
+    for (int i = 0; i < n; ++i) {
+        const int64_t *t = h_times + 4 * i;
+        const double h0 = (double)t[0], h1 = (double)t[1], d0 = (double)t[2], d1 = (double)t[3];
+        const double L = std::min(h1, d1) - std::max(h0, d0);
+        if (L <= 0) continue;
+        // solo work = time outside the overlap at full speed + rho * overlap
+        sh += (double)h_solo[2 * i] - ((h1 - h0) - L);
+        sd += (double)h_solo[2 * i + 1] - ((d1 - d0) - L);
+        wh += L;
+        wd += L;
+    }
+    if (!(wh > 0)) return fail(TGO_EINVAL, "no experiment overlaps");
+    *rho_htd = sh / wh;
+    *rho_dth = sd / wd;
+    return TGO_OK;
+}
+
+}  // extern "C"

@@ -118,6 +118,15 @@ def lib():
         for f in (L.tgo_server_create, L.tgo_server_submit, L.tgo_server_poll, L.tgo_server_drain,
                   L.tgo_server_get_stats, L.tgo_server_replay):
             f.restype = i32
+        L.tgo_hw_create.argtypes = [i32, i64, i64, ctypes.POINTER(vp)]
+        L.tgo_hw_destroy.argtypes = [vp]
+        L.tgo_hw_destroy.restype = None
+        L.tgo_hw_run.argtypes = [vp, vp, i32, vp, i32, ctypes.POINTER(ctypes.c_int64), vp]
+        L.tgo_hw_overlap.argtypes = [vp, i64, i64, i64, vp]
+        L.tgo_fit_line.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.tgo_fit_overlap.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        for f in (L.tgo_hw_create, L.tgo_hw_run, L.tgo_hw_overlap, L.tgo_fit_line, L.tgo_fit_overlap):
+            f.restype = i32
         L.tgo_plan_destroy.argtypes = [vp]
         L.tgo_plan_destroy.restype = None
         for f in (L.tgo_evaluate, L.tgo_exhaustive, L.tgo_heuristic, L.tgo_rounds, L.tgo_rank, L.tgo_unrank,
@@ -525,6 +534,68 @@ class Server:
         _check(lib().tgo_server_replay(self._h, t.ctypes.data, o.ctypes.data, a.ctypes.data, n,
                                        out.ctypes.data, timeout_ms), "tgo_server_replay")
         return out
+
+
+HW_TASK_DTYPE = np.dtype([("htd_bytes", "<i8"), ("dth_bytes", "<i8"), ("kern_elems", "<i8"),
+                          ("kern_iters", "<i4"), ("pad", "<i4")])
+HW_TIMES_DTYPE = np.dtype([("start_ns", "<i8", (3,)), ("end_ns", "<i8", (3,))])
+
+
+class HwRunner:
+    """Real HtD / kernel / DtH tasks on the current device (tgo_hw_*)."""
+
+    def __init__(self, max_tasks: int, max_bytes: int, max_kern_elems: int):
+        self._h = ctypes.c_void_p()
+        _check(lib().tgo_hw_create(max_tasks, max_bytes, max_kern_elems, ctypes.byref(self._h)),
+               "tgo_hw_create")
+
+    def close(self):
+        if self._h:
+            lib().tgo_hw_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, tasks: np.ndarray, order, dma_engines: int = 2):
+        """tasks: HW_TASK_DTYPE [n].  Returns (makespan ns, HW_TIMES_DTYPE [n])."""
+        tasks = np.ascontiguousarray(tasks, dtype=HW_TASK_DTYPE)
+        n = len(tasks)
+        o = np.ascontiguousarray(order, dtype=np.uint8)
+        times = np.zeros(n, dtype=HW_TIMES_DTYPE)
+        total = ctypes.c_int64()
+        _check(lib().tgo_hw_run(self._h, tasks.ctypes.data, n, o.ctypes.data, dma_engines,
+                                ctypes.byref(total), times.ctypes.data), "tgo_hw_run")
+        return int(total.value), times
+
+    def overlap(self, htd_bytes: int, dth_bytes: int, delay_ns: int) -> np.ndarray:
+        out = np.zeros(4, dtype=np.int64)
+        _check(lib().tgo_hw_overlap(self._h, htd_bytes, dth_bytes, delay_ns, out.ctypes.data),
+               "tgo_hw_overlap")
+        return out
+
+
+def fit_line(x, y):
+    """(slope, intercept) of the least-squares line (tgo_fit_line)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(lib().tgo_fit_line(x.ctypes.data, y.ctypes.data, len(x), ctypes.byref(a), ctypes.byref(b)),
+           "tgo_fit_line")
+    return a.value, b.value
+
+
+def fit_overlap(times, solo):
+    """(rho_htd, rho_dth) from overlap experiments (tgo_fit_overlap)."""
+    t = np.ascontiguousarray(times, dtype=np.int64).reshape(-1, 4)
+    so = np.ascontiguousarray(solo, dtype=np.int64).reshape(-1, 2)
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(lib().tgo_fit_overlap(t.ctypes.data, so.ctypes.data, len(t), ctypes.byref(a), ctypes.byref(b)),
+           "tgo_fit_overlap")
+    return a.value, b.value
 
 
 def rank(order) -> int:

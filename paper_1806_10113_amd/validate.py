@@ -1,0 +1,206 @@
+"""Validation of the temporal execution model on the device it runs on
+(Sections 4.2 and 4.3): calibrate the command-time models, measure real task
+groups launched with the Section 3.2 schemes, and compare with the model's
+prediction for every ordering.
+
+Steps (each measurement is the median of ``reps`` runs):
+  1. Transfers: solo HtD and DtH times over a range of sizes, fitted to a line
+     (latency + bytes / bandwidth) with tgo_fit_line.
+  2. Overlap (Section 4.2.1): an HtD and a DtH of equal size issued together
+     (and with the DtH delayed to overlap 75 / 50 / 25 % of the HtD); the
+     overlap rates rho_htd, rho_dth come from tgo_fit_overlap over the fully
+     overlapped runs and give the model's p/q (q = 1024).  Each experiment's
+     total is predicted by tgo_evaluate with the fitted rates (partial
+     overlap, the model), with no slowdown (non-overlapped model) and with
+     both transfers slowed for their whole length (fully overlapped model).
+  3. Kernel (Eq. 1): T = eta * m + gamma with m = floats scaled x passes.
+  4. Task groups: the synthetic tasks T0..T7 of Section 4.3 (fractions of a
+     time unit, 10 ms in the paper) built from the fitted models, every
+     ordering of each benchmark BK0..BK100 run on the device, and the model's
+     prediction for every ordering (tgo_exhaustive with the tasks' measured
+     solo command times) compared with the measured makespan.
+
+Everything that runs on the device goes through the C ABI (tgo_hw_*,
+tgo_evaluate, tgo_exhaustive); this module only orchestrates and summarises.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+from . import tgo
+from . import workloads as W
+
+MB = 1 << 20
+Q_LOG2 = 10  # fitted rates are expressed as p / 1024
+
+
+def _median_run(hw, tasks, order, dma, reps):
+    runs = [hw.run(tasks, order, dma) for _ in range(reps)]
+    totals = [r[0] for r in runs]
+    i = int(np.argsort(totals)[len(totals) // 2])
+    return totals[i], runs[i][1]
+
+
+def _one(htd=0, dth=0, elems=0, iters=0):
+    t = np.zeros(1, dtype=tgo.HW_TASK_DTYPE)
+    t["htd_bytes"], t["dth_bytes"], t["kern_elems"], t["kern_iters"] = htd, dth, elems, iters
+    return t
+
+
+def calibrate_transfers(hw, sizes_mb, reps):
+    out = {}
+    for kind, c in (("htd", 0), ("dth", 2)):
+        xs, ys = [], []
+        for mb in sizes_mb:
+            b = int(mb * MB)
+            task = _one(htd=b) if kind == "htd" else _one(dth=b)
+            _, times = _median_run(hw, task, [0], 2, reps)
+            xs.append(b)
+            ys.append(float(times[0]["end_ns"][c] - times[0]["start_ns"][c]))
+        slope, icept = tgo.fit_line(xs, ys)
+        out[kind] = {"ns_per_byte": slope, "latency_ns": icept, "gb_per_s": 1.0 / slope,
+                     "sizes_bytes": xs, "ns": ys}
+    return out
+
+
+def calibrate_kernel(hw, elems, iters_list, reps):
+    xs, ys = [], []
+    for it in iters_list:
+        _, times = _median_run(hw, _one(elems=elems, iters=it), [0], 2, reps)
+        xs.append(float(elems) * it)
+        ys.append(float(times[0]["end_ns"][1] - times[0]["start_ns"][1]))
+    eta, gamma = tgo.fit_line(xs, ys)
+    return {"eta_ns_per_elem_pass": eta, "gamma_ns": gamma, "m": xs, "ns": ys}
+
+
+def overlap_experiments(hw, sizes_mb, reps, dev):
+    """Fig. overlap_error on this device."""
+    import torch
+    solo, full, records = [], [], []
+    for mb in sizes_mb:
+        b = int(mb * MB)
+        sh = int(np.median([t[1] - t[0] for t in (hw.overlap(b, 0, 0) for _ in range(reps))]))
+        sd = int(np.median([t[3] - t[2] for t in (hw.overlap(0, b, 0) for _ in range(reps))]))
+        for frac in (1.0, 0.75, 0.5, 0.25, 0.0):
+            delay = int(round((1.0 - frac) * sh))
+            runs = [hw.overlap(b, b, delay) for _ in range(reps)]
+            tot = [max(t[1], t[3]) - t[0] for t in runs]
+            t = runs[int(np.argsort(tot)[len(tot) // 2])]
+            records.append({"mb": mb, "overlap": frac, "times": [int(v) for v in t], "solo": [sh, sd]})
+            if frac == 1.0:
+                full.append(t)
+                solo.append([sh, sd])
+    rho_h, rho_d = tgo.fit_overlap(np.array(full), np.array(solo))
+    q = 1 << Q_LOG2
+    p_h = int(min(q, max(1, round(rho_h * q))))
+    p_d = int(min(q, max(1, round(rho_d * q))))
+    fitted = tgo.Model(Q_LOG2, p_h, p_d)
+    flat = tgo.Model(Q_LOG2, q, q)
+    errs = {"partial": [], "non_overlapped": [], "fully_overlapped": []}
+    # the two transfers as a two-task group: task 0 = (0, delay, d): its
+    # kernel holds the DtH back until the measured DtH start; task 1 = (h, 0, 0)
+    tasks = []
+    for rec in records:
+        t = rec["times"]
+        h, d = rec["solo"]
+        off = t[2] - t[0]
+        tasks.append(np.array([[0, max(0, off), d], [h, 0, 0]], dtype=np.int64))
+    order = torch.tensor([[0, 1]], dtype=torch.uint8, device=dev)
+    for rec, tk in zip(records, tasks):
+        t = rec["times"]
+        meas = max(t[1], t[3]) - t[0]
+        td = torch.as_tensor(tk).to(dev)
+        pred_p = int(tgo.evaluate(td, order, fitted).cpu()[0])
+        pred_n = int(tgo.evaluate(td, order, flat).cpu()[0])
+        h, d = rec["solo"]
+        off = max(0, t[2] - t[0])
+        pred_f = max(h / rho_h, off + d / rho_d)
+        for k, v in (("partial", pred_p), ("non_overlapped", pred_n), ("fully_overlapped", pred_f)):
+            e = abs(v - meas) / meas
+            errs[k].append(e)
+        rec.update({"measured_ns": int(meas), "pred_partial_ns": pred_p, "pred_non_overlapped_ns": pred_n,
+                    "pred_fully_overlapped_ns": pred_f})
+    summary = {k: {"mean_pct": 100 * float(np.mean(v)), "max_pct": 100 * float(np.max(v))}
+               for k, v in errs.items()}
+    return {"rho_htd": rho_h, "rho_dth": rho_d, "model": [Q_LOG2, p_h, p_d], "errors": summary,
+            "records": records}, fitted
+
+
+def build_task(frac, unit_ns, xfer, kern, elems):
+    """Commands sized for (h, k, d) = frac * unit from the fitted models."""
+    h_ns, k_ns, d_ns = (f * unit_ns for f in frac)
+    hb = max(0, int((h_ns - xfer["htd"]["latency_ns"]) / xfer["htd"]["ns_per_byte"]))
+    db = max(0, int((d_ns - xfer["dth"]["latency_ns"]) / xfer["dth"]["ns_per_byte"]))
+    it = max(1, int(round((k_ns - kern["gamma_ns"]) / (kern["eta_ns_per_elem_pass"] * elems))))
+    return hb, db, it
+
+
+def validate_benchmarks(hw, dev, xfer, kern, model, unit_ns, elems, reps, dma_engines=2):
+    """Fig. prediction_error on this device: every ordering of each benchmark."""
+    import torch
+    out = {}
+    mdl = tgo.Model(model.q_log2, model.p_htd, model.p_dth, dma_engines)
+    for bk, names in W.PAPER_BENCHMARKS.items():
+        tasks = np.zeros(4, dtype=tgo.HW_TASK_DTYPE)
+        for i, nm in enumerate(names):
+            hb, db, it = build_task(W.PAPER_TASKS_UNITS[nm], unit_ns, xfer, kern, elems)
+            tasks[i] = (hb, db, elems, it, 0)
+        # measured solo command times feed the model
+        solo = np.zeros((4, 3), dtype=np.int64)
+        for i in range(4):
+            _, tm = _median_run(hw, tasks[i:i + 1], [0], 2, reps)
+            solo[i] = tm[0]["end_ns"] - tm[0]["start_ns"]
+        solo_dev = torch.as_tensor(solo).to(dev)
+        summ, po = tgo.exhaustive(solo_dev, mdl, per_order=True)
+        horder, _ = tgo.heuristic(solo_dev, torch.tensor([0, 4], dtype=torch.int32, device=dev), mdl)
+        pred = po.cpu().numpy()
+        s = tgo.read_summary(summ)
+        heur = [int(v) for v in horder.cpu().numpy()[0, :4]]
+        meas = np.zeros(24, dtype=np.int64)
+        for rk, order in enumerate(itertools.permutations(range(4))):
+            meas[rk], _ = _median_run(hw, tasks, list(order), dma_engines, reps)
+        err = np.abs(pred - meas) / meas
+        heur_rank = tgo.rank(heur)
+        out[bk] = {
+            "solo_ns": solo.tolist(), "pred_ns": pred.tolist(), "measured_ns": meas.tolist(),
+            "mean_err_pct": 100 * float(err.mean()), "max_err_pct": 100 * float(err.max()),
+            "measured_speedup_best": float(meas.max() / meas.min()),
+            "measured_speedup_heuristic": float(meas.max() / meas[heur_rank]),
+            "predicted_best_rank": int(s["argmin_rank"]), "measured_best_rank": int(np.argmin(meas)),
+            "measured_time_of_predicted_best_vs_best_pct":
+                100 * float(meas[s["argmin_rank"]] / meas.min() - 1.0),
+        }
+    geo = math.exp(np.mean([math.log(max(v["mean_err_pct"], 1e-9)) for v in out.values()]))
+    return {"benchmarks": out, "geomean_err_pct": geo}
+
+
+def run(dev=None, unit_ms: float = 10.0, reps: int = 3, quick: bool = False):
+    import torch
+    dev = dev or torch.device("cuda:0")
+    sizes = [8, 16, 32, 64] if quick else [16, 32, 64, 128, 256, 512]
+    iters = [1, 2, 4, 8, 16, 32] if quick else [1, 2, 4, 8, 16, 32, 64, 128]
+    elems = 1 << 24
+    unit_ns = unit_ms * 1e6
+    hw = tgo.HwRunner(4, int(max(sizes) * MB), elems)
+    try:
+        xfer = calibrate_transfers(hw, sizes, reps)
+        kern = calibrate_kernel(hw, elems, iters, reps)
+        ov, model = overlap_experiments(hw, sizes[-3:], reps, dev)
+        need = max(build_task(f, unit_ns, xfer, kern, elems)[i]
+                   for f in W.PAPER_TASKS_UNITS.values() for i in (0, 1))
+        if need > int(max(sizes) * MB):
+            hw.close()
+            hw = tgo.HwRunner(4, need, elems)
+        res2 = validate_benchmarks(hw, dev, xfer, kern, model, unit_ns, elems, reps, 2)
+        res1 = validate_benchmarks(hw, dev, xfer, kern, model, unit_ns, elems, reps, 1)
+    finally:
+        hw.close()
+    return {"unit_ms": unit_ms, "reps": reps,
+            "transfers": {k: {kk: v[kk] for kk in ("gb_per_s", "latency_ns")} for k, v in xfer.items()},
+            "kernel": {k: kern[k] for k in ("eta_ns_per_elem_pass", "gamma_ns")},
+            "overlap": {k: ov[k] for k in ("rho_htd", "rho_dth", "model", "errors")},
+            "overlap_records": ov["records"],
+            "two_dma": res2, "one_dma_scheme": res1}
