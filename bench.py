@@ -51,7 +51,7 @@ def parse():
     p.add_argument("--train-pairs", type=float, default=2e7,
                    help="exact (ordering, time) pairs used to train the proposal network")
     p.add_argument("--eval-groups", type=int, default=1024)
-    p.add_argument("--serve-seconds", type=float, default=2.0)
+    p.add_argument("--serve-seconds", type=float, default=10.0)
     p.add_argument("--hw-unit-ms", type=float, default=10.0,
                    help="time unit of the synthetic tasks run on the device (0: skip that validation)")
     p.add_argument("--calibrate-copy", action="store_true",
@@ -327,7 +327,8 @@ def serving_extra(dev, sur, seconds: float):
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
-    warm = arr.t_ns[0] + int(0.25 * seconds * 1e9)
+    warm_s = min(1.0, 0.25 * seconds)  # the first second (or quarter) is warm-up
+    warm = arr.t_ns[0] + int(warm_s * 1e9)
     keep = arr.t_ns >= warm
     lat = (out["t_done_ns"] - out["t_arrive_ns"])[keep] / 1e3
     small = (out["path"] == 0)[keep]
@@ -341,7 +342,7 @@ def serving_extra(dev, sur, seconds: float):
             "p99_us_proposal": float(np.percentile(lat[~small], 99)) if (~small).any() else None,
             "bad_status": int((out["status"] != 0).sum()), "batches": st["batches"],
             "max_queued": st["max_queued"], "max_in_use_bytes": st["max_in_use_bytes"],
-            "latency_window": "arrivals after the first quarter of the trace",
+            "latency_window": f"arrivals after the first {warm_s:g} s of a {seconds:g} s trace",
             "config": {"streams": 4, "max_batch": 256, "max_batch_large": 64, "samples": 4096,
                        "topk": 64, "budget_bytes": 8 << 30}}
 
