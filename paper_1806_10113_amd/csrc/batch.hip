@@ -134,7 +134,9 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
     return x;
 }
 
-template <int DMA>
+// MMAX: deepest per-lane walk compiled in (the plan's largest m); a smaller
+// bound lets the compiler keep fewer level snapshots live, so more waves fit.
+template <int DMA, int MMAX>
 __global__ __launch_bounds__(BT_THREADS) void batch_kernel(const tgo_task *__restrict__ tasks,
                                                            const int32_t *__restrict__ offs, int G,
                                                            Rates r, BatchCfg cfg, GroupAcc *acc,
@@ -143,7 +145,7 @@ __global__ __launch_bounds__(BT_THREADS) void batch_kernel(const tgo_task *__res
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ Quad<uint32_t> Ht[BT_WAVES][MAXN];
     __shared__ DRec<uint32_t> Dt[BT_WAVES][MAXN];
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     View<uint32_t, 1, BT_THREADS> v;
     v.H = Ht[w];
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(BT_THREADS) void batch_kernel(const tgo_task *__res
     for (;;) {
         uint32_t tile = 0;
         if (lane == 0) tile = atomicAdd(&hdr->next_tile, 1u);
-        tile = __shfl(tile, 0);
+        tile = __builtin_amdgcn_readfirstlane(__shfl(tile, 0));  // wave-uniform: keep it scalar
         if (tile >= total) break;
         // group of this tile: largest g with tile_off[g] <= tile
         int lo = 0, hi = G;  // tile_off[lo] <= tile < tile_off[hi]
@@ -188,8 +190,12 @@ __global__ __launch_bounds__(BT_THREADS) void batch_kernel(const tgo_task *__res
                     case 1: run_subtree<1, DMA>(c, v, st, list, u); break;
                     case 2: run_subtree<2, DMA>(c, v, st, list, u); break;
                     case 3: run_subtree<3, DMA>(c, v, st, list, u); break;
-                    case 4: run_subtree<4, DMA>(c, v, st, list, u); break;
-                    default: run_subtree<5, DMA>(c, v, st, list, u); break;
+                    case 4:
+                        if constexpr (MMAX >= 4) run_subtree<4, DMA>(c, v, st, list, u);
+                        break;
+                    default:
+                        if constexpr (MMAX >= 5) run_subtree<5, DMA>(c, v, st, list, u);
+                        break;
                 }
                 const uint64_t r0 = (uint64_t)s * fact_c(m);
                 const unsigned long long a = ((unsigned long long)u.min_t << 32) | (r0 + u.min_l);
@@ -313,14 +319,31 @@ static int enqueue_batch(tgo_plan *p, const BatchCfg &cfg, const tgo_task *d_tas
                          const int32_t *d_offs, int G, tgo_summary *d_out, hipStream_t st) {
     hipLaunchKernelGGL(batch_prepare, dim3(1), dim3(1024), 0, st, d_tasks, d_offs, G, p->r, cfg,
                        p->acc, p->tile_off, p->hdr);
+    int mmax = 1;
+    for (int n = 1; n <= BT_MAX_N; ++n) mmax = std::max(mmax, (int)cfg.m[n]);
+    // no kernel-completion queue with one DMA engine
+    const size_t shm = p->r.one_dma ? 0 : sizeof(Slot<uint32_t>) * BT_THREADS * BT_MAX_N;
+    const dim3 grid(cfg.blocks), block(BT_THREADS);
     if (p->r.one_dma) {
-        // no kernel-completion queue with one DMA engine
-        hipLaunchKernelGGL(batch_kernel<DMA_ONE>, dim3(cfg.blocks), dim3(BT_THREADS), 0, st, d_tasks,
-                           d_offs, G, p->r, cfg, p->acc, p->tile_off, p->hdr);
+        if (mmax <= 3)
+            hipLaunchKernelGGL((batch_kernel<DMA_ONE, 3>), grid, block, shm, st, d_tasks, d_offs, G, p->r, cfg,
+                               p->acc, p->tile_off, p->hdr);
+        else if (mmax == 4)
+            hipLaunchKernelGGL((batch_kernel<DMA_ONE, 4>), grid, block, shm, st, d_tasks, d_offs, G, p->r, cfg,
+                               p->acc, p->tile_off, p->hdr);
+        else
+            hipLaunchKernelGGL((batch_kernel<DMA_ONE, 5>), grid, block, shm, st, d_tasks, d_offs, G, p->r, cfg,
+                               p->acc, p->tile_off, p->hdr);
     } else {
-        const size_t shm = sizeof(Slot<uint32_t>) * BT_THREADS * BT_MAX_N;
-        hipLaunchKernelGGL(batch_kernel<DMA_TWO>, dim3(cfg.blocks), dim3(BT_THREADS), shm, st, d_tasks,
-                           d_offs, G, p->r, cfg, p->acc, p->tile_off, p->hdr);
+        if (mmax <= 3)
+            hipLaunchKernelGGL((batch_kernel<DMA_TWO, 3>), grid, block, shm, st, d_tasks, d_offs, G, p->r, cfg,
+                               p->acc, p->tile_off, p->hdr);
+        else if (mmax == 4)
+            hipLaunchKernelGGL((batch_kernel<DMA_TWO, 4>), grid, block, shm, st, d_tasks, d_offs, G, p->r, cfg,
+                               p->acc, p->tile_off, p->hdr);
+        else
+            hipLaunchKernelGGL((batch_kernel<DMA_TWO, 5>), grid, block, shm, st, d_tasks, d_offs, G, p->r, cfg,
+                               p->acc, p->tile_off, p->hdr);
     }
     hipLaunchKernelGGL(batch_finalize, dim3((G + 255) / 256), dim3(256), 0, st, p->acc, G, d_out);
     int rc = launch_heuristic(p->r, d_tasks, d_offs, G, &d_out[0].heur[0], (int)sizeof(tgo_summary),
@@ -445,6 +468,7 @@ int tgo_plan_autotune(tgo_plan *p, const tgo_task *d_tasks, const int32_t *d_off
         for (int mult : {1, 2, 4})
             for (int bpc : {4, 8}) {
                 BatchCfg c = default_cfg(p->cus);
+                for (int n = 1; n <= BT_MAX_N; ++n) c.m[n] = (int8_t)std::min((int)c.m[n], mbig);
                 for (int n = 8; n <= BT_MAX_N; ++n) c.m[n] = (int8_t)std::min(n, mbig);
                 c.lane_mult = mult;
                 c.blocks = p->cus * bpc;
