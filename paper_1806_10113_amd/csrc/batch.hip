@@ -464,7 +464,7 @@ int tgo_plan_autotune(tgo_plan *p, const tgo_task *d_tasks, const int32_t *d_off
     TGO_HIP(hipEventCreate(&e0));
     TGO_HIP(hipEventCreate(&e1));
     std::vector<BatchCfg> cands;
-    for (int mbig = 3; mbig <= BT_MAX_M; ++mbig)
+    for (int mbig = 4; mbig <= BT_MAX_M; ++mbig)
         for (int mult : {1, 2, 4})
             for (int bpc : {4, 8}) {
                 BatchCfg c = default_cfg(p->cus);
