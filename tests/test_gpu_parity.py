@@ -244,3 +244,48 @@ def test_heuristic_hand_cases_and_paper_benchmarks(dev):
         assert list(orders[i, :len(c["order"])]) == c["order"]
     for i, g in enumerate(groups):
         assert list(orders[i, :len(g)]) == M.heuristic(g, M.NO_SLOWDOWN)
+
+
+def johnson_makespan(a, b):
+    """Johnson's rule for the two-machine flow shop (a first, then b)."""
+    first = sorted([i for i in range(len(a)) if a[i] <= b[i]], key=lambda i: a[i])
+    last = sorted([i for i in range(len(a)) if a[i] > b[i]], key=lambda i: -b[i])
+    t1 = t2 = 0
+    for i in first + last:
+        t1 += a[i]
+        t2 = max(t1, t2) + b[i]
+    return t2
+
+
+def test_exhaustive_n13_largest_group(dev):
+    """N = 13, the largest group enumerated (6,227,020,800 orderings, ranks
+    beyond 32 bits), checked through closed forms that hold at any size."""
+    from paper_1806_10113_amd import tgo
+    n, R = 13, math.factorial(13)
+    rng = np.random.default_rng(106)
+    # identical tasks: every ordering ties
+    same = np.array([[300_000, 900_000, 200_000]] * n, dtype=np.int64)
+    s = tgo.read_summary(tgo.exhaustive(to_dev(same, dev))[0])
+    T = M.simulate(same, list(range(n)), M.DEFAULT)
+    assert s["status"] == 0 and s["count"] == R
+    assert s["min_ns"] == T and s["max_ns"] == T and s["argmin_rank"] == 0 and s["argmax_rank"] == 0
+    assert s["sum"] == T * R and s["fingerprint"] == (T * R * R) % (1 << 64)
+    # full-speed transfers and no HtD work: Johnson's two-machine flow shop
+    t = rng.integers(0, 2_000_000, size=(n, 3)).astype(np.int64)
+    t[:, 0] = 0
+    s = tgo.read_summary(tgo.exhaustive(to_dev(t, dev), tmodel(M.NO_SLOWDOWN))[0])
+    assert s["min_ns"] == johnson_makespan(t[:, 1].tolist(), t[:, 2].tolist())
+    # a general group under the default model: the reported extremes are
+    # reproduced by their orderings, and sampled orderings lie between them
+    t = W.single_group_mixed(n, 7)
+    s = tgo.read_summary(tgo.exhaustive(to_dev(t, dev))[0])
+    assert s["status"] == 0 and s["count"] == R
+    assert cmodel.simulate(t, s["best"], M.DEFAULT) == s["min_ns"]
+    assert cmodel.simulate(t, s["worst"], M.DEFAULT) == s["max_ns"]
+    assert s["argmin_rank"] == M.lehmer_rank(s["best"]) and s["argmax_rank"] == M.lehmer_rank(s["worst"])
+    assert s["min_ns"] <= s["mean_ns"] <= s["max_ns"]
+    ranks = rng.integers(0, R, size=3000)
+    orders = np.array([M.nth_permutation(n, int(r)) for r in ranks], dtype=np.uint8)
+    got = tgo.evaluate(to_dev(t, dev), to_dev(orders, dev)).cpu().numpy()
+    assert np.array_equal(got, cmodel.eval_orders(t, orders, M.DEFAULT))
+    assert (got >= s["min_ns"]).all() and (got <= s["max_ns"]).all()

@@ -92,6 +92,24 @@ def test_every_ordering_small_shapes(dev, T, R):
             check_heuristic(s, groups, tasks.tolist(), T, R, m)
 
 
+@pytest.mark.parametrize("T,R", [(4, 3), (5, 2), (3, 4)])
+def test_every_ordering_many_tiles(dev, T, R):
+    """13,824 / 14,400 / 1,296 orderings: many 256-lane blocks and a ragged
+    last one, every ordering against the oracle."""
+    from paper_1806_10113_amd import tgo
+    rng = np.random.default_rng(650 + 10 * T + R)
+    tasks = rng.integers(0, 5_000_000, size=(T * R, 3)).astype(np.int64)
+    for m in (M.DEFAULT, M.Model(4, 3, 3, 1)):
+        ref = RD.noreorder_summary([tuple(t) for t in tasks.tolist()], T, R, m)
+        summ, po, groups = tgo.rounds(to_dev(tasks, dev), T, R, tmodel(m), per_order=True)
+        s = tgo.read_summary(summ)
+        assert np.array_equal(po.cpu().numpy(), np.asarray(ref["times"])), (T, R, m)
+        for k in ("min_ns", "argmin_rank", "max_ns", "argmax_rank", "fingerprint"):
+            assert int(s[k]) == int(ref[k]), k
+        assert s["sum"] == ref["sum"]
+        check_heuristic(s, groups, tasks.tolist(), T, R, m)
+
+
 @pytest.mark.parametrize("T,R", [(4, 4), (6, 2), (8, 1), (4, 2)])
 def test_paper_shapes_sampled(dev, T, R):
     """The shapes of Section 6.2 (T = 4, 6, 8 workers; 1, 2, 4 dependent tasks)
