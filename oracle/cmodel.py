@@ -53,6 +53,13 @@ def lib():
         L.oracle_eval_orders.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
                                          ctypes.c_void_p]
+        L.oracle_rounds_simulate.restype = ctypes.c_int64
+        L.oracle_rounds_simulate.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.oracle_rounds_times.restype = ctypes.c_int
+        L.oracle_rounds_times.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -105,4 +112,17 @@ def exhaustive(tasks, model: Model = DEFAULT, lo: int = 0, hi: int | None = None
            "fingerprint": s.fingerprint, "threads": threads}
     if po is not None:
         out["times"] = po
+    return out
+
+
+def rounds_times(tasks, T: int, R: int, model: Model = DEFAULT, threads: int | None = None) -> np.ndarray:
+    """NoReorder T of every ordering of T workers x R dependent tasks, by rank
+    (C transcription of oracle/rounds.py)."""
+    import math
+    t = _tasks(tasks)
+    assert len(t) == T * R
+    out = np.empty(math.factorial(T) ** R, dtype=np.int64)
+    rc = lib().oracle_rounds_times(t.ctypes.data, T, R, model.q, model.p_htd, model.p_dth,
+                                   model.dma_engines, threads or default_threads(), out.ctypes.data)
+    assert rc == 0
     return out

@@ -245,3 +245,130 @@ int oracle_eval_orders(const int64_t *tasks, int n, int q, int p_htd, int p_dth,
     }
     return 0;
 }
+
+/* ---------------------------------------------------------------------------
+ * Workers with dependent tasks (oracle/rounds.py, NoReorder setup): task
+ * (w, r) at index w * R + r; seq holds the T * R task indices in launch order,
+ * round by round.  The HtD of (w, r) is ready once the DtH of (w, r - 1) has
+ * ended.  Two DMA engines: three FIFO queues in seq order.  One DMA engine:
+ * the transfer queue holds, per round, that round's HtDs then its DtHs.
+ */
+int64_t oracle_rounds_simulate(const int64_t *tasks, int T, int R, const int *seq, int q, int p_htd,
+                               int p_dth, int dma) {
+    int n = T * R;
+    int neng = dma == 2 ? 3 : 2;
+    int qkind[3][2 * OMAXN], qtask[3][2 * OMAXN], qlen[3] = {0, 0, 0}, qhead[3] = {0, 0, 0};
+    int run_kind[3] = {-1, -1, -1}, run_task[3] = {-1, -1, -1};
+    int64_t left[3] = {0, 0, 0}, rate[3], est[3];
+    unsigned char done[3][OMAXN];
+    memset(done, 0, sizeof(done));
+    if (dma == 2) {
+        for (int j = 0; j < n; ++j)
+            for (int e = 0; e < 3; ++e) { qkind[e][qlen[e]] = e; qtask[e][qlen[e]++] = seq[j]; }
+    } else {
+        for (int r = 0; r < R; ++r) {
+            for (int i = 0; i < T; ++i) { qkind[0][qlen[0]] = K_HTD; qtask[0][qlen[0]++] = seq[r * T + i]; }
+            for (int i = 0; i < T; ++i) { qkind[0][qlen[0]] = K_DTH; qtask[0][qlen[0]++] = seq[r * T + i]; }
+        }
+        for (int j = 0; j < n; ++j) { qkind[1][qlen[1]] = K_KER; qtask[1][qlen[1]++] = seq[j]; }
+    }
+    int64_t t = 0, total = 0;
+    for (;;) {
+        int changed = 1;
+        while (changed) {
+            changed = 0;
+            for (int e = 0; e < neng; ++e) {
+                if (run_kind[e] >= 0 && left[e] == 0) {
+                    done[run_kind[e]][run_task[e]] = 1;
+                    if (t > total) total = t;
+                    run_kind[e] = -1;
+                    changed = 1;
+                }
+            }
+            for (int e = 0; e < neng; ++e) {
+                if (run_kind[e] >= 0 || qhead[e] >= qlen[e]) continue;
+                int k = qkind[e][qhead[e]], x = qtask[e][qhead[e]];
+                int ready = k == K_HTD ? (x % R == 0 || done[K_DTH][x - 1])
+                          : k == K_KER ? done[K_HTD][x] : done[K_KER][x];
+                if (!ready) continue;
+                qhead[e]++;
+                run_kind[e] = k;
+                run_task[e] = x;
+                left[e] = tasks[x * 3 + k] * (k == K_KER ? 1 : q);
+                changed = 1;
+            }
+        }
+        int busy = 0, hbusy = 0, dbusy = 0;
+        for (int e = 0; e < neng; ++e) {
+            if (run_kind[e] < 0) continue;
+            busy = 1;
+            if (run_kind[e] == K_HTD) hbusy = 1;
+            if (run_kind[e] == K_DTH) dbusy = 1;
+        }
+        if (!busy) break;
+        int64_t delta = INT64_MAX;
+        for (int e = 0; e < neng; ++e) {
+            if (run_kind[e] < 0) continue;
+            int k = run_kind[e];
+            rate[e] = k == K_KER ? 1 : (hbusy && dbusy ? (k == K_HTD ? p_htd : p_dth) : q);
+            est[e] = ceil_div(left[e], rate[e]);
+            if (est[e] < delta) delta = est[e];
+        }
+        t += delta;
+        for (int e = 0; e < neng; ++e) {
+            if (run_kind[e] < 0) continue;
+            left[e] = est[e] == delta ? 0 : left[e] - rate[e] * delta;
+        }
+    }
+    return total;
+}
+
+typedef struct {
+    const int64_t *tasks;
+    int T, R, q, p_htd, p_dth, dma;
+    uint64_t lo, hi;
+    int64_t *out;
+} rjob_t;
+
+static void *rounds_worker(void *arg) {
+    rjob_t *j = (rjob_t *)arg;
+    uint64_t tf = 1;
+    for (int i = 2; i <= j->T; ++i) tf *= (uint64_t)i;
+    int seq[OMAXN];
+    for (uint64_t rk = j->lo; rk < j->hi; ++rk) {
+        uint64_t rem = rk;
+        for (int r = j->R - 1; r >= 0; --r) {
+            int perm[OMAXN];
+            decode_rank(j->T, rem % tf, perm);
+            rem /= tf;
+            for (int i = 0; i < j->T; ++i) seq[r * j->T + i] = perm[i] * j->R + r;
+        }
+        j->out[rk] = oracle_rounds_simulate(j->tasks, j->T, j->R, seq, j->q, j->p_htd, j->p_dth, j->dma);
+    }
+    return NULL;
+}
+
+/* T of every NoReorder ordering, out[rank] (rank: mixed radix T!, round 0
+ * most significant), on nthreads threads. */
+int oracle_rounds_times(const int64_t *tasks, int T, int R, int q, int p_htd, int p_dth, int dma,
+                        int nthreads, int64_t *out) {
+    if (T < 1 || R < 1 || T * R > OMAXN || nthreads < 1) return -1;
+    uint64_t tf = 1, count = 1;
+    for (int i = 2; i <= T; ++i) tf *= (uint64_t)i;
+    for (int r = 0; r < R; ++r) count *= tf;
+    rjob_t *jobs = (rjob_t *)calloc((size_t)nthreads, sizeof(rjob_t));
+    pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    uint64_t per = (count + (uint64_t)nthreads - 1) / (uint64_t)nthreads;
+    for (int i = 0; i < nthreads; ++i) {
+        rjob_t *j = &jobs[i];
+        j->tasks = tasks; j->T = T; j->R = R; j->q = q; j->p_htd = p_htd; j->p_dth = p_dth; j->dma = dma;
+        j->lo = (uint64_t)i * per < count ? (uint64_t)i * per : count;
+        j->hi = j->lo + per < count ? j->lo + per : count;
+        j->out = out;
+        pthread_create(&th[i], NULL, rounds_worker, j);
+    }
+    for (int i = 0; i < nthreads; ++i) pthread_join(th[i], NULL);
+    free(jobs);
+    free(th);
+    return 0;
+}

@@ -8,6 +8,7 @@ import os
 import numpy as np
 import pytest
 
+from oracle import cmodel
 from oracle import model as M
 from oracle import rounds as RD
 from paper_1806_10113_amd import workloads as W
@@ -113,8 +114,10 @@ def test_every_ordering_many_tiles(dev, T, R):
 @pytest.mark.parametrize("T,R", [(4, 4), (6, 2), (8, 1), (4, 2)])
 def test_paper_shapes_sampled(dev, T, R):
     """The shapes of Section 6.2 (T = 4, 6, 8 workers; 1, 2, 4 dependent tasks)
-    on benchmark tasks: sampled orderings one by one, the extremes reproduced
-    by their launch sequences, and the Heuristic setup exactly."""
+    on benchmark tasks: every ordering against the C transcription of the
+    oracle, sampled orderings against the Python oracle one by one, the
+    extremes reproduced by their launch sequences, and the Heuristic setup
+    exactly."""
     from paper_1806_10113_amd import tgo
     count = math.factorial(T) ** R
     rng = np.random.default_rng(700 + T)
@@ -126,6 +129,7 @@ def test_paper_shapes_sampled(dev, T, R):
             s = tgo.read_summary(summ)
             got = po.cpu().numpy()
             assert s["status"] == 0 and s["count"] == count
+            assert np.array_equal(got, cmodel.rounds_times(tasks, T, R, m)), (bk, m)
             for rk in rng.integers(0, count, size=40):
                 want = RD.simulate(tl, T, R, m, perms=RD.unrank(T, R, int(rk)))
                 assert int(got[rk]) == want, (bk, m, int(rk))

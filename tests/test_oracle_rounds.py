@@ -8,6 +8,7 @@ import os
 
 import numpy as np
 
+from oracle import cmodel
 from oracle import model as M
 from oracle import rounds as RD
 
@@ -173,3 +174,17 @@ def test_integer_mode_within_rounding_bound_of_exact():
             Ti = RD.simulate(tasks, T, R, m, perms=perms)
             Te = RD.simulate(tasks, T, R, m, perms=perms, exact=True)
             assert abs(Ti - Te) <= 3 * T * R * math.ceil(m.q / min(m.p_htd, m.p_dth))
+
+
+def test_c_transcription_matches():
+    rng = np.random.default_rng(47)
+    for _ in range(25):
+        T = int(rng.integers(1, 5))
+        R = int(rng.integers(1, 4))
+        if math.factorial(T) ** R > 2000:
+            continue
+        tasks = rand_tasks(rng, T * R, 0, 200)
+        for m in MODELS:
+            want = RD.noreorder_times(tasks, T, R, m)
+            got = cmodel.rounds_times(tasks, T, R, m, threads=3)
+            assert list(got) == want, (T, R, m)
