@@ -193,17 +193,14 @@ __global__ void group_features_kernel(const tgo_task *__restrict__ tasks, const 
     }
 }
 
-// Rows of the first-layer input (bf16 [rows][64]): either given orderings
-// (orders != null: row i uses orders[i] and gid[i]) or sampled ones (row
-// row0 + i is sample (row mod spad) of group (row div spad); samples >= S are
-// padding rows, flagged in `valid`).
-__global__ void features_kernel(const float *__restrict__ F, const int32_t *__restrict__ offs,
-                                const uint32_t *__restrict__ gkeys,
-                                const uint8_t *__restrict__ orders, const int32_t *__restrict__ gid,
-                                int64_t row0, int64_t rows, int64_t spad, int64_t S, uint64_t seed,
-                                uint16_t *X, uint16_t *Xt, int64_t xt_rows, uint8_t *valid) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rows) return;
+// First-layer input of one row as 32 words of packed bf16 pairs (48
+// features + 16 zeros): the ordering is orders[i] (orders != null, group
+// gid[i]) or sample (row mod spad) of group (row div spad) for row = row0 + i
+// (samples >= S are padding: *ok = false, all-zero input).
+__device__ __forceinline__ void row_input(const float *__restrict__ F, const int32_t *__restrict__ offs,
+                                          const uint32_t *__restrict__ gkeys, const uint8_t *__restrict__ orders,
+                                          const int32_t *__restrict__ gid, int64_t i, int64_t row0, int64_t spad,
+                                          int64_t S, uint64_t seed, uint32_t (&w)[SG_K0 / 2], bool *okp) {
     int g;
     uint64_t perm;
     int n;
@@ -221,8 +218,6 @@ __global__ void features_kernel(const float *__restrict__ F, const int32_t *__re
         ok = s < S && n >= 1 && n <= SG_POS;
         perm = ok ? sample_ordering(n, gkeys ? gkeys[g] : (uint32_t)g, (uint64_t)s, seed) : 0;
     }
-    // 48 features + 16 zeros as 32 packed bf16 pairs; every index static
-    uint32_t w[SG_K0 / 2];
 #pragma unroll
     for (int c = 0; c < SG_K0 / 2; ++c) w[c] = 0;
     const float *Fg = F + (int64_t)g * SG_POS * 3;
@@ -242,6 +237,21 @@ __global__ void features_kernel(const float *__restrict__ F, const int32_t *__re
             }
         }
     }
+    *okp = ok;
+}
+
+// Rows of the first-layer input (bf16 [rows][64]), see row_input; padding
+// rows are flagged in `valid`.
+__global__ void features_kernel(const float *__restrict__ F, const int32_t *__restrict__ offs,
+                                const uint32_t *__restrict__ gkeys,
+                                const uint8_t *__restrict__ orders, const int32_t *__restrict__ gid,
+                                int64_t row0, int64_t rows, int64_t spad, int64_t S, uint64_t seed,
+                                uint16_t *X, uint16_t *Xt, int64_t xt_rows, uint8_t *valid) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    uint32_t w[SG_K0 / 2];
+    bool ok;
+    row_input(F, offs, gkeys, orders, gid, i, row0, spad, S, seed, w, &ok);
     uint4 *dst = reinterpret_cast<uint4 *>(X + i * SG_K0);
 #pragma unroll
     for (int c = 0; c < SG_K0 / 8; ++c) {
@@ -467,6 +477,165 @@ __global__ void head_kernel(const uint16_t *__restrict__ H3, const float *__rest
     if (l == 0) score[row] = (valid && !valid[row]) ? INFINITY : s + b4[0];
 }
 
+// float -> uint32 with the same order (top-k keys compare as integers)
+__device__ __forceinline__ uint32_t orderable(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// --------------------------------------------------------- fused inference
+// One block scores 64 rows end to end: it builds their first-layer inputs in
+// LDS, runs the three hidden layers on MFMA with the activations kept in LDS
+// (rounded to bf16, as the layer-by-layer path stores them) and applies the
+// head, so only the 64 scores (or top-k keys) leave the block.  Each of the
+// 8 waves computes 32 output columns of each layer for all 64 rows as 4 x 2
+// MFMA tiles; weights (bf16 [out][in]) come from global memory, where every
+// block reads the same 282 KB.
+constexpr int FM_ROWS = 64;
+constexpr int FM_LD = SG_H + 8;        // LDS row pitch in bf16
+constexpr int FM_WAVES = 8;            // wave w owns output columns FM_CT * 16 * w ..
+constexpr int FM_CT = SG_H / 16 / FM_WAVES;  // column tiles per wave
+constexpr int FM_THREADS = 64 * FM_WAVES;
+
+template <int K>
+__device__ __forceinline__ void fm_layer(const uint16_t (*Hs)[FM_LD], const uint16_t *__restrict__ W, int w, int l,
+                                         f32x4 (&acc)[4][FM_CT]) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < FM_CT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t *wrow = W + (int64_t)(16 * FM_CT * w + (l & 15)) * K + (l >> 4) * 8;
+    bf16x8 fb[FM_CT], nb[FM_CT];
+#pragma unroll
+    for (int t = 0; t < FM_CT; ++t) fb[t] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * t * K);
+#pragma unroll 1
+    for (int k0 = 0; k0 < K; k0 += GK) {
+        if (k0 + GK < K) {
+#pragma unroll
+            for (int t = 0; t < FM_CT; ++t)
+                nb[t] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * t * K + k0 + GK);
+        }
+        bf16x8 fa[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            fa[t] = *reinterpret_cast<const bf16x8 *>(&Hs[16 * t + (l & 15)][k0 + (l >> 4) * 8]);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < FM_CT; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < FM_CT; ++t) fb[t] = nb[t];
+    }
+}
+
+// relu(acc + bias) as bf16 into Hs (lane l holds rows 16a + 4(l/16) + i of
+// column 16 (FM_CT w + b) + l%16)
+__device__ __forceinline__ void fm_store(uint16_t (*Hs)[FM_LD], const float *__restrict__ bias, int w, int l,
+                                         const f32x4 (&acc)[4][FM_CT]) {
+#pragma unroll
+    for (int b = 0; b < FM_CT; ++b) {
+        const int col = 16 * (FM_CT * w + b) + (l & 15);
+        const float bb = bias[col];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float v = acc[a][b][i] + bb;
+                Hs[16 * a + 4 * (l >> 4) + i][col] = f2bf(v > 0.f ? v : 0.f);
+            }
+    }
+}
+
+// Rows are chosen as in features_kernel.  Output: score[i] (keys == null) or
+// the top-k key of row i (keys != null: orderable score bits << 32 | sample
+// index, ~0 for padding rows).
+__global__ __launch_bounds__(FM_THREADS) void mlp_fused_kernel(const float *__restrict__ F,
+                                                               const int32_t *__restrict__ offs,
+                                                               const uint32_t *__restrict__ gkeys,
+                                                               const uint8_t *__restrict__ orders,
+                                                               const int32_t *__restrict__ gid, int64_t row0,
+                                                               int64_t rows, int64_t spad, int64_t S, uint64_t seed,
+                                                               const uint16_t *__restrict__ W1,
+                                                               const uint16_t *__restrict__ W2,
+                                                               const uint16_t *__restrict__ W3,
+                                                               const float *__restrict__ p, float *score,
+                                                               unsigned long long *keys) {
+    __shared__ __align__(16) uint16_t Hs[FM_ROWS][FM_LD];
+    __shared__ float part[FM_WAVES][FM_ROWS];
+    __shared__ uint8_t okrow[FM_ROWS];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int64_t base = (int64_t)blockIdx.x * FM_ROWS;
+    if (tid < FM_ROWS) {
+        const int64_t i = base + tid;
+        uint32_t x[SG_K0 / 2];
+        bool ok = false;
+        if (i < rows) {
+            row_input(F, offs, gkeys, orders, gid, i, row0, spad, S, seed, x, &ok);
+        } else {
+#pragma unroll
+            for (int c = 0; c < SG_K0 / 2; ++c) x[c] = 0;
+        }
+        okrow[tid] = ok ? 1 : 0;
+        uint4 *dst = reinterpret_cast<uint4 *>(&Hs[tid][0]);
+#pragma unroll
+        for (int c = 0; c < SG_K0 / 8; ++c) dst[c] = uint4{x[4 * c], x[4 * c + 1], x[4 * c + 2], x[4 * c + 3]};
+    }
+    __syncthreads();
+    f32x4 acc[4][FM_CT];
+    fm_layer<SG_K0>(Hs, W1, w, l, acc);
+    __syncthreads();
+    fm_store(Hs, p + SG_OFF_B1, w, l, acc);
+    __syncthreads();
+    fm_layer<SG_H>(Hs, W2, w, l, acc);
+    __syncthreads();
+    fm_store(Hs, p + SG_OFF_B2, w, l, acc);
+    __syncthreads();
+    fm_layer<SG_H>(Hs, W3, w, l, acc);
+    // head on the bf16-rounded third layer: per-row partial sums over this
+    // wave's columns, reduced across the 16 lanes that share rows
+    float sum[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sum[a][i] = 0.f;
+#pragma unroll
+    for (int b = 0; b < FM_CT; ++b) {
+        const int col = 16 * (FM_CT * w + b) + (l & 15);
+        const float bb = p[SG_OFF_B3 + col], w4 = p[SG_OFF_W4 + col];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float v = acc[a][b][i] + bb;
+                sum[a][i] += bf2f(f2bf(v > 0.f ? v : 0.f)) * w4;
+            }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float v = sum[a][i];
+            for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m);
+            if ((l & 15) == 0) part[w][16 * a + 4 * (l >> 4) + i] = v;
+        }
+    __syncthreads();
+    if (tid < FM_ROWS) {
+        const int64_t i = base + tid;
+        if (i < rows) {
+            float sc = p[SG_OFF_B4];
+#pragma unroll
+            for (int v = 0; v < FM_WAVES; ++v) sc += part[v][tid];
+            if (keys) {
+                const int64_t smp = (row0 + i) % spad;
+                keys[i] = okrow[tid] ? (((unsigned long long)orderable(sc) << 32) | (uint64_t)smp) : ~0ull;
+            } else {
+                score[i] = okrow[tid] ? sc : INFINITY;
+            }
+        }
+    }
+}
+
 // targets y = T / LB - 1 (LB: largest machine lower bound of the group)
 __global__ void target_kernel(const tgo_task *__restrict__ tasks, const int32_t *__restrict__ offs,
                               const int32_t *__restrict__ gid, const int64_t *__restrict__ T, int rows,
@@ -622,20 +791,6 @@ __global__ void init_params_kernel(float *p, uint64_t seed) {
 // Keys (orderable score bits << 32 | sample index) per group; each pass keeps
 // the 64 smallest of every run of 1024 keys (bitonic sort in LDS).
 
-__device__ __forceinline__ uint32_t orderable(float f) {
-    const uint32_t u = __float_as_uint(f);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
-// keys from scores of sampled rows: row r of the chunk is sample (row0 + r) mod spad
-__global__ void score_keys_kernel(const float *__restrict__ score, int64_t row0, int64_t rows, int64_t spad,
-                                  unsigned long long *keys) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rows) return;
-    const int64_t s = (row0 + i) % spad;
-    const float f = score[i];
-    keys[i] = isinf(f) ? ~0ull : (((unsigned long long)orderable(f) << 32) | (uint64_t)s);
-}
 
 constexpr int TK_RUN = 1024;
 constexpr int TK_THREADS = 256;
@@ -916,13 +1071,11 @@ int tgo_surrogate_score(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t
     if (rows < 1 || rows > s->max_rows || !d_orders || !d_gid || !d_scores)
         return fail(TGO_EINVAL, "rows out of range or NULL buffer");
     hipStream_t st = (hipStream_t)stream;
-    rc = given_features(s, d_tasks, d_offs, G, d_orders, d_gid, rows, false, st);
-    if (rc) return rc;
-    const int64_t pad = (rows + 63) / 64 * 64;
-    rc = sur_forward(s, pad, false, st);
-    if (rc) return rc;
-    hipLaunchKernelGGL(head_kernel, dim3((unsigned)((rows * 64 + 255) / 256)), dim3(256), 0, st, s->H3,
-                       s->p + SG_OFF_W4, s->p + SG_OFF_B4, rows, (const uint8_t *)nullptr, d_scores);
+    hipLaunchKernelGGL(group_features_kernel, dim3((G * SG_POS + 255) / 256), dim3(256), 0, st, d_tasks, d_offs,
+                       G, s->F);
+    hipLaunchKernelGGL(mlp_fused_kernel, dim3((unsigned)((rows + FM_ROWS - 1) / FM_ROWS)), dim3(FM_THREADS), 0, st, s->F,
+                       d_offs, (const uint32_t *)nullptr, d_orders, d_gid, (int64_t)0, rows, (int64_t)1, (int64_t)1,
+                       (uint64_t)0, s->W1, s->W2, s->W3, s->p, d_scores, (unsigned long long *)nullptr);
     TGO_HIP(hipGetLastError());
     return TGO_OK;
 }
@@ -1053,15 +1206,10 @@ int tgo_surrogate_search(tgo_surrogate *s, const tgo_model *model, const tgo_tas
     const int64_t total = (int64_t)G * spad;
     for (int64_t row0 = 0; row0 < total; row0 += chunk) {
         const int64_t rows = std::min(chunk, total - row0);
-        hipLaunchKernelGGL(features_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, s->F, d_offs,
-                           d_keys, (const uint8_t *)nullptr, (const int32_t *)nullptr, row0, rows, spad, samples, seed,
-                           s->X, (uint16_t *)nullptr, rows, s->valid);
-        rc = sur_forward(s, rows, false, st);
-        if (rc) return rc;
-        hipLaunchKernelGGL(head_kernel, dim3((unsigned)((rows * 64 + 255) / 256)), dim3(256), 0, st, s->H3,
-                           s->p + SG_OFF_W4, s->p + SG_OFF_B4, rows, s->valid, s->score);
-        hipLaunchKernelGGL(score_keys_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, s->score,
-                           row0, rows, spad, s->keys);
+        // rows is a multiple of TK_RUN, hence of FM_ROWS
+        hipLaunchKernelGGL(mlp_fused_kernel, dim3((unsigned)(rows / FM_ROWS)), dim3(FM_THREADS), 0, st, s->F, d_offs, d_keys,
+                           (const uint8_t *)nullptr, (const int32_t *)nullptr, row0, rows, spad, samples, seed, s->W1,
+                           s->W2, s->W3, s->p, (float *)nullptr, s->keys);
         const int nrun = (int)(rows / TK_RUN);
         hipLaunchKernelGGL(topk_pass_kernel, dim3(nrun, 1), dim3(TK_THREADS), 0, st, s->keys, (int64_t)0, rows, nrun,
                            s->cand[0] + (row0 / TK_RUN) * TK_KEEP, (int64_t)0);
