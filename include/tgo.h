@@ -113,6 +113,18 @@ int tgo_evaluate(const tgo_model *model, const tgo_task *d_tasks, int n, const u
                  int64_t m, int64_t *d_out, tgo_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * tgo_predict -- one ordering from host buffers (Section 4's prediction for a
+ * given ordering), computed on the current device: the call allocates a
+ * small device buffer and a stream of its own, runs the evaluation kernel,
+ * waits, and frees them.  *out_ns = T in ns.  Returns TGO_EINVAL for a bad
+ * model, n outside 1..TGO_MAX_N or an h_order that is not a permutation,
+ * TGO_ERANGE for durations outside [0, 2^40), TGO_EDEVICE on a HIP error.
+ * Blocking; for many orderings use tgo_evaluate.
+ */
+int tgo_predict(const tgo_model *model, const tgo_task *h_tasks, int n, const uint8_t *h_order,
+                int64_t *out_ns);
+
+/* ---------------------------------------------------------------------------
  * tgo_exhaustive -- every ordering of one group (the brute force that Section 1
  * and Section 5.1 call infeasible at runtime), reduced to best / worst / mean.
  *   d_tasks     : n tasks, 1 <= n <= TGO_MAX_EXHAUSTIVE_N.
@@ -217,6 +229,12 @@ int tgo_surrogate_init(tgo_surrogate *s, uint64_t seed, tgo_stream stream);
 /* Host float32 parameters in (set; resets Adam) and out (get); both synchronize. */
 int tgo_surrogate_set_params(tgo_surrogate *s, const float *h_params, tgo_stream stream);
 int tgo_surrogate_get_params(tgo_surrogate *s, float *h_params, tgo_stream stream);
+/* Parameters to / from a file: 8-byte magic "TGOSURR1", uint32 count
+ * (TGO_SURROGATE_PARAMS), uint32 0, then the float32 masters little-endian.
+ * Load rejects a wrong magic, count, length or a non-finite value
+ * (TGO_EINVAL) and resets the optimizer state like set_params.  Blocking. */
+int tgo_surrogate_save(tgo_surrogate *s, const char *path);
+int tgo_surrogate_load(tgo_surrogate *s, const char *path);
 /* Training pairs: per_group (multiple of 64) sampled orderings of every group,
  * d_orders [G*per_group][16] (0xff past n), d_gid, exact d_T (or the group's
  * negative status). d_status [G]. */

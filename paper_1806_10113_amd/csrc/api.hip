@@ -145,6 +145,37 @@ int tgo_rounds(const tgo_model *model, const tgo_task *d_tasks, int workers, int
                          (hipStream_t)stream);
 }
 
+int tgo_predict(const tgo_model *model, const tgo_task *h_tasks, int n, const uint8_t *h_order,
+                int64_t *out_ns) {
+    Rates r;
+    int rc = make_rates(model, &r);
+    if (rc) return rc;
+    if (n < 1 || n > TGO_MAX_N) return fail(TGO_EINVAL, "n must be in 1..16");
+    if (!h_tasks || !h_order || !out_ns) return fail(TGO_EINVAL, "NULL argument");
+    // a buffer of its own (no shared workspace): tasks, ordering, result
+    const size_t tb = sizeof(tgo_task) * (size_t)n;
+    char *d = nullptr;
+    TGO_HIP(hipMalloc((void **)&d, tb + 256 + 16 + 8));
+    tgo_task *dt = (tgo_task *)d;
+    uint8_t *dord = (uint8_t *)(d + tb);
+    int64_t *dout = (int64_t *)(d + tb + 256);
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMemcpyAsync(dt, h_tasks, tb, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dord, h_order, (size_t)n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        rc = launch_evaluate(r, dt, n, dord, 1, dout, st);
+        if (rc == TGO_OK) e = hipMemcpyAsync(out_ns, dout, 8, hipMemcpyDeviceToHost, st);
+    }
+    if (e == hipSuccess && rc == TGO_OK) e = hipStreamSynchronize(st);
+    if (st) (void)hipStreamDestroy(st);
+    (void)hipFree(d);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "tgo_predict");
+    if (*out_ns < 0) return fail((int)*out_ns, "invalid ordering or tasks out of range");
+    return TGO_OK;
+}
+
 int tgo_rank(int n, const uint8_t *h_order, uint64_t *rank) {
     if (n < 1 || n > TGO_MAX_N || !h_order || !rank) return fail(TGO_EINVAL, "bad argument");
     uint32_t seen = 0;

@@ -11,6 +11,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include <cmath>
 #include <cstdlib>
 #include <string>
 #include <vector>
@@ -1016,6 +1020,44 @@ int tgo_surrogate_get_params(tgo_surrogate *s, float *h_params, tgo_stream strea
     TGO_HIP(hipMemcpyAsync(h_params, s->p, 4 * SG_NPARAM, hipMemcpyDeviceToHost, st));
     TGO_HIP(hipStreamSynchronize(st));
     return TGO_OK;
+}
+
+// File: 8-byte magic, uint32 parameter count, uint32 zero, float32 masters
+// (little-endian, the layout of tgo_surrogate_get_params).
+static const char SG_MAGIC[8] = {'T', 'G', 'O', 'S', 'U', 'R', 'R', '1'};
+
+int tgo_surrogate_save(tgo_surrogate *s, const char *path) {
+    if (!s || !path) return fail(TGO_EINVAL, "bad argument");
+    std::vector<float> h(SG_NPARAM);
+    int rc = tgo_surrogate_get_params(s, h.data(), nullptr);
+    if (rc) return rc;
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(TGO_EINVAL, std::string("cannot open ") + path);
+    const uint32_t hdr[2] = {(uint32_t)SG_NPARAM, 0u};
+    const bool ok = std::fwrite(SG_MAGIC, 1, 8, f) == 8 && std::fwrite(hdr, 4, 2, f) == 2 &&
+                    std::fwrite(h.data(), 4, SG_NPARAM, f) == (size_t)SG_NPARAM;
+    const bool closed = std::fclose(f) == 0;
+    if (!ok || !closed) return fail(TGO_EINVAL, std::string("write failed: ") + path);
+    return TGO_OK;
+}
+
+int tgo_surrogate_load(tgo_surrogate *s, const char *path) {
+    if (!s || !path) return fail(TGO_EINVAL, "bad argument");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(TGO_EINVAL, std::string("cannot open ") + path);
+    char magic[8];
+    uint32_t hdr[2];
+    std::vector<float> h(SG_NPARAM);
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, SG_MAGIC, 8) == 0 &&
+              std::fread(hdr, 4, 2, f) == 2 && hdr[0] == (uint32_t)SG_NPARAM &&
+              std::fread(h.data(), 4, SG_NPARAM, f) == (size_t)SG_NPARAM;
+    char extra;
+    ok = ok && std::fread(&extra, 1, 1, f) == 0;  // nothing after the parameters
+    std::fclose(f);
+    if (!ok) return fail(TGO_EINVAL, std::string("not a parameter file of this network: ") + path);
+    for (float v : h)
+        if (!std::isfinite(v)) return fail(TGO_EINVAL, "parameter file holds a non-finite value");
+    return tgo_surrogate_set_params(s, h.data(), nullptr);
 }
 
 static int check_groups(const tgo_task *d_tasks, const int32_t *d_offs, int G, int max_groups) {

@@ -81,6 +81,12 @@ def lib():
         L.tgo_exhaustive.argtypes = [M, vp, i32, vp, vp, vp]
         L.tgo_heuristic.argtypes = [M, vp, vp, i32, vp, vp, vp]
         L.tgo_rounds.argtypes = [M, vp, i32, i32, vp, vp, vp, vp]
+        L.tgo_predict.argtypes = [M, vp, i32, vp, ctypes.POINTER(ctypes.c_int64)]
+        L.tgo_predict.restype = i32
+        L.tgo_surrogate_save.argtypes = [vp, ctypes.c_char_p]
+        L.tgo_surrogate_save.restype = i32
+        L.tgo_surrogate_load.argtypes = [vp, ctypes.c_char_p]
+        L.tgo_surrogate_load.restype = i32
         L.tgo_rank.argtypes = [i32, vp, ctypes.POINTER(ctypes.c_uint64)]
         L.tgo_unrank.argtypes = [i32, ctypes.c_uint64, vp]
         L.tgo_plan_create.argtypes = [M, i32, ctypes.POINTER(vp)]
@@ -194,6 +200,16 @@ def exhaustive(tasks, model: Model = DEFAULT, per_order: bool = False, summary=N
                                 po.data_ptr() if po is not None else None, summary.data_ptr(),
                                 _stream(stream)), "tgo_exhaustive")
     return summary, po
+
+
+def predict(tasks, order, model: Model = DEFAULT) -> int:
+    """T (ns) of one ordering of host tasks (int64 [n, 3]), computed on the device."""
+    t = np.ascontiguousarray(np.asarray(tasks, dtype=np.int64).reshape(-1, 3))
+    o = np.ascontiguousarray(np.asarray(order, dtype=np.uint8))
+    out = ctypes.c_int64()
+    _check(lib().tgo_predict(ctypes.byref(model._c()), t.ctypes.data, len(t), o.ctypes.data, ctypes.byref(out)),
+           "tgo_predict")
+    return int(out.value)
 
 
 def rounds(tasks, workers: int, rounds: int, model: Model = DEFAULT, per_order: bool = False,
@@ -391,6 +407,12 @@ class Surrogate:
 
     def init(self, seed: int, stream=None):
         _check(lib().tgo_surrogate_init(self._h, seed, _stream(stream)), "tgo_surrogate_init")
+
+    def save(self, path: str):
+        _check(lib().tgo_surrogate_save(self._h, os.fsencode(path)), "tgo_surrogate_save")
+
+    def load(self, path: str):
+        _check(lib().tgo_surrogate_load(self._h, os.fsencode(path)), "tgo_surrogate_load")
 
     def set_params(self, params: np.ndarray, stream=None):
         p = np.ascontiguousarray(params, dtype=np.float32)

@@ -64,6 +64,11 @@ def test_host_argument_errors(L):
     assert L.tgo_evaluate(ctypes.byref(good), None, 4, fake, 3, fake, None) == tgo.TGO_EINVAL
     assert L.tgo_heuristic(ctypes.byref(good), fake, fake, -1, fake, fake, None) == tgo.TGO_EINVAL
     assert b"n must be" in L.tgo_last_error() or L.tgo_last_error()
+    out = ctypes.c_int64()
+    assert L.tgo_predict(None, fake, 3, fake, ctypes.byref(out)) == tgo.TGO_EINVAL
+    assert L.tgo_predict(ctypes.byref(good), fake, 0, fake, ctypes.byref(out)) == tgo.TGO_EINVAL
+    assert L.tgo_predict(ctypes.byref(good), fake, 17, fake, ctypes.byref(out)) == tgo.TGO_EINVAL
+    assert L.tgo_predict(ctypes.byref(good), None, 3, fake, ctypes.byref(out)) == tgo.TGO_EINVAL
     # multi-round shapes: workers * rounds <= 16, (workers!)^rounds < 2^32,
     # per-ordering output only up to 12! orderings
     for T, R, po in ((0, 2, None), (2, 0, None), (9, 2, None), (13, 1, None), (7, 3, None),

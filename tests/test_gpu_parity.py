@@ -289,3 +289,21 @@ def test_exhaustive_n13_largest_group(dev):
     got = tgo.evaluate(to_dev(t, dev), to_dev(orders, dev)).cpu().numpy()
     assert np.array_equal(got, cmodel.eval_orders(t, orders, M.DEFAULT))
     assert (got >= s["min_ns"]).all() and (got <= s["max_ns"]).all()
+
+
+def test_predict_host_buffers(dev):
+    """tgo_predict: one ordering from host memory, computed on the device."""
+    from paper_1806_10113_amd import tgo
+    rng = np.random.default_rng(107)
+    for n in (1, 2, 5, 9, 16):
+        tasks = rand_tasks(rng, n, 20_000_000)
+        for m in (M.DEFAULT, M.PAPER_EXAMPLE, M.Model(4, 3, 3, 1)):
+            order = [int(v) for v in rng.permutation(n)]
+            assert tgo.predict(tasks, order, tmodel(m)) == M.simulate(tasks, order, m)
+    g = json.load(open(os.path.join(GOLDEN, "paper_worked_timeline.json")))
+    m = M.Model(**g["model"])
+    assert tgo.predict(np.array(g["tasks_ns"]), g["order"], tmodel(m)) == M.simulate(g["tasks_ns"], g["order"], m)
+    with pytest.raises(tgo.TgoError):
+        tgo.predict(rand_tasks(rng, 3, 100), [0, 0, 1])
+    with pytest.raises(tgo.TgoError):
+        tgo.predict(np.array([[1, -2, 3], [4, 5, 6]]), [0, 1])

@@ -181,3 +181,32 @@ def test_random_search_matches_oracle(dev):
         assert res[g]["cand_best_ns"] == T[s] and res[g]["best_sample"] == s
         h = M.simulate(grp, M.heuristic(grp, M.DEFAULT), M.DEFAULT)
         assert res[g]["best_ns"] == min(T[s], h)
+
+
+def test_save_load_roundtrip(dev, tmp_path):
+    from paper_1806_10113_amd import tgo
+    b = W.batch_groups(8, 8, 16, seed=304, per_task_label=True)
+    tasks, offs = to_dev(b.tasks, dev), to_dev(b.offs, dev)
+    orders, gid, T, _ = tgo.pairs(tasks, offs, 64, seed=14)
+    a = tgo.Surrogate(max_rows=1024, max_groups=16)
+    a.init(5)
+    path = str(tmp_path / "net.bin")
+    a.save(path)
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"TGOSURR1" and len(raw) == 16 + 4 * tgo.SURROGATE_PARAMS
+    c = tgo.Surrogate(max_rows=1024, max_groups=16)
+    c.init(6)
+    c.load(path)
+    assert np.array_equal(a.get_params(), c.get_params())
+    sa = a.score(tasks, offs, orders, gid).cpu().numpy()
+    sc = c.score(tasks, offs, orders, gid).cpu().numpy()
+    assert np.array_equal(sa, sc)
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(raw[:-4])
+    with pytest.raises(tgo.TgoError):
+        c.load(str(bad))
+    bad.write_bytes(b"XXXXXXXX" + raw[8:])
+    with pytest.raises(tgo.TgoError):
+        c.load(str(bad))
+    a.close()
+    c.close()
