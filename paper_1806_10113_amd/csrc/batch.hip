@@ -112,7 +112,7 @@ template <int M, int DMA>
 __device__ __forceinline__ void run_subtree(const Ctx &c, const View<uint32_t, 1, BT_THREADS> &v,
                                             const Lane<uint32_t> &st, uint32_t list,
                                             Sub<uint32_t> &u) {
-    level<uint32_t, M, false, 1, BT_THREADS, false, DMA>(c, v, st, list, 0u, u);
+    level<uint32_t, M, false, 1, BT_THREADS, DMA>(c, v, st, list, 0u, u);
 }
 
 __device__ __forceinline__ unsigned long long wave_min(unsigned long long x) {

@@ -53,7 +53,7 @@ struct Ctx {
 
 // Level with L positions left (position n - L is being chosen).  list holds
 // the remaining tasks in increasing order, one per nibble.
-template <typename TT, int L, bool STORE, int TS, int QS, bool SELECT, int DMA>
+template <typename TT, int L, bool STORE, int TS, int QS, int DMA>
 __device__ __forceinline__ void level(const Ctx &c, const View<TT, TS, QS> &v, const Lane<TT> &s,
                                       uint32_t list, uint32_t l, Sub<TT> &u) {
     const int j = c.n - L;
@@ -61,14 +61,14 @@ __device__ __forceinline__ void level(const Ctx &c, const View<TT, TS, QS> &v, c
     for (int ci = 0; ci < L; ++ci) {
         const uint32_t x = (list >> (4 * ci)) & 15u;
         Lane<TT> s2 = s;
-        window<DMA, SELECT>(s2, j, x, v, c.r);
+        window<DMA>(s2, j, x, v, c.r);
         const uint32_t l2 = l + (uint32_t)ci * (uint32_t)fact_c(L - 1);
         if constexpr (L == 1) {
             leaf<TT, STORE>(tail<DMA>(s2, c.r), l2, u, c.out_sub);
         } else {
             const uint32_t lo = list & ((1u << (4 * ci)) - 1u);
             const uint32_t hi = (list >> (4 * ci + 4)) << (4 * ci);
-            level<TT, L - 1, STORE, TS, QS, SELECT, DMA>(c, v, s2, lo | hi, l2, u);
+            level<TT, L - 1, STORE, TS, QS, DMA>(c, v, s2, lo | hi, l2, u);
         }
     }
 }

@@ -90,7 +90,7 @@ __device__ void block_reduce_write(Partial p, Partial *dst) {
 // MODE: 0 = 32-bit time path, 1 = 64-bit.  Both instantiations are launched;
 // a block whose group does not belong to its mode returns at once.  DMA is
 // the launch scheme (DMA_TWO or DMA_ONE, fixed per instantiation).
-template <typename TT, int M, bool STORE, bool SELECT, int DMA>
+template <typename TT, int M, bool STORE, int DMA>
 __global__ __launch_bounds__(EX_THREADS) void exhaustive_kernel(const tgo_task *__restrict__ tasks,
                                                                 int n, Rates r, uint32_t n_sub,
                                                                 int64_t *out, Partial *partials) {
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(EX_THREADS) void exhaustive_kernel(const tgo_task *
         if constexpr (STORE) c.out_sub = out + r0;
         Sub<TT> u;
         sub_init(u);
-        level<TT, M, STORE, 1, EX_THREADS, SELECT, DMA>(c, v, st, (uint32_t)list, 0u, u);
+        level<TT, M, STORE, 1, EX_THREADS, DMA>(c, v, st, (uint32_t)list, 0u, u);
         fold(a, u, r0);
     }
     Partial p;
@@ -260,27 +260,13 @@ static int choose_m(int n, bool one_dma) {
     return m;
 }
 
-// TGO_EXHAUSTIVE_SELECT=1 picks the window loop written with selects
-// instead of branches (a tuning experiment; both give identical results).
-static bool use_select() {
-    static const bool v = [] {
-        const char *e = std::getenv("TGO_EXHAUSTIVE_SELECT");
-        return e && e[0] == '1';
-    }();
-    return v;
-}
-
 template <int M, bool STORE, int DMA>
 static void launch_pair(dim3 grid, size_t shm32, size_t shm64, hipStream_t st, const tgo_task *t,
                         int n, const Rates &r, uint32_t n_sub, int64_t *out, Partial *parts) {
-    if (DMA == DMA_TWO && !STORE && use_select())
-        hipLaunchKernelGGL((exhaustive_kernel<uint32_t, M, STORE, true, DMA>), grid, dim3(EX_THREADS),
-                           shm32, st, t, n, r, n_sub, out, parts);
-    else
-        hipLaunchKernelGGL((exhaustive_kernel<uint32_t, M, STORE, false, DMA>), grid, dim3(EX_THREADS),
-                           shm32, st, t, n, r, n_sub, out, parts);
-    hipLaunchKernelGGL((exhaustive_kernel<uint64_t, M, STORE, false, DMA>), grid, dim3(EX_THREADS), shm64,
-                       st, t, n, r, n_sub, out, parts);
+    hipLaunchKernelGGL((exhaustive_kernel<uint32_t, M, STORE, DMA>), grid, dim3(EX_THREADS), shm32, st, t, n, r,
+                       n_sub, out, parts);
+    hipLaunchKernelGGL((exhaustive_kernel<uint64_t, M, STORE, DMA>), grid, dim3(EX_THREADS), shm64, st, t, n, r,
+                       n_sub, out, parts);
 }
 
 template <bool STORE, int DMA>

@@ -163,7 +163,7 @@ __device__ __forceinline__ void window_one(Lane<TT> &s, uint32_t x, const View<T
 // the HtD end estimate stays valid; only a change of the DtH engine between
 // busy and idle changes the HtD rate and forces a new estimate from the exact
 // remaining work.
-template <int DMA = DMA_RUNTIME, bool SELECT = false, typename TT, int TS, int QS>
+template <int DMA = DMA_RUNTIME, typename TT, int TS, int QS>
 __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const View<TT, TS, QS> &v,
                                        const Rates &r) {
     using ST = typename Signed<TT>::type;
@@ -185,34 +185,18 @@ __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const Vie
         // slot inew is in bounds for every inew <= j; it is only used if inew < j
         const Slot<TT> nx = v.q(inew);
         const bool start = inew < j && nx.ck <= ev;
-        if constexpr (SELECT) {
-            // same updates as below, computed on every lane and selected
-            const TT uh2 = uh - (s.drun ? TT(r.p_h) : q) * (ev - th0);
-            const TT eh2 = ev + (start ? (TT)ceil_p(uh2, r.p_h, r.inv_ph, r.c_ph) : ceil_q(uh2, r.q_log2));
-            const bool chg = start != s.drun;
-            uh = chg ? uh2 : uh;
-            th0 = chg ? ev : th0;
-            eh = chg ? eh2 : eh;
-            const DRec<TT> dd = v.d(nx.x & (MAXN - 1));
-            s.dthru += start ? dd.d : TT(0);
-            s.slack = start ? dd.slack : s.slack;
-            s.dev = start ? ev + dd.dp : (inew < j ? nx.ck : inf_time<TT>());
-        } else {
-            if (start != s.drun) {
-                // the HtD rate changes at ev: exact remaining work, new estimate
-                uh -= (s.drun ? TT(r.p_h) : q) * (ev - th0);
-                th0 = ev;
-                eh = ev + (start ? (TT)ceil_p(uh, r.p_h, r.inv_ph, r.c_ph) : ceil_q(uh, r.q_log2));
-            }
-            if (start) {
-                const DRec<TT> dd = v.d(nx.x);
-                s.dthru += dd.d;
-                s.slack = dd.slack;
-                s.dev = ev + dd.dp;
-            } else {
-                s.dev = inew < j ? nx.ck : inf_time<TT>();
-            }
+        if (start != s.drun) {
+            // the HtD rate changes at ev: exact remaining work, new estimate
+            uh -= (s.drun ? TT(r.p_h) : q) * (ev - th0);
+            th0 = ev;
+            eh = ev + (start ? (TT)ceil_p(uh, r.p_h, r.inv_ph, r.c_ph) : ceil_q(uh, r.q_log2));
         }
+        // the DtH that starts (or not): computed on every lane and selected,
+        // which measured faster than a second divergent branch
+        const DRec<TT> dd = v.d(nx.x & (MAXN - 1));
+        s.dthru += start ? dd.d : TT(0);
+        s.slack = start ? dd.slack : s.slack;
+        s.dev = start ? ev + dd.dp : (inew < j ? nx.ck : inf_time<TT>());
         s.drun = start;
         s.i = inew;
     }
