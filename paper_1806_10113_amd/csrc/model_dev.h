@@ -187,9 +187,12 @@ __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const Vie
         const bool start = inew < j && nx.ck <= ev;
         if (start != s.drun) {
             // the HtD rate changes at ev: exact remaining work, new estimate
+            // (both roundings computed and selected: no nested branch)
             uh -= (s.drun ? TT(r.p_h) : q) * (ev - th0);
             th0 = ev;
-            eh = ev + (start ? (TT)ceil_p(uh, r.p_h, r.inv_ph, r.c_ph) : ceil_q(uh, r.q_log2));
+            const TT cp = (TT)ceil_p(uh, r.p_h, r.inv_ph, r.c_ph);
+            const TT cq = ceil_q(uh, r.q_log2);
+            eh = ev + (start ? cp : cq);
         }
         // the DtH that starts (or not): computed on every lane and selected,
         // which measured faster than a second divergent branch
