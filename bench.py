@@ -74,9 +74,26 @@ def cpu_baseline(tasks, seconds: float):
     t0 = time.perf_counter()
     cmodel.exhaustive(tasks, M.DEFAULT, lo=0, hi=count, threads=threads)
     dt = time.perf_counter() - t0
+    # the same simulator on one thread, over a tenth of the sample's ranks
+    one = max(1, count // (10 * threads))
+    t1 = time.perf_counter()
+    cmodel.exhaustive(tasks, M.DEFAULT, lo=0, hi=one, threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": count / dt, "unit": "orderings/s", "cores": threads, "kind": "oracle",
             "sample": f"ranks 0..{count - 1} of the N=12 group ({count / math.factorial(N):.2%} "
-                      f"of 12!), plain C event simulator, {threads} threads, {dt:.1f} s"}
+                      f"of 12!), plain C event simulator, {threads} threads, {dt:.1f} s",
+            "single_thread_value": one / dt1, "cpu_model": _cpu_model()}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def batch_extra(dev, reps: int = 5):
