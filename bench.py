@@ -224,7 +224,8 @@ def hw_validation_extra(dev, unit_ms: float):
     prediction error over every ordering of each BK benchmark."""
     from paper_1806_10113_amd import validate
     r = validate.run(dev, unit_ms=unit_ms, reps=3)
-    out = {"unit_ms": unit_ms, "transfers": r["transfers"], "kernel": r["kernel"], "overlap": r["overlap"]}
+    out = {"unit_ms": unit_ms, "transfers": r["transfers"], "kernel": r["kernel"], "overlap": r["overlap"],
+           "rounds": r["rounds"]}
     for sc in ("two_dma", "one_dma_scheme"):
         out[sc] = {"geomean_err_pct": r[sc]["geomean_err_pct"],
                    "benchmarks": {b: {k: v[k] for k in ("mean_err_pct", "max_err_pct", "measured_speedup_best",

@@ -396,6 +396,15 @@ void tgo_hw_destroy(tgo_hw *hw);
  * does not delay the device.  Blocking. */
 int tgo_hw_run(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *h_order, int dma_engines,
                int64_t *h_total_ns, tgo_hw_times *h_cmds);
+/* Several workers with dependent tasks (Section 6.2, NoReorder setup) on the
+ * device: task (w, r) at index w * rounds + r of h_tasks; h_seq lists the
+ * workers * rounds task indices round by round (positions r * workers ..
+ * hold round r's tasks).  The HtD of (w, r) waits for the DtH of (w, r - 1)
+ * through an event on the in-order HtD stream; with one DMA engine each
+ * round's HtDs then its DtHs go to the transfer stream.  Otherwise as
+ * tgo_hw_run (h_cmds indexed by task).  Blocking. */
+int tgo_hw_run_rounds(tgo_hw *hw, const tgo_hw_task *h_tasks, int workers, int rounds, const uint8_t *h_seq,
+                      int dma_engines, int64_t *h_total_ns, tgo_hw_times *h_cmds);
 /* An HtD of htd_bytes and, on another stream, a DtH of dth_bytes issued
  * dth_delay_ns after it (a device-side wait), as in the overlap experiment of
  * Section 4.2.1.  h_times[4] = HtD start, HtD end, DtH start, DtH end (ns).

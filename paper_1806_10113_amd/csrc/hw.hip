@@ -150,15 +150,20 @@ void tgo_hw_destroy(tgo_hw *hw) {
     hw_free(hw);
 }
 
-int tgo_hw_run(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *h_order, int dma_engines,
-               int64_t *h_total_ns, tgo_hw_times *h_cmds) {
-    if (!hw || !h_tasks || !h_order || !h_total_ns) return fail(TGO_EINVAL, "NULL argument");
-    if (n < 1 || n > hw->max_tasks) return fail(TGO_EINVAL, "n must be in 1..max_tasks");
-    if (dma_engines != 1 && dma_engines != 2) return fail(TGO_EINVAL, "dma_engines must be 1 or 2");
+}  // extern "C"
+
+namespace tgo {
+
+// Run n tasks in launch order seq.  Groups of g consecutive positions form
+// the units of the one-DMA transfer queue (every HtD of a group, then its
+// DtHs).  With R > 1 task x is worker x / R's task x % R and its HtD waits
+// for the DtH of task x - 1 (an event wait on the in-order HtD queue).
+static int hw_run_impl(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *seq, int g, int R,
+                       int dma_engines, int64_t *h_total_ns, tgo_hw_times *h_cmds) {
     uint32_t seen = 0;
     for (int i = 0; i < n; ++i) {
-        if (h_order[i] >= n || ((seen >> h_order[i]) & 1u)) return fail(TGO_EINVAL, "not a permutation");
-        seen |= 1u << h_order[i];
+        if (seq[i] >= n || ((seen >> seq[i]) & 1u)) return fail(TGO_EINVAL, "not a permutation");
+        seen |= 1u << seq[i];
         const tgo_hw_task &t = h_tasks[i];
         if (t.htd_bytes < 0 || t.htd_bytes > hw->max_bytes || t.dth_bytes < 0 || t.dth_bytes > hw->max_bytes ||
             t.kern_elems < 0 || t.kern_elems > hw->max_elems || t.kern_iters < 0)
@@ -175,6 +180,7 @@ int tgo_hw_run(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *h_o
     auto E = [&](int x, int c) { return hw->ev[6 * x + c]; };
     auto htd = [&](int x) -> int {
         const tgo_hw_task &t = h_tasks[x];
+        if (R > 1 && x % R) TGO_HIP(hipStreamWaitEvent(sx, E(x - 1, 5), 0));  // the worker's previous task
         TGO_HIP(hipEventRecord(E(x, 0), sx));
         if (t.htd_bytes > 0)
             TGO_HIP(hipMemcpyAsync(hw->bufs[x].dev_in, hw->bufs[x].host_in, (size_t)t.htd_bytes,
@@ -210,15 +216,18 @@ int tgo_hw_run(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *h_o
     if (dma_engines == 2) {
         // three queues, commands in launch order (Section 3.2, two DMA engines)
         for (int i = 0; i < n; ++i) {
-            const int x = h_order[i];
+            const int x = seq[i];
             if ((rc = htd(x)) || (rc = kern(x)) || (rc = dth(x))) return rc;
         }
     } else {
-        // one transfer queue: every HtD, then every DtH; kernels on their own queue
-        for (int i = 0; i < n; ++i)
-            if ((rc = htd(h_order[i])) || (rc = kern(h_order[i]))) return rc;
-        for (int i = 0; i < n; ++i)
-            if ((rc = dth(h_order[i]))) return rc;
+        // one transfer queue: per group every HtD, then every DtH; kernels on their own queue
+        for (int b = 0; b < n; b += g) {
+            const int e = std::min(n, b + g);
+            for (int i = b; i < e; ++i)
+                if ((rc = htd(seq[i])) || (rc = kern(seq[i]))) return rc;
+            for (int i = b; i < e; ++i)
+                if ((rc = dth(seq[i]))) return rc;
+        }
     }
     TGO_HIP(hipStreamSynchronize(hw->sh));
     TGO_HIP(hipStreamSynchronize(hw->sk));
@@ -235,6 +244,32 @@ int tgo_hw_run(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *h_o
     }
     *h_total_ns = total;
     return TGO_OK;
+}
+
+}  // namespace tgo
+
+extern "C" {
+
+int tgo_hw_run(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *h_order, int dma_engines,
+               int64_t *h_total_ns, tgo_hw_times *h_cmds) {
+    if (!hw || !h_tasks || !h_order || !h_total_ns) return fail(TGO_EINVAL, "NULL argument");
+    if (n < 1 || n > hw->max_tasks) return fail(TGO_EINVAL, "n must be in 1..max_tasks");
+    if (dma_engines != 1 && dma_engines != 2) return fail(TGO_EINVAL, "dma_engines must be 1 or 2");
+    return hw_run_impl(hw, h_tasks, n, h_order, n, 1, dma_engines, h_total_ns, h_cmds);
+}
+
+int tgo_hw_run_rounds(tgo_hw *hw, const tgo_hw_task *h_tasks, int workers, int rounds, const uint8_t *h_seq,
+                      int dma_engines, int64_t *h_total_ns, tgo_hw_times *h_cmds) {
+    if (!hw || !h_tasks || !h_seq || !h_total_ns) return fail(TGO_EINVAL, "NULL argument");
+    if (workers < 1 || rounds < 1 || workers * rounds > hw->max_tasks)
+        return fail(TGO_EINVAL, "need 1 <= workers * rounds <= max_tasks");
+    if (dma_engines != 1 && dma_engines != 2) return fail(TGO_EINVAL, "dma_engines must be 1 or 2");
+    const int n = workers * rounds;
+    // round r of the sequence must hold exactly the tasks (w, r)
+    for (int i = 0; i < n; ++i)
+        if (h_seq[i] >= n || h_seq[i] % rounds != i / workers)
+            return fail(TGO_EINVAL, "h_seq must list round r's tasks at positions r*workers ..");
+    return hw_run_impl(hw, h_tasks, n, h_seq, workers, rounds, dma_engines, h_total_ns, h_cmds);
 }
 
 int tgo_hw_overlap(tgo_hw *hw, int64_t htd_bytes, int64_t dth_bytes, int64_t dth_delay_ns, int64_t *h_times) {

@@ -129,6 +129,8 @@ def lib():
         L.tgo_hw_destroy.restype = None
         L.tgo_hw_run.argtypes = [vp, vp, i32, vp, i32, ctypes.POINTER(ctypes.c_int64), vp]
         L.tgo_hw_overlap.argtypes = [vp, i64, i64, i64, vp]
+        L.tgo_hw_run_rounds.argtypes = [vp, vp, i32, i32, vp, i32, ctypes.POINTER(ctypes.c_int64), vp]
+        L.tgo_hw_run_rounds.restype = i32
         L.tgo_fit_line.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.tgo_fit_overlap.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         for f in (L.tgo_hw_create, L.tgo_hw_run, L.tgo_hw_overlap, L.tgo_fit_line, L.tgo_fit_overlap):
@@ -591,6 +593,17 @@ class HwRunner:
         total = ctypes.c_int64()
         _check(lib().tgo_hw_run(self._h, tasks.ctypes.data, n, o.ctypes.data, dma_engines,
                                 ctypes.byref(total), times.ctypes.data), "tgo_hw_run")
+        return int(total.value), times
+
+    def run_rounds(self, tasks: np.ndarray, workers: int, rounds: int, seq, dma_engines: int = 2):
+        """Dependent tasks (task (w, r) at row w * rounds + r), launched in
+        ``seq`` round by round.  Returns (makespan ns, HW_TIMES_DTYPE [n])."""
+        tasks = np.ascontiguousarray(tasks, dtype=HW_TASK_DTYPE)
+        o = np.ascontiguousarray(seq, dtype=np.uint8)
+        times = np.zeros(len(tasks), dtype=HW_TIMES_DTYPE)
+        total = ctypes.c_int64()
+        _check(lib().tgo_hw_run_rounds(self._h, tasks.ctypes.data, workers, rounds, o.ctypes.data, dma_engines,
+                                       ctypes.byref(total), times.ctypes.data), "tgo_hw_run_rounds")
         return int(total.value), times
 
     def overlap(self, htd_bytes: int, dth_bytes: int, delay_ns: int) -> np.ndarray:

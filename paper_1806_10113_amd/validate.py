@@ -177,6 +177,52 @@ def validate_benchmarks(hw, dev, xfer, kern, model, unit_ns, elems, reps, dma_en
     return {"benchmarks": out, "geomean_err_pct": geo}
 
 
+def validate_rounds(hw, dev, xfer, kern, model, unit_ns, elems, reps, workers=4, rounds=2, bk="BK50",
+                    seed=0, sample=24, dma_engines=2):
+    """Section 6.2 on the device: workers x dependent tasks drawn from a BK
+    benchmark, NoReorder orderings (a seeded sample plus the predicted best
+    and worst) run with the dependencies and compared with tgo_rounds."""
+    import torch
+    T, R = workers, rounds
+    units = W.rounds_experiment(bk, T, R, seed)
+    names = {tuple(int(round(f * W.PAPER_UNIT_NS)) for f in W.PAPER_TASKS_UNITS[k]): k
+             for k in W.PAPER_TASKS_UNITS}
+    tasks = np.zeros(T * R, dtype=tgo.HW_TASK_DTYPE)
+    for x, row in enumerate(units):
+        hb, db, it = build_task(W.PAPER_TASKS_UNITS[names[tuple(int(v) for v in row)]], unit_ns, xfer, kern, elems)
+        tasks[x] = (hb, db, elems, it, 0)
+    solo = np.zeros((T * R, 3), dtype=np.int64)
+    for x in range(T * R):
+        _, tm = _median_run(hw, tasks[x:x + 1], [0], 2, reps)
+        solo[x] = tm[0]["end_ns"] - tm[0]["start_ns"]
+    mdl = tgo.Model(model.q_log2, model.p_htd, model.p_dth, dma_engines)
+    summ, po, _ = tgo.rounds(torch.as_tensor(solo).to(dev), T, R, mdl, per_order=True)
+    pred = po.cpu().numpy()
+    s = tgo.read_summary(summ)
+    count = len(pred)
+    rng = np.random.default_rng(seed)
+    ranks = sorted(set(rng.choice(count, size=min(sample, count), replace=False).tolist())
+                   | {int(s["argmin_rank"]), int(s["argmax_rank"])})
+    tf = math.factorial(T)
+    errs, meas = [], {}
+    for rk in ranks:
+        seq, rem = [], rk
+        perms = []
+        for _ in range(R):
+            rem, d = divmod(rem, tf)
+            perms.append(tgo.unrank(T, d))
+        perms = perms[::-1]
+        seq = [w * R + r for r, p in enumerate(perms) for w in p]
+        runs = [hw.run_rounds(tasks, T, R, seq, dma_engines)[0] for _ in range(reps)]
+        m = int(np.median(runs))
+        meas[rk] = m
+        errs.append(abs(int(pred[rk]) - m) / m)
+    return {"workers": T, "rounds": R, "benchmark": bk, "orderings": count, "measured": len(ranks),
+            "mean_err_pct": 100 * float(np.mean(errs)), "max_err_pct": 100 * float(np.max(errs)),
+            "predicted_best_ns": int(s["min_ns"]), "measured_at_predicted_best_ns": meas[int(s["argmin_rank"])],
+            "predicted_worst_ns": int(s["max_ns"]), "measured_at_predicted_worst_ns": meas[int(s["argmax_rank"])]}
+
+
 def run(dev=None, unit_ms: float = 10.0, reps: int = 3, quick: bool = False):
     import torch
     dev = dev or torch.device("cuda:0")
@@ -196,6 +242,11 @@ def run(dev=None, unit_ms: float = 10.0, reps: int = 3, quick: bool = False):
             hw = tgo.HwRunner(4, need, elems)
         res2 = validate_benchmarks(hw, dev, xfer, kern, model, unit_ns, elems, reps, 2)
         res1 = validate_benchmarks(hw, dev, xfer, kern, model, unit_ns, elems, reps, 1)
+        hw.close()
+        hw = tgo.HwRunner(8, need, elems)
+        rounds = [validate_rounds(hw, dev, xfer, kern, model, unit_ns, elems, reps, 4, 2, bk,
+                                  sample=8 if quick else 24)
+                  for bk in (("BK50",) if quick else ("BK25", "BK50", "BK75"))]
     finally:
         hw.close()
     return {"unit_ms": unit_ms, "reps": reps,
@@ -203,4 +254,4 @@ def run(dev=None, unit_ms: float = 10.0, reps: int = 3, quick: bool = False):
             "kernel": {k: kern[k] for k in ("eta_ns_per_elem_pass", "gamma_ns")},
             "overlap": {k: ov[k] for k in ("rho_htd", "rho_dth", "model", "errors")},
             "overlap_records": ov["records"],
-            "two_dma": res2, "one_dma_scheme": res1}
+            "two_dma": res2, "one_dma_scheme": res1, "rounds": rounds}

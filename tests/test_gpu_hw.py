@@ -48,6 +48,30 @@ def test_launch_schemes_keep_dependencies_and_order(dev):
     hw.close()
 
 
+def test_dependent_tasks_wait_for_their_worker(dev):
+    from paper_1806_10113_amd import tgo
+    hw = tgo.HwRunner(8, 16 * MB, 1 << 22)
+    T, R = 4, 2
+    tasks = np.zeros(T * R, dtype=tgo.HW_TASK_DTYPE)
+    for x in range(T * R):
+        tasks[x] = ((1 + x % 3) * MB, (1 + (x * 5) % 4) * MB, 1 << 22, 1 + x % 4, 0)
+    slack = 20_000
+    for dma in (2, 1):
+        for perms in ([[0, 1, 2, 3], [0, 1, 2, 3]], [[3, 1, 0, 2], [2, 0, 3, 1]]):
+            seq = [w * R + r for r, p in enumerate(perms) for w in p]
+            total, t = hw.run_rounds(tasks, T, R, seq, dma)
+            s, e = t["start_ns"], t["end_ns"]
+            assert total == int(e.max())
+            for w in range(T):
+                assert s[w * R + 1, 0] + slack >= e[w * R, 2]   # HtD of (w, 1) after DtH of (w, 0)
+            hq = [(x, 0) for x in seq]
+            for (a, ca), (b, cb) in zip(hq, hq[1:]):
+                assert e[a, ca] <= s[b, cb] + slack
+    with pytest.raises(tgo.TgoError):
+        hw.run_rounds(tasks, T, R, list(range(8)), 2)   # round 0 must come first
+    hw.close()
+
+
 def test_fits_and_prediction_on_this_device(dev):
     from paper_1806_10113_amd import validate
     res = validate.run(dev, unit_ms=2.0, reps=3, quick=True)
@@ -59,3 +83,5 @@ def test_fits_and_prediction_on_this_device(dev):
     for scheme in ("two_dma", "one_dma_scheme"):
         for bk, v in res[scheme]["benchmarks"].items():
             assert v["mean_err_pct"] < 10.0, (scheme, bk, v["mean_err_pct"])
+    for v in res["rounds"]:
+        assert v["mean_err_pct"] < 10.0, v
