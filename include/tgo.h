@@ -405,6 +405,18 @@ int tgo_hw_run(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *h_o
  * tgo_hw_run (h_cmds indexed by task).  Blocking. */
 int tgo_hw_run_rounds(tgo_hw *hw, const tgo_hw_task *h_tasks, int workers, int rounds, const uint8_t *h_seq,
                       int dma_engines, int64_t *h_total_ns, tgo_hw_times *h_cmds);
+/* The Heuristic setup of Section 6.2 on the device: a host proxy loop offers
+ * task (w, r) once the DtH of (w, r - 1) has ended (polling its event), takes
+ * every offered task as a group, orders it with Algorithm 1 (run on the
+ * device, from the solo durations h_dur of the tasks, under `model`) and
+ * enqueues it with the scheme of model->dma_engines; it looks again once the
+ * HtD of the group's last task has started, or at the next arrival.
+ * h_seq (16 bytes, optional) receives the submission order and h_groups
+ * (optional) the group ends (bit j: position j ends a group); otherwise as
+ * tgo_hw_run.  Blocking; TGO_ERANGE if the tasks do not finish within 120 s. */
+int tgo_hw_run_proxy(tgo_hw *hw, const tgo_model *model, const tgo_hw_task *h_tasks, const tgo_task *h_dur,
+                     int workers, int rounds, int64_t *h_total_ns, uint8_t *h_seq, uint16_t *h_groups,
+                     tgo_hw_times *h_cmds);
 /* An HtD of htd_bytes and, on another stream, a DtH of dth_bytes issued
  * dth_delay_ns after it (a device-side wait), as in the overlap experiment of
  * Section 4.2.1.  h_times[4] = HtD start, HtD end, DtH start, DtH end (ns).

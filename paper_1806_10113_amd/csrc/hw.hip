@@ -9,7 +9,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <thread>
 #include <vector>
 
 #include "tgo_internal.h"
@@ -57,6 +59,12 @@ struct tgo_hw {
     std::vector<TaskBufs> bufs;
     hipEvent_t t0 = nullptr;
     std::vector<hipEvent_t> ev;  // 6 per task slot: HtD, K, DtH start and end
+    // the proxy's Algorithm 1 runs on the device: its own stream and buffers
+    hipStream_t sp = nullptr;
+    tgo_task *p_tasks = nullptr;
+    int32_t *p_offs = nullptr;
+    uint8_t *p_order = nullptr;
+    int64_t *p_ns = nullptr;
 };
 
 namespace tgo {
@@ -74,6 +82,8 @@ static void hw_free(tgo_hw *hw) {
     if (hw->sh) (void)hipStreamDestroy(hw->sh);
     if (hw->sk) (void)hipStreamDestroy(hw->sk);
     if (hw->sd) (void)hipStreamDestroy(hw->sd);
+    if (hw->sp) (void)hipStreamDestroy(hw->sp);
+    if (hw->p_tasks) (void)hipFree(hw->p_tasks);
     delete hw;
 }
 
@@ -121,6 +131,11 @@ int tgo_hw_create(int max_tasks, int64_t max_bytes, int64_t max_kern_elems, tgo_
     if ((e = hipStreamCreateWithFlags(&hw->sh, hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
     if ((e = hipStreamCreateWithFlags(&hw->sk, hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
     if ((e = hipStreamCreateWithFlags(&hw->sd, hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
+    if ((e = hipStreamCreateWithFlags(&hw->sp, hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
+    if ((e = hipMalloc((void **)&hw->p_tasks, 1024)) != hipSuccess) return bail(e, "hipMalloc");
+    hw->p_offs = (int32_t *)((char *)hw->p_tasks + 512);
+    hw->p_order = (uint8_t *)((char *)hw->p_tasks + 640);
+    hw->p_ns = (int64_t *)((char *)hw->p_tasks + 768);
     if ((e = hipEventCreate(&hw->t0)) != hipSuccess) return bail(e, "event");
     hw->ev.resize(6 * max_tasks, nullptr);
     for (auto &ev : hw->ev)
@@ -246,9 +261,178 @@ static int hw_run_impl(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint
     return TGO_OK;
 }
 
+// Heuristic setup (Section 6.2) on the device: a host proxy loop.  Task
+// (w, r) is offered when the DtH of (w, r - 1) has ended (seen by polling its
+// event); the proxy takes every offered task as a group, orders it with
+// Algorithm 1 (run on the device from the tasks' solo durations h_dur) and
+// enqueues it; it looks again once the HtD of the group's last task has
+// started (its start event has been reached), or at the next arrival.
+static int hw_proxy_impl(tgo_hw *hw, const Rates &r, const tgo_hw_task *h_tasks, const tgo_task *h_dur, int T,
+                         int R, int dma_engines, int64_t *h_total_ns, uint8_t *h_seq, uint16_t *h_groups,
+                         tgo_hw_times *h_cmds) {
+    const int n = T * R;
+    for (int i = 0; i < n; ++i) {
+        const tgo_hw_task &t = h_tasks[i];
+        if (t.htd_bytes < 0 || t.htd_bytes > hw->max_bytes || t.dth_bytes < 0 || t.dth_bytes > hw->max_bytes ||
+            t.kern_elems < 0 || t.kern_elems > hw->max_elems || t.kern_iters < 0)
+            return fail(TGO_EINVAL, "task exceeds the runner's buffers");
+    }
+    TGO_HIP(hipSetDevice(hw->device));
+    hipStream_t sx = hw->sh;
+    hipStream_t sd = dma_engines == 2 ? hw->sd : hw->sh;
+    auto E = [&](int x, int c) { return hw->ev[6 * x + c]; };
+    auto enqueue = [&](const uint8_t *ord, int g) -> int {
+        auto htd = [&](int x) -> int {
+            const tgo_hw_task &t = h_tasks[x];
+            TGO_HIP(hipEventRecord(E(x, 0), sx));
+            if (t.htd_bytes > 0)
+                TGO_HIP(hipMemcpyAsync(hw->bufs[x].dev_in, hw->bufs[x].host_in, (size_t)t.htd_bytes,
+                                       hipMemcpyHostToDevice, sx));
+            TGO_HIP(hipEventRecord(E(x, 1), sx));
+            const tgo_hw_task &tk = h_tasks[x];
+            TGO_HIP(hipStreamWaitEvent(hw->sk, E(x, 1), 0));
+            TGO_HIP(hipEventRecord(E(x, 2), hw->sk));
+            if (tk.kern_iters > 0 && tk.kern_elems > 0) {
+                const int64_t want = (tk.kern_elems + 255) / 256;
+                const int blocks = (int)std::min<int64_t>(want, hw->blocks);
+                hipLaunchKernelGGL(tgo_hw_scale_kernel, dim3(blocks), dim3(256), 0, hw->sk, hw->bufs[x].dev_k,
+                                   tk.kern_elems, tk.kern_iters, 0.999f, 0.001f);
+                TGO_HIP(hipGetLastError());
+            }
+            TGO_HIP(hipEventRecord(E(x, 3), hw->sk));
+            return TGO_OK;
+        };
+        auto dth = [&](int x) -> int {
+            const tgo_hw_task &t = h_tasks[x];
+            TGO_HIP(hipStreamWaitEvent(sd, E(x, 3), 0));
+            TGO_HIP(hipEventRecord(E(x, 4), sd));
+            if (t.dth_bytes > 0)
+                TGO_HIP(hipMemcpyAsync(hw->bufs[x].host_out, hw->bufs[x].dev_out, (size_t)t.dth_bytes,
+                                       hipMemcpyDeviceToHost, sd));
+            TGO_HIP(hipEventRecord(E(x, 5), sd));
+            return TGO_OK;
+        };
+        int rc;
+        if (dma_engines == 2) {
+            for (int i = 0; i < g; ++i)
+                if ((rc = htd(ord[i])) || (rc = dth(ord[i]))) return rc;
+        } else {
+            for (int i = 0; i < g; ++i)
+                if ((rc = htd(ord[i]))) return rc;
+            for (int i = 0; i < g; ++i)
+                if ((rc = dth(ord[i]))) return rc;
+        }
+        return TGO_OK;
+    };
+    // Algorithm 1 on a group, on the device (synchronous)
+    auto order_group = [&](const uint8_t *mem, int g, uint8_t *out) -> int {
+        tgo_task tk[TGO_MAX_N];
+        for (int i = 0; i < g; ++i) tk[i] = h_dur[mem[i]];
+        const int32_t offs[2] = {0, g};
+        TGO_HIP(hipMemcpyAsync(hw->p_tasks, tk, sizeof(tgo_task) * g, hipMemcpyHostToDevice, hw->sp));
+        TGO_HIP(hipMemcpyAsync(hw->p_offs, offs, sizeof(offs), hipMemcpyHostToDevice, hw->sp));
+        int rc = launch_heuristic(r, hw->p_tasks, hw->p_offs, 1, hw->p_order, 16, hw->p_ns, 1, hw->sp);
+        if (rc) return rc;
+        uint8_t ord[16];
+        TGO_HIP(hipMemcpyAsync(ord, hw->p_order, 16, hipMemcpyDeviceToHost, hw->sp));
+        TGO_HIP(hipStreamSynchronize(hw->sp));
+        for (int i = 0; i < g; ++i) {
+            if (ord[i] >= g) return fail(TGO_ERANGE, "heuristic failed on a group");
+            out[i] = mem[ord[i]];
+        }
+        return TGO_OK;
+    };
+    delay(hw, hw->sh, GATE_NS);
+    TGO_HIP(hipEventRecord(hw->t0, hw->sh));
+    TGO_HIP(hipStreamWaitEvent(hw->sk, hw->t0, 0));
+    if (sd != sx) TGO_HIP(hipStreamWaitEvent(sd, hw->t0, 0));
+    uint32_t buffer = 0, submitted = 0, done = 0;
+    for (int w = 0; w < T; ++w) buffer |= 1u << (w * R);
+    bool armed = true;
+    int trig = -1, nsub = 0;
+    uint16_t gend = 0;
+    uint8_t seq[TGO_MAX_N];
+    const uint32_t all = (n == 32) ? ~0u : ((1u << n) - 1u);
+    int rc = TGO_OK;
+    // every task is submitted once and completes, so the loop ends; a
+    // device error ends it at once, and so does a wall-clock limit
+    const auto start = std::chrono::steady_clock::now();
+    while (done != all) {
+        if (std::chrono::steady_clock::now() - start > std::chrono::seconds(120))
+            return fail(TGO_ERANGE, "proxy: tasks did not complete within 120 s");
+        bool progress = false;
+        for (int x = 0; x < n; ++x) {
+            if (!((submitted >> x) & 1u) || ((done >> x) & 1u)) continue;
+            const hipError_t q = hipEventQuery(E(x, 5));
+            if (q == hipSuccess) {
+                done |= 1u << x;
+                if (x % R + 1 < R) buffer |= 1u << (x + 1);
+                progress = true;
+            } else if (q != hipErrorNotReady) {
+                return hip_fail(q, "hipEventQuery");
+            }
+        }
+        if (!armed && trig >= 0) {
+            const hipError_t q = hipEventQuery(E(trig, 0));
+            if (q == hipSuccess) armed = true;
+            else if (q != hipErrorNotReady) return hip_fail(q, "hipEventQuery");
+        }
+        if (armed && buffer) {
+            uint8_t mem[TGO_MAX_N], ord[TGO_MAX_N];
+            int g = 0;
+            for (int x = 0; x < n; ++x)
+                if ((buffer >> x) & 1u) mem[g++] = (uint8_t)x;
+            if ((rc = order_group(mem, g, ord))) return rc;
+            if ((rc = enqueue(ord, g))) return rc;
+            for (int i = 0; i < g; ++i) {
+                seq[nsub + i] = ord[i];
+                submitted |= 1u << ord[i];
+            }
+            nsub += g;
+            gend |= (uint16_t)(1u << (nsub - 1));
+            trig = ord[g - 1];
+            buffer = 0;
+            armed = false;
+            progress = true;
+        }
+        if (!progress) std::this_thread::yield();
+    }
+    TGO_HIP(hipStreamSynchronize(hw->sh));
+    TGO_HIP(hipStreamSynchronize(hw->sk));
+    TGO_HIP(hipStreamSynchronize(hw->sd));
+    int64_t total = 0;
+    for (int x = 0; x < n; ++x) {
+        tgo_hw_times c;
+        for (int k = 0; k < 3; ++k) {
+            c.start_ns[k] = ns_between(hw->t0, E(x, 2 * k));
+            c.end_ns[k] = ns_between(hw->t0, E(x, 2 * k + 1));
+            total = std::max(total, c.end_ns[k]);
+        }
+        if (h_cmds) h_cmds[x] = c;
+    }
+    *h_total_ns = total;
+    if (h_seq)
+        for (int i = 0; i < TGO_MAX_N; ++i) h_seq[i] = i < n ? seq[i] : (uint8_t)0xff;
+    if (h_groups) *h_groups = gend;
+    return TGO_OK;
+}
+
 }  // namespace tgo
 
 extern "C" {
+
+int tgo_hw_run_proxy(tgo_hw *hw, const tgo_model *model, const tgo_hw_task *h_tasks, const tgo_task *h_dur,
+                     int workers, int rounds, int64_t *h_total_ns, uint8_t *h_seq, uint16_t *h_groups,
+                     tgo_hw_times *h_cmds) {
+    Rates r;
+    int rc = make_rates(model, &r);
+    if (rc) return rc;
+    if (!hw || !h_tasks || !h_dur || !h_total_ns) return fail(TGO_EINVAL, "NULL argument");
+    if (workers < 1 || rounds < 1 || workers * rounds > hw->max_tasks)
+        return fail(TGO_EINVAL, "need 1 <= workers * rounds <= max_tasks");
+    return hw_proxy_impl(hw, r, h_tasks, h_dur, workers, rounds, model->dma_engines, h_total_ns, h_seq, h_groups,
+                         h_cmds);
+}
 
 int tgo_hw_run(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *h_order, int dma_engines,
                int64_t *h_total_ns, tgo_hw_times *h_cmds) {

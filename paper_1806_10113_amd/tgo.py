@@ -131,6 +131,8 @@ def lib():
         L.tgo_hw_overlap.argtypes = [vp, i64, i64, i64, vp]
         L.tgo_hw_run_rounds.argtypes = [vp, vp, i32, i32, vp, i32, ctypes.POINTER(ctypes.c_int64), vp]
         L.tgo_hw_run_rounds.restype = i32
+        L.tgo_hw_run_proxy.argtypes = [vp, M, vp, vp, i32, i32, ctypes.POINTER(ctypes.c_int64), vp, vp, vp]
+        L.tgo_hw_run_proxy.restype = i32
         L.tgo_fit_line.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.tgo_fit_overlap.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         for f in (L.tgo_hw_create, L.tgo_hw_run, L.tgo_hw_overlap, L.tgo_fit_line, L.tgo_fit_overlap):
@@ -605,6 +607,22 @@ class HwRunner:
         _check(lib().tgo_hw_run_rounds(self._h, tasks.ctypes.data, workers, rounds, o.ctypes.data, dma_engines,
                                        ctypes.byref(total), times.ctypes.data), "tgo_hw_run_rounds")
         return int(total.value), times
+
+    def run_proxy(self, tasks: np.ndarray, durations, workers: int, rounds: int, model: Model = DEFAULT):
+        """The Heuristic setup with a host proxy (tgo_hw_run_proxy).  Returns
+        (makespan ns, submission order, group-end positions, HW_TIMES_DTYPE [n])."""
+        tasks = np.ascontiguousarray(tasks, dtype=HW_TASK_DTYPE)
+        dur = np.ascontiguousarray(np.asarray(durations, dtype=np.int64).reshape(-1, 3))
+        n = len(tasks)
+        seq = np.zeros(16, dtype=np.uint8)
+        groups = np.zeros(1, dtype=np.uint16)
+        times = np.zeros(n, dtype=HW_TIMES_DTYPE)
+        total = ctypes.c_int64()
+        _check(lib().tgo_hw_run_proxy(self._h, ctypes.byref(model._c()), tasks.ctypes.data, dur.ctypes.data,
+                                      workers, rounds, ctypes.byref(total), seq.ctypes.data, groups.ctypes.data,
+                                      times.ctypes.data), "tgo_hw_run_proxy")
+        ends = [j for j in range(16) if (int(groups[0]) >> j) & 1]
+        return int(total.value), [int(v) for v in seq[:n]], ends, times
 
     def overlap(self, htd_bytes: int, dth_bytes: int, delay_ns: int) -> np.ndarray:
         out = np.zeros(4, dtype=np.int64)

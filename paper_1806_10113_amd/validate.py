@@ -217,7 +217,17 @@ def validate_rounds(hw, dev, xfer, kern, model, unit_ns, elems, reps, workers=4,
         m = int(np.median(runs))
         meas[rk] = m
         errs.append(abs(int(pred[rk]) - m) / m)
+    # the Heuristic setup with a real proxy, against the model's prediction
+    hruns = [hw.run_proxy(tasks, solo, T, R, mdl) for _ in range(reps)]
+    htot = [h[0] for h in hruns]
+    hmed = hruns[int(np.argsort(htot)[len(htot) // 2])]
+    model_seq = [int(v) for v in s["heur"][:T * R]]
     return {"workers": T, "rounds": R, "benchmark": bk, "orderings": count, "measured": len(ranks),
+            "heuristic_setup_measured_ns": int(hmed[0]), "heuristic_setup_predicted_ns": int(s["heur_ns"]),
+            "heuristic_setup_err_pct": 100 * abs(int(s["heur_ns"]) - hmed[0]) / hmed[0],
+            "heuristic_setup_same_order": hmed[1] == model_seq,
+            "measured_speedup_heuristic_vs_worst": meas[int(s["argmax_rank"])] / hmed[0],
+            "measured_speedup_best_vs_worst": meas[int(s["argmax_rank"])] / meas[int(s["argmin_rank"])],
             "mean_err_pct": 100 * float(np.mean(errs)), "max_err_pct": 100 * float(np.max(errs)),
             "predicted_best_ns": int(s["min_ns"]), "measured_at_predicted_best_ns": meas[int(s["argmin_rank"])],
             "predicted_worst_ns": int(s["max_ns"]), "measured_at_predicted_worst_ns": meas[int(s["argmax_rank"])]}
@@ -246,7 +256,7 @@ def run(dev=None, unit_ms: float = 10.0, reps: int = 3, quick: bool = False):
         hw = tgo.HwRunner(8, need, elems)
         rounds = [validate_rounds(hw, dev, xfer, kern, model, unit_ns, elems, reps, 4, 2, bk,
                                   sample=8 if quick else 24)
-                  for bk in (("BK50",) if quick else ("BK25", "BK50", "BK75"))]
+                  for bk in (("BK25",) if quick else ("BK25", "BK50", "BK75"))]
     finally:
         hw.close()
     return {"unit_ms": unit_ms, "reps": reps,

@@ -72,6 +72,31 @@ def test_dependent_tasks_wait_for_their_worker(dev):
     hw.close()
 
 
+def test_proxy_runs_the_heuristic_setup(dev):
+    """The Section 6.2 proxy on the device: the first group is every worker's
+    first task in Algorithm 1 order, later tasks start only after their
+    worker's previous DtH, and every task runs once."""
+    from oracle import model as M
+    from paper_1806_10113_amd import tgo
+    hw = tgo.HwRunner(8, 16 * MB, 1 << 22)
+    T, R = 4, 2
+    tasks = np.zeros(T * R, dtype=tgo.HW_TASK_DTYPE)
+    dur = np.zeros((T * R, 3), dtype=np.int64)
+    for x in range(T * R):
+        h, d, it = (1 + x % 3), (1 + (x * 5) % 4), 1 + (x * 3) % 5
+        tasks[x] = (h * MB, d * MB, 1 << 22, it, 0)
+        dur[x] = (h * 20_000, it * 6_000, d * 20_000)   # nominal durations for Algorithm 1
+    total, seq, ends, t = hw.run_proxy(tasks, dur, T, R, tgo.DEFAULT)
+    assert sorted(seq) == list(range(T * R)) and ends[-1] == T * R - 1
+    first = [x for x in seq[:ends[0] + 1]]
+    assert first == [w * R for w in M.heuristic([tuple(dur[w * R]) for w in range(T)], M.DEFAULT)]
+    s, e = t["start_ns"], t["end_ns"]
+    assert total == int(e.max())
+    for w in range(T):
+        assert s[w * R + 1, 0] + 20_000 >= e[w * R, 2]
+    hw.close()
+
+
 def test_fits_and_prediction_on_this_device(dev):
     from paper_1806_10113_amd import validate
     res = validate.run(dev, unit_ms=2.0, reps=3, quick=True)
@@ -85,3 +110,4 @@ def test_fits_and_prediction_on_this_device(dev):
             assert v["mean_err_pct"] < 10.0, (scheme, bk, v["mean_err_pct"])
     for v in res["rounds"]:
         assert v["mean_err_pct"] < 10.0, v
+        assert v["heuristic_setup_err_pct"] < 15.0, v
