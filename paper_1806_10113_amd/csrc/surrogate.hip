@@ -107,30 +107,41 @@ __global__ __launch_bounds__(SG_THREADS) void pairs_kernel(const tgo_task *__res
 
 // Plain exact search: `per` sampled orderings per group (a multiple of 64),
 // keep the smallest (T << 32 | sample).
+// Each wave takes chunks of `chunk` consecutive 64-sample tiles of one group,
+// so the group's table is loaded and the wave's minimum published once per
+// chunk; wave-uniform values are kept in scalar registers.
+
 __global__ __launch_bounds__(SG_THREADS) void random_search_kernel(const tgo_task *__restrict__ tasks,
                                                                    const int32_t *__restrict__ offs,
                                                                    int G, Rates r, int64_t per,
-                                                                   uint64_t seed,
+                                                                   uint64_t seed, int64_t chunk_tiles,
                                                                    const int32_t *__restrict__ status,
                                                                    unsigned long long *best) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ WaveTables wt;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     View<uint32_t, 1, SG_THREADS> v;
     v.H = wt.H[w];
     v.D = wt.D[w];
     v.Q = reinterpret_cast<Slot<uint32_t> *>(smem) + threadIdx.x;
     const int64_t tiles_per_group = per / 64;
-    const int64_t total = tiles_per_group * G;
+    const int64_t chunks_per_group = (tiles_per_group + chunk_tiles - 1) / chunk_tiles;
+    const int64_t total = chunks_per_group * G;
     const int64_t wstride = (int64_t)gridDim.x * (SG_THREADS / 64);
-    for (int64_t tile = (int64_t)blockIdx.x * (SG_THREADS / 64) + w; tile < total; tile += wstride) {
-        const int g = (int)(tile / tiles_per_group);
+    for (int64_t chunk = (int64_t)blockIdx.x * (SG_THREADS / 64) + w; chunk < total; chunk += wstride) {
+        const int g = (int)(chunk / chunks_per_group);
         if (status[g] != 0) continue;
-        const int64_t s = (tile % tiles_per_group) * 64 + lane;
         const int n = offs[g + 1] - offs[g];
         load_group(wt, w, lane, tasks + offs[g], n, r);
-        const uint64_t perm = sample_ordering(n, (uint32_t)g, (uint64_t)s, seed);
-        unsigned long long key = ((unsigned long long)eval_perm(perm, n, v, r) << 32) | (uint64_t)s;
+        const int64_t t0 = (chunk % chunks_per_group) * chunk_tiles;
+        const int64_t t1 = t0 + chunk_tiles < tiles_per_group ? t0 + chunk_tiles : tiles_per_group;
+        unsigned long long key = ~0ull;
+        for (int64_t tile = t0; tile < t1; ++tile) {
+            const int64_t s = tile * 64 + lane;
+            const uint64_t perm = sample_ordering(n, (uint32_t)g, (uint64_t)s, seed);
+            const unsigned long long k = ((unsigned long long)eval_perm(perm, n, v, r) << 32) | (uint64_t)s;
+            key = k < key ? k : key;
+        }
         for (int m = 32; m >= 1; m >>= 1) {
             const unsigned long long o = __shfl_xor(key, m);
             key = o < key ? o : key;
@@ -1299,10 +1310,13 @@ int tgo_random_search(const tgo_model *model, const tgo_task *d_tasks, const int
     hipLaunchKernelGGL(fill_u64_kernel, dim3((G + 255) / 256), dim3(256), 0, st, best, (int64_t)G, ~0ull);
     if (per > 0) {
         const size_t shm = sizeof(Slot<uint32_t>) * SG_THREADS * SG_POS;
+        // chunks of up to 64 tiles, while keeping at least ~64k wave tasks
         const int64_t tiles = per / 64 * G;
-        const int blocks = (int)std::min<int64_t>((tiles + 3) / 4, 16384);
+        const int64_t chunk_tiles = std::max<int64_t>(1, std::min<int64_t>(64, tiles >> 16));
+        const int64_t chunks = (per / 64 + chunk_tiles - 1) / chunk_tiles * G;
+        const int blocks = (int)std::min<int64_t>((chunks + 3) / 4, 16384);
         hipLaunchKernelGGL(random_search_kernel, dim3(blocks), dim3(SG_THREADS), shm, st, d_tasks, d_offs, G, r,
-                           per, seed, status, best);
+                           per, seed, chunk_tiles, status, best);
     }
     hipLaunchKernelGGL(search_finish_kernel, dim3((G + 255) / 256), dim3(256), 0, st, d_offs, G, seed,
                        (const uint32_t *)nullptr, status, best, horders, hns, d_out);

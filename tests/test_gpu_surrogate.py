@@ -183,6 +183,32 @@ def test_random_search_matches_oracle(dev):
         assert res[g]["best_ns"] == min(T[s], h)
 
 
+@pytest.mark.parametrize("n,groups,tiles", [(8, 3, 65539), (7, 16, 262147)])
+def test_random_search_many_samples_exact(dev, n, groups, tiles):
+    # millions of samples per group (several 64-sample tiles per wave, the
+    # last chunk of each group ragged): with n! small beside the sample
+    # count an optimal ordering is all but surely drawn, so the result is
+    # fixed exactly: the optimum over all n! orderings (brute force) and the
+    # first sample index that draws an optimal ordering
+    import itertools
+    from paper_1806_10113_amd import tgo
+    ev = W.fixed_size_groups(groups, n, seed=305 + n)
+    samples = tiles * 64 - 5                      # rounded up to tiles * 64
+    res = tgo.read_search(tgo.random_search(to_dev(ev.tasks, dev), to_dev(ev.offs, dev), samples=samples,
+                                            seed=24))
+    allp = np.array(list(itertools.permutations(range(n))), dtype=np.uint8)
+    for g in range(groups):
+        grp = ev.group(g)
+        T = cmodel.eval_orders(grp, allp, M.DEFAULT)
+        best = int(T.min())
+        optimal = {tuple(int(v) for v in p) for p in allp[T == best]}
+        s = 0
+        while tuple(philox.sample_ordering(n, g, s, 24)) not in optimal:
+            s += 1
+        assert s < tiles * 64
+        assert res[g]["cand_best_ns"] == best and res[g]["best_sample"] == s, (g, res[g], best, s)
+
+
 def test_save_load_roundtrip(dev, tmp_path):
     from paper_1806_10113_amd import tgo
     b = W.batch_groups(8, 8, 16, seed=304, per_task_label=True)
