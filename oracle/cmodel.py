@@ -60,6 +60,14 @@ def lib():
         L.oracle_rounds_times.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_void_p]
+        L.oracle_mem_simulate.restype = ctypes.c_int64
+        L.oracle_mem_simulate.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                                          ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int]
+        L.oracle_mem_times.restype = ctypes.c_int
+        L.oracle_mem_times.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -124,5 +132,31 @@ def rounds_times(tasks, T: int, R: int, model: Model = DEFAULT, threads: int | N
     out = np.empty(math.factorial(T) ** R, dtype=np.int64)
     rc = lib().oracle_rounds_times(t.ctypes.data, T, R, model.q, model.p_htd, model.p_dth,
                                    model.dma_engines, threads or default_threads(), out.ctypes.data)
+    assert rc == 0
+    return out
+
+
+def mem_simulate(tasks, mem, capacity: int, order, model: Model = DEFAULT) -> int:
+    """T of one ordering under the device-memory limit (C transcription of
+    oracle/memory.py)."""
+    t = _tasks(tasks)
+    m = np.ascontiguousarray(np.asarray(mem, dtype=np.int64))
+    o = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    return int(lib().oracle_mem_simulate(t.ctypes.data, m.ctypes.data, len(t), int(capacity), o.ctypes.data,
+                                         model.q, model.p_htd, model.p_dth, model.dma_engines))
+
+
+def mem_times(tasks, mem, capacity: int, model: Model = DEFAULT, lo: int = 0, hi: int | None = None,
+              threads: int | None = None) -> np.ndarray:
+    """T under the device-memory limit for the orderings of ranks [lo, hi)."""
+    import math
+    t = _tasks(tasks)
+    m = np.ascontiguousarray(np.asarray(mem, dtype=np.int64))
+    n = len(t)
+    hi = math.factorial(n) if hi is None else hi
+    out = np.empty(hi - lo, dtype=np.int64)
+    rc = lib().oracle_mem_times(t.ctypes.data, m.ctypes.data, n, int(capacity), model.q, model.p_htd,
+                                model.p_dth, model.dma_engines, lo, hi, threads or default_threads(),
+                                out.ctypes.data)
     assert rc == 0
     return out

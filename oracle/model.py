@@ -271,13 +271,14 @@ def select_next(tasks, rt, t_h, t_k, t_d):
     return best[1]
 
 
-def select_last(tasks, rt, ot, model):
+def select_last(tasks, rt, ot, model, update_fn=None):
+    update_fn = update_fn or update
     a, b = sorted(rt)
-    t_h, t_k, t_d = update(tasks, ot, model)
+    t_h, t_k, t_d = update_fn(tasks, ot, model)
     best = None
     for x, y in ((a, b), (b, a)):
         s1 = _fit(tasks[x], t_h, t_k, t_d)
-        u_h, u_k, u_d = update(tasks, ot + [x], model)
+        u_h, u_k, u_d = update_fn(tasks, ot + [x], model)
         s2 = _fit(tasks[y], u_h, u_k, u_d)
         key = (s1 + s2 + int(tasks[y][2]), int(tasks[y][2]))
         if best is None or key < best[0]:
@@ -285,8 +286,10 @@ def select_last(tasks, rt, ot, model):
     return best[1]
 
 
-def heuristic(tasks, model: Model = DEFAULT):
-    """Ordering chosen by Algorithm 1 (under the readings above)."""
+def heuristic(tasks, model: Model = DEFAULT, update_fn=None):
+    """Ordering chosen by Algorithm 1 (under the readings above).  update_fn
+    (default ``update``) simulates the ordered set alone."""
+    update_fn = update_fn or update
     tasks = [tuple(int(v) for v in t) for t in tasks]
     n = len(tasks)
     if n == 0:
@@ -298,14 +301,14 @@ def heuristic(tasks, model: Model = DEFAULT):
     rt.remove(first)
     if len(rt) == 0:
         return ot
-    t_h, t_k, t_d = update(tasks, ot, model)
+    t_h, t_k, t_d = update_fn(tasks, ot, model)
     while len(rt) > 2:
         nxt = select_next(tasks, rt, t_h, t_k, t_d)
         ot.append(nxt)
         rt.remove(nxt)
-        t_h, t_k, t_d = update(tasks, ot, model)
+        t_h, t_k, t_d = update_fn(tasks, ot, model)
     if len(rt) == 2:
-        ot += select_last(tasks, rt, ot, model)
+        ot += select_last(tasks, rt, ot, model, update_fn)
     else:
         ot.append(rt[0])
     return ot

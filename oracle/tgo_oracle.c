@@ -372,3 +372,134 @@ int oracle_rounds_times(const int64_t *tasks, int T, int R, int q, int p_htd, in
     free(th);
     return 0;
 }
+
+/* ------------------------------------------------------ device-memory limit */
+/*
+ * Transcription of oracle/memory.py: task x holds mem[x] bytes from the start
+ * of its HtD to the end of its DtH, at most cap bytes at once.  Two DMA
+ * engines: the HtD at the head of its queue waits until its buffers fit.  One
+ * DMA engine: the ordering is cut greedily into consecutive sub-groups whose
+ * buffers fit together, each launched as its HtDs then its DtHs.
+ * Returns the total time, or -1 if commands were left unstarted.
+ */
+int64_t oracle_mem_simulate(const int64_t *tasks, const int64_t *mem, int n, int64_t cap,
+                            const int *order, int q, int p_htd, int p_dth, int dma) {
+    int neng = dma == 2 ? 3 : 2;
+    int qkind[3][2 * OMAXN], qtask[3][2 * OMAXN], qlen[3] = {0, 0, 0}, qhead[3] = {0, 0, 0};
+    int run_kind[3] = {-1, -1, -1}, run_task[3] = {-1, -1, -1};
+    int64_t left[3] = {0, 0, 0}, rate[3], est[3];
+    unsigned char done[3][OMAXN];
+    memset(done, 0, sizeof(done));
+    if (dma == 2) {
+        for (int j = 0; j < n; ++j)
+            for (int e = 0; e < 3; ++e) { qkind[e][qlen[e]] = e; qtask[e][qlen[e]++] = order[j]; }
+    } else {
+        int b = 0;
+        while (b < n) {
+            int e = b;
+            int64_t held = 0;
+            while (e < n && (e == b || held + mem[order[e]] <= cap)) held += mem[order[e++]];
+            for (int i = b; i < e; ++i) { qkind[0][qlen[0]] = K_HTD; qtask[0][qlen[0]++] = order[i]; }
+            for (int i = b; i < e; ++i) { qkind[0][qlen[0]] = K_DTH; qtask[0][qlen[0]++] = order[i]; }
+            b = e;
+        }
+        for (int j = 0; j < n; ++j) { qkind[1][qlen[1]] = K_KER; qtask[1][qlen[1]++] = order[j]; }
+    }
+    int64_t t = 0, total = 0, held = 0;
+    for (;;) {
+        int changed = 1;
+        while (changed) {
+            changed = 0;
+            for (int e = 0; e < neng; ++e) {
+                if (run_kind[e] >= 0 && left[e] == 0) {
+                    done[run_kind[e]][run_task[e]] = 1;
+                    if (run_kind[e] == K_DTH) held -= mem[run_task[e]];
+                    if (t > total) total = t;
+                    run_kind[e] = -1;
+                    changed = 1;
+                }
+            }
+            for (int e = 0; e < neng; ++e) {
+                if (run_kind[e] >= 0 || qhead[e] >= qlen[e]) continue;
+                int k = qkind[e][qhead[e]], x = qtask[e][qhead[e]];
+                int ready = k == K_HTD ? held + mem[x] <= cap : k == K_KER ? done[K_HTD][x] : done[K_KER][x];
+                if (!ready) continue;
+                qhead[e]++;
+                if (k == K_HTD) held += mem[x];
+                run_kind[e] = k;
+                run_task[e] = x;
+                left[e] = tasks[x * 3 + k] * (k == K_KER ? 1 : q);
+                changed = 1;
+            }
+        }
+        int busy = 0, hbusy = 0, dbusy = 0;
+        for (int e = 0; e < neng; ++e) {
+            if (run_kind[e] < 0) continue;
+            busy = 1;
+            if (run_kind[e] == K_HTD) hbusy = 1;
+            if (run_kind[e] == K_DTH) dbusy = 1;
+        }
+        if (!busy) break;
+        int64_t delta = INT64_MAX;
+        for (int e = 0; e < neng; ++e) {
+            if (run_kind[e] < 0) continue;
+            int k = run_kind[e];
+            rate[e] = k == K_KER ? 1 : (hbusy && dbusy ? (k == K_HTD ? p_htd : p_dth) : q);
+            est[e] = ceil_div(left[e], rate[e]);
+            if (est[e] < delta) delta = est[e];
+        }
+        t += delta;
+        for (int e = 0; e < neng; ++e) {
+            if (run_kind[e] < 0) continue;
+            left[e] = est[e] == delta ? 0 : left[e] - rate[e] * delta;
+        }
+    }
+    for (int e = 0; e < neng; ++e)
+        if (qhead[e] < qlen[e]) return -1;
+    return total;
+}
+
+typedef struct {
+    const int64_t *tasks, *mem;
+    int n, q, p_htd, p_dth, dma;
+    int64_t cap;
+    uint64_t lo, hi, base;
+    int64_t *out;
+} mjob_t;
+
+static void *mem_worker(void *arg) {
+    mjob_t *j = (mjob_t *)arg;
+    int perm[OMAXN];
+    if (j->lo >= j->hi) return NULL;
+    decode_rank(j->n, j->lo, perm);
+    for (uint64_t rk = j->lo; rk < j->hi; ++rk) {
+        j->out[rk - j->base] = oracle_mem_simulate(j->tasks, j->mem, j->n, j->cap, perm, j->q, j->p_htd,
+                                                   j->p_dth, j->dma);
+        next_perm(j->n, perm);
+    }
+    return NULL;
+}
+
+/* T of the orderings of ranks [lo, hi) under the memory limit, out[rank - lo],
+ * on nthreads threads. */
+int oracle_mem_times(const int64_t *tasks, const int64_t *mem, int n, int64_t cap, int q, int p_htd,
+                     int p_dth, int dma, uint64_t lo, uint64_t hi, int nthreads, int64_t *out) {
+    if (n < 1 || n > OMAXN || nthreads < 1 || hi < lo) return -1;
+    mjob_t *jobs = (mjob_t *)calloc((size_t)nthreads, sizeof(mjob_t));
+    pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    uint64_t count = hi - lo, per = (count + (uint64_t)nthreads - 1) / (uint64_t)nthreads;
+    for (int i = 0; i < nthreads; ++i) {
+        mjob_t *j = &jobs[i];
+        j->tasks = tasks; j->mem = mem; j->n = n; j->cap = cap;
+        j->q = q; j->p_htd = p_htd; j->p_dth = p_dth; j->dma = dma;
+        j->lo = lo + ((uint64_t)i * per < count ? (uint64_t)i * per : count);
+        j->hi = j->lo + per < hi ? j->lo + per : hi;
+        j->base = lo;
+        j->out = out;
+        pthread_create(&th[i], NULL, mem_worker, j);
+    }
+    for (int i = 0; i < nthreads; ++i) pthread_join(th[i], NULL);
+    free(jobs);
+    free(th);
+    return 0;
+}
