@@ -49,6 +49,8 @@ extern "C" {
 #define TGO_MAX_N 16            /* largest group for evaluate / heuristic      */
 #define TGO_MAX_EXHAUSTIVE_N 13 /* largest group enumerated in full (13! ranks) */
 #define TGO_ROUNDS_MAX_PER_ORDER 479001600ull /* per-ordering output limit of tgo_rounds */
+#define TGO_MAX_MEM_N 12        /* largest group of tgo_exhaustive_mem (12! ranks) */
+#define TGO_MAX_CAPACITY (1ll << 62) /* largest device-memory capacity, bytes     */
 
 enum {
     TGO_OK = 0,
@@ -362,6 +364,43 @@ void tgo_server_destroy(tgo_server *srv);
  */
 int tgo_rounds(const tgo_model *model, const tgo_task *d_tasks, int workers, int rounds,
                int64_t *d_per_order, tgo_summary *d_summary, uint16_t *d_groups, tgo_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * tgo_exhaustive_mem -- every ordering of a task group under a device-memory
+ * limit.  Section 5 notes that tasks running concurrently hold their input
+ * and output buffers at the same time, so the device memory can restrict
+ * which tasks may form a group; the paper leaves it aside and assumes enough
+ * memory.  Reading:
+ *   task x holds d_mem[x] bytes of device memory from the start of its HtD
+ *   to the end of its DtH, and at most `capacity` bytes are held at once.
+ *   Two DMA engines: the HtD at the head of its queue starts only when its
+ *   bytes fit beside those held (the HtDs behind it wait too).  One DMA
+ *   engine: the ordering is cut greedily into consecutive sub-groups whose
+ *   bytes fit together, each launched as its HtDs, then its DtHs (Section
+ *   3.2 scheme), behind the previous sub-group.
+ *   With capacity >= the sum of d_mem the results equal tgo_exhaustive's.
+ *   d_tasks  : n tasks, 1 <= n <= TGO_MAX_MEM_N, durations in [0, 2^40) ns
+ *              (else status = TGO_ERANGE).
+ *   d_mem    : n int64 footprints in bytes, each in [0, capacity] (else
+ *              status = TGO_EINVAL: a task that cannot fit alone never runs).
+ *   capacity : bytes, 1..TGO_MAX_CAPACITY.
+ *   d_per_order: NULL, or n! int64 receiving T at index = lexicographic rank.
+ *   d_summary: min / argmin / max / argmax / sum / mean / fingerprint over the
+ *              n! orderings as tgo_exhaustive (ties to the lowest rank);
+ *              heur[] / heur_ns: Algorithm 1's ordering (same selection
+ *              rules, its update step simulated under the limit) and its T.
+ * Device buffers belong to the caller; the call enqueues on `stream` and
+ * returns at once.
+ */
+int tgo_exhaustive_mem(const tgo_model *model, const tgo_task *d_tasks, const int64_t *d_mem, int n,
+                       int64_t capacity, int64_t *d_per_order, tgo_summary *d_summary, tgo_stream stream);
+
+/* tgo_evaluate_mem -- T of m given orderings (row-major m x n bytes, n <=
+ * TGO_MAX_N, m <= 2^40) under the device-memory limit of tgo_exhaustive_mem.
+ * d_out[i] = T in ns, or TGO_EINVAL for a row that is not a permutation or a
+ * footprint outside [0, capacity], TGO_ERANGE for durations out of range. */
+int tgo_evaluate_mem(const tgo_model *model, const tgo_task *d_tasks, const int64_t *d_mem, int n,
+                     int64_t capacity, const uint8_t *d_orders, int64_t m, int64_t *d_out, tgo_stream stream);
 
 /* ---------------------------------------------------------------------------
  * Real execution on the device, to validate the model (Sections 4.2, 4.3):

@@ -145,6 +145,33 @@ int tgo_rounds(const tgo_model *model, const tgo_task *d_tasks, int workers, int
                          (hipStream_t)stream);
 }
 
+static int check_memory_args(const tgo_model *model, Rates *r, int n, int max_n, int64_t capacity) {
+    int rc = make_rates(model, r);
+    if (rc) return rc;
+    if (n < 1 || n > max_n) return fail(TGO_EINVAL, "n out of range");
+    if (capacity < 1 || capacity > TGO_MAX_CAPACITY) return fail(TGO_EINVAL, "capacity must be in 1..2^62");
+    return TGO_OK;
+}
+
+int tgo_exhaustive_mem(const tgo_model *model, const tgo_task *d_tasks, const int64_t *d_mem, int n,
+                       int64_t capacity, int64_t *d_per_order, tgo_summary *d_summary, tgo_stream stream) {
+    Rates r;
+    int rc = check_memory_args(model, &r, n, TGO_MAX_MEM_N, capacity);
+    if (rc) return rc;
+    if (!d_tasks || !d_mem || !d_summary) return fail(TGO_EINVAL, "NULL buffer");
+    return launch_memory(r, d_tasks, d_mem, n, capacity, d_per_order, d_summary, (hipStream_t)stream);
+}
+
+int tgo_evaluate_mem(const tgo_model *model, const tgo_task *d_tasks, const int64_t *d_mem, int n,
+                     int64_t capacity, const uint8_t *d_orders, int64_t m, int64_t *d_out, tgo_stream stream) {
+    Rates r;
+    int rc = check_memory_args(model, &r, n, TGO_MAX_N, capacity);
+    if (rc) return rc;
+    if (m < 0 || m > ((int64_t)1 << 40)) return fail(TGO_EINVAL, "m must be in 0..2^40");
+    if (m > 0 && (!d_tasks || !d_mem || !d_orders || !d_out)) return fail(TGO_EINVAL, "NULL buffer");
+    return launch_memory_evaluate(r, d_tasks, d_mem, n, capacity, d_orders, m, d_out, (hipStream_t)stream);
+}
+
 int tgo_predict(const tgo_model *model, const tgo_task *h_tasks, int n, const uint8_t *h_order,
                 int64_t *out_ns) {
     Rates r;

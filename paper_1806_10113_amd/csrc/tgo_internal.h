@@ -48,6 +48,10 @@ int launch_evaluate(const Rates &r, const tgo_task *d_tasks, int n, const uint8_
                     int64_t m, int64_t *d_out, hipStream_t st);
 int launch_rounds(const Rates &r, const tgo_task *d_tasks, int T, int R, int64_t *d_per_order,
                   tgo_summary *d_out, uint16_t *d_groups, hipStream_t st);
+int launch_memory(const Rates &r, const tgo_task *d_tasks, const int64_t *d_mem, int n, int64_t cap,
+                  int64_t *d_per_order, tgo_summary *d_out, hipStream_t st);
+int launch_memory_evaluate(const Rates &r, const tgo_task *d_tasks, const int64_t *d_mem, int n, int64_t cap,
+                           const uint8_t *d_orders, int64_t m, int64_t *d_out, hipStream_t st);
 int launch_heuristic(const Rates &r, const tgo_task *d_tasks, const int32_t *d_offs, int n_groups,
                      uint8_t *d_orders, int order_stride, int64_t *d_ns, int ns_stride,
                      hipStream_t st);

@@ -81,6 +81,10 @@ def lib():
         L.tgo_exhaustive.argtypes = [M, vp, i32, vp, vp, vp]
         L.tgo_heuristic.argtypes = [M, vp, vp, i32, vp, vp, vp]
         L.tgo_rounds.argtypes = [M, vp, i32, i32, vp, vp, vp, vp]
+        L.tgo_exhaustive_mem.argtypes = [M, vp, vp, i32, i64, vp, vp, vp]
+        L.tgo_exhaustive_mem.restype = i32
+        L.tgo_evaluate_mem.argtypes = [M, vp, vp, i32, i64, vp, i64, vp, vp]
+        L.tgo_evaluate_mem.restype = i32
         L.tgo_predict.argtypes = [M, vp, i32, vp, ctypes.POINTER(ctypes.c_int64)]
         L.tgo_predict.restype = i32
         L.tgo_surrogate_save.argtypes = [vp, ctypes.c_char_p]
@@ -238,6 +242,50 @@ def rounds(tasks, workers: int, rounds: int, model: Model = DEFAULT, per_order: 
                             po.data_ptr() if po is not None else None, summary.data_ptr(),
                             groups.data_ptr(), _stream(stream)), "tgo_rounds")
     return summary, po, groups
+
+
+def exhaustive_mem(tasks, mem, capacity: int, model: Model = DEFAULT, per_order: bool = False, summary=None,
+                   stream=None):
+    """Every ordering under a device-memory limit: task x holds mem[x] bytes
+    (int64 [n] device tensor) from its HtD start to its DtH end, at most
+    ``capacity`` at once.  Returns (summary uint8 device tensor with the
+    heuristic under the limit in heur / heur_ns, per-ordering int64 device
+    tensor or None)."""
+    import math
+    import torch
+    _dev_tensor(tasks, torch.int64, 3, "tasks")
+    _dev_tensor(mem, torch.int64, None, "mem")
+    n = tasks.shape[0]
+    if mem.shape != (n,):
+        raise ValueError("mem must be int64 [n]")
+    po = torch.empty(math.factorial(n), dtype=torch.int64, device=tasks.device) if per_order else None
+    if summary is None:
+        summary = torch.empty(SUMMARY_DTYPE.itemsize, dtype=torch.uint8, device=tasks.device)
+    _check(lib().tgo_exhaustive_mem(ctypes.byref(model._c()), tasks.data_ptr(), mem.data_ptr(), n, int(capacity),
+                                    po.data_ptr() if po is not None else None, summary.data_ptr(),
+                                    _stream(stream)), "tgo_exhaustive_mem")
+    return summary, po
+
+
+def evaluate_mem(tasks, mem, capacity: int, orders, model: Model = DEFAULT, out=None, stream=None):
+    """T (int64 ns) of each row of ``orders`` (uint8 [m, n]) under the
+    device-memory limit of ``exhaustive_mem``."""
+    import torch
+    _dev_tensor(tasks, torch.int64, 3, "tasks")
+    _dev_tensor(mem, torch.int64, None, "mem")
+    _dev_tensor(orders, torch.uint8, None, "orders")
+    n = tasks.shape[0]
+    if mem.shape != (n,):
+        raise ValueError("mem must be int64 [n]")
+    if orders.dim() != 2 or orders.shape[1] != n:
+        raise ValueError("orders must be [m, n]")
+    m = orders.shape[0]
+    if out is None:
+        out = torch.empty(m, dtype=torch.int64, device=tasks.device)
+    _dev_tensor(out, torch.int64, None, "out")
+    _check(lib().tgo_evaluate_mem(ctypes.byref(model._c()), tasks.data_ptr(), mem.data_ptr(), n, int(capacity),
+                                  orders.data_ptr(), m, out.data_ptr(), _stream(stream)), "tgo_evaluate_mem")
+    return out
 
 
 def read_groups(groups) -> list:

@@ -168,3 +168,22 @@ def rounds_experiment(benchmark: str, workers: int, rounds: int, seed: int) -> n
     rng = np.random.Generator(np.random.PCG64(seed))
     idx = rng.integers(0, len(base), size=workers * rounds)
     return np.ascontiguousarray(base[idx])
+
+
+# Host-to-device copy rate used to turn transfer times into buffer sizes
+# (about 57 GB/s, pinned-memory copies measured on the target).
+FOOTPRINT_BYTES_PER_NS = 57.0
+
+
+def footprints(tasks, bytes_per_ns: float = FOOTPRINT_BYTES_PER_NS) -> np.ndarray:
+    """Device-memory footprint of each task (int64 bytes): its input and
+    output buffers, sized from its HtD and DtH times at ``bytes_per_ns``."""
+    t = np.asarray(tasks, dtype=np.int64).reshape(-1, 3)
+    return np.rint((t[:, 0] + t[:, 2]).astype(np.float64) * bytes_per_ns).astype(np.int64)
+
+
+def capacity_fraction(mem, frac: float) -> int:
+    """A capacity of ``frac`` of the group's total footprint, never below the
+    largest single footprint (every task must fit alone) nor below 1."""
+    m = np.asarray(mem, dtype=np.int64)
+    return int(max(1, int(m.max(initial=0)), int(math.floor(float(m.sum()) * frac))))

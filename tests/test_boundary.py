@@ -77,6 +77,16 @@ def test_host_argument_errors(L):
     assert L.tgo_rounds(ctypes.byref(good), None, 2, 2, None, fake, None, None) == tgo.TGO_EINVAL
     assert L.tgo_rounds(ctypes.byref(tgo._Model(3, 2, 3, 3)), fake, 2, 2, None, fake, None,
                         None) == tgo.TGO_EINVAL
+    # device-memory limit: n in 1..12 (evaluate 1..16), capacity in 1..2^62,
+    # m in 0..2^40, buffers present
+    for n, cap in ((0, 10), (13, 10), (4, 0), (4, -5), (4, (1 << 62) + 1)):
+        assert L.tgo_exhaustive_mem(ctypes.byref(good), fake, fake, n, cap, None, fake, None) == tgo.TGO_EINVAL
+    assert L.tgo_exhaustive_mem(ctypes.byref(good), fake, None, 4, 10, None, fake, None) == tgo.TGO_EINVAL
+    assert L.tgo_exhaustive_mem(ctypes.byref(good), None, fake, 4, 10, None, fake, None) == tgo.TGO_EINVAL
+    assert L.tgo_exhaustive_mem(None, fake, fake, 4, 10, None, fake, None) == tgo.TGO_EINVAL
+    for n, cap, m in ((0, 10, 1), (17, 10, 1), (4, 0, 1), (4, 10, -1), (4, 10, (1 << 40) + 1)):
+        assert L.tgo_evaluate_mem(ctypes.byref(good), fake, fake, n, cap, fake, m, fake, None) == tgo.TGO_EINVAL
+    assert L.tgo_evaluate_mem(ctypes.byref(good), fake, None, 4, 10, fake, 5, fake, None) == tgo.TGO_EINVAL
 
 
 def test_rank_unrank_match_lexicographic_order():
