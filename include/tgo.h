@@ -410,12 +410,20 @@ int tgo_evaluate_mem(const tgo_model *model, const tgo_task *d_tasks, const int6
  */
 typedef struct tgo_hw tgo_hw;
 
+/* Kernel kinds of a tgo_hw_task: HBM streams x = x * s + b through device
+ * memory on every pass (bound by memory bandwidth); ALU loads each float once
+ * and runs 64 dependent multiply-adds per pass in registers. */
+#define TGO_HW_KERNEL_HBM 0
+#define TGO_HW_KERNEL_ALU 1
+
 typedef struct {
     int64_t htd_bytes;   /* bytes copied host -> device (0: no HtD)           */
     int64_t dth_bytes;   /* bytes copied device -> host (0: no DtH)           */
     int64_t kern_elems;  /* floats the kernel scales per pass                 */
     int32_t kern_iters;  /* passes (0: no kernel); the duration is linear in   */
-    int32_t pad;         /* kern_elems * kern_iters (Eq. 1)                   */
+                         /* kern_elems * kern_iters (Eq. 1)                   */
+    int32_t kern_kind;   /* TGO_HW_KERNEL_HBM or TGO_HW_KERNEL_ALU (else       */
+                         /* TGO_EINVAL)                                        */
 } tgo_hw_task;
 
 typedef struct {
@@ -444,6 +452,18 @@ int tgo_hw_run(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *h_o
  * tgo_hw_run (h_cmds indexed by task).  Blocking. */
 int tgo_hw_run_rounds(tgo_hw *hw, const tgo_hw_task *h_tasks, int workers, int rounds, const uint8_t *h_seq,
                       int dma_engines, int64_t *h_total_ns, tgo_hw_times *h_cmds);
+
+/* Like tgo_hw_run, under a device-memory limit (the reading of
+ * tgo_exhaustive_mem): h_mem[x] = task x's footprint in bytes (0..capacity),
+ * capacity in 1..TGO_MAX_CAPACITY.  Two DMA engines: the HtD at position j is
+ * made to wait (an event wait on the in-order HtD queue) for the DtH of the
+ * last position whose buffers would not fit beside those of positions up to
+ * j.  One DMA engine: the ordering is cut greedily into sub-groups whose
+ * footprints fit together, each enqueued as its HtDs then its DtHs.  The
+ * runner's buffers are allocated up front; the limit is enforced by these
+ * waits, which is what a pool of `capacity` bytes would impose. */
+int tgo_hw_run_mem(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *h_order, const int64_t *h_mem,
+                   int64_t capacity, int dma_engines, int64_t *h_total_ns, tgo_hw_times *h_cmds);
 /* The Heuristic setup of Section 6.2 on the device: a host proxy loop offers
  * task (w, r) once the DtH of (w, r - 1) has ended (polling its event), takes
  * every offered task as a group, orders it with Algorithm 1 (run on the

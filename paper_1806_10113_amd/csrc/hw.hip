@@ -26,6 +26,20 @@ __global__ __launch_bounds__(256) void tgo_hw_scale_kernel(float *x, int64_t n, 
             x[i] = x[i] * s + b;
 }
 
+// Register-resident variant: one load and one store per float, 64 dependent
+// multiply-adds per pass in between, so the duration is set by the ALUs and
+// the kernel hardly touches device memory.
+__global__ __launch_bounds__(256) void tgo_hw_fma_kernel(float *x, int64_t n, int iters, float s, float b) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        float v = x[i];
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int k = 0; k < 64; ++k) v = v * s + b;
+        x[i] = v;
+    }
+}
+
 // One thread waits until `ticks` of the constant-rate wall clock have passed
 // (bounded by max_polls reads of the clock).
 __global__ void tgo_hw_delay_kernel(int64_t ticks, int64_t max_polls) {
@@ -39,7 +53,21 @@ __global__ void tgo_hw_delay_kernel(int64_t ticks, int64_t max_polls) {
 
 namespace {
 
-constexpr int64_t GATE_NS = 2000000;  // streams held back while the host enqueues
+constexpr int64_t GATE_NS = 2000000;
+
+int launch_task_kernel(float *buf, const tgo_hw_task &t, int max_blocks, hipStream_t st) {
+    if (t.kern_iters <= 0 || t.kern_elems <= 0) return TGO_OK;
+    const int64_t want = (t.kern_elems + 255) / 256;
+    const int blocks = (int)std::min<int64_t>(want, max_blocks);
+    if (t.kern_kind == TGO_HW_KERNEL_ALU)
+        hipLaunchKernelGGL(tgo_hw_fma_kernel, dim3(blocks), dim3(256), 0, st, buf, t.kern_elems, t.kern_iters,
+                           0.999f, 0.001f);
+    else
+        hipLaunchKernelGGL(tgo_hw_scale_kernel, dim3(blocks), dim3(256), 0, st, buf, t.kern_elems, t.kern_iters,
+                           0.999f, 0.001f);
+    TGO_HIP(hipGetLastError());
+    return TGO_OK;
+}  // streams held back while the host enqueues
 
 struct TaskBufs {
     void *host_in = nullptr, *host_out = nullptr;
@@ -173,15 +201,20 @@ namespace tgo {
 // the units of the one-DMA transfer queue (every HtD of a group, then its
 // DtHs).  With R > 1 task x is worker x / R's task x % R and its HtD waits
 // for the DtH of task x - 1 (an event wait on the in-order HtD queue).
-static int hw_run_impl(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *seq, int g, int R,
-                       int dma_engines, int64_t *h_total_ns, tgo_hw_times *h_cmds) {
+// seq: task per launch position.  gend (one DMA engine): bit j set if
+// position j ends a launch group.  R > 1: task x waits for the DtH of task
+// x - 1 unless x % R == 0 (multi-round workers).  gate (may be NULL): the
+// HtD at position j waits for the DtH at position gate[j] (< 0: none).
+static int hw_run_impl(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *seq, uint32_t gend, int R,
+                       const int *gate, int dma_engines, int64_t *h_total_ns, tgo_hw_times *h_cmds) {
     uint32_t seen = 0;
     for (int i = 0; i < n; ++i) {
         if (seq[i] >= n || ((seen >> seq[i]) & 1u)) return fail(TGO_EINVAL, "not a permutation");
         seen |= 1u << seq[i];
         const tgo_hw_task &t = h_tasks[i];
         if (t.htd_bytes < 0 || t.htd_bytes > hw->max_bytes || t.dth_bytes < 0 || t.dth_bytes > hw->max_bytes ||
-            t.kern_elems < 0 || t.kern_elems > hw->max_elems || t.kern_iters < 0)
+            t.kern_elems < 0 || t.kern_elems > hw->max_elems || t.kern_iters < 0 ||
+            (t.kern_kind != TGO_HW_KERNEL_HBM && t.kern_kind != TGO_HW_KERNEL_ALU))
             return fail(TGO_EINVAL, "task exceeds the runner's buffers");
     }
     TGO_HIP(hipSetDevice(hw->device));
@@ -193,9 +226,11 @@ static int hw_run_impl(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint
     TGO_HIP(hipStreamWaitEvent(hw->sk, hw->t0, 0));
     if (sd != sx) TGO_HIP(hipStreamWaitEvent(sd, hw->t0, 0));
     auto E = [&](int x, int c) { return hw->ev[6 * x + c]; };
-    auto htd = [&](int x) -> int {
+    auto htd = [&](int i) -> int {
+        const int x = seq[i];
         const tgo_hw_task &t = h_tasks[x];
         if (R > 1 && x % R) TGO_HIP(hipStreamWaitEvent(sx, E(x - 1, 5), 0));  // the worker's previous task
+        if (gate && gate[i] >= 0) TGO_HIP(hipStreamWaitEvent(sx, E(seq[gate[i]], 5), 0));  // memory given back
         TGO_HIP(hipEventRecord(E(x, 0), sx));
         if (t.htd_bytes > 0)
             TGO_HIP(hipMemcpyAsync(hw->bufs[x].dev_in, hw->bufs[x].host_in, (size_t)t.htd_bytes,
@@ -207,13 +242,7 @@ static int hw_run_impl(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint
         const tgo_hw_task &t = h_tasks[x];
         TGO_HIP(hipStreamWaitEvent(hw->sk, E(x, 1), 0));
         TGO_HIP(hipEventRecord(E(x, 2), hw->sk));
-        if (t.kern_iters > 0 && t.kern_elems > 0) {
-            const int64_t want = (t.kern_elems + 255) / 256;
-            const int blocks = (int)std::min<int64_t>(want, hw->blocks);
-            hipLaunchKernelGGL(tgo_hw_scale_kernel, dim3(blocks), dim3(256), 0, hw->sk, hw->bufs[x].dev_k,
-                               t.kern_elems, t.kern_iters, 0.999f, 0.001f);
-            TGO_HIP(hipGetLastError());
-        }
+        if (int rc = launch_task_kernel(hw->bufs[x].dev_k, t, hw->blocks, hw->sk)) return rc;
         TGO_HIP(hipEventRecord(E(x, 3), hw->sk));
         return TGO_OK;
     };
@@ -232,16 +261,18 @@ static int hw_run_impl(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint
         // three queues, commands in launch order (Section 3.2, two DMA engines)
         for (int i = 0; i < n; ++i) {
             const int x = seq[i];
-            if ((rc = htd(x)) || (rc = kern(x)) || (rc = dth(x))) return rc;
+            if ((rc = htd(i)) || (rc = kern(x)) || (rc = dth(x))) return rc;
         }
     } else {
         // one transfer queue: per group every HtD, then every DtH; kernels on their own queue
-        for (int b = 0; b < n; b += g) {
-            const int e = std::min(n, b + g);
+        for (int b = 0; b < n;) {
+            int e = b + 1;
+            while (e < n && !((gend >> (e - 1)) & 1u)) ++e;
             for (int i = b; i < e; ++i)
-                if ((rc = htd(seq[i])) || (rc = kern(seq[i]))) return rc;
+                if ((rc = htd(i)) || (rc = kern(seq[i]))) return rc;
             for (int i = b; i < e; ++i)
                 if ((rc = dth(seq[i]))) return rc;
+            b = e;
         }
     }
     TGO_HIP(hipStreamSynchronize(hw->sh));
@@ -274,7 +305,8 @@ static int hw_proxy_impl(tgo_hw *hw, const Rates &r, const tgo_hw_task *h_tasks,
     for (int i = 0; i < n; ++i) {
         const tgo_hw_task &t = h_tasks[i];
         if (t.htd_bytes < 0 || t.htd_bytes > hw->max_bytes || t.dth_bytes < 0 || t.dth_bytes > hw->max_bytes ||
-            t.kern_elems < 0 || t.kern_elems > hw->max_elems || t.kern_iters < 0)
+            t.kern_elems < 0 || t.kern_elems > hw->max_elems || t.kern_iters < 0 ||
+            (t.kern_kind != TGO_HW_KERNEL_HBM && t.kern_kind != TGO_HW_KERNEL_ALU))
             return fail(TGO_EINVAL, "task exceeds the runner's buffers");
     }
     TGO_HIP(hipSetDevice(hw->device));
@@ -292,13 +324,7 @@ static int hw_proxy_impl(tgo_hw *hw, const Rates &r, const tgo_hw_task *h_tasks,
             const tgo_hw_task &tk = h_tasks[x];
             TGO_HIP(hipStreamWaitEvent(hw->sk, E(x, 1), 0));
             TGO_HIP(hipEventRecord(E(x, 2), hw->sk));
-            if (tk.kern_iters > 0 && tk.kern_elems > 0) {
-                const int64_t want = (tk.kern_elems + 255) / 256;
-                const int blocks = (int)std::min<int64_t>(want, hw->blocks);
-                hipLaunchKernelGGL(tgo_hw_scale_kernel, dim3(blocks), dim3(256), 0, hw->sk, hw->bufs[x].dev_k,
-                                   tk.kern_elems, tk.kern_iters, 0.999f, 0.001f);
-                TGO_HIP(hipGetLastError());
-            }
+            if (int rc = launch_task_kernel(hw->bufs[x].dev_k, tk, hw->blocks, hw->sk)) return rc;
             TGO_HIP(hipEventRecord(E(x, 3), hw->sk));
             return TGO_OK;
         };
@@ -439,7 +465,7 @@ int tgo_hw_run(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *h_o
     if (!hw || !h_tasks || !h_order || !h_total_ns) return fail(TGO_EINVAL, "NULL argument");
     if (n < 1 || n > hw->max_tasks) return fail(TGO_EINVAL, "n must be in 1..max_tasks");
     if (dma_engines != 1 && dma_engines != 2) return fail(TGO_EINVAL, "dma_engines must be 1 or 2");
-    return hw_run_impl(hw, h_tasks, n, h_order, n, 1, dma_engines, h_total_ns, h_cmds);
+    return hw_run_impl(hw, h_tasks, n, h_order, 1u << (n - 1), 1, nullptr, dma_engines, h_total_ns, h_cmds);
 }
 
 int tgo_hw_run_rounds(tgo_hw *hw, const tgo_hw_task *h_tasks, int workers, int rounds, const uint8_t *h_seq,
@@ -453,7 +479,47 @@ int tgo_hw_run_rounds(tgo_hw *hw, const tgo_hw_task *h_tasks, int workers, int r
     for (int i = 0; i < n; ++i)
         if (h_seq[i] >= n || h_seq[i] % rounds != i / workers)
             return fail(TGO_EINVAL, "h_seq must list round r's tasks at positions r*workers ..");
-    return hw_run_impl(hw, h_tasks, n, h_seq, workers, rounds, dma_engines, h_total_ns, h_cmds);
+    uint32_t gend = 0;
+    for (int r = 0; r < rounds; ++r) gend |= 1u << ((r + 1) * workers - 1);
+    return hw_run_impl(hw, h_tasks, n, h_seq, gend, rounds, nullptr, dma_engines, h_total_ns, h_cmds);
+}
+
+int tgo_hw_run_mem(tgo_hw *hw, const tgo_hw_task *h_tasks, int n, const uint8_t *h_order, const int64_t *h_mem,
+                   int64_t capacity, int dma_engines, int64_t *h_total_ns, tgo_hw_times *h_cmds) {
+    if (!hw || !h_tasks || !h_order || !h_mem || !h_total_ns) return fail(TGO_EINVAL, "NULL argument");
+    if (n < 1 || n > hw->max_tasks) return fail(TGO_EINVAL, "n must be in 1..max_tasks");
+    if (dma_engines != 1 && dma_engines != 2) return fail(TGO_EINVAL, "dma_engines must be 1 or 2");
+    if (capacity < 1 || capacity > TGO_MAX_CAPACITY) return fail(TGO_EINVAL, "capacity must be in 1..2^62");
+    for (int i = 0; i < n; ++i) {
+        if (h_order[i] >= n) return fail(TGO_EINVAL, "not a permutation");
+        if (h_mem[i] < 0 || h_mem[i] > capacity) return fail(TGO_EINVAL, "every footprint must fit the capacity");
+    }
+    int gate[TGO_MAX_N];
+    uint32_t gend = 0;
+    if (dma_engines == 2) {
+        // the HtD at position j starts once every position before a_j has
+        // ended its DtH, a_j the first position from which the footprints
+        // through j fit
+        for (int j = 0; j < n; ++j) {
+            int64_t held = h_mem[h_order[j]];
+            int a = j;
+            while (a > 0 && held + h_mem[h_order[a - 1]] <= capacity) held += h_mem[h_order[--a]];
+            gate[j] = a - 1;
+        }
+    } else {
+        // greedy sub-groups whose footprints fit together
+        int64_t held = 0;
+        for (int j = 0; j < n; ++j) {
+            if (j > 0 && held + h_mem[h_order[j]] > capacity) {
+                gend |= 1u << (j - 1);
+                held = 0;
+            }
+            held += h_mem[h_order[j]];
+        }
+        gend |= 1u << (n - 1);
+    }
+    return hw_run_impl(hw, h_tasks, n, h_order, gend, 1, dma_engines == 2 ? gate : nullptr, dma_engines,
+                       h_total_ns, h_cmds);
 }
 
 int tgo_hw_overlap(tgo_hw *hw, int64_t htd_bytes, int64_t dth_bytes, int64_t dth_delay_ns, int64_t *h_times) {

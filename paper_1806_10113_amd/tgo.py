@@ -135,6 +135,8 @@ def lib():
         L.tgo_hw_overlap.argtypes = [vp, i64, i64, i64, vp]
         L.tgo_hw_run_rounds.argtypes = [vp, vp, i32, i32, vp, i32, ctypes.POINTER(ctypes.c_int64), vp]
         L.tgo_hw_run_rounds.restype = i32
+        L.tgo_hw_run_mem.argtypes = [vp, vp, i32, vp, vp, i64, i32, ctypes.POINTER(ctypes.c_int64), vp]
+        L.tgo_hw_run_mem.restype = i32
         L.tgo_hw_run_proxy.argtypes = [vp, M, vp, vp, i32, i32, ctypes.POINTER(ctypes.c_int64), vp, vp, vp]
         L.tgo_hw_run_proxy.restype = i32
         L.tgo_fit_line.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -611,7 +613,8 @@ class Server:
 
 
 HW_TASK_DTYPE = np.dtype([("htd_bytes", "<i8"), ("dth_bytes", "<i8"), ("kern_elems", "<i8"),
-                          ("kern_iters", "<i4"), ("pad", "<i4")])
+                          ("kern_iters", "<i4"), ("kern_kind", "<i4")])
+HW_KERNEL_HBM, HW_KERNEL_ALU = 0, 1
 HW_TIMES_DTYPE = np.dtype([("start_ns", "<i8", (3,)), ("end_ns", "<i8", (3,))])
 
 
@@ -654,6 +657,20 @@ class HwRunner:
         total = ctypes.c_int64()
         _check(lib().tgo_hw_run_rounds(self._h, tasks.ctypes.data, workers, rounds, o.ctypes.data, dma_engines,
                                        ctypes.byref(total), times.ctypes.data), "tgo_hw_run_rounds")
+        return int(total.value), times
+
+    def run_mem(self, tasks: np.ndarray, order, mem, capacity: int, dma_engines: int = 2):
+        """``run`` under a device-memory limit (tgo_hw_run_mem): mem[x] bytes
+        per task, at most ``capacity`` held.  Returns (makespan ns,
+        HW_TIMES_DTYPE [n])."""
+        tasks = np.ascontiguousarray(tasks, dtype=HW_TASK_DTYPE)
+        o = np.ascontiguousarray(order, dtype=np.uint8)
+        m = np.ascontiguousarray(np.asarray(mem, dtype=np.int64))
+        times = np.zeros(len(tasks), dtype=HW_TIMES_DTYPE)
+        total = ctypes.c_int64()
+        _check(lib().tgo_hw_run_mem(self._h, tasks.ctypes.data, len(tasks), o.ctypes.data, m.ctypes.data,
+                                    int(capacity), dma_engines, ctypes.byref(total), times.ctypes.data),
+               "tgo_hw_run_mem")
         return int(total.value), times
 
     def run_proxy(self, tasks: np.ndarray, durations, workers: int, rounds: int, model: Model = DEFAULT):

@@ -19,6 +19,14 @@ Steps (each measurement is the median of ``reps`` runs):
      ordering of each benchmark BK0..BK100 run on the device, and the model's
      prediction for every ordering (tgo_exhaustive with the tasks' measured
      solo command times) compared with the measured makespan.
+  5. Dependent tasks (Section 6.2): NoReorder orderings and a proxy running
+     the Heuristic setup, against tgo_rounds.
+  6. A device-memory limit: six of the synthetic tasks with their buffers
+     counted against a capacity, run with tgo_hw_run_mem, against
+     tgo_exhaustive_mem, with memory-streaming and with register-resident
+     task kernels.
+  7. Transfer speed under a concurrent kernel of each kind (the model has
+     transfers and kernels independent).
 
 Everything that runs on the device goes through the C ABI (tgo_hw_*,
 tgo_evaluate, tgo_exhaustive); this module only orchestrates and summarises.
@@ -44,9 +52,10 @@ def _median_run(hw, tasks, order, dma, reps):
     return totals[i], runs[i][1]
 
 
-def _one(htd=0, dth=0, elems=0, iters=0):
+def _one(htd=0, dth=0, elems=0, iters=0, kind=tgo.HW_KERNEL_HBM):
     t = np.zeros(1, dtype=tgo.HW_TASK_DTYPE)
     t["htd_bytes"], t["dth_bytes"], t["kern_elems"], t["kern_iters"] = htd, dth, elems, iters
+    t["kern_kind"] = kind
     return t
 
 
@@ -66,10 +75,10 @@ def calibrate_transfers(hw, sizes_mb, reps):
     return out
 
 
-def calibrate_kernel(hw, elems, iters_list, reps):
+def calibrate_kernel(hw, elems, iters_list, reps, kind=tgo.HW_KERNEL_HBM):
     xs, ys = [], []
     for it in iters_list:
-        _, times = _median_run(hw, _one(elems=elems, iters=it), [0], 2, reps)
+        _, times = _median_run(hw, _one(elems=elems, iters=it, kind=kind), [0], 2, reps)
         xs.append(float(elems) * it)
         ys.append(float(times[0]["end_ns"][1] - times[0]["start_ns"][1]))
     eta, gamma = tgo.fit_line(xs, ys)
@@ -233,6 +242,88 @@ def validate_rounds(hw, dev, xfer, kern, model, unit_ns, elems, reps, workers=4,
             "predicted_worst_ns": int(s["max_ns"]), "measured_at_predicted_worst_ns": meas[int(s["argmax_rank"])]}
 
 
+MEMORY_TASKS = ("T0", "T4", "T5", "T6", "T1", "T7")
+
+
+def interference(hw, xfer, kern, elems, reps, kind, mb=256):
+    """A transfer alone and under a concurrent kernel of the given kind (long
+    enough to cover it): the transfer's speed under the kernel as a fraction
+    of its solo speed.  The model of Section 4.2 has transfers and kernels
+    run independently (a rate of 1)."""
+    b = int(mb * MB)
+    solo_ns = {"htd": xfer["htd"]["latency_ns"] + b * xfer["htd"]["ns_per_byte"],
+               "dth": xfer["dth"]["latency_ns"] + b * xfer["dth"]["ns_per_byte"]}
+    it = max(1, int(round(2.5 * max(solo_ns.values()) / (kern["eta_ns_per_elem_pass"] * elems))))
+    k = _one(elems=elems, iters=it, kind=kind)
+    out = {"kernel_kind": kind, "bytes": b}
+    for name, tasks, order, x, c in (("htd", np.concatenate([k, _one(htd=b)]), [0, 1], 1, 0),
+                                     ("dth", np.concatenate([_one(dth=b), k]), [0, 1], 0, 2)):
+        _, alone = _median_run(hw, tasks[x:x + 1], [0], 2, reps)
+        _, tm = _median_run(hw, tasks, order, 2, reps)
+        t_alone = int(alone[0]["end_ns"][c] - alone[0]["start_ns"][c])
+        t_with = int(tm[x]["end_ns"][c] - tm[x]["start_ns"][c])
+        ks, ke = int(tm[1 - x]["start_ns"][1]), int(tm[1 - x]["end_ns"][1])
+        covered = ks <= int(tm[x]["start_ns"][c]) + 50_000 and ke >= int(tm[x]["end_ns"][c])
+        out[name] = {"alone_ns": t_alone, "with_kernel_ns": t_with, "rate": t_alone / t_with,
+                     "kernel_covers_transfer": bool(covered)}
+    return out
+
+
+def validate_memory(hw, dev, xfer, kern, model, unit_ns, elems, reps, frac=0.4, names=MEMORY_TASKS, seed=0,
+                    sample=16, dma_engines=2, kind=tgo.HW_KERNEL_HBM):
+    """A task group under a device-memory limit on the device: each task's
+    footprint is its bytes moved (input + output buffers), the capacity a
+    fraction of the group's total.  A seeded sample of orderings plus the
+    predicted best, worst and Algorithm 1's ordering run with tgo_hw_run_mem
+    and compared with tgo_exhaustive_mem's prediction; the predicted best
+    ordering without the limit is run under it too."""
+    import torch
+    n = len(names)
+    tasks = np.zeros(n, dtype=tgo.HW_TASK_DTYPE)
+    for i, nm in enumerate(names):
+        hb, db, it = build_task(W.PAPER_TASKS_UNITS[nm], unit_ns, xfer, kern, elems)
+        tasks[i] = (hb, db, elems, it, kind)
+    mem = (tasks["htd_bytes"] + tasks["dth_bytes"]).astype(np.int64)
+    cap = W.capacity_fraction(mem, frac)
+    solo = np.zeros((n, 3), dtype=np.int64)
+    for i in range(n):
+        _, tm = _median_run(hw, tasks[i:i + 1], [0], 2, reps)
+        solo[i] = tm[0]["end_ns"] - tm[0]["start_ns"]
+    mdl = tgo.Model(model.q_log2, model.p_htd, model.p_dth, dma_engines)
+    sd, md = torch.as_tensor(solo).to(dev), torch.as_tensor(mem).to(dev)
+    summ, po = tgo.exhaustive_mem(sd, md, cap, mdl, per_order=True)
+    pred = po.cpu().numpy()
+    s = tgo.read_summary(summ)
+    free, _ = tgo.exhaustive(sd, mdl)
+    free = tgo.read_summary(free)
+    count = len(pred)
+    rng = np.random.default_rng(seed)
+    heur = [int(v) for v in s["heur"][:n]]
+    ranks = sorted(set(rng.choice(count, size=min(sample, count), replace=False).tolist())
+                   | {int(s["argmin_rank"]), int(s["argmax_rank"]), tgo.rank(heur), int(free["argmin_rank"])})
+
+    def measure(order):
+        runs = [hw.run_mem(tasks, order, mem, cap, dma_engines)[0] for _ in range(reps)]
+        return int(np.median(runs))
+
+    meas = {rk: measure(tgo.unrank(n, rk)) for rk in ranks}
+    errs = [abs(int(pred[rk]) - m) / m for rk, m in meas.items()]
+    worst = meas[int(s["argmax_rank"])]
+    return {"tasks": list(names), "kernel_kind": kind, "dma_engines": dma_engines,
+            "capacity_frac": frac, "capacity_bytes": cap, "footprint_bytes": mem.tolist(),
+            "orderings": count, "measured": len(ranks),
+            "mean_err_pct": 100 * float(np.mean(errs)), "max_err_pct": 100 * float(np.max(errs)),
+            "predicted_best_ns": int(s["min_ns"]), "measured_at_predicted_best_ns": meas[int(s["argmin_rank"])],
+            "predicted_worst_ns": int(s["max_ns"]), "measured_at_predicted_worst_ns": worst,
+            "heuristic_predicted_ns": int(s["heur_ns"]), "heuristic_measured_ns": meas[tgo.rank(heur)],
+            "measured_speedup_best_vs_worst": worst / meas[int(s["argmin_rank"])],
+            "measured_speedup_heuristic_vs_worst": worst / meas[tgo.rank(heur)],
+            "unlimited_best_predicted_under_limit_ns": int(pred[int(free["argmin_rank"])]),
+            "unlimited_best_measured_under_limit_ns": meas[int(free["argmin_rank"])],
+            "unlimited_min_ns": int(free["min_ns"]),
+            "per_ordering": [[rk, int(pred[rk]), m] for rk, m in sorted(meas.items())]}
+
+
 def run(dev=None, unit_ms: float = 10.0, reps: int = 3, quick: bool = False):
     import torch
     dev = dev or torch.device("cuda:0")
@@ -244,6 +335,9 @@ def run(dev=None, unit_ms: float = 10.0, reps: int = 3, quick: bool = False):
     try:
         xfer = calibrate_transfers(hw, sizes, reps)
         kern = calibrate_kernel(hw, elems, iters, reps)
+        kern_alu = calibrate_kernel(hw, elems, [max(1, i // 4) for i in iters], reps, tgo.HW_KERNEL_ALU)
+        interf = [interference(hw, xfer, k, elems, reps, kind, mb=min(256, max(sizes)))
+                  for k, kind in ((kern, tgo.HW_KERNEL_HBM), (kern_alu, tgo.HW_KERNEL_ALU))]
         ov, model = overlap_experiments(hw, sizes[-3:], reps, dev)
         need = max(build_task(f, unit_ns, xfer, kern, elems)[i]
                    for f in W.PAPER_TASKS_UNITS.values() for i in (0, 1))
@@ -257,11 +351,20 @@ def run(dev=None, unit_ms: float = 10.0, reps: int = 3, quick: bool = False):
         rounds = [validate_rounds(hw, dev, xfer, kern, model, unit_ns, elems, reps, 4, 2, bk,
                                   sample=8 if quick else 24)
                   for bk in (("BK25",) if quick else ("BK25", "BK50", "BK75"))]
+        cases = (((0.4, 2, tgo.HW_KERNEL_HBM), (0.4, 2, tgo.HW_KERNEL_ALU)) if quick else
+                 ((0.25, 2, tgo.HW_KERNEL_HBM), (0.4, 2, tgo.HW_KERNEL_HBM), (0.6, 2, tgo.HW_KERNEL_HBM),
+                  (0.4, 1, tgo.HW_KERNEL_HBM), (0.4, 2, tgo.HW_KERNEL_ALU), (0.6, 2, tgo.HW_KERNEL_ALU),
+                  (0.4, 1, tgo.HW_KERNEL_ALU)))
+        memory = [validate_memory(hw, dev, xfer, kern if kind == tgo.HW_KERNEL_HBM else kern_alu, model, unit_ns,
+                                  elems, reps, frac, dma_engines=dma, sample=6 if quick else 16, kind=kind)
+                  for frac, dma, kind in cases]
     finally:
         hw.close()
     return {"unit_ms": unit_ms, "reps": reps,
             "transfers": {k: {kk: v[kk] for kk in ("gb_per_s", "latency_ns")} for k, v in xfer.items()},
             "kernel": {k: kern[k] for k in ("eta_ns_per_elem_pass", "gamma_ns")},
+            "kernel_alu": {k: kern_alu[k] for k in ("eta_ns_per_elem_pass", "gamma_ns")},
+            "interference": interf,
             "overlap": {k: ov[k] for k in ("rho_htd", "rho_dth", "model", "errors")},
             "overlap_records": ov["records"],
-            "two_dma": res2, "one_dma_scheme": res1, "rounds": rounds}
+            "two_dma": res2, "one_dma_scheme": res1, "rounds": rounds, "memory": memory}

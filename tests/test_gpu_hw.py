@@ -97,6 +97,44 @@ def test_proxy_runs_the_heuristic_setup(dev):
     hw.close()
 
 
+def test_memory_limit_holds_htds_back(dev):
+    """tgo_hw_run_mem: two DMA engines -- an HtD starts only after enough
+    earlier DtHs have ended to give its bytes back; one DMA engine -- greedy
+    sub-groups, each its HtDs then its DtHs."""
+    from paper_1806_10113_amd import tgo
+    hw = tgo.HwRunner(6, 16 * MB, 1 << 22)
+    tasks = np.zeros(6, dtype=tgo.HW_TASK_DTYPE)
+    for x in range(6):
+        tasks[x] = ((1 + x % 3) * MB, (1 + (x * 5) % 4) * MB, 1 << 22, 1 + x % 4, 0)
+    mem = (tasks["htd_bytes"] + tasks["dth_bytes"]).astype(np.int64)
+    cap = int(mem.sum() * 0.4)
+    slack = 20_000
+    for order in ([0, 1, 2, 3, 4, 5], [5, 3, 1, 0, 2, 4]):
+        total, t = hw.run_mem(tasks, order, mem, cap, 2)
+        s, e = t["start_ns"], t["end_ns"]
+        assert total == int(e.max())
+        for j, x in enumerate(order):
+            # every earlier task still holding memory at this HtD's start
+            held = sum(int(mem[order[i]]) for i in range(j) if e[order[i], 2] > s[x, 0] + slack)
+            assert held + int(mem[x]) <= cap
+        total1, t1 = hw.run_mem(tasks, order, mem, cap, 1)
+        s1, e1 = t1["start_ns"], t1["end_ns"]
+        groups, cur, held = [], [], 0
+        for x in order:
+            if cur and held + mem[x] > cap:
+                groups.append(cur)
+                cur, held = [], 0
+            cur.append(x)
+            held += int(mem[x])
+        groups.append(cur)
+        xq = [(x, c) for g in groups for c in (0, 2) for x in g]
+        for (a, ca), (b, cb) in zip(xq, xq[1:]):
+            assert e1[a, ca] <= s1[b, cb] + slack
+    with pytest.raises(tgo.TgoError):
+        hw.run_mem(tasks, list(range(6)), mem, int(mem.max()) - 1, 2)   # a task that cannot fit
+    hw.close()
+
+
 def test_fits_and_prediction_on_this_device(dev):
     from paper_1806_10113_amd import validate
     res = validate.run(dev, unit_ms=2.0, reps=3, quick=True)
@@ -111,3 +149,5 @@ def test_fits_and_prediction_on_this_device(dev):
     for v in res["rounds"]:
         assert v["mean_err_pct"] < 10.0, v
         assert v["heuristic_setup_err_pct"] < 15.0, v
+    for v in res["memory"]:
+        assert v["mean_err_pct"] < 10.0, v
