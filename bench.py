@@ -26,8 +26,11 @@ METRIC = "orderings evaluated/sec at N=12 (exact); groups/sec + p99 latency, Nâ‰
 N = 12
 SEED = 1
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 32-bit VALU lane-ops/s.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# MI355X: 256 CUs x 128 32-bit VALU lanes per clock x 2.4 GHz = 78.6e12
+# lane-ops/s (the same lane rate as the 157.3 TFLOP/s FP32 vector figure,
+# which counts an FMA as two operations); the integer issue probe reaches 1.92
+# of the 2 wave-instructions per CU-clock this implies.
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 # VALU lane-ops per ordering issued by exhaustive_kernel<u32, M=4> on this
 # workload: SQ_INSTS_VALU per launch x 64 lanes / 12! (rocprofv3 counter run
@@ -48,12 +51,17 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-extras", action="store_true",
                    help="skip the batched, learned-proposal and serving measurements")
+    p.add_argument("--extras", default="all",
+                   help="comma-separated subset of: batch, one_dma, rounds, memory, proposal, serving, hw "
+                        "(default all)")
     p.add_argument("--train-pairs", type=float, default=2e7,
                    help="exact (ordering, time) pairs used to train the proposal network")
     p.add_argument("--eval-groups", type=int, default=1024)
     p.add_argument("--serve-seconds", type=float, default=10.0)
     p.add_argument("--hw-unit-ms", type=float, default=10.0,
                    help="time unit of the synthetic tasks run on the device (0: skip that validation)")
+    p.add_argument("--calibrate-valu", action="store_true",
+                   help="also run the integer issue probe (for the ALU peak, read with counters)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a 256 MiB device copy (for HBM counter calibration)")
     return p.parse_args()
@@ -218,6 +226,53 @@ def rounds_extra(dev, seed: int = 11):
             "orderings_per_s": total_orderings / (total_ms / 1e3)}
 
 
+def memory_extra(dev):
+    """Task groups under a device-memory limit: the N = 12 group (footprint
+    = bytes moved at 57 GB/s) with capacities from its whole footprint down
+    to its largest task.  Per capacity and launch scheme: every ordering
+    (tgo_exhaustive_mem, timed with HIP events), speedups against the worst
+    ordering, and what ignoring the limit costs (the best ordering without
+    it, evaluated under it)."""
+    import numpy as np
+    import torch
+    from paper_1806_10113_amd import tgo, workloads as W
+    stream = torch.cuda.current_stream()
+    t_np = W.single_group_mixed(12, seed=1)
+    mem_np = W.footprints(t_np)
+    tasks, mem = torch.as_tensor(t_np).to(dev), torch.as_tensor(mem_np).to(dev)
+    out, total_ms, total_ord = {}, 0.0, 0
+    for dma in (2, 1):
+        model = tgo.Model(2, 3, 3, dma)
+        free, _ = tgo.exhaustive(tasks, model)
+        free = tgo.read_summary(free)
+        for frac in (1.0, 0.6, 0.4, 0.25, 0.0):
+            cap = W.capacity_fraction(mem_np, frac)
+            summ, _ = tgo.exhaustive_mem(tasks, mem, cap, model, stream=stream)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(3):
+                tgo.exhaustive_mem(tasks, mem, cap, model, summary=summ, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 3
+            s = tgo.read_summary(summ)
+            order = torch.as_tensor(np.asarray([free["best"]], dtype=np.uint8)).to(dev)
+            t_free = int(tgo.evaluate_mem(tasks, mem, cap, order, model).cpu()[0])
+            total_ms += ms
+            total_ord += s["count"]
+            out[f"dma{dma}_cap{frac:g}"] = {
+                "capacity_bytes": cap, "ms": ms, "orderings_per_s": s["count"] / (ms / 1e3),
+                "status": s["status"], "min_ns": s["min_ns"], "max_ns": s["max_ns"], "mean_ns": s["mean_ns"],
+                "heur_ns": s["heur_ns"], "speedup_best": s["max_ns"] / s["min_ns"],
+                "speedup_heuristic": s["max_ns"] / s["heur_ns"],
+                "unlimited_best_under_limit_ns": t_free,
+                "unlimited_best_vs_best_pct": 100.0 * (t_free / s["min_ns"] - 1.0)}
+    return {"workload": "N=12 mixed group (seed 1), footprint = (h + d) x 57 B/ns, total "
+                        f"{int(mem_np.sum())} B", "cases": out,
+            "orderings_per_s": total_ord / (total_ms / 1e3)}
+
+
 def hw_validation_extra(dev, unit_ms: float):
     """The model against real HtD / kernel / DtH tasks on this device
     (Sections 4.2, 4.3): fitted rates, overlap-model errors, and the mean
@@ -225,7 +280,8 @@ def hw_validation_extra(dev, unit_ms: float):
     from paper_1806_10113_amd import validate
     r = validate.run(dev, unit_ms=unit_ms, reps=3)
     out = {"unit_ms": unit_ms, "transfers": r["transfers"], "kernel": r["kernel"], "overlap": r["overlap"],
-           "rounds": r["rounds"]}
+           "rounds": r["rounds"], "kernel_alu": r["kernel_alu"], "interference": r["interference"],
+           "memory": [{k: v for k, v in m.items() if k != "per_ordering"} for m in r["memory"]]}
     for sc in ("two_dma", "one_dma_scheme"):
         out[sc] = {"geomean_err_pct": r[sc]["geomean_err_pct"],
                    "benchmarks": {b: {k: v[k] for k in ("mean_err_pct", "max_err_pct", "measured_speedup_best",
@@ -384,6 +440,17 @@ def main():
     stream = torch.cuda.current_stream()
     summary = torch.empty(tgo.SUMMARY_DTYPE.itemsize, dtype=torch.uint8, device=dev)
 
+    if args.calibrate_valu:
+        # 8,192 blocks x 256 threads x 2,000 x 16 x 8 x 2 instructions
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tgo.valu_probe(8192, 2000, stream)
+        e0.record(stream)
+        tgo.valu_probe(8192, 2000, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        lane_ops = 8192 * 256 * 2000 * 16 * 8 * 2
+        print(json.dumps({"valu_probe_ms": e0.elapsed_time(e1),
+                          "valu_probe_tops": lane_ops / (e0.elapsed_time(e1) / 1e3) / 1e12}), file=sys.stderr)
     if args.calibrate_copy:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
@@ -456,14 +523,23 @@ def main():
         "min_ns": s["min_ns"], "mean_ns": s["mean_ns"],
     }
     if not args.no_extras:
-        extras = {"batch": batch_extra(dev), "one_dma": one_dma_extra(dev), "rounds": rounds_extra(dev)}
-        sur, tr = train_surrogate(dev, args.train_pairs)
-        extras["proposal_training"] = tr
-        extras["proposal_n16"] = surrogate_extra(dev, sur, args.eval_groups)
-        extras["serving"] = serving_extra(dev, sur, args.serve_seconds)
-        if args.hw_unit_ms > 0:
+        want = set(args.extras.split(",")) if args.extras != "all" else \
+            {"batch", "one_dma", "rounds", "memory", "proposal", "serving", "hw"}
+        extras = {}
+        for name, fn in (("batch", batch_extra), ("one_dma", one_dma_extra), ("rounds", rounds_extra),
+                         ("memory", memory_extra)):
+            if name in want:
+                extras[name] = fn(dev)
+        if want & {"proposal", "serving"}:
+            sur, tr = train_surrogate(dev, args.train_pairs)
+            extras["proposal_training"] = tr
+            if "proposal" in want:
+                extras["proposal_n16"] = surrogate_extra(dev, sur, args.eval_groups)
+            if "serving" in want:
+                extras["serving"] = serving_extra(dev, sur, args.serve_seconds)
+            sur.close()
+        if "hw" in want and args.hw_unit_ms > 0:
             extras["hw_validation"] = hw_validation_extra(dev, args.hw_unit_ms)
-        sur.close()
         out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(tasks_np, args.cpu_seconds)

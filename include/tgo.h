@@ -481,6 +481,12 @@ int tgo_hw_run_proxy(tgo_hw *hw, const tgo_model *model, const tgo_hw_task *h_ta
  * Section 4.2.1.  h_times[4] = HtD start, HtD end, DtH start, DtH end (ns).
  * Blocking. */
 int tgo_hw_overlap(tgo_hw *hw, int64_t htd_bytes, int64_t dth_bytes, int64_t dth_delay_ns, int64_t *h_times);
+/* Integer issue probe for the ALU roofline: `blocks` blocks of 256 threads,
+ * each thread running eight independent chains of 32-bit shift-and-add for
+ * iters x 16 steps (2 VALU instructions per step and chain, no memory
+ * traffic).  Its counter run gives the 32-bit VALU instructions a CU issues
+ * per clock.  Enqueued on `stream`. */
+int tgo_valu_probe(int blocks, int iters, tgo_stream stream);
 /* Least-squares line y = slope * x + intercept over n >= 2 points (host); the
  * kernel model T = eta * m + gamma of Eq. 1, and transfer time against size. */
 int tgo_fit_line(const double *h_x, const double *h_y, int n, double *slope, double *intercept);

@@ -1,0 +1,195 @@
+// Task groups under a device-memory limit: lane-level simulators.
+//
+// Section 5 observes that tasks running at the same time hold their input and
+// output buffers at once, so the device memory can restrict which tasks may
+// run together; the paper assumes enough memory.  Reading: task x holds
+// mem[x] bytes from the start of its HtD to the end of its DtH, at most `cap`
+// bytes at once.
+//
+// Two DMA engines (GSim): the HtD at the head of its queue starts only when
+// its bytes fit beside those held; the HtDs behind it wait too.  The engine
+// can then sit idle while a DtH finishes, which breaks the premise of the
+// window formulation (an HtD engine busy without gaps), so the simulation
+// steps events: at each instant finished commands retire and ready heads
+// start until nothing changes, then time advances to the earliest
+// completion estimate.  Remaining transfer work is exact in 1/q solo-ns;
+// estimates round up to whole ns; an HtD and a DtH moving data together
+// advance at p_htd/q and p_dth/q.  DtHs end in launch order, so the bytes
+// held are those of positions [DtHs done, HtDs started).
+//
+// One DMA engine (Chain): the ordering is cut greedily into consecutive
+// sub-groups whose bytes fit together, each launched as its HtDs and then its
+// DtHs on the one transfer engine.  Transfers never overlap, so no rate
+// applies and the schedule is the closed-form chain: HtDs back to back,
+// K_i = max(HtD_i end, K_{i-1} end) + k_i, and after the sub-group's last HtD
+// its DtHs in order, D_i = max(K_i, D_{i-1}) + d_i; the next sub-group's HtDs
+// follow its last DtH.
+//
+// Both expose push (place the next task; for GSim the simulation then runs
+// to the instant that task's HtD ends, after which nothing depends on later
+// positions) and finish (run to the end, return T).  An enumeration can thus
+// keep the state after a common prefix and extend it per suffix.
+#pragma once
+
+#include "model_dev.h"
+
+namespace tgo {
+
+template <typename TT>
+struct MemTab {
+    TT qh[MAXN], k[MAXN], qd[MAXN];  // q * h, k, q * d
+    TT h[MAXN], d[MAXN];
+    uint64_t m[MAXN];
+};
+
+__device__ __forceinline__ uint32_t mnib(uint64_t v, int i) { return (uint32_t)(v >> (4 * i)) & 15u; }
+
+template <typename TT>
+struct GSim {
+    TT t, uh, ud, kend;
+    uint64_t held;
+    uint64_t seq;   // nibble j: task at position j
+    int n;          // positions placed
+    int hc, kc, dc; // next position to start on each engine
+    int hd, kd, dd; // positions finished on each engine (running: started > finished)
+};
+
+template <typename TT>
+__device__ __forceinline__ void gsim_init(GSim<TT> &s) {
+    s.t = s.uh = s.ud = s.kend = 0;
+    s.held = 0;
+    s.seq = 0;
+    s.n = s.hc = s.kc = s.dc = s.hd = s.kd = s.dd = 0;
+}
+
+// All retirements and starts at the current instant.
+template <typename TT>
+__device__ __forceinline__ void gsim_pass(GSim<TT> &s, const MemTab<TT> &tb, uint64_t cap) {
+    bool changed = true;
+    while (changed) {
+        changed = false;
+        if (s.hc > s.hd && s.uh == 0) { ++s.hd; changed = true; }
+        if (s.kc > s.kd && s.kend == s.t) { ++s.kd; changed = true; }
+        if (s.dc > s.dd && s.ud == 0) {
+            s.held -= tb.m[mnib(s.seq, s.dd)];
+            ++s.dd;
+            changed = true;
+        }
+        if (s.hc == s.hd && s.hc < s.n) {
+            const uint32_t x = mnib(s.seq, s.hc);
+            if (s.held + tb.m[x] <= cap) {
+                s.held += tb.m[x];
+                s.uh = tb.qh[x];
+                ++s.hc;
+                changed = true;
+            }
+        }
+        if (s.kc == s.kd && s.kc < s.hd) {
+            s.kend = s.t + tb.k[mnib(s.seq, s.kc)];
+            ++s.kc;
+            changed = true;
+        }
+        if (s.dc == s.dd && s.dc < s.kd) {
+            s.ud = tb.qd[mnib(s.seq, s.dc)];
+            ++s.dc;
+            changed = true;
+        }
+    }
+}
+
+// Advance to the earliest completion estimate; false when nothing runs.
+template <typename TT>
+__device__ __forceinline__ bool gsim_advance(GSim<TT> &s, const Rates &r) {
+    const bool hrun = s.hc > s.hd, krun = s.kc > s.kd, drun = s.dc > s.dd;
+    if (!hrun && !krun && !drun) return false;
+    const bool both = hrun && drun;
+    const TT INF = inf_time<TT>();
+    const TT eh = hrun ? (both ? (TT)ceil_p(s.uh, r.p_h, r.inv_ph, r.c_ph) : ceil_q(s.uh, r.q_log2)) : INF;
+    const TT ed = drun ? (both ? (TT)ceil_p(s.ud, r.p_d, r.inv_pd, r.c_pd) : ceil_q(s.ud, r.q_log2)) : INF;
+    const TT ek = krun ? s.kend - s.t : INF;
+    TT dt = eh < ed ? eh : ed;
+    dt = ek < dt ? ek : dt;
+    const TT q = TT(1) << r.q_log2;
+    if (hrun) s.uh = eh == dt ? TT(0) : s.uh - (both ? TT(r.p_h) : q) * dt;
+    if (drun) s.ud = ed == dt ? TT(0) : s.ud - (both ? TT(r.p_d) : q) * dt;
+    s.t += dt;
+    return true;
+}
+
+// Place task x at the next position and run to the instant its HtD ends.
+template <typename TT>
+__device__ __forceinline__ void gsim_push(GSim<TT> &s, uint32_t x, const MemTab<TT> &tb, uint64_t cap,
+                                          const Rates &r) {
+    s.seq |= (uint64_t)x << (4 * s.n);
+    ++s.n;
+    for (;;) {
+        gsim_pass(s, tb, cap);
+        if (s.hd == s.n) break;
+        if (!gsim_advance(s, r)) break;
+    }
+}
+
+// Run to the end; returns T.  *tk (if given) receives the end of the last
+// kernel.
+template <typename TT>
+__device__ __forceinline__ TT gsim_finish(GSim<TT> &s, const MemTab<TT> &tb, uint64_t cap, const Rates &r,
+                                          TT *tk = nullptr) {
+    for (;;) {
+        gsim_pass(s, tb, cap);
+        if (tk && s.kd == s.n && *tk == inf_time<TT>()) *tk = s.t;
+        if (!gsim_advance(s, r)) break;
+    }
+    return s.t;
+}
+
+template <typename TT>
+struct Chain {
+    TT x;         // transfer engine: end of the open sub-group's last HtD
+    TT kp;        // end of the last kernel
+    TT x0, kp0;   // transfer end and kernel end when the open sub-group began
+    uint64_t held;
+    uint64_t seq;
+    int n, b;     // positions placed; the open sub-group starts at b
+};
+
+template <typename TT>
+__device__ __forceinline__ void chain_init(Chain<TT> &c) {
+    c.x = c.kp = c.x0 = c.kp0 = 0;
+    c.held = 0;
+    c.seq = 0;
+    c.n = c.b = 0;
+}
+
+// The open sub-group's DtHs (its kernel ends recomputed from its start).
+template <typename TT>
+__device__ __forceinline__ void chain_close(Chain<TT> &c, const MemTab<TT> &tb) {
+    TT X = c.x0, K = c.kp0, D = c.x;
+    for (int i = c.b; i < c.n; ++i) {
+        const uint32_t y = mnib(c.seq, i);
+        X += tb.h[y];
+        K = tmax(X, K) + tb.k[y];
+        D = tmax(K, D) + tb.d[y];
+    }
+    c.x = c.x0 = D;
+    c.kp0 = c.kp;
+    c.b = c.n;
+    c.held = 0;
+}
+
+template <typename TT>
+__device__ __forceinline__ void chain_push(Chain<TT> &c, uint32_t x, const MemTab<TT> &tb, uint64_t cap) {
+    if (c.n > c.b && c.held + tb.m[x] > cap) chain_close(c, tb);
+    c.seq |= (uint64_t)x << (4 * c.n);
+    ++c.n;
+    c.held += tb.m[x];
+    c.x += tb.h[x];
+    c.kp = tmax(c.x, c.kp) + tb.k[x];
+}
+
+template <typename TT>
+__device__ __forceinline__ TT chain_finish(Chain<TT> &c, const MemTab<TT> &tb) {
+    if (c.n > c.b) chain_close(c, tb);
+    return c.x;
+}
+
+}  // namespace tgo

@@ -24,17 +24,6 @@
 // DtH at p_htd/q and p_dth/q).  Launch schemes of Section 3.2: two DMA
 // engines = three FIFO queues in submission order; one DMA engine = one
 // transfer queue holding, per submitted group, its HtDs then its DtHs.
-//
-// The same stepping evaluates single task groups under a device-memory limit
-// (Section 5 notes that concurrent tasks hold their buffers at once; the
-// paper assumes enough memory).  Reading: task x holds mem[x] bytes from the
-// start of its HtD to the end of its DtH, at most `cap` at once.  With two
-// DMA engines the HtD at the head of its queue starts only when its bytes fit
-// beside those held (DtHs end in launch order, so the wait always ends when
-// every task fits alone); with one DMA engine the ordering is cut greedily
-// into consecutive sub-groups whose buffers fit together, each launched as
-// its HtDs then its DtHs.  Algorithm 1 keeps its rules, its update step
-// simulated under the same limit.
 #include <hip/hip_runtime.h>
 
 #include "enum_dev.h"
@@ -73,7 +62,6 @@ struct RSim {
     bool hrun, krun, drun;  // one engine: hrun/drun say which transfer runs
     int hpos, dpos;         // position of the running transfer(s)
     int64_t uh, ud, kend;   // remaining transfer work (1/q ns), kernel end
-    int64_t held;           // device-memory limit: bytes held by started tasks
 };
 
 __device__ __forceinline__ void rsim_init(RSim &s) {
@@ -88,7 +76,6 @@ __device__ __forceinline__ void rsim_init(RSim &s) {
     s.hrun = s.krun = s.drun = false;
     s.hpos = s.dpos = 0;
     s.uh = s.ud = s.kend = 0;
-    s.held = 0;
 }
 
 // Append a group of tasks (in launch order) at the current instant.
@@ -116,12 +103,9 @@ __device__ __forceinline__ bool dep_ok(const RSim &s, int j, int R) {
 // ready head.  Returns whether anything changed; finished DtHs are reported
 // in *arrived (bit x: the worker's next task x became available), the start
 // of the HtD at position trig in *trig_started.
-// MEM: the HtD of task x also waits until mem[x] fits beside the bytes held
-// (cap); its bytes are held until its DtH ends.
-template <bool ONE, bool MEM = false>
+template <bool ONE>
 __device__ __forceinline__ bool rsim_pass(RSim &s, const Dur *tab, int R, const Rates &r, int trig,
-                                          uint32_t *arrived, bool *trig_started,
-                                          const int64_t *mem = nullptr, int64_t cap = 0) {
+                                          uint32_t *arrived, bool *trig_started) {
     bool changed = false;
     const int64_t q = int64_t(1) << r.q_log2;
     // retire
@@ -133,14 +117,11 @@ __device__ __forceinline__ bool rsim_pass(RSim &s, const Dur *tab, int R, const 
         changed = true;
         const uint32_t x = nib(s.seq, s.dpos);
         if (x % (uint32_t)R + 1 < (uint32_t)R) *arrived |= 1u << (x + 1);
-        if constexpr (MEM) s.held -= mem[x];
     }
     // start ready heads
     if constexpr (!ONE) {
-        if (!s.hrun && s.hc < s.nsub && dep_ok(s, s.hc, R) &&
-            (!MEM || s.held + mem[nib(s.seq, s.hc)] <= cap)) {
+        if (!s.hrun && s.hc < s.nsub && dep_ok(s, s.hc, R)) {
             s.hpos = s.hc++;
-            if constexpr (MEM) s.held += mem[nib(s.seq, s.hpos)];
             s.uh = q * tab[nib(s.seq, s.hpos)].h;
             s.hrun = true;
             changed = true;
@@ -164,9 +145,8 @@ __device__ __forceinline__ bool rsim_pass(RSim &s, const Dur *tab, int R, const 
             const int len = s.xe - s.xb;
             if (s.xo < len) {
                 const int j = s.xb + s.xo;
-                if (dep_ok(s, j, R) && (!MEM || s.held + mem[nib(s.seq, j)] <= cap)) {
+                if (dep_ok(s, j, R)) {
                     s.hpos = j;
-                    if constexpr (MEM) s.held += mem[nib(s.seq, j)];
                     s.uh = q * tab[nib(s.seq, j)].h;
                     s.hrun = true;
                     ++s.xo;
@@ -214,35 +194,15 @@ __device__ __forceinline__ bool rsim_advance(RSim &s, const Rates &r) {
 }
 
 // NoReorder: simulate one fully queued launch sequence (groups are rounds).
-template <bool ONE, bool MEM = false>
-__device__ int64_t rsim_noreorder(RSim &s, const Dur *tab, int R, const Rates &r, const int64_t *mem = nullptr,
-                                  int64_t cap = 0) {
+template <bool ONE>
+__device__ int64_t rsim_noreorder(RSim &s, const Dur *tab, int R, const Rates &r) {
     for (;;) {
         uint32_t arrived = 0;
         bool trig = false;
-        while (rsim_pass<ONE, MEM>(s, tab, R, r, -1, &arrived, &trig, mem, cap)) {}
+        while (rsim_pass<ONE>(s, tab, R, r, -1, &arrived, &trig)) {}
         if (!rsim_advance<ONE>(s, r)) break;
     }
     return s.t;
-}
-
-// Device-memory limit: queue one group launched in `order` (n tasks); one DMA
-// engine cuts it into consecutive sub-groups whose bytes fit together.
-template <bool ONE>
-__device__ __forceinline__ void rsim_submit_mem(RSim &s, const uint8_t *order, int n, const int64_t *mem,
-                                                int64_t cap) {
-    if constexpr (!ONE) {
-        rsim_submit(s, order, n);
-    } else {
-        int b = 0;
-        while (b < n) {
-            int e = b;
-            int64_t held = 0;
-            while (e < n && (e == b || held + mem[order[e]] <= cap)) held += mem[order[e++]];
-            rsim_submit(s, order + b, e - b);
-            b = e;
-        }
-    }
 }
 
 __device__ __forceinline__ bool valid_task(const tgo_task &t) {
@@ -255,16 +215,12 @@ struct RAcc {
     uint64_t min_t, min_r, max_t, max_r, sum_lo, sum_hi, fp;
 };
 
-// MEM: one group (R = 1) under the device-memory limit (mem, cap).
-template <bool ONE, bool STORE, bool MEM = false>
+template <bool ONE, bool STORE>
 __global__ __launch_bounds__(RD_THREADS) void rounds_kernel(const tgo_task *__restrict__ tasks, int T,
                                                             int R, Rates r, uint32_t count,
                                                             uint32_t tfact, int64_t *out,
-                                                            Partial *partials,
-                                                            const int64_t *__restrict__ mem = nullptr,
-                                                            int64_t cap = 0) {
+                                                            Partial *partials) {
     __shared__ Dur tab[MAXN];
-    __shared__ int64_t mtab[MAXN];
     __shared__ int bad;
     const int n = T * R;
     if (threadIdx.x == 0) bad = 0;
@@ -273,17 +229,12 @@ __global__ __launch_bounds__(RD_THREADS) void rounds_kernel(const tgo_task *__re
         const tgo_task t = tasks[threadIdx.x];
         if (!valid_task(t)) atomicOr(&bad, 1);
         tab[threadIdx.x] = Dur{t.htd_ns, t.kern_ns, t.dth_ns};
-        if constexpr (MEM) {
-            const int64_t m = mem[threadIdx.x];
-            if (m < 0 || m > cap) atomicOr(&bad, 2);
-            mtab[threadIdx.x] = m;
-        }
     }
     __syncthreads();
     if (bad) {
         if (threadIdx.x == 0) {
             Partial p = {};
-            p.status = (bad & 2) ? TGO_EINVAL : TGO_ERANGE;
+            p.status = TGO_ERANGE;
             partials[blockIdx.x] = p;
         }
         return;
@@ -316,10 +267,8 @@ __global__ __launch_bounds__(RD_THREADS) void rounds_kernel(const tgo_task *__re
         }
         RSim s;
         rsim_init(s);
-        if constexpr (MEM) rsim_submit_mem<ONE>(s, order, n, mtab, cap);
-        else
-            for (int rr = 0; rr < R; ++rr) rsim_submit(s, order + rr * T, T);
-        const uint64_t Tt = (uint64_t)rsim_noreorder<ONE, MEM>(s, tab, R, r, mtab, cap);
+        for (int rr = 0; rr < R; ++rr) rsim_submit(s, order + rr * T, T);
+        const uint64_t Tt = (uint64_t)rsim_noreorder<ONE>(s, tab, R, r);
         if constexpr (STORE) out[rk] = (int64_t)Tt;
         if (Tt < a.min_t) { a.min_t = Tt; a.min_r = rk; }
         if (Tt + 1 > a.max_t) { a.max_t = Tt + 1; a.max_r = rk; }
@@ -509,6 +458,13 @@ __global__ __launch_bounds__(64) void rounds_heuristic_kernel(const tgo_task *__
     if (groups) *groups = (uint16_t)s.gend;
 }
 
+int launch_summary_finalize(const Partial *d_parts, int nparts, int T, int R, uint64_t count, uint64_t tfact,
+                            tgo_summary *d_out, hipStream_t st) {
+    hipLaunchKernelGGL(rounds_finalize, dim3(1), dim3(256), 0, st, d_parts, nparts, T, R, count, tfact, d_out);
+    TGO_HIP(hipGetLastError());
+    return TGO_OK;
+}
+
 int launch_rounds(const Rates &r, const tgo_task *d_tasks, int T, int R, int64_t *d_per_order,
                   tgo_summary *d_out, uint16_t *d_groups, hipStream_t st) {
     const uint64_t tf = factorial(T);
@@ -545,189 +501,6 @@ int launch_rounds(const Rates &r, const tgo_task *d_tasks, int T, int R, int64_t
     else
         hipLaunchKernelGGL(rounds_heuristic_kernel<false>, dim3(1), dim3(64), 0, st, d_tasks, T, R, r, d_out,
                            d_groups);
-    TGO_HIP(hipGetLastError());
-    return TGO_OK;
-}
-
-// ------------------------------------------------------ device-memory limit
-
-// The group launched in ord[0..len) simulated alone under the limit: the end
-// of the last HtD, of the last kernel and of the last DtH (Algorithm 1's
-// update).  th / tk are taken at the instant their count reaches len.
-template <bool ONE>
-__device__ Fit3 mem_update(const uint8_t *ord, int len, const Dur *tab, const int64_t *mem, int64_t cap,
-                           const Rates &r) {
-    RSim s;
-    rsim_init(s);
-    rsim_submit_mem<ONE>(s, ord, len, mem, cap);
-    Fit3 u{-1, -1, -1};
-    for (;;) {
-        uint32_t arrived = 0;
-        bool trig = false;
-        while (rsim_pass<ONE, true>(s, tab, 1, r, -1, &arrived, &trig, mem, cap)) {}
-        if (u.th < 0 && s.h_done == len) u.th = s.t;
-        if (u.tk < 0 && s.k_done == len) u.tk = s.t;
-        if (!rsim_advance<ONE>(s, r)) break;
-    }
-    u.td = s.t;
-    return u;
-}
-
-// Algorithm 1 under the device-memory limit (one thread): the selection
-// rules of the unconstrained heuristic, every update step simulated with
-// mem_update.
-template <bool ONE>
-__global__ __launch_bounds__(64) void mem_heuristic_kernel(const tgo_task *__restrict__ tasks,
-                                                           const int64_t *__restrict__ mem, int n, int64_t cap,
-                                                           Rates r, tgo_summary *out) {
-    __shared__ Dur tab[MAXN];
-    __shared__ int64_t mtab[MAXN];
-    if (threadIdx.x != 0) return;
-    for (int x = 0; x < n; ++x) {
-        const tgo_task t = tasks[x];
-        const int64_t m = mem[x];
-        if (!valid_task(t) || m < 0 || m > cap) {
-            out->heur_ns = valid_task(t) ? TGO_EINVAL : TGO_ERANGE;
-            return;
-        }
-        tab[x] = Dur{t.htd_ns, t.kern_ns, t.dth_ns};
-        mtab[x] = m;
-    }
-    uint8_t ord[MAXN];
-    uint32_t rt = (1u << n) - 1u;
-    int first = 0;
-    for (int x = 1; x < n; ++x) {
-        const int64_t kh = tab[x].k - tab[x].h, bkh = tab[first].k - tab[first].h;
-        if (kh > bkh || (kh == bkh && tab[x].d > tab[first].d)) first = x;
-    }
-    ord[0] = (uint8_t)first;
-    rt &= ~(1u << first);
-    int pos = 1;
-    while (__popc(rt) > 2) {
-        const Fit3 u = mem_update<ONE>(ord, pos, tab, mtab, cap, r);
-        int best = -1;
-        int64_t bf = 0;
-        for (int c = 0; c < n; ++c) {
-            if (!((rt >> c) & 1u)) continue;
-            const int64_t f = fit(tab[c].h, tab[c].k, u);
-            if (best < 0 || f < bf) { best = c; bf = f; }
-        }
-        ord[pos++] = (uint8_t)best;
-        rt &= ~(1u << best);
-    }
-    if (__popc(rt) == 2) {
-        const int a = __ffs(rt) - 1, b = 31 - __clz(rt);
-        const Fit3 u = mem_update<ONE>(ord, pos, tab, mtab, cap, r);
-        int bx = -1, by = -1;
-        int64_t bs = 0, bdy = 0;
-        for (int o = 0; o < 2; ++o) {
-            const int x = o == 0 ? a : b, y = o == 0 ? b : a;
-            ord[pos] = (uint8_t)x;
-            const Fit3 w = mem_update<ONE>(ord, pos + 1, tab, mtab, cap, r);
-            const int64_t sc = fit(tab[x].h, tab[x].k, u) + fit(tab[y].h, tab[y].k, w) + tab[y].d;
-            if (bx < 0 || sc < bs || (sc == bs && tab[y].d < bdy)) { bx = x; by = y; bs = sc; bdy = tab[y].d; }
-        }
-        ord[pos] = (uint8_t)bx;
-        ord[pos + 1] = (uint8_t)by;
-        pos += 2;
-    } else if (__popc(rt) == 1) {
-        ord[pos++] = (uint8_t)(__ffs(rt) - 1);
-    }
-    const Fit3 f = mem_update<ONE>(ord, n, tab, mtab, cap, r);
-    for (int j = 0; j < 16; ++j) out->heur[j] = j < n ? ord[j] : (uint8_t)0xff;
-    out->heur_ns = f.td;
-}
-
-// T of given orderings (rows of n bytes) under the limit; one lane per row.
-template <bool ONE>
-__global__ __launch_bounds__(RD_THREADS) void mem_evaluate_kernel(const tgo_task *__restrict__ tasks,
-                                                                  const int64_t *__restrict__ mem, int n,
-                                                                  int64_t cap, Rates r,
-                                                                  const uint8_t *__restrict__ orders, int64_t m,
-                                                                  int64_t *out) {
-    __shared__ Dur tab[MAXN];
-    __shared__ int64_t mtab[MAXN];
-    __shared__ int bad;
-    if (threadIdx.x == 0) bad = 0;
-    __syncthreads();
-    if ((int)threadIdx.x < n) {
-        const tgo_task t = tasks[threadIdx.x];
-        const int64_t mm = mem[threadIdx.x];
-        if (!valid_task(t)) atomicOr(&bad, 1);
-        if (mm < 0 || mm > cap) atomicOr(&bad, 2);
-        tab[threadIdx.x] = Dur{t.htd_ns, t.kern_ns, t.dth_ns};
-        mtab[threadIdx.x] = mm;
-    }
-    __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    if (bad) {
-        out[i] = (bad & 2) ? TGO_EINVAL : TGO_ERANGE;
-        return;
-    }
-    uint8_t ord[MAXN];
-    uint32_t seen = 0;
-    for (int j = 0; j < n; ++j) {
-        const uint8_t x = orders[i * n + j];
-        if (x >= n || ((seen >> x) & 1u)) {
-            out[i] = TGO_EINVAL;
-            return;
-        }
-        seen |= 1u << x;
-        ord[j] = x;
-    }
-    RSim s;
-    rsim_init(s);
-    rsim_submit_mem<ONE>(s, ord, n, mtab, cap);
-    out[i] = rsim_noreorder<ONE, true>(s, tab, 1, r, mtab, cap);
-}
-
-int launch_memory(const Rates &r, const tgo_task *d_tasks, const int64_t *d_mem, int n, int64_t cap,
-                  int64_t *d_per_order, tgo_summary *d_out, hipStream_t st) {
-    const uint64_t count = factorial(n);
-    const uint64_t want = (count + RD_THREADS - 1) / RD_THREADS;
-    const uint32_t blocks = (uint32_t)(want < RD_MAX_BLOCKS ? want : RD_MAX_BLOCKS);
-    Partial *parts = nullptr;
-    int rc = workspace(sizeof(Partial) * blocks, (void **)&parts);
-    if (rc) return rc;
-    const uint32_t c32 = (uint32_t)count;
-    if (r.one_dma) {
-        if (d_per_order)
-            hipLaunchKernelGGL((rounds_kernel<true, true, true>), dim3(blocks), dim3(RD_THREADS), 0, st, d_tasks,
-                               n, 1, r, c32, c32, d_per_order, parts, d_mem, cap);
-        else
-            hipLaunchKernelGGL((rounds_kernel<true, false, true>), dim3(blocks), dim3(RD_THREADS), 0, st,
-                               d_tasks, n, 1, r, c32, c32, nullptr, parts, d_mem, cap);
-    } else {
-        if (d_per_order)
-            hipLaunchKernelGGL((rounds_kernel<false, true, true>), dim3(blocks), dim3(RD_THREADS), 0, st,
-                               d_tasks, n, 1, r, c32, c32, d_per_order, parts, d_mem, cap);
-        else
-            hipLaunchKernelGGL((rounds_kernel<false, false, true>), dim3(blocks), dim3(RD_THREADS), 0, st,
-                               d_tasks, n, 1, r, c32, c32, nullptr, parts, d_mem, cap);
-    }
-    TGO_HIP(hipGetLastError());
-    hipLaunchKernelGGL(rounds_finalize, dim3(1), dim3(256), 0, st, parts, (int)blocks, n, 1, count, count, d_out);
-    TGO_HIP(hipGetLastError());
-    if (r.one_dma)
-        hipLaunchKernelGGL(mem_heuristic_kernel<true>, dim3(1), dim3(64), 0, st, d_tasks, d_mem, n, cap, r, d_out);
-    else
-        hipLaunchKernelGGL(mem_heuristic_kernel<false>, dim3(1), dim3(64), 0, st, d_tasks, d_mem, n, cap, r,
-                           d_out);
-    TGO_HIP(hipGetLastError());
-    return TGO_OK;
-}
-
-int launch_memory_evaluate(const Rates &r, const tgo_task *d_tasks, const int64_t *d_mem, int n, int64_t cap,
-                           const uint8_t *d_orders, int64_t m, int64_t *d_out, hipStream_t st) {
-    if (m == 0) return TGO_OK;
-    const int64_t blocks = (m + RD_THREADS - 1) / RD_THREADS;
-    if (r.one_dma)
-        hipLaunchKernelGGL(mem_evaluate_kernel<true>, dim3((uint32_t)blocks), dim3(RD_THREADS), 0, st, d_tasks,
-                           d_mem, n, cap, r, d_orders, m, d_out);
-    else
-        hipLaunchKernelGGL(mem_evaluate_kernel<false>, dim3((uint32_t)blocks), dim3(RD_THREADS), 0, st, d_tasks,
-                           d_mem, n, cap, r, d_orders, m, d_out);
     TGO_HIP(hipGetLastError());
     return TGO_OK;
 }

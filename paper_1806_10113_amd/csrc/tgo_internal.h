@@ -48,6 +48,10 @@ int launch_evaluate(const Rates &r, const tgo_task *d_tasks, int n, const uint8_
                     int64_t m, int64_t *d_out, hipStream_t st);
 int launch_rounds(const Rates &r, const tgo_task *d_tasks, int T, int R, int64_t *d_per_order,
                   tgo_summary *d_out, uint16_t *d_groups, hipStream_t st);
+// Block partials -> summary over (T!)^R ranks of T*R tasks (T = n, R = 1 for
+// one group); best / worst decoded as launch sequences.
+int launch_summary_finalize(const Partial *d_parts, int nparts, int T, int R, uint64_t count, uint64_t tfact,
+                            tgo_summary *d_out, hipStream_t st);
 int launch_memory(const Rates &r, const tgo_task *d_tasks, const int64_t *d_mem, int n, int64_t cap,
                   int64_t *d_per_order, tgo_summary *d_out, hipStream_t st);
 int launch_memory_evaluate(const Rates &r, const tgo_task *d_tasks, const int64_t *d_mem, int n, int64_t cap,

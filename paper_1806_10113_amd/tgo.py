@@ -137,6 +137,8 @@ def lib():
         L.tgo_hw_run_rounds.restype = i32
         L.tgo_hw_run_mem.argtypes = [vp, vp, i32, vp, vp, i64, i32, ctypes.POINTER(ctypes.c_int64), vp]
         L.tgo_hw_run_mem.restype = i32
+        L.tgo_valu_probe.argtypes = [i32, i32, vp]
+        L.tgo_valu_probe.restype = i32
         L.tgo_hw_run_proxy.argtypes = [vp, M, vp, vp, i32, i32, ctypes.POINTER(ctypes.c_int64), vp, vp, vp]
         L.tgo_hw_run_proxy.restype = i32
         L.tgo_fit_line.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -288,6 +290,11 @@ def evaluate_mem(tasks, mem, capacity: int, orders, model: Model = DEFAULT, out=
     _check(lib().tgo_evaluate_mem(ctypes.byref(model._c()), tasks.data_ptr(), mem.data_ptr(), n, int(capacity),
                                   orders.data_ptr(), m, out.data_ptr(), _stream(stream)), "tgo_evaluate_mem")
     return out
+
+
+def valu_probe(blocks: int, iters: int, stream=None):
+    """Launch the integer issue probe (tgo_valu_probe)."""
+    _check(lib().tgo_valu_probe(int(blocks), int(iters), _stream(stream)), "tgo_valu_probe")
 
 
 def read_groups(groups) -> list:
