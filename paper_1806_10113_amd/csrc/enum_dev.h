@@ -61,7 +61,7 @@ __device__ __forceinline__ void level(const Ctx &c, const View<TT, TS, QS> &v, c
     for (int ci = 0; ci < L; ++ci) {
         const uint32_t x = (list >> (4 * ci)) & 15u;
         Lane<TT> s2 = s;
-        window<DMA>(s2, j, x, v, c.r);
+        window<DMA, (L > 1)>(s2, j, x, v, c.r);
         const uint32_t l2 = l + (uint32_t)ci * (uint32_t)fact_c(L - 1);
         if constexpr (L == 1) {
             leaf<TT, STORE>(tail<DMA>(s2, c.r), l2, u, c.out_sub);

@@ -62,38 +62,42 @@ __device__ __forceinline__ void gsim_init(GSim<TT> &s) {
     s.n = s.hc = s.kc = s.dc = s.hd = s.kd = s.dd = 0;
 }
 
-// All retirements and starts at the current instant.
+// All retirements and starts at the current instant.  One sweep (retire
+// HtD, K, DtH, then start HtD, K, DtH) follows every chain of causes within
+// the instant (an HtD end frees the kernel engine's next start, a DtH end
+// frees memory for the next HtD, ...); only a command that starts with zero
+// duration needs another sweep to retire it.
 template <typename TT>
 __device__ __forceinline__ void gsim_pass(GSim<TT> &s, const MemTab<TT> &tb, uint64_t cap) {
-    bool changed = true;
-    while (changed) {
-        changed = false;
-        if (s.hc > s.hd && s.uh == 0) { ++s.hd; changed = true; }
-        if (s.kc > s.kd && s.kend == s.t) { ++s.kd; changed = true; }
+    for (;;) {
+        if (s.hc > s.hd && s.uh == 0) ++s.hd;
+        if (s.kc > s.kd && s.kend == s.t) ++s.kd;
         if (s.dc > s.dd && s.ud == 0) {
             s.held -= tb.m[mnib(s.seq, s.dd)];
             ++s.dd;
-            changed = true;
         }
+        bool again = false;
         if (s.hc == s.hd && s.hc < s.n) {
             const uint32_t x = mnib(s.seq, s.hc);
             if (s.held + tb.m[x] <= cap) {
                 s.held += tb.m[x];
                 s.uh = tb.qh[x];
                 ++s.hc;
-                changed = true;
+                again = again || s.uh == 0;
             }
         }
         if (s.kc == s.kd && s.kc < s.hd) {
-            s.kend = s.t + tb.k[mnib(s.seq, s.kc)];
+            const TT k = tb.k[mnib(s.seq, s.kc)];
+            s.kend = s.t + k;
             ++s.kc;
-            changed = true;
+            again = again || k == 0;
         }
         if (s.dc == s.dd && s.dc < s.kd) {
             s.ud = tb.qd[mnib(s.seq, s.dc)];
             ++s.dc;
-            changed = true;
+            again = again || s.ud == 0;
         }
+        if (!again) break;
     }
 }
 
@@ -140,6 +144,28 @@ __device__ __forceinline__ TT gsim_finish(GSim<TT> &s, const MemTab<TT> &tb, uin
         if (!gsim_advance(s, r)) break;
     }
     return s.t;
+}
+
+// Run to the end once every HtD has ended (the state gsim_push leaves after
+// the last position): no transfer overlaps any more, so the running DtH
+// ends ceil(ud / q) later, each later DtH takes its solo time and starts
+// when both its kernel and the previous DtH have ended, and the kernels
+// follow their chain -- the event stepping of gsim_finish in closed form.
+template <typename TT>
+__device__ __forceinline__ TT gsim_finish_closed(const GSim<TT> &s, const MemTab<TT> &tb, const Rates &r) {
+    TT D = s.dc > s.dd ? s.t + ceil_q(s.ud, r.q_log2) : s.t;
+    TT K = s.kc > s.kd ? s.kend : s.t;
+    for (int i = s.dc; i < s.n; ++i) {
+        const uint32_t y = mnib(s.seq, i);
+        TT Ki = s.t;                                   // kernel already ended
+        if (i == s.kc - 1 && s.kc > s.kd) Ki = s.kend; // kernel running
+        if (i >= s.kc) {                               // kernel not started
+            K = tmax(K, s.t) + tb.k[y];
+            Ki = K;
+        }
+        D = tmax(Ki, D) + tb.d[y];
+    }
+    return D;
 }
 
 template <typename TT>

@@ -163,7 +163,9 @@ __device__ __forceinline__ void window_one(Lane<TT> &s, uint32_t x, const View<T
 // the HtD end estimate stays valid; only a change of the DtH engine between
 // busy and idle changes the HtD rate and forces a new estimate from the exact
 // remaining work.
-template <int DMA = DMA_RUNTIME, typename TT, int TS, int QS>
+// PUT = false skips writing the position's queue slot (the last position of
+// an ordering: no later window reads it).
+template <int DMA = DMA_RUNTIME, bool PUT = true, typename TT, int TS, int QS>
 __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const View<TT, TS, QS> &v,
                                        const Rates &r) {
     using ST = typename Signed<TT>::type;
@@ -208,10 +210,12 @@ __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const Vie
     const ST e = (ST)s.ck - (ST)s.dpre;
     s.emax = e > s.emax ? e : s.emax;
     s.dpre += tx.d;
-    Slot<TT> sl;
-    sl.ck = s.ck;
-    sl.x = x;
-    v.put(j, sl);
+    if constexpr (PUT) {
+        Slot<TT> sl;
+        sl.ck = s.ck;
+        sl.x = x;
+        v.put(j, sl);
+    }
 }
 
 // Total time once the last placed HtD has ended at s.t (used for the whole
