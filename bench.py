@@ -282,7 +282,7 @@ def hw_validation_extra(dev, unit_ms: float):
     out = {"unit_ms": unit_ms, "transfers": r["transfers"], "kernel": r["kernel"], "overlap": r["overlap"],
            "rounds": r["rounds"], "kernel_alu": r["kernel_alu"], "interference": r["interference"],
            "memory": [{k: v for k, v in m.items() if k != "per_ordering"} for m in r["memory"]]}
-    for sc in ("two_dma", "one_dma_scheme"):
+    for sc in ("two_dma", "one_dma_scheme", "two_dma_alu_kernels"):
         out[sc] = {"geomean_err_pct": r[sc]["geomean_err_pct"],
                    "benchmarks": {b: {k: v[k] for k in ("mean_err_pct", "max_err_pct", "measured_speedup_best",
                                                           "measured_speedup_heuristic",

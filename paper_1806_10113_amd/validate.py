@@ -147,8 +147,10 @@ def build_task(frac, unit_ns, xfer, kern, elems):
     return hb, db, it
 
 
-def validate_benchmarks(hw, dev, xfer, kern, model, unit_ns, elems, reps, dma_engines=2):
-    """Fig. prediction_error on this device: every ordering of each benchmark."""
+def validate_benchmarks(hw, dev, xfer, kern, model, unit_ns, elems, reps, dma_engines=2,
+                        kind=tgo.HW_KERNEL_HBM):
+    """Fig. prediction_error on this device: every ordering of each benchmark
+    (task kernels of the given kind, sized with its calibration `kern`)."""
     import torch
     out = {}
     mdl = tgo.Model(model.q_log2, model.p_htd, model.p_dth, dma_engines)
@@ -156,7 +158,7 @@ def validate_benchmarks(hw, dev, xfer, kern, model, unit_ns, elems, reps, dma_en
         tasks = np.zeros(4, dtype=tgo.HW_TASK_DTYPE)
         for i, nm in enumerate(names):
             hb, db, it = build_task(W.PAPER_TASKS_UNITS[nm], unit_ns, xfer, kern, elems)
-            tasks[i] = (hb, db, elems, it, 0)
+            tasks[i] = (hb, db, elems, it, kind)
         # measured solo command times feed the model
         solo = np.zeros((4, 3), dtype=np.int64)
         for i in range(4):
@@ -346,6 +348,7 @@ def run(dev=None, unit_ms: float = 10.0, reps: int = 3, quick: bool = False):
             hw = tgo.HwRunner(4, need, elems)
         res2 = validate_benchmarks(hw, dev, xfer, kern, model, unit_ns, elems, reps, 2)
         res1 = validate_benchmarks(hw, dev, xfer, kern, model, unit_ns, elems, reps, 1)
+        res2a = validate_benchmarks(hw, dev, xfer, kern_alu, model, unit_ns, elems, reps, 2, tgo.HW_KERNEL_ALU)
         hw.close()
         hw = tgo.HwRunner(8, need, elems)
         rounds = [validate_rounds(hw, dev, xfer, kern, model, unit_ns, elems, reps, 4, 2, bk,
@@ -367,4 +370,5 @@ def run(dev=None, unit_ms: float = 10.0, reps: int = 3, quick: bool = False):
             "interference": interf,
             "overlap": {k: ov[k] for k in ("rho_htd", "rho_dth", "model", "errors")},
             "overlap_records": ov["records"],
-            "two_dma": res2, "one_dma_scheme": res1, "rounds": rounds, "memory": memory}
+            "two_dma": res2, "one_dma_scheme": res1, "two_dma_alu_kernels": res2a, "rounds": rounds,
+            "memory": memory}

@@ -143,7 +143,7 @@ def test_fits_and_prediction_on_this_device(dev):
     assert res["kernel"]["eta_ns_per_elem_pass"] > 0
     # the model with fitted rates predicts every ordering of every benchmark
     # within 10 % on average (the paper reports about 1 % on its devices)
-    for scheme in ("two_dma", "one_dma_scheme"):
+    for scheme in ("two_dma", "one_dma_scheme", "two_dma_alu_kernels"):
         for bk, v in res[scheme]["benchmarks"].items():
             assert v["mean_err_pct"] < 10.0, (scheme, bk, v["mean_err_pct"])
     for v in res["rounds"]:
