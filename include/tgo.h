@@ -103,8 +103,8 @@ const char *tgo_last_error(void);
 int tgo_version(void);
 
 /* ---------------------------------------------------------------------------
- * tgo_evaluate -- predicted total time of given orderings (Section 4: "given a
- * specific ordering ... predict the total execution time").
+ * tgo_evaluate -- predicted total time of given orderings (Section 4: the
+ * model predicts a group's total time for a given launch ordering).
  *   d_tasks : n tasks (1 <= n <= TGO_MAX_N).
  *   d_orders: m orderings, row-major m x n bytes, each a permutation of 0..n-1.
  *   d_out   : m int64; T in ns, or a negative TGO_E* for a row that is not a
