@@ -425,7 +425,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: the path is measured on a single MI355X "
-              "(a multi-GPU run would shard the rank range; not part of this build)", file=sys.stderr)
+              "(several GPUs would split the rank range; that is not implemented)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
