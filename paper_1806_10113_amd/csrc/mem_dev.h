@@ -22,8 +22,8 @@
 // DtHs on the one transfer engine.  Transfers never overlap, so no rate
 // applies and the schedule is the closed-form chain: HtDs back to back,
 // K_i = max(HtD_i end, K_{i-1} end) + k_i, and after the sub-group's last HtD
-// its DtHs in order, D_i = max(K_i, D_{i-1}) + d_i; the next sub-group's HtDs
-// follow its last DtH.
+// its DtHs in order, D_i = max(K_i, D_{i-1}) + d_i (kept as a running max, so
+// each position costs O(1)); the next sub-group's HtDs follow its last DtH.
 //
 // Both expose push (place the next task; for GSim the simulation then runs
 // to the instant that task's HtD ends, after which nothing depends on later
@@ -170,51 +170,58 @@ __device__ __forceinline__ TT gsim_finish_closed(const GSim<TT> &s, const MemTab
 
 template <typename TT>
 struct Chain {
-    TT x;         // transfer engine: end of the open sub-group's last HtD
-    TT kp;        // end of the last kernel
-    TT x0, kp0;   // transfer end and kernel end when the open sub-group began
+    using ST = typename Signed<TT>::type;
+    TT x;      // transfer engine: end of the open sub-group's last HtD (or of
+               // the previous sub-group's last DtH while none is open)
+    TT kp;     // end of the last kernel
+    ST emax;   // open sub-group: max over its positions p of
+               // (K_p end - its DtH time before p)
+    TT dsum;   // open sub-group: its DtH time so far
     uint64_t held;
-    uint64_t seq;
-    int n, b;     // positions placed; the open sub-group starts at b
+    int open;  // positions in the open sub-group
 };
 
 template <typename TT>
 __device__ __forceinline__ void chain_init(Chain<TT> &c) {
-    c.x = c.kp = c.x0 = c.kp0 = 0;
+    using ST = typename Signed<TT>::type;
+    c.x = c.kp = 0;
+    c.emax = (ST)(((TT)1) << (8 * sizeof(TT) - 1));  // most negative
+    c.dsum = 0;
     c.held = 0;
-    c.seq = 0;
-    c.n = c.b = 0;
+    c.open = 0;
 }
 
-// The open sub-group's DtHs (its kernel ends recomputed from its start).
+// The open sub-group's DtHs: after its last HtD they run in order, each when
+// its kernel has ended, so the last one ends at
+// max(x, max_p (K_p - sum_{s<p} d_s)) + sum d (the recurrence
+// D_p = max(K_p, D_{p-1}) + d_p unrolled).
 template <typename TT>
-__device__ __forceinline__ void chain_close(Chain<TT> &c, const MemTab<TT> &tb) {
-    TT X = c.x0, K = c.kp0, D = c.x;
-    for (int i = c.b; i < c.n; ++i) {
-        const uint32_t y = mnib(c.seq, i);
-        X += tb.h[y];
-        K = tmax(X, K) + tb.k[y];
-        D = tmax(K, D) + tb.d[y];
-    }
-    c.x = c.x0 = D;
-    c.kp0 = c.kp;
-    c.b = c.n;
+__device__ __forceinline__ void chain_close(Chain<TT> &c) {
+    using ST = typename Signed<TT>::type;
+    const ST e = (ST)c.x > c.emax ? (ST)c.x : c.emax;
+    c.x = (TT)(e + (ST)c.dsum);
+    c.emax = (ST)(((TT)1) << (8 * sizeof(TT) - 1));
+    c.dsum = 0;
     c.held = 0;
+    c.open = 0;
 }
 
 template <typename TT>
 __device__ __forceinline__ void chain_push(Chain<TT> &c, uint32_t x, const MemTab<TT> &tb, uint64_t cap) {
-    if (c.n > c.b && c.held + tb.m[x] > cap) chain_close(c, tb);
-    c.seq |= (uint64_t)x << (4 * c.n);
-    ++c.n;
-    c.held += tb.m[x];
+    using ST = typename Signed<TT>::type;
+    if (c.open > 0 && c.held + tb.m[x] > cap) chain_close(c);
     c.x += tb.h[x];
     c.kp = tmax(c.x, c.kp) + tb.k[x];
+    const ST e = (ST)c.kp - (ST)c.dsum;
+    c.emax = e > c.emax ? e : c.emax;
+    c.dsum += tb.d[x];
+    c.held += tb.m[x];
+    ++c.open;
 }
 
 template <typename TT>
-__device__ __forceinline__ TT chain_finish(Chain<TT> &c, const MemTab<TT> &tb) {
-    if (c.n > c.b) chain_close(c, tb);
+__device__ __forceinline__ TT chain_finish(Chain<TT> &c, const MemTab<TT> &) {
+    if (c.open > 0) chain_close(c);
     return c.x;
 }
 
