@@ -27,7 +27,7 @@
 //
 // Both expose push (place the next task; for GSim the simulation then runs
 // to the instant that task's HtD ends, after which nothing depends on later
-// positions) and finish (run to the end, return T).  An enumeration can thus
+// positions) and finish (the rest in closed form, return T).  An enumeration can thus
 // keep the state after a common prefix and extend it per suffix.
 #pragma once
 
@@ -44,34 +44,49 @@ struct MemTab {
 
 __device__ __forceinline__ uint32_t mnib(uint64_t v, int i) { return (uint32_t)(v >> (4 * i)) & 15u; }
 
+// Per-lane queue of kernel end times (LDS, one slot per position, slots of a
+// wave's lanes adjacent): the end of K_i is fixed once HtD_i has ended.
+template <typename TT>
+struct KQ {
+    TT *base;
+    int stride;
+    __device__ __forceinline__ TT get(int i) const { return base[i * stride]; }
+    __device__ __forceinline__ void put(int i, TT v) const { base[i * stride] = v; }
+};
+
 template <typename TT>
 struct GSim {
-    TT t, uh, ud, kend;
+    TT t, uh, ud;   // now; HtD and DtH work left (1/q solo-ns)
+    TT kp;          // end of the kernel of the last position whose HtD ended
     uint64_t held;
     uint64_t seq;   // nibble j: task at position j
     int n;          // positions placed
-    int hc, kc, dc; // next position to start on each engine
-    int hd, kd, dd; // positions finished on each engine (running: started > finished)
+    int hc, dc;     // next position to start on the HtD / DtH engine
+    int hd, dd;     // positions finished on the HtD / DtH engine
 };
 
 template <typename TT>
 __device__ __forceinline__ void gsim_init(GSim<TT> &s) {
-    s.t = s.uh = s.ud = s.kend = 0;
+    s.t = s.uh = s.ud = s.kp = 0;
     s.held = 0;
     s.seq = 0;
-    s.n = s.hc = s.kc = s.dc = s.hd = s.kd = s.dd = 0;
+    s.n = s.hc = s.dc = s.hd = s.dd = 0;
 }
 
-// All retirements and starts at the current instant.  One sweep (retire
-// HtD, K, DtH, then start HtD, K, DtH) follows every chain of causes within
-// the instant (an HtD end frees the kernel engine's next start, a DtH end
-// frees memory for the next HtD, ...); only a command that starts with zero
-// duration needs another sweep to retire it.
+// All retirements and starts at the current instant.  The kernel engine
+// needs no events: K_i = max(HtD_i end, K_{i-1} end) + k_i is fixed when
+// HtD_i ends and kept in the queue; the DtH of position i starts once the
+// engine is free and t has reached K_i.  One sweep (retire HtD, DtH, then
+// start HtD, DtH) follows every chain of causes within the instant; only a
+// command that starts with zero duration needs another sweep.
 template <typename TT>
-__device__ __forceinline__ void gsim_pass(GSim<TT> &s, const MemTab<TT> &tb, uint64_t cap) {
+__device__ __forceinline__ void gsim_pass(GSim<TT> &s, const MemTab<TT> &tb, uint64_t cap, const KQ<TT> &kq) {
     for (;;) {
-        if (s.hc > s.hd && s.uh == 0) ++s.hd;
-        if (s.kc > s.kd && s.kend == s.t) ++s.kd;
+        if (s.hc > s.hd && s.uh == 0) {
+            s.kp = tmax(s.t, s.kp) + tb.k[mnib(s.seq, s.hd)];
+            kq.put(s.hd, s.kp);
+            ++s.hd;
+        }
         if (s.dc > s.dd && s.ud == 0) {
             s.held -= tb.m[mnib(s.seq, s.dd)];
             ++s.dd;
@@ -86,13 +101,7 @@ __device__ __forceinline__ void gsim_pass(GSim<TT> &s, const MemTab<TT> &tb, uin
                 again = again || s.uh == 0;
             }
         }
-        if (s.kc == s.kd && s.kc < s.hd) {
-            const TT k = tb.k[mnib(s.seq, s.kc)];
-            s.kend = s.t + k;
-            ++s.kc;
-            again = again || k == 0;
-        }
-        if (s.dc == s.dd && s.dc < s.kd) {
+        if (s.dc == s.dd && s.dc < s.hd && kq.get(s.dc) <= s.t) {
             s.ud = tb.qd[mnib(s.seq, s.dc)];
             ++s.dc;
             again = again || s.ud == 0;
@@ -101,16 +110,18 @@ __device__ __forceinline__ void gsim_pass(GSim<TT> &s, const MemTab<TT> &tb, uin
     }
 }
 
-// Advance to the earliest completion estimate; false when nothing runs.
+// Advance to the earliest completion estimate (a transfer's end, or the end
+// of the kernel an idle DtH engine waits for); false when nothing is pending.
 template <typename TT>
-__device__ __forceinline__ bool gsim_advance(GSim<TT> &s, const Rates &r) {
-    const bool hrun = s.hc > s.hd, krun = s.kc > s.kd, drun = s.dc > s.dd;
-    if (!hrun && !krun && !drun) return false;
+__device__ __forceinline__ bool gsim_advance(GSim<TT> &s, const Rates &r, const KQ<TT> &kq) {
+    const bool hrun = s.hc > s.hd, drun = s.dc > s.dd;
+    const bool dwait = !drun && s.dc < s.hd;
+    if (!hrun && !drun && !dwait) return false;
     const bool both = hrun && drun;
     const TT INF = inf_time<TT>();
     const TT eh = hrun ? (both ? (TT)ceil_p(s.uh, r.p_h, r.inv_ph, r.c_ph) : ceil_q(s.uh, r.q_log2)) : INF;
     const TT ed = drun ? (both ? (TT)ceil_p(s.ud, r.p_d, r.inv_pd, r.c_pd) : ceil_q(s.ud, r.q_log2)) : INF;
-    const TT ek = krun ? s.kend - s.t : INF;
+    const TT ek = dwait ? kq.get(s.dc) - s.t : INF;
     TT dt = eh < ed ? eh : ed;
     dt = ek < dt ? ek : dt;
     const TT q = TT(1) << r.q_log2;
@@ -123,48 +134,25 @@ __device__ __forceinline__ bool gsim_advance(GSim<TT> &s, const Rates &r) {
 // Place task x at the next position and run to the instant its HtD ends.
 template <typename TT>
 __device__ __forceinline__ void gsim_push(GSim<TT> &s, uint32_t x, const MemTab<TT> &tb, uint64_t cap,
-                                          const Rates &r) {
+                                          const Rates &r, const KQ<TT> &kq) {
     s.seq |= (uint64_t)x << (4 * s.n);
     ++s.n;
     for (;;) {
-        gsim_pass(s, tb, cap);
+        gsim_pass(s, tb, cap, kq);
         if (s.hd == s.n) break;
-        if (!gsim_advance(s, r)) break;
+        if (!gsim_advance(s, r, kq)) break;
     }
 }
 
-// Run to the end; returns T.  *tk (if given) receives the end of the last
-// kernel.
+// Total time once every HtD has ended (the state gsim_push leaves after the
+// last position): no transfer overlaps any more, so the running DtH ends
+// ceil(ud / q) later and each later DtH takes its solo time, starting when
+// both its kernel and the previous DtH have ended.
 template <typename TT>
-__device__ __forceinline__ TT gsim_finish(GSim<TT> &s, const MemTab<TT> &tb, uint64_t cap, const Rates &r,
-                                          TT *tk = nullptr) {
-    for (;;) {
-        gsim_pass(s, tb, cap);
-        if (tk && s.kd == s.n && *tk == inf_time<TT>()) *tk = s.t;
-        if (!gsim_advance(s, r)) break;
-    }
-    return s.t;
-}
-
-// Run to the end once every HtD has ended (the state gsim_push leaves after
-// the last position): no transfer overlaps any more, so the running DtH
-// ends ceil(ud / q) later, each later DtH takes its solo time and starts
-// when both its kernel and the previous DtH have ended, and the kernels
-// follow their chain -- the event stepping of gsim_finish in closed form.
-template <typename TT>
-__device__ __forceinline__ TT gsim_finish_closed(const GSim<TT> &s, const MemTab<TT> &tb, const Rates &r) {
+__device__ __forceinline__ TT gsim_finish(const GSim<TT> &s, const MemTab<TT> &tb, const Rates &r,
+                                          const KQ<TT> &kq) {
     TT D = s.dc > s.dd ? s.t + ceil_q(s.ud, r.q_log2) : s.t;
-    TT K = s.kc > s.kd ? s.kend : s.t;
-    for (int i = s.dc; i < s.n; ++i) {
-        const uint32_t y = mnib(s.seq, i);
-        TT Ki = s.t;                                   // kernel already ended
-        if (i == s.kc - 1 && s.kc > s.kd) Ki = s.kend; // kernel running
-        if (i >= s.kc) {                               // kernel not started
-            K = tmax(K, s.t) + tb.k[y];
-            Ki = K;
-        }
-        D = tmax(Ki, D) + tb.d[y];
-    }
+    for (int i = s.dc; i < s.n; ++i) D = tmax(kq.get(i), D) + tb.d[mnib(s.seq, i)];
     return D;
 }
 

@@ -3,7 +3,7 @@
 // orderings, and Algorithm 1 with its update step under the limit.
 //
 // Enumeration.  Lexicographic ranks put the orderings that share their first
-// n - M positions in one block of M! consecutive ranks (M = 5 at n >= 5).  One lane owns such a
+// n - M positions in one block of M! consecutive ranks.  One lane owns such a
 // block: it places the prefix once, then walks the last M positions depth
 // first in ascending task order (which is rank order), keeping the state
 // after each placed position and extending a copy of it for every choice of
@@ -63,20 +63,20 @@ __device__ __forceinline__ int mem_tables(const tgo_task *__restrict__ tasks, co
 
 template <typename TT>
 __device__ __forceinline__ void mem_push(GSim<TT> &s, uint32_t x, const MemTab<TT> &tb, uint64_t cap,
-                                         const Rates &r) {
-    gsim_push(s, x, tb, cap, r);
+                                         const Rates &r, const KQ<TT> &kq) {
+    gsim_push(s, x, tb, cap, r, kq);
 }
 template <typename TT>
 __device__ __forceinline__ void mem_push(Chain<TT> &c, uint32_t x, const MemTab<TT> &tb, uint64_t cap,
-                                         const Rates &) {
+                                         const Rates &, const KQ<TT> &) {
     chain_push(c, x, tb, cap);
 }
 template <typename TT>
-__device__ __forceinline__ TT mem_finish(GSim<TT> &s, const MemTab<TT> &tb, uint64_t, const Rates &r) {
-    return gsim_finish_closed(s, tb, r);
+__device__ __forceinline__ TT mem_finish(GSim<TT> &s, const MemTab<TT> &tb, const Rates &r, const KQ<TT> &kq) {
+    return gsim_finish(s, tb, r, kq);
 }
 template <typename TT>
-__device__ __forceinline__ TT mem_finish(Chain<TT> &c, const MemTab<TT> &tb, uint64_t, const Rates &) {
+__device__ __forceinline__ TT mem_finish(Chain<TT> &c, const MemTab<TT> &tb, const Rates &, const KQ<TT> &) {
     return chain_finish(c, tb);
 }
 
@@ -99,17 +99,17 @@ __device__ __forceinline__ void mem_leaf(MAcc &a, uint64_t T, int64_t *out) {
 // (ascending task index = lexicographic rank order).
 template <int D, bool STORE, typename S, typename TT>
 __device__ __forceinline__ void mem_dfs(const S &s, uint32_t rem, const MemTab<TT> &tb, uint64_t cap,
-                                        const Rates &r, MAcc &a, int64_t *out) {
+                                        const Rates &r, const KQ<TT> &kq, MAcc &a, int64_t *out) {
     uint32_t m = rem;
     for (int i = 0; i < D; ++i) {
         const uint32_t x = (uint32_t)(__ffs(m) - 1);
         m &= m - 1;
         S c = s;
-        mem_push(c, x, tb, cap, r);
+        mem_push(c, x, tb, cap, r, kq);
         if constexpr (D == 1) {
-            mem_leaf<STORE>(a, (uint64_t)mem_finish(c, tb, cap, r), out);
+            mem_leaf<STORE>(a, (uint64_t)mem_finish(c, tb, r, kq), out);
         } else {
-            mem_dfs<D - 1, STORE>(c, rem & ~(1u << x), tb, cap, r, a, out);
+            mem_dfs<D - 1, STORE>(c, rem & ~(1u << x), tb, cap, r, kq, a, out);
         }
     }
 }
@@ -119,6 +119,7 @@ __global__ __launch_bounds__(MEM_THREADS) void mem_enum_kernel(const tgo_task *_
                                                                const int64_t *__restrict__ mem, int n,
                                                                uint64_t cap, Rates r, uint32_t n_sub,
                                                                int64_t *out, Partial *partials) {
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ MemTab<TT> tb;
     __shared__ int flag;
     const int st = mem_tables<TT>(tasks, mem, n, cap, r, tb, &flag);
@@ -132,6 +133,8 @@ __global__ __launch_bounds__(MEM_THREADS) void mem_enum_kernel(const tgo_task *_
     }
     if (st != 0) return;
     using S = typename std::conditional<ONE, Chain<TT>, GSim<TT>>::type;
+    // two engines: the lane's kernel-end queue, n slots (none with one engine)
+    const KQ<TT> kq{reinterpret_cast<TT *>(smem) + threadIdx.x, MEM_THREADS};
     MAcc a;
     a.min_t = ~0ull; a.min_r = ~0ull; a.max_t1 = 0; a.max_r = ~0ull;
     a.sum_lo = 0; a.sum_hi = 0; a.fp = 0; a.rank = 0;
@@ -151,12 +154,12 @@ __global__ __launch_bounds__(MEM_THREADS) void mem_enum_kernel(const tgo_task *_
             const uint32_t x = (uint32_t)(list >> (4 * c)) & 15u;
             const uint64_t lo = list & ((1ull << (4 * c)) - 1ull);
             list = lo | ((list >> (4 * c + 4)) << (4 * c));
-            mem_push(s, x, tb, cap, r);
+            mem_push(s, x, tb, cap, r, kq);
         }
         uint32_t remset = 0;
         for (int i = 0; i < M; ++i) remset |= 1u << ((list >> (4 * i)) & 15u);
         a.rank = (uint64_t)sub * MEM_FACT[M];
-        mem_dfs<M, STORE>(s, remset, tb, cap, r, a, out);
+        mem_dfs<M, STORE>(s, remset, tb, cap, r, kq, a, out);
     }
     Partial p;
     p.min_t = a.min_t; p.min_r = a.min_r; p.max_t = a.max_t1; p.max_r = a.max_r;
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(MEM_THREADS) void mem_enum_kernel(const tgo_task *_
 // kernel, DtH) -- Algorithm 1's update -- in 64-bit time.
 template <bool ONE>
 __device__ Fit3 mem_update(const uint8_t *ord, int len, const MemTab<uint64_t> &tb, uint64_t cap,
-                           const Rates &r) {
+                           const Rates &r, const KQ<uint64_t> &kq) {
     Fit3 u;
     if constexpr (ONE) {
         Chain<uint64_t> c;
@@ -204,11 +207,10 @@ __device__ Fit3 mem_update(const uint8_t *ord, int len, const MemTab<uint64_t> &
     } else {
         GSim<uint64_t> s;
         gsim_init(s);
-        for (int i = 0; i < len; ++i) gsim_push(s, ord[i], tb, cap, r);
+        for (int i = 0; i < len; ++i) gsim_push(s, ord[i], tb, cap, r, kq);
         u.th = (int64_t)s.t;
-        uint64_t tk = inf_time<uint64_t>();
-        u.td = (int64_t)gsim_finish(s, tb, cap, r, &tk);
-        u.tk = (int64_t)tk;
+        u.tk = (int64_t)s.kp;
+        u.td = (int64_t)gsim_finish(s, tb, r, kq);
     }
     return u;
 }
@@ -221,6 +223,8 @@ __global__ __launch_bounds__(64) void mem_heuristic_kernel(const tgo_task *__res
                                                            Rates r, tgo_summary *out) {
     __shared__ MemTab<uint64_t> tb;
     __shared__ int flag;
+    __shared__ uint64_t kqs[MAXN];
+    const KQ<uint64_t> kq{kqs, 1};
     const int st = mem_tables<uint64_t>(tasks, mem, n, cap, r, tb, &flag);
     if (threadIdx.x != 0) return;
     if (st < 0) {
@@ -239,7 +243,7 @@ __global__ __launch_bounds__(64) void mem_heuristic_kernel(const tgo_task *__res
     rt &= ~(1u << first);
     int pos = 1;
     while (__popc(rt) > 2) {
-        const Fit3 u = mem_update<ONE>(ord, pos, tb, cap, r);
+        const Fit3 u = mem_update<ONE>(ord, pos, tb, cap, r, kq);
         int best = -1;
         int64_t bf = 0;
         for (int c = 0; c < n; ++c) {
@@ -252,13 +256,13 @@ __global__ __launch_bounds__(64) void mem_heuristic_kernel(const tgo_task *__res
     }
     if (__popc(rt) == 2) {
         const int a = __ffs(rt) - 1, b = 31 - __clz(rt);
-        const Fit3 u = mem_update<ONE>(ord, pos, tb, cap, r);
+        const Fit3 u = mem_update<ONE>(ord, pos, tb, cap, r, kq);
         int bx = -1, by = -1;
         int64_t bs = 0, bdy = 0;
         for (int o = 0; o < 2; ++o) {
             const int x = o == 0 ? a : b, y = o == 0 ? b : a;
             ord[pos] = (uint8_t)x;
-            const Fit3 w = mem_update<ONE>(ord, pos + 1, tb, cap, r);
+            const Fit3 w = mem_update<ONE>(ord, pos + 1, tb, cap, r, kq);
             const int64_t dy = (int64_t)tb.d[y];
             const int64_t sc = fit((int64_t)tb.h[x], (int64_t)tb.k[x], u) +
                                fit((int64_t)tb.h[y], (int64_t)tb.k[y], w) + dy;
@@ -270,7 +274,7 @@ __global__ __launch_bounds__(64) void mem_heuristic_kernel(const tgo_task *__res
     } else if (__popc(rt) == 1) {
         ord[pos++] = (uint8_t)(__ffs(rt) - 1);
     }
-    const Fit3 f = mem_update<ONE>(ord, n, tb, cap, r);
+    const Fit3 f = mem_update<ONE>(ord, n, tb, cap, r, kq);
     for (int j = 0; j < 16; ++j) out->heur[j] = j < n ? ord[j] : (uint8_t)0xff;
     out->heur_ns = f.td;
 }
@@ -285,6 +289,8 @@ __global__ __launch_bounds__(MEM_THREADS) void mem_evaluate_kernel(const tgo_tas
                                                                    int64_t *out) {
     __shared__ MemTab<uint64_t> tb;
     __shared__ int flag;
+    __shared__ uint64_t kqs[MAXN * MEM_THREADS];
+    const KQ<uint64_t> kq{kqs + threadIdx.x, MEM_THREADS};
     const int st = mem_tables<uint64_t>(tasks, mem, n, cap, r, tb, &flag);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
@@ -303,14 +309,15 @@ __global__ __launch_bounds__(MEM_THREADS) void mem_evaluate_kernel(const tgo_tas
         seen |= 1u << x;
         ord[j] = x;
     }
-    out[i] = mem_update<ONE>(ord, n, tb, cap, r).td;
+    out[i] = mem_update<ONE>(ord, n, tb, cap, r, kq).td;
 }
 
 template <typename TT, bool ONE, bool STORE>
 static void launch_enum_width(int M, dim3 grid, hipStream_t st, const tgo_task *t, const int64_t *mem, int n,
                               uint64_t cap, const Rates &r, uint32_t n_sub, int64_t *out, Partial *parts) {
-#define TGO_MEM_ENUM(MM)                                                                                       \
-    hipLaunchKernelGGL((mem_enum_kernel<TT, ONE, STORE, MM>), grid, dim3(MEM_THREADS), 0, st, t, mem, n, cap, \
+    const size_t shm = ONE ? 0 : sizeof(TT) * MEM_THREADS * (size_t)n;
+#define TGO_MEM_ENUM(MM)                                                                                         \
+    hipLaunchKernelGGL((mem_enum_kernel<TT, ONE, STORE, MM>), grid, dim3(MEM_THREADS), shm, st, t, mem, n, cap, \
                        r, n_sub, out, parts)
     switch (M) {
         case 1: TGO_MEM_ENUM(1); break;
@@ -329,11 +336,12 @@ static void launch_enum(int M, dim3 grid, hipStream_t st, const tgo_task *t, con
     launch_enum_width<uint64_t, ONE, STORE>(M, grid, st, t, mem, n, cap, r, n_sub, out, parts);
 }
 
-// Positions walked depth first per lane (5, or n if smaller: measured a few
-// per cent faster than 4 at n = 12 with both schemes, at the same
-// occupancy); TGO_MEM_M overrides it for tuning experiments (1..5).
-static int choose_mem_m(int n) {
-    int m = 5;
+// Positions walked depth first per lane, or n if smaller: 4 with two DMA
+// engines (12.4 vs 14.9 ms at n = 12: one more wave per SIMD), 5 with one
+// (a few per cent faster); TGO_MEM_M overrides it for tuning experiments
+// (1..5).
+static int choose_mem_m(int n, bool one_dma) {
+    int m = one_dma ? 5 : 4;
     if (const char *e = std::getenv("TGO_MEM_M")) {
         const int v = std::atoi(e);
         if (v >= 1 && v <= 5) m = v;
@@ -343,7 +351,7 @@ static int choose_mem_m(int n) {
 
 int launch_memory(const Rates &r, const tgo_task *d_tasks, const int64_t *d_mem, int n, int64_t cap,
                   int64_t *d_per_order, tgo_summary *d_out, hipStream_t st) {
-    const int M = choose_mem_m(n);
+    const int M = choose_mem_m(n, r.one_dma != 0);
     const uint64_t count = factorial(n);
     const uint32_t n_sub = (uint32_t)(count / factorial(M));
     const uint64_t want = ((uint64_t)n_sub + MEM_THREADS - 1) / MEM_THREADS;
