@@ -87,6 +87,9 @@ def test_host_argument_errors(L):
     for n, cap, m in ((0, 10, 1), (17, 10, 1), (4, 0, 1), (4, 10, -1), (4, 10, (1 << 40) + 1)):
         assert L.tgo_evaluate_mem(ctypes.byref(good), fake, fake, n, cap, fake, m, fake, None) == tgo.TGO_EINVAL
     assert L.tgo_evaluate_mem(ctypes.byref(good), fake, None, 4, 10, fake, 5, fake, None) == tgo.TGO_EINVAL
+    # the integer issue probe: 1..2^20 blocks and iterations
+    for blocks, iters in ((0, 1), (1, 0), ((1 << 20) + 1, 1), (1, (1 << 20) + 1)):
+        assert L.tgo_valu_probe(blocks, iters, None) == tgo.TGO_EINVAL
 
 
 def test_rank_unrank_match_lexicographic_order():

@@ -135,6 +135,13 @@ def test_memory_limit_holds_htds_back(dev):
     hw.close()
 
 
+def test_valu_probe_runs(dev):
+    import torch
+    from paper_1806_10113_amd import tgo
+    tgo.valu_probe(64, 4)
+    torch.cuda.synchronize()
+
+
 def test_fits_and_prediction_on_this_device(dev):
     from paper_1806_10113_amd import validate
     res = validate.run(dev, unit_ms=2.0, reps=3, quick=True)
