@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
+#include <mutex>
 
 #include "enum_dev.h"
 #include "tables_dev.h"
@@ -17,7 +18,6 @@
 namespace tgo {
 
 constexpr int EX_THREADS = 256;
-constexpr int EX_MAX_BLOCKS_PER_PASS = 4096;
 
 // Per-lane accumulators over all ranks the lane owns.
 template <typename TT>
@@ -58,8 +58,9 @@ template <typename TT>
 using ExView = View<TT, 1, EX_THREADS>;
 
 // Reduce a block's lane accumulators into one Partial (thread 0 writes it).
-__device__ void block_reduce_write(Partial p, Partial *dst) {
-    __shared__ Partial wsum[EX_THREADS / 64];
+// wsum: LDS for one Partial per wave; it may alias memory the block used
+// before (every thread has left its loop once the barrier below is passed).
+__device__ void block_reduce_write(Partial p, Partial *dst, Partial *wsum) {
     for (int m = 32; m >= 1; m >>= 1) {
         const uint64_t mt = shfl_xor64(p.min_t, m), mr = shfl_xor64(p.min_r, m);
         const uint64_t xt = shfl_xor64(p.max_t, m), xr = shfl_xor64(p.max_r, m);
@@ -71,6 +72,7 @@ __device__ void block_reduce_write(Partial p, Partial *dst) {
         p.fp += f;
     }
     const int w = threadIdx.x / 64;
+    __syncthreads();
     if ((threadIdx.x & 63) == 0) wsum[w] = p;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -87,17 +89,42 @@ __device__ void block_reduce_write(Partial p, Partial *dst) {
     }
 }
 
+// Dynamic LDS of the exhaustive kernel: the task tables (n entries each),
+// then the per-lane kernel-completion queue, n - 1 slots (the last position's
+// slot is never read; none with one DMA engine).  The block reduction reuses
+// the queue's memory at the end.
+template <typename TT>
+__host__ __device__ constexpr size_t ex_tables_bytes(int n) {
+    return (size_t)n * (sizeof(Quad<TT>) + sizeof(DRec<TT>));
+}
+template <typename TT>
+__host__ __device__ constexpr int ex_queue_slots(int n, bool one_dma) {
+    return one_dma ? 0 : (n > 1 ? n - 1 : 1);
+}
+template <typename TT>
+inline size_t ex_shm_bytes(int n, bool one_dma) {
+    const size_t q = sizeof(Slot<TT>) * EX_THREADS * (size_t)ex_queue_slots<TT>(n, one_dma);
+    const size_t red = sizeof(Partial) * (EX_THREADS / 64);
+    return ex_tables_bytes<TT>(n) + (q > red ? q : red);
+}
+
+// 32-bit time path: at most 72 VGPRs so that 7 waves fit per SIMD (with the
+// n - 1 slot queue, 7 blocks also fit in LDS at n = 12).
+template <typename TT>
+constexpr int ex_min_waves() { return sizeof(TT) == 4 ? 7 : 1; }
+
 // MODE: 0 = 32-bit time path, 1 = 64-bit.  Both instantiations are launched;
 // a block whose group does not belong to its mode returns at once.  DMA is
 // the launch scheme (DMA_TWO or DMA_ONE, fixed per instantiation).
 template <typename TT, int M, bool STORE, int DMA>
-__global__ __launch_bounds__(EX_THREADS) void exhaustive_kernel(const tgo_task *__restrict__ tasks,
-                                                                int n, Rates r, uint32_t n_sub,
-                                                                int64_t *out, Partial *partials) {
+__global__ __launch_bounds__(EX_THREADS) __attribute__((amdgpu_waves_per_eu(ex_min_waves<TT>())))
+void exhaustive_kernel(const tgo_task *__restrict__ tasks, int n, Rates r, uint32_t n_sub, int64_t *out,
+                       Partial *partials) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int MODE = sizeof(TT) == 4 ? 0 : 1;
-    __shared__ Quad<TT> Ht[MAXN];
-    __shared__ DRec<TT> Dt[MAXN];
+    Quad<TT> *Ht = reinterpret_cast<Quad<TT> *>(smem);
+    DRec<TT> *Dt = reinterpret_cast<DRec<TT> *>(smem + (size_t)n * sizeof(Quad<TT>));
+    unsigned char *qbase = smem + ex_tables_bytes<TT>(n);
     __shared__ int mode;
     if (threadIdx.x == 0) mode = classify_group(tasks, n, r);
     if ((int)threadIdx.x < n) table_entry<TT>(tasks[threadIdx.x], r, &Ht[threadIdx.x], &Dt[threadIdx.x]);
@@ -115,7 +142,7 @@ __global__ __launch_bounds__(EX_THREADS) void exhaustive_kernel(const tgo_task *
     ExView<TT> v;
     v.H = Ht;
     v.D = Dt;
-    v.Q = reinterpret_cast<Slot<TT> *>(smem) + threadIdx.x;
+    v.Q = reinterpret_cast<Slot<TT> *>(qbase) + threadIdx.x;
     Ctx c;
     c.n = n;
     c.r = r;
@@ -147,7 +174,7 @@ __global__ __launch_bounds__(EX_THREADS) void exhaustive_kernel(const tgo_task *
     p.fp = a.fp;
     p.status = 0;
     p.pad = 0;
-    block_reduce_write(p, &partials[blockIdx.x]);
+    block_reduce_write(p, &partials[blockIdx.x], reinterpret_cast<Partial *>(qbase));
 }
 
 __device__ inline void unrank_dev(int n, uint64_t r, uint8_t *out) {
@@ -260,31 +287,81 @@ static int choose_m(int n, bool one_dma) {
     return m;
 }
 
+// Blocks that fit on the device at once for a kernel and its dynamic LDS.
+static uint32_t resident_blocks(const void *kern, size_t shm) {
+    struct Entry { int dev; const void *k; size_t shm; uint32_t blocks; };
+    static std::mutex mu;
+    static Entry cache[64];
+    static int used = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(mu);
+    for (int i = 0; i < used; ++i)
+        if (cache[i].dev == dev && cache[i].k == kern && cache[i].shm == shm) return cache[i].blocks;
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, EX_THREADS, shm) != hipSuccess || per_cu <= 0)
+        per_cu = 1;
+    const uint32_t b = (uint32_t)cus * (uint32_t)per_cu;
+    if (used < 64) cache[used++] = Entry{dev, kern, shm, b};
+    return b;
+}
+
+// Blocks per launch, in units of the blocks the 32-bit kernel keeps resident
+// at once.  A subtree's cost varies with its DtH events, so blocks finish at
+// different times: one resident round leaves SIMDs idle at the end, many
+// short blocks let the dispatcher fill them.  At N = 12 on MI355X (1,536
+// resident blocks) 8 rounds gave 3.06-3.11 ms per launch against 3.82 ms for
+// one round and 3.30 ms for 20 subtrees per lane; beyond ~20 rounds the
+// per-block partials and their reduction cost more than they balance.
+constexpr uint32_t EX_ROUNDS = 8;
+
+// Launch the 32-bit and 64-bit instantiations (the one that does not match
+// the group returns at once) and the finalize.  The grid is sized from the
+// 32-bit kernel (the fast path), capped at one subtree per lane;
+// TGO_EXHAUSTIVE_BLOCKS overrides it for tuning experiments.
 template <int M, bool STORE, int DMA>
-static void launch_pair(dim3 grid, size_t shm32, size_t shm64, hipStream_t st, const tgo_task *t,
-                        int n, const Rates &r, uint32_t n_sub, int64_t *out, Partial *parts) {
+static int launch_pair(size_t shm32, size_t shm64, hipStream_t st, const tgo_task *t, int n,
+                       const Rates &r, uint32_t n_sub, int64_t *out, tgo_summary *d_out) {
+    const void *k32 = reinterpret_cast<const void *>(&exhaustive_kernel<uint32_t, M, STORE, DMA>);
+    const uint64_t want = ((uint64_t)n_sub + EX_THREADS - 1) / EX_THREADS;
+    uint32_t blocks = resident_blocks(k32, shm32);
+    blocks = blocks == 0 ? 8192u : blocks * EX_ROUNDS;
+    if (const char *e = std::getenv("TGO_EXHAUSTIVE_BLOCKS")) {
+        const long v = std::atol(e);
+        if (v >= 1 && v <= (1l << 20)) blocks = (uint32_t)v;
+    }
+    if ((uint64_t)blocks > want) blocks = (uint32_t)want;
+    Partial *parts = nullptr;
+    int rc = workspace(sizeof(Partial) * blocks, (void **)&parts);
+    if (rc) return rc;
+    const dim3 grid(blocks);
     hipLaunchKernelGGL((exhaustive_kernel<uint32_t, M, STORE, DMA>), grid, dim3(EX_THREADS), shm32, st, t, n, r,
                        n_sub, out, parts);
     hipLaunchKernelGGL((exhaustive_kernel<uint64_t, M, STORE, DMA>), grid, dim3(EX_THREADS), shm64, st, t, n, r,
                        n_sub, out, parts);
+    TGO_HIP(hipGetLastError());
+    hipLaunchKernelGGL(exhaustive_finalize, dim3(1), dim3(256), 0, st, parts, (int)blocks, n,
+                       factorial(n), d_out);
+    TGO_HIP(hipGetLastError());
+    return TGO_OK;
 }
 
 template <bool STORE, int DMA>
-static void launch_m(int m, dim3 grid, size_t shm32, size_t shm64, hipStream_t st,
-                     const tgo_task *t, int n, const Rates &r, uint32_t n_sub, int64_t *out,
-                     Partial *parts) {
+static int launch_m(int m, size_t shm32, size_t shm64, hipStream_t st, const tgo_task *t, int n,
+                    const Rates &r, uint32_t n_sub, int64_t *out, tgo_summary *d_out) {
     switch (m) {
-        case 1: launch_pair<1, STORE, DMA>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
-        case 2: launch_pair<2, STORE, DMA>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
-        case 3: launch_pair<3, STORE, DMA>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
-        case 4: launch_pair<4, STORE, DMA>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
-        case 5: launch_pair<5, STORE, DMA>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts); break;
+        case 1: return launch_pair<1, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out);
+        case 2: return launch_pair<2, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out);
+        case 3: return launch_pair<3, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out);
+        case 4: return launch_pair<4, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out);
+        case 5: return launch_pair<5, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out);
         default:
             if constexpr (DMA == DMA_ONE)
-                launch_pair<6, STORE, DMA>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts);
+                return launch_pair<6, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out);
             else
-                launch_pair<5, STORE, DMA>(grid, shm32, shm64, st, t, n, r, n_sub, out, parts);
-            break;
+                return launch_pair<5, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out);
     }
 }
 
@@ -295,33 +372,14 @@ int launch_exhaustive(const Rates &r, const tgo_task *d_tasks, int n, int64_t *d
     const uint64_t n_sub64 = factorial(n) / factorial(m);
     if (n_sub64 >= (1ull << 32)) return fail(TGO_EINVAL, "group too large to enumerate");
     const uint32_t n_sub = (uint32_t)n_sub64;
-    const uint64_t lanes_per_pass = (uint64_t)EX_THREADS * EX_MAX_BLOCKS_PER_PASS;
-    const uint64_t passes = (n_sub64 + lanes_per_pass - 1) / lanes_per_pass;
-    const uint64_t per_block = (uint64_t)EX_THREADS * passes;
-    const uint32_t blocks = (uint32_t)((n_sub64 + per_block - 1) / per_block);
-    Partial *parts = nullptr;
-    int rc = workspace(sizeof(Partial) * blocks, (void **)&parts);
-    if (rc) return rc;
-    // the kernel-completion queue is read only by the two-engine DtH events
-    const size_t shm32 = one ? 0 : sizeof(Slot<uint32_t>) * EX_THREADS * n;
-    const size_t shm64 = one ? 0 : sizeof(Slot<uint64_t>) * EX_THREADS * n;
-    const dim3 g(blocks);
+    const size_t shm32 = ex_shm_bytes<uint32_t>(n, one);
+    const size_t shm64 = ex_shm_bytes<uint64_t>(n, one);
     if (one) {
-        if (d_per_order)
-            launch_m<true, DMA_ONE>(m, g, shm32, shm64, st, d_tasks, n, r, n_sub, d_per_order, parts);
-        else
-            launch_m<false, DMA_ONE>(m, g, shm32, shm64, st, d_tasks, n, r, n_sub, nullptr, parts);
-    } else {
-        if (d_per_order)
-            launch_m<true, DMA_TWO>(m, g, shm32, shm64, st, d_tasks, n, r, n_sub, d_per_order, parts);
-        else
-            launch_m<false, DMA_TWO>(m, g, shm32, shm64, st, d_tasks, n, r, n_sub, nullptr, parts);
+        return d_per_order ? launch_m<true, DMA_ONE>(m, shm32, shm64, st, d_tasks, n, r, n_sub, d_per_order, d_out)
+                           : launch_m<false, DMA_ONE>(m, shm32, shm64, st, d_tasks, n, r, n_sub, nullptr, d_out);
     }
-    TGO_HIP(hipGetLastError());
-    hipLaunchKernelGGL(exhaustive_finalize, dim3(1), dim3(256), 0, st, parts, (int)blocks, n,
-                       factorial(n), d_out);
-    TGO_HIP(hipGetLastError());
-    return TGO_OK;
+    return d_per_order ? launch_m<true, DMA_TWO>(m, shm32, shm64, st, d_tasks, n, r, n_sub, d_per_order, d_out)
+                       : launch_m<false, DMA_TWO>(m, shm32, shm64, st, d_tasks, n, r, n_sub, nullptr, d_out);
 }
 
 }  // namespace tgo

@@ -17,7 +17,8 @@
 //     recomputed (one multiply) only when its rate changes.
 //   * The kernel engine needs no events of its own: K_j = max(HtD_j end,
 //     K_{j-1} end) + k.  A kernel completion matters only to the DtH engine,
-//     which reads it from a per-lane queue in LDS (slot j = K_j end, task).
+//     which reads it from a per-lane queue in LDS (slot j = K_j end and the
+//     overlapped duration of DtH j, so one read serves each DtH event).
 //   * The simulation is cut into "windows": window j runs from the start to
 //     the end of HtD at position j and processes the DtH events inside it.
 //     The state at the start of window j depends only on positions < j, which
@@ -59,8 +60,9 @@ struct alignas(4 * sizeof(TT)) Quad {
 
 template <typename TT>
 struct alignas(2 * sizeof(TT)) Slot {
-    TT ck;       // completion time of the kernel at this position
-    uint32_t x;  // task at this position
+    TT ck;  // completion time of the kernel at this position
+    TT dp;  // its DtH while overlapped: ceil(q d / p_dth).  p_dth dp = q d + slack
+            // with slack < p_dth <= q, so d and slack follow from p_dth dp
 };
 
 template <typename TT> struct Signed;
@@ -177,6 +179,7 @@ __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const Vie
     const Quad<TT> tx = v.task(x);
     // an idle DtH waiting for the previous position's kernel now knows its time
     if (!s.drun && s.i == j - 1) s.dev = s.ck;
+    const int jlast = j > 0 ? j - 1 : 0;
     TT uh = tx.h << r.q_log2;  // remaining HtD work at th0
     TT th0 = s.t;
     TT eh = s.t + (s.drun ? tx.hp : tx.h);
@@ -184,8 +187,10 @@ __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const Vie
         const TT ev = s.dev;
         if (!(ev < eh)) break;
         const int inew = s.i + (s.drun ? 1 : 0);
-        // slot inew is in bounds for every inew <= j; it is only used if inew < j
-        const Slot<TT> nx = v.q(inew);
+        // slot inew is only used if inew < j.  The last position's window
+        // (PUT = false) reads slot min(inew, j - 1) so that a queue of n - 1
+        // slots suffices; other windows read slots <= j < n - 1
+        const Slot<TT> nx = v.q(PUT ? inew : (inew < jlast ? inew : jlast));
         const bool start = inew < j && nx.ck <= ev;
         if (start != s.drun) {
             // the HtD rate changes at ev: exact remaining work, new estimate
@@ -197,11 +202,13 @@ __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const Vie
             eh = ev + (start ? cp : cq);
         }
         // the DtH that starts (or not): computed on every lane and selected,
-        // which measured faster than a second divergent branch
-        const DRec<TT> dd = v.d(nx.x & (MAXN - 1));
-        s.dthru += start ? dd.d : TT(0);
-        s.slack = start ? dd.slack : s.slack;
-        s.dev = start ? ev + dd.dp : (inew < j ? nx.ck : inf_time<TT>());
+        // which measured faster than a second divergent branch.  Its solo time
+        // and rounding slack come from w = p_dth dp = q d + slack (no further
+        // LDS read on the loop's path)
+        const TT w = TT(r.p_d) * nx.dp;
+        s.dthru += start ? (w >> r.q_log2) : TT(0);
+        s.slack = start ? (w & (q - 1)) : s.slack;
+        s.dev = start ? ev + nx.dp : (inew < j ? nx.ck : inf_time<TT>());
         s.drun = start;
         s.i = inew;
     }
@@ -213,7 +220,7 @@ __device__ __forceinline__ void window(Lane<TT> &s, int j, uint32_t x, const Vie
     if constexpr (PUT) {
         Slot<TT> sl;
         sl.ck = s.ck;
-        sl.x = x;
+        sl.dp = v.d(x).dp;
         v.put(j, sl);
     }
 }
