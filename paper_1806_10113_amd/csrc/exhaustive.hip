@@ -44,12 +44,15 @@ __device__ __forceinline__ void acc_init(Acc<TT> &a) {
 // lane meets its subtrees in increasing rank order, so strict comparisons
 // keep the lowest rank on ties.  fingerprint: sum of (2r+1) T with
 // r = r0 + l is 2 (r0 sum T + sum l T) + sum T.
+// On the 32-bit time path every T is below 2^31 and a group has at most
+// 13! < 2^33 orderings, so even the sum over all of them stays below 2^64:
+// the lane keeps no carry word there (two fewer live registers).
 template <typename TT>
 __device__ __forceinline__ void fold(Acc<TT> &a, const Sub<TT> &u, uint64_t r0) {
     if (u.min_t < a.min_t) { a.min_t = u.min_t; a.min_r = r0 + u.min_l; }
     if (u.max_t1 > a.max_t1) { a.max_t1 = u.max_t1; a.max_r = r0 + u.max_l; }
     const uint64_t lo = a.sum_lo + u.sum;
-    a.sum_hi += lo < a.sum_lo ? 1ull : 0ull;
+    if constexpr (sizeof(TT) == 8) a.sum_hi += lo < a.sum_lo ? 1ull : 0ull;
     a.sum_lo = lo;
     a.fp += 2ull * (r0 * u.sum + u.s2) + u.sum;
 }
@@ -113,31 +116,28 @@ inline size_t ex_shm_bytes(int n, bool one_dma) {
 template <typename TT>
 constexpr int ex_min_waves() { return sizeof(TT) == 4 ? 7 : 1; }
 
+// The group's time path, decided once before the enumeration: 0 = 32-bit,
+// 1 = 64-bit, or a negative error code (classify_group).
+__global__ void exhaustive_classify(const tgo_task *__restrict__ tasks, int n, Rates r, int *mode) {
+    if (threadIdx.x == 0) *mode = classify_group(tasks, n, r);
+}
+
 // MODE: 0 = 32-bit time path, 1 = 64-bit.  Both instantiations are launched;
-// a block whose group does not belong to its mode returns at once.  DMA is
-// the launch scheme (DMA_TWO or DMA_ONE, fixed per instantiation).
+// every block of the one that does not match the group's path (or of both,
+// on an error) returns after reading one word.  DMA is the launch scheme
+// (DMA_TWO or DMA_ONE, fixed per instantiation).
 template <typename TT, int M, bool STORE, int DMA>
 __global__ __launch_bounds__(EX_THREADS) __attribute__((amdgpu_waves_per_eu(ex_min_waves<TT>())))
 void exhaustive_kernel(const tgo_task *__restrict__ tasks, int n, Rates r, uint32_t n_sub, int64_t *out,
-                       Partial *partials) {
+                       Partial *partials, const int *__restrict__ modep) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int MODE = sizeof(TT) == 4 ? 0 : 1;
+    if (*modep != MODE) return;
     Quad<TT> *Ht = reinterpret_cast<Quad<TT> *>(smem);
     DRec<TT> *Dt = reinterpret_cast<DRec<TT> *>(smem + (size_t)n * sizeof(Quad<TT>));
     unsigned char *qbase = smem + ex_tables_bytes<TT>(n);
-    __shared__ int mode;
-    if (threadIdx.x == 0) mode = classify_group(tasks, n, r);
     if ((int)threadIdx.x < n) table_entry<TT>(tasks[threadIdx.x], r, &Ht[threadIdx.x], &Dt[threadIdx.x]);
     __syncthreads();
-    if (mode < 0) {
-        if (MODE == 0 && threadIdx.x == 0) {
-            Partial p = {};
-            p.status = mode;
-            partials[blockIdx.x] = p;
-        }
-        return;
-    }
-    if (mode != MODE) return;
 
     ExView<TT> v;
     v.H = Ht;
@@ -194,36 +194,56 @@ __device__ inline void unrank_dev(int n, uint64_t r, uint8_t *out) {
     for (int i = n; i < 16; ++i) out[i] = 0xff;
 }
 
-__global__ __launch_bounds__(256) void exhaustive_finalize(const Partial *__restrict__ parts,
-                                                           int nparts, int n, uint64_t count,
-                                                           tgo_summary *out) {
-    __shared__ Partial red[256];
-    __shared__ int status;
-    if (threadIdx.x == 0) status = 0;
-    __syncthreads();
+constexpr int EX_FIN_THREADS = 1024;
+
+__global__ __launch_bounds__(EX_FIN_THREADS) void exhaustive_finalize(const Partial *__restrict__ parts,
+                                                                      int nparts, int n, uint64_t count,
+                                                                      const int *__restrict__ modep,
+                                                                      tgo_summary *out) {
+    __shared__ Partial red[EX_FIN_THREADS / 64];
+    const int status = *modep < 0 ? *modep : 0;
     Partial p;
     p.min_t = ~0ull; p.min_r = ~0ull; p.max_t = 0; p.max_r = ~0ull;
     p.sum_lo = 0; p.sum_hi = 0; p.fp = 0; p.status = 0; p.pad = 0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
-        const Partial q = parts[i];
-        if (q.status != 0) atomicMin(&status, q.status);
+    auto take = [&p](const Partial &q) {
         merge_min(p.min_t, p.min_r, q.min_t, q.min_r);
         merge_max(p.max_t, p.max_r, q.max_t, q.max_r);
         add128(p.sum_lo, p.sum_hi, q.sum_lo, q.sum_hi);
         p.fp += q.fp;
-    }
-    red[threadIdx.x] = p;
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            Partial q = red[threadIdx.x + s];
-            Partial &o = red[threadIdx.x];
-            merge_min(o.min_t, o.min_r, q.min_t, q.min_r);
-            merge_max(o.max_t, o.max_r, q.max_t, q.max_r);
-            add128(o.sum_lo, o.sum_hi, q.sum_lo, q.sum_hi);
-            o.fp += q.fp;
+    };
+    if (status == 0) {
+        // four partials in flight per thread: the loads, not the merges, set the time
+        const int b = (int)blockDim.x;
+        int i = (int)threadIdx.x;
+        for (; i + 3 * b < nparts; i += 4 * b) {
+            const Partial q0 = parts[i], q1 = parts[i + b], q2 = parts[i + 2 * b], q3 = parts[i + 3 * b];
+            take(q0);
+            take(q1);
+            take(q2);
+            take(q3);
         }
-        __syncthreads();
+        for (; i < nparts; i += b) take(parts[i]);
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t mt = shfl_xor64(p.min_t, m), mr = shfl_xor64(p.min_r, m);
+        const uint64_t xt = shfl_xor64(p.max_t, m), xr = shfl_xor64(p.max_r, m);
+        const uint64_t sl = shfl_xor64(p.sum_lo, m), sh = shfl_xor64(p.sum_hi, m);
+        const uint64_t f = shfl_xor64(p.fp, m);
+        merge_min(p.min_t, p.min_r, mt, mr);
+        merge_max(p.max_t, p.max_r, xt, xr);
+        add128(p.sum_lo, p.sum_hi, sl, sh);
+        p.fp += f;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = p;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x / 64); ++i) {
+            const Partial &q = red[i];
+            merge_min(red[0].min_t, red[0].min_r, q.min_t, q.min_r);
+            merge_max(red[0].max_t, red[0].max_r, q.max_t, q.max_r);
+            add128(red[0].sum_lo, red[0].sum_hi, q.sum_lo, q.sum_hi);
+            red[0].fp += q.fp;
+        }
     }
     if (threadIdx.x == 0) {
         tgo_summary s;
@@ -333,17 +353,20 @@ static int launch_pair(size_t shm32, size_t shm64, hipStream_t st, const tgo_tas
         if (v >= 1 && v <= (1l << 20)) blocks = (uint32_t)v;
     }
     if ((uint64_t)blocks > want) blocks = (uint32_t)want;
+    // workspace: the block partials, then the group's time path
     Partial *parts = nullptr;
-    int rc = workspace(sizeof(Partial) * blocks, (void **)&parts);
+    int rc = workspace(sizeof(Partial) * (blocks + 1), (void **)&parts);
     if (rc) return rc;
+    int *mode = reinterpret_cast<int *>(parts + blocks);
+    hipLaunchKernelGGL(exhaustive_classify, dim3(1), dim3(64), 0, st, t, n, r, mode);
     const dim3 grid(blocks);
     hipLaunchKernelGGL((exhaustive_kernel<uint32_t, M, STORE, DMA>), grid, dim3(EX_THREADS), shm32, st, t, n, r,
-                       n_sub, out, parts);
+                       n_sub, out, parts, mode);
     hipLaunchKernelGGL((exhaustive_kernel<uint64_t, M, STORE, DMA>), grid, dim3(EX_THREADS), shm64, st, t, n, r,
-                       n_sub, out, parts);
+                       n_sub, out, parts, mode);
     TGO_HIP(hipGetLastError());
-    hipLaunchKernelGGL(exhaustive_finalize, dim3(1), dim3(256), 0, st, parts, (int)blocks, n,
-                       factorial(n), d_out);
+    hipLaunchKernelGGL(exhaustive_finalize, dim3(1), dim3(EX_FIN_THREADS), 0, st, parts, (int)blocks, n,
+                       factorial(n), mode, d_out);
     TGO_HIP(hipGetLastError());
     return TGO_OK;
 }
