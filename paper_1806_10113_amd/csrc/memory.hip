@@ -114,8 +114,18 @@ __device__ __forceinline__ void mem_dfs(const S &s, uint32_t rem, const MemTab<T
     }
 }
 
+// 32-bit time path: VGPRs capped for 8 waves per SIMD with two DMA engines
+// (64 VGPRs; the per-lane queue is 12 KB per block, so 8 blocks fit per CU)
+// and 6 with one.  The compiler spills some saved walk state to scratch,
+// which the extra waves more than pay for: at n = 12, capacity 100 / 60 /
+// 40 / 25 % of the footprint, 12.4 / 18.2 / 19.9 / 19.9 ms uncapped (90
+// VGPRs, 5 waves), 11.1 / 16.0 / 17.4 / 17.5 ms at 7 waves, 10.8 / 15.6 /
+// 16.9 / 16.9 ms at 8; one engine 1.20-1.24 -> 1.16-1.22 ms.
+template <typename TT, bool ONE>
+constexpr int mem_min_waves() { return sizeof(TT) == 4 ? (ONE ? 6 : 8) : 1; }
+
 template <typename TT, bool ONE, bool STORE, int M>
-__global__ __launch_bounds__(MEM_THREADS) void mem_enum_kernel(const tgo_task *__restrict__ tasks,
+__global__ __launch_bounds__(MEM_THREADS) __attribute__((amdgpu_waves_per_eu(mem_min_waves<TT, ONE>()))) void mem_enum_kernel(const tgo_task *__restrict__ tasks,
                                                                const int64_t *__restrict__ mem, int n,
                                                                uint64_t cap, Rates r, uint32_t n_sub,
                                                                int64_t *out, Partial *partials) {
