@@ -4,8 +4,7 @@ Workload: one group of N=12 tasks (6 dominant-kernel: K log-uniform 1-20 ms,
 HtD/DtH 0.1-2 ms; 6 dominant-transfer: ranges swapped), int64 ns, seed 1;
 overlap rates 3/4.  One step = all 12! = 479,001,600 orderings evaluated and
 reduced to best / worst / mean (one exhaustive call) plus the ordering
-heuristic for the same group, on a second stream beside the enumeration.
-Inputs are resident in HBM before timing.
+heuristic for the same group.  Inputs are resident in HBM before timing.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
@@ -458,31 +457,21 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
 
-    # Algorithm 1 for the same group runs on a second stream (default
-    # priority) beside the enumeration; the step ends when both have.  Its
-    # outputs are allocated on that stream and kept until the next sync.
-    side = torch.cuda.Stream(device=dev)
-    held = []
-
+    # One stream: the process keeps few streams alive, because HIP maps them
+    # onto 4 hardware queues and the device validation below needs its HtD
+    # and DtH streams on queues of their own (a second stream for Algorithm 1
+    # here, kept alive by torch's stream pool, made those copies serialise).
     def step(ev_pair=None):
-        fork = torch.cuda.Event()
-        fork.record(stream)
-        side.wait_event(fork)
-        with torch.cuda.stream(side):
-            held.append(tgo.heuristic(tasks, offs, model, stream=side))
         if ev_pair is not None:
             ev_pair[0].record(stream)
         tgo.exhaustive(tasks, model, summary=summary, stream=stream)
         if ev_pair is not None:
             ev_pair[1].record(stream)
-        join = torch.cuda.Event()
-        join.record(side)
-        stream.wait_event(join)
+        tgo.heuristic(tasks, offs, model, stream=stream)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    held.clear()
 
     k = args.steps
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k)]
@@ -494,7 +483,6 @@ def main():
         step(evs[i])
     t_end.record(stream)
     torch.cuda.synchronize()
-    held.clear()
     total_ms = t_start.elapsed_time(t_end)
     launch_ms = [a.elapsed_time(b) for a, b in evs]
     avg_launch_ms = sum(launch_ms) / k
@@ -542,20 +530,45 @@ def main():
         want = set(args.extras.split(",")) if args.extras != "all" else \
             {"batch", "one_dma", "rounds", "memory", "proposal", "serving", "hw"}
         extras = {}
+        device_ok = [True]
+
+        def run_extra(name, fn, *a):
+            # an extra that fails is reported in its place and the headline
+            # line still prints; after a device-side error no further GPU
+            # work is started in this process
+            if not device_ok[0]:
+                extras[name] = {"error": "skipped after a device error in an earlier extra"}
+                return None
+            try:
+                r = fn(*a)
+                extras[name] = r
+                return r
+            except Exception as e:  # noqa: BLE001 - reported, not swallowed
+                msg = f"{type(e).__name__}: {e}"
+                extras[name] = {"error": msg}
+                print(json.dumps({"extra_failed": name, "error": msg}), file=sys.stderr, flush=True)
+                dev_err = (isinstance(e, tgo.TgoError) and e.code == tgo.TGO_EDEVICE) or \
+                    ("HIP error" in str(e) or "CUDA error" in str(e))
+                if dev_err:
+                    device_ok[0] = False
+                return None
+
         for name, fn in (("batch", batch_extra), ("one_dma", one_dma_extra), ("rounds", rounds_extra),
                          ("memory", memory_extra)):
             if name in want:
-                extras[name] = fn(dev)
+                run_extra(name, fn, dev)
         if want & {"proposal", "serving"}:
-            sur, tr = train_surrogate(dev, args.train_pairs)
-            extras["proposal_training"] = tr
-            if "proposal" in want:
-                extras["proposal_n16"] = surrogate_extra(dev, sur, args.eval_groups)
-            if "serving" in want:
-                extras["serving"] = serving_extra(dev, sur, args.serve_seconds)
-            sur.close()
+            trained = run_extra("proposal_training", lambda: train_surrogate(dev, args.train_pairs))
+            if trained is not None:
+                sur, tr = trained
+                extras["proposal_training"] = tr
+                if "proposal" in want:
+                    run_extra("proposal_n16", surrogate_extra, dev, sur, args.eval_groups)
+                if "serving" in want:
+                    run_extra("serving", serving_extra, dev, sur, args.serve_seconds)
+                sur.close()
         if "hw" in want and args.hw_unit_ms > 0:
-            extras["hw_validation"] = hw_validation_extra(dev, args.hw_unit_ms)
+            run_extra("hw_validation", hw_validation_extra, dev, args.hw_unit_ms)
         out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(tasks_np, args.cpu_seconds)

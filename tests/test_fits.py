@@ -66,5 +66,8 @@ def test_fit_overlap_skips_non_overlapping(tgo):
     t_ov, _ = overlap_times(1200, 1200, 0, m)
     rh, rd = tgo.fit_overlap(np.array([t_no, t_ov]), np.array([[1000, 1000], [1200, 1200]]))
     assert rh == pytest.approx(0.75) and rd == pytest.approx(0.75)
-    with pytest.raises(tgo.TgoError):
+    # no overlap at all: an argument error (the device validation then keeps
+    # solo rates and reports that no overlap was observed)
+    with pytest.raises(tgo.TgoError) as ei:
         tgo.fit_overlap(np.array([t_no]), np.array([[1000, 1000]]))
+    assert ei.value.code == tgo.TGO_EINVAL
