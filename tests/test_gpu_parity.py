@@ -160,6 +160,30 @@ def test_exhaustive_n10_per_ordering(dev):
         check_summary(tgo.read_summary(summ), ref, 10)
 
 
+def test_exhaustive_grid_sizes_agree(dev, monkeypatch):
+    """The launch grid does not change the answer: one block (each lane strides
+    over hundreds of subtrees, folding them in rank order), a few blocks, and
+    the default grid of many short blocks; ties are resolved to the lowest
+    rank across block partials.  TGO_EXHAUSTIVE_BLOCKS sets the grid."""
+    from paper_1806_10113_amd import tgo
+    tasks = W.batch_groups(2, 9, 9, seed=11).group(0)
+    ties = np.array([[5, 7, 3]] * 8, dtype=np.int64)
+    models = (M.DEFAULT, M.Model(4, 3, 3, 1))
+    refs = {m: cmodel.exhaustive(tasks, m, per_order=True) for m in models}
+    for blocks in (None, "1", "3", "200"):
+        if blocks is None:
+            monkeypatch.delenv("TGO_EXHAUSTIVE_BLOCKS", raising=False)
+        else:
+            monkeypatch.setenv("TGO_EXHAUSTIVE_BLOCKS", blocks)
+        for m in models:
+            summ, po = tgo.exhaustive(to_dev(tasks, dev), tmodel(m), per_order=True)
+            assert np.array_equal(po.cpu().numpy(), refs[m]["times"]), (blocks, m)
+            check_summary(tgo.read_summary(summ), refs[m], 9)
+            s = tgo.read_summary(tgo.exhaustive(to_dev(ties, dev), tmodel(m))[0])
+            assert s["argmin_rank"] == 0 and s["argmax_rank"] == 0 and s["min_ns"] == s["max_ns"], (blocks, m)
+    monkeypatch.delenv("TGO_EXHAUSTIVE_BLOCKS", raising=False)
+
+
 def test_exhaustive_64bit_path(dev):
     from paper_1806_10113_amd import tgo
     rng = np.random.default_rng(103)
