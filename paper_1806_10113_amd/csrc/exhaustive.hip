@@ -60,10 +60,10 @@ __device__ __forceinline__ void fold(Acc<TT> &a, const Sub<TT> &u, uint64_t r0) 
 template <typename TT>
 using ExView = View<TT, 1, EX_THREADS>;
 
-// Reduce a block's lane accumulators into one Partial (thread 0 writes it).
+// Reduce a block's lane accumulators into one Partial, returned to thread 0.
 // wsum: LDS for one Partial per wave; it may alias memory the block used
 // before (every thread has left its loop once the barrier below is passed).
-__device__ void block_reduce_write(Partial p, Partial *dst, Partial *wsum) {
+__device__ Partial block_reduce(Partial p, Partial *wsum) {
     for (int m = 32; m >= 1; m >>= 1) {
         const uint64_t mt = shfl_xor64(p.min_t, m), mr = shfl_xor64(p.min_r, m);
         const uint64_t xt = shfl_xor64(p.max_t, m), xr = shfl_xor64(p.max_r, m);
@@ -78,8 +78,8 @@ __device__ void block_reduce_write(Partial p, Partial *dst, Partial *wsum) {
     __syncthreads();
     if ((threadIdx.x & 63) == 0) wsum[w] = p;
     __syncthreads();
+    Partial o = wsum[0];
     if (threadIdx.x == 0) {
-        Partial o = wsum[0];
         for (int i = 1; i < (int)(blockDim.x / 64); ++i) {
             merge_min(o.min_t, o.min_r, wsum[i].min_t, wsum[i].min_r);
             merge_max(o.max_t, o.max_r, wsum[i].max_t, wsum[i].max_r);
@@ -88,9 +88,21 @@ __device__ void block_reduce_write(Partial p, Partial *dst, Partial *wsum) {
         }
         o.status = 0;
         o.pad = 0;
-        *dst = o;
     }
+    return o;
 }
+
+// Whole-group accumulator of the 32-bit time path, folded into by every
+// block with 64-bit atomics.  There T < 2^31 and a rank < 13! < 2^33, so
+// (T << 33) | rank orders by time and then by rank: the smallest key is the
+// best ordering with the lowest rank, and with the rank complemented the
+// largest key is the worst ordering with the lowest rank.  The sum over all
+// orderings stays below 13! * 2^31 < 2^64; the fingerprint wraps.
+struct ExAcc {
+    unsigned long long minkey, maxkey, sum, fp;
+};
+constexpr uint64_t EX_RANK_MASK = (1ull << 33) - 1;
+
 
 // Dynamic LDS of the exhaustive kernel: the task tables (n entries each),
 // then the per-lane kernel-completion queue, n - 1 slots (the last position's
@@ -118,8 +130,15 @@ constexpr int ex_min_waves() { return sizeof(TT) == 4 ? 7 : 1; }
 
 // The group's time path, decided once before the enumeration: 0 = 32-bit,
 // 1 = 64-bit, or a negative error code (classify_group).
-__global__ void exhaustive_classify(const tgo_task *__restrict__ tasks, int n, Rates r, int *mode) {
-    if (threadIdx.x == 0) *mode = classify_group(tasks, n, r);
+__global__ void exhaustive_classify(const tgo_task *__restrict__ tasks, int n, Rates r, int *mode,
+                                    ExAcc *acc) {
+    if (threadIdx.x == 0) {
+        *mode = classify_group(tasks, n, r);
+        acc->minkey = ~0ull;
+        acc->maxkey = 0;
+        acc->sum = 0;
+        acc->fp = 0;
+    }
 }
 
 // MODE: 0 = 32-bit time path, 1 = 64-bit.  Both instantiations are launched;
@@ -129,7 +148,7 @@ __global__ void exhaustive_classify(const tgo_task *__restrict__ tasks, int n, R
 template <typename TT, int M, bool STORE, int DMA>
 __global__ __launch_bounds__(EX_THREADS) __attribute__((amdgpu_waves_per_eu(ex_min_waves<TT>())))
 void exhaustive_kernel(const tgo_task *__restrict__ tasks, int n, Rates r, uint32_t n_sub, int64_t *out,
-                       Partial *partials, const int *__restrict__ modep) {
+                       Partial *partials, ExAcc *acc, const int *__restrict__ modep) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int MODE = sizeof(TT) == 4 ? 0 : 1;
     if (*modep != MODE) return;
@@ -174,7 +193,18 @@ void exhaustive_kernel(const tgo_task *__restrict__ tasks, int n, Rates r, uint3
     p.fp = a.fp;
     p.status = 0;
     p.pad = 0;
-    block_reduce_write(p, &partials[blockIdx.x], reinterpret_cast<Partial *>(qbase));
+    const Partial o = block_reduce(p, reinterpret_cast<Partial *>(qbase));
+    if (threadIdx.x == 0) {
+        if constexpr (sizeof(TT) == 4) {
+            // every block owns at least one subtree, so o holds an ordering
+            atomicMin(&acc->minkey, (unsigned long long)((o.min_t << 33) | o.min_r));
+            atomicMax(&acc->maxkey, (unsigned long long)(((o.max_t - 1) << 33) | (EX_RANK_MASK - o.max_r)));
+            atomicAdd(&acc->sum, (unsigned long long)o.sum_lo);
+            atomicAdd(&acc->fp, (unsigned long long)o.fp);
+        } else {
+            partials[blockIdx.x] = o;
+        }
+    }
 }
 
 __device__ inline void unrank_dev(int n, uint64_t r, uint8_t *out) {
@@ -198,10 +228,12 @@ constexpr int EX_FIN_THREADS = 1024;
 
 __global__ __launch_bounds__(EX_FIN_THREADS) void exhaustive_finalize(const Partial *__restrict__ parts,
                                                                       int nparts, int n, uint64_t count,
+                                                                      const ExAcc *__restrict__ acc,
                                                                       const int *__restrict__ modep,
                                                                       tgo_summary *out) {
     __shared__ Partial red[EX_FIN_THREADS / 64];
-    const int status = *modep < 0 ? *modep : 0;
+    const int mode = *modep;
+    const int status = mode < 0 ? mode : 0;
     Partial p;
     p.min_t = ~0ull; p.min_r = ~0ull; p.max_t = 0; p.max_r = ~0ull;
     p.sum_lo = 0; p.sum_hi = 0; p.fp = 0; p.status = 0; p.pad = 0;
@@ -211,7 +243,7 @@ __global__ __launch_bounds__(EX_FIN_THREADS) void exhaustive_finalize(const Part
         add128(p.sum_lo, p.sum_hi, q.sum_lo, q.sum_hi);
         p.fp += q.fp;
     };
-    if (status == 0) {
+    if (mode == 1) {
         // four partials in flight per thread: the loads, not the merges, set the time
         const int b = (int)blockDim.x;
         int i = (int)threadIdx.x;
@@ -243,6 +275,15 @@ __global__ __launch_bounds__(EX_FIN_THREADS) void exhaustive_finalize(const Part
             merge_max(red[0].max_t, red[0].max_r, q.max_t, q.max_r);
             add128(red[0].sum_lo, red[0].sum_hi, q.sum_lo, q.sum_hi);
             red[0].fp += q.fp;
+        }
+        if (mode == 0) {
+            red[0].min_t = acc->minkey >> 33;
+            red[0].min_r = acc->minkey & EX_RANK_MASK;
+            red[0].max_t = (acc->maxkey >> 33) + 1;
+            red[0].max_r = EX_RANK_MASK - (acc->maxkey & EX_RANK_MASK);
+            red[0].sum_lo = acc->sum;
+            red[0].sum_hi = 0;
+            red[0].fp = acc->fp;
         }
     }
     if (threadIdx.x == 0) {
@@ -353,20 +394,22 @@ static int launch_pair(size_t shm32, size_t shm64, hipStream_t st, const tgo_tas
         if (v >= 1 && v <= (1l << 20)) blocks = (uint32_t)v;
     }
     if ((uint64_t)blocks > want) blocks = (uint32_t)want;
-    // workspace: the block partials, then the group's time path
+    // workspace: the block partials (64-bit path), the 32-bit path's
+    // accumulator, then the group's time path
     Partial *parts = nullptr;
-    int rc = workspace(sizeof(Partial) * (blocks + 1), (void **)&parts);
+    int rc = workspace(sizeof(Partial) * (blocks + 1) + sizeof(ExAcc), (void **)&parts);
     if (rc) return rc;
-    int *mode = reinterpret_cast<int *>(parts + blocks);
-    hipLaunchKernelGGL(exhaustive_classify, dim3(1), dim3(64), 0, st, t, n, r, mode);
+    ExAcc *acc = reinterpret_cast<ExAcc *>(parts + blocks);
+    int *mode = reinterpret_cast<int *>(acc + 1);
+    hipLaunchKernelGGL(exhaustive_classify, dim3(1), dim3(64), 0, st, t, n, r, mode, acc);
     const dim3 grid(blocks);
     hipLaunchKernelGGL((exhaustive_kernel<uint32_t, M, STORE, DMA>), grid, dim3(EX_THREADS), shm32, st, t, n, r,
-                       n_sub, out, parts, mode);
+                       n_sub, out, parts, acc, mode);
     hipLaunchKernelGGL((exhaustive_kernel<uint64_t, M, STORE, DMA>), grid, dim3(EX_THREADS), shm64, st, t, n, r,
-                       n_sub, out, parts, mode);
+                       n_sub, out, parts, acc, mode);
     TGO_HIP(hipGetLastError());
     hipLaunchKernelGGL(exhaustive_finalize, dim3(1), dim3(EX_FIN_THREADS), 0, st, parts, (int)blocks, n,
-                       factorial(n), mode, d_out);
+                       factorial(n), acc, mode, d_out);
     TGO_HIP(hipGetLastError());
     return TGO_OK;
 }
