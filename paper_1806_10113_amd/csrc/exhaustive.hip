@@ -4,8 +4,9 @@
 // Section 5.1 rule out at runtime on a CPU), reduced to the best, worst and
 // average ordering (the quantities plotted in Section 6).
 //
-// One lane per subtree (see enum_dev.h); lanes meet their ranks in increasing
-// order, so the reduction keeps the lowest rank on ties.
+// Each lane walks subtrees (see enum_dev.h), striding over the grid; a lane
+// meets its ranks in increasing order, and every merge prefers the lower rank,
+// so the reduction keeps the lowest rank on ties.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -372,10 +373,11 @@ static uint32_t resident_blocks(const void *kern, size_t shm) {
 // Blocks per launch, in units of the blocks the 32-bit kernel keeps resident
 // at once.  A subtree's cost varies with its DtH events, so blocks finish at
 // different times: one resident round leaves SIMDs idle at the end, many
-// short blocks let the dispatcher fill them.  At N = 12 on MI355X (1,536
-// resident blocks) 8 rounds gave 3.06-3.11 ms per launch against 3.82 ms for
-// one round and 3.30 ms for 20 subtrees per lane; beyond ~20 rounds the
-// per-block partials and their reduction cost more than they balance.
+// short blocks let the dispatcher fill them.  Measured at N = 12 on MI355X
+// with 6 waves per SIMD (1,536 resident blocks): 8 rounds gave 3.06-3.11 ms
+// per launch against 3.82 ms for one round and 3.30 ms for 20 subtrees per
+// lane; beyond ~20 rounds the per-block work around the walk costs more than
+// it balances.  At 7 waves the grid is 8 x 1,792 = 14,336 blocks.
 constexpr uint32_t EX_ROUNDS = 8;
 
 // Launch the 32-bit and 64-bit instantiations (the one that does not match
