@@ -30,7 +30,13 @@
 namespace tgo {
 
 constexpr int MEM_THREADS = 256;
-constexpr int MEM_MAX_BLOCKS = 8192;
+// Blocks per launch at most: about 8 rounds of the resident blocks with two
+// engines (2,048 at 8 waves per SIMD), where subtrees vary most in cost
+// (n = 12: 16,384 blocks 10.4 / 14.9 / 16.2 ms at capacity 100 / 60 / 40 %
+// against 10.7 / 15.6 / 16.9 ms with 8,192); with one engine 8,192 (16,384
+// was 4-6 % slower, 4,096 the same).
+constexpr int MEM_MAX_BLOCKS_TWO = 16384;
+constexpr int MEM_MAX_BLOCKS_ONE = 8192;
 
 __constant__ uint32_t MEM_FACT[13] = {1u,      1u,       2u,        6u,         24u,        120u,     720u,
                                       5040u,   40320u,   362880u,   3628800u,   39916800u,  479001600u};
@@ -365,7 +371,8 @@ int launch_memory(const Rates &r, const tgo_task *d_tasks, const int64_t *d_mem,
     const uint64_t count = factorial(n);
     const uint32_t n_sub = (uint32_t)(count / factorial(M));
     const uint64_t want = ((uint64_t)n_sub + MEM_THREADS - 1) / MEM_THREADS;
-    const uint32_t blocks = (uint32_t)(want < MEM_MAX_BLOCKS ? want : MEM_MAX_BLOCKS);
+    const uint64_t most = r.one_dma ? MEM_MAX_BLOCKS_ONE : MEM_MAX_BLOCKS_TWO;
+    const uint32_t blocks = (uint32_t)(want < most ? want : most);
     Partial *parts = nullptr;
     int rc = workspace(sizeof(Partial) * blocks, (void **)&parts);
     if (rc) return rc;
