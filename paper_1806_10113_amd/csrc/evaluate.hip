@@ -107,7 +107,7 @@ __global__ __launch_bounds__(HEU_THREADS) void heuristic_kernel(const tgo_task *
         table_entry<TT>(t[x], r, &Ht[x * blockDim.x + threadIdx.x], &Dt[x * blockDim.x + threadIdx.x]);
 
     uint8_t ord[MAXN];
-    *nsg = heuristic_order([t](int x) { return t[x]; }, n, v, r, ord);
+    *nsg = heuristic_order(n, v, r, ord);
     for (int i = 0; i < n; ++i) orow[i] = ord[i];
 }
 

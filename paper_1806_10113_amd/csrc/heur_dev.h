@@ -41,13 +41,21 @@ __device__ __forceinline__ Fit3 fit_state(const Lane<TT> &st, const Rates &r) {
     return u;
 }
 
-// Algorithm 1 on n tasks: task(x) returns task x (0 <= x < n); v holds the
-// lane's tables of those n tasks (built by the caller) and its queue.
-// Writes the ordering to ord[0..n-1] and returns its total time.
-template <typename TaskFn, int TS, int QS>
-__device__ int64_t heuristic_order(TaskFn task, int n, const View<uint64_t, TS, QS> &v,
-                                   const Rates &r, uint8_t *ord) {
+// Algorithm 1 on n tasks: v holds the lane's tables of tasks 0..n-1 (built
+// by the caller) and its queue; the candidates' durations are read from those
+// LDS tables, not from global memory, since every selection step scans all of
+// them.  Writes the ordering to ord[0..n-1] and returns its total time.
+template <int TS, int QS>
+__device__ int64_t heuristic_order(int n, const View<uint64_t, TS, QS> &v, const Rates &r, uint8_t *ord) {
     using TT = uint64_t;
+    auto task = [&v](int x) {
+        const Quad<TT> q = v.task((uint32_t)x);
+        tgo_task t;
+        t.htd_ns = (int64_t)q.h;
+        t.kern_ns = (int64_t)q.k;
+        t.dth_ns = (int64_t)q.d;
+        return t;
+    };
     uint32_t rt = (1u << n) - 1u;
     int first = -1;
     int64_t bkh = 0, bd = 0;

@@ -439,7 +439,7 @@ __global__ __launch_bounds__(64) void rounds_heuristic_kernel(const tgo_task *__
                     if ((buffer >> x) & 1u) mem[g++] = (uint8_t)x;
                 for (int i = 0; i < g; ++i) table_entry<uint64_t>(tasks[mem[i]], r, &Ht[i], &Dt[i]);
                 uint8_t ord[MAXN];
-                heuristic_order([&](int i) { return tasks[mem[i]]; }, g, v, r, ord);
+                heuristic_order(g, v, r, ord);
                 uint8_t launch[MAXN];
                 for (int i = 0; i < g; ++i) launch[i] = mem[ord[i]];
                 rsim_submit(s, launch, g);
