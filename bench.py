@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0
 VALU_LANE_OPS_PER_ORDERING = 257.29
 # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, each scaled by
 # what the counter reads for a 256 MiB device copy (same profile file).
-TRAFFIC_BYTES_PER_LAUNCH = 1_990_632
+TRAFFIC_BYTES_PER_LAUNCH = 1_970_156
 
 
 def parse():

@@ -27,13 +27,22 @@ FLAGS = [
 ]
 
 
+# Per-file extra flags.  The enumeration kernels are latency-bound event loops
+# with little independent work per wave; LLVM's max-ILP machine scheduler
+# orders them 0.5-1.5 % faster on MI355X (N = 12 two engines, N = 13 one
+# engine), with the same registers and results.
+FILE_FLAGS = {
+    "exhaustive.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+}
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
