@@ -35,6 +35,14 @@
  *     reported through the status fields of the outputs.
  *   - Functions are reentrant; a handle (plan, surrogate, server) must not be
  *     used from two threads at once.
+ *   - Scratch memory: tgo_exhaustive, tgo_exhaustive_mem, tgo_rounds,
+ *     tgo_random_search and tgo_valu_probe use device scratch owned by the
+ *     library, one buffer per (device, stream), grown on demand (a growth
+ *     waits for that stream's earlier work and allocates) and kept until the
+ *     process ends.  Calls on different streams may therefore overlap; calls
+ *     on one stream are ordered by the stream.  Destroy a stream only after
+ *     its work has finished: a later stream with the same handle reuses its
+ *     scratch.
  */
 #ifndef TGO_H
 #define TGO_H

@@ -41,35 +41,46 @@ int make_rates(const tgo_model *m, Rates *r) {
     return TGO_OK;
 }
 
-struct DevWs {
+// One workspace per (device, stream): calls on different streams never share
+// one, and calls on one stream are ordered by the stream itself.
+struct StreamWs {
+    int dev = 0;
+    hipStream_t st = nullptr;
     void *ptr = nullptr;
     size_t bytes = 0;
 };
 static std::mutex g_ws_mu;
-static std::vector<DevWs> g_ws;
+static std::vector<StreamWs> g_ws;
 
-int workspace(size_t bytes, void **ptr) {
+int workspace(size_t bytes, void **ptr, hipStream_t st) {
     int dev = 0;
     TGO_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_ws_mu);
-    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
-    DevWs &w = g_ws[dev];
-    if (w.bytes < bytes) {
-        // Wait for work that may still use the old buffer before freeing it.
-        if (w.ptr) {
-            TGO_HIP(hipDeviceSynchronize());
-            TGO_HIP(hipFree(w.ptr));
-            w.ptr = nullptr;
-            w.bytes = 0;
+    StreamWs *w = nullptr;
+    for (StreamWs &e : g_ws)
+        if (e.dev == dev && e.st == st) { w = &e; break; }
+    if (!w) {
+        g_ws.emplace_back();
+        w = &g_ws.back();
+        w->dev = dev;
+        w->st = st;
+    }
+    if (w->bytes < bytes) {
+        // Earlier calls on this stream may still use the old buffer.
+        if (w->ptr) {
+            TGO_HIP(hipStreamSynchronize(st));
+            TGO_HIP(hipFree(w->ptr));
+            w->ptr = nullptr;
+            w->bytes = 0;
         }
         size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
         void *p = nullptr;
         hipError_t e = hipMalloc(&p, want);
         if (e != hipSuccess) return fail(TGO_ENOMEM, std::string("workspace: ") + hipGetErrorString(e));
-        w.ptr = p;
-        w.bytes = want;
+        w->ptr = p;
+        w->bytes = want;
     }
-    *ptr = w.ptr;
+    *ptr = w->ptr;
     return TGO_OK;
 }
 

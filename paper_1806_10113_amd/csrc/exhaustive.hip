@@ -399,7 +399,7 @@ static int launch_pair(size_t shm32, size_t shm64, hipStream_t st, const tgo_tas
     // workspace: the block partials (64-bit path), the 32-bit path's
     // accumulator, then the group's time path
     Partial *parts = nullptr;
-    int rc = workspace(sizeof(Partial) * (blocks + 1) + sizeof(ExAcc), (void **)&parts);
+    int rc = workspace(sizeof(Partial) * (blocks + 1) + sizeof(ExAcc), (void **)&parts, st);
     if (rc) return rc;
     ExAcc *acc = reinterpret_cast<ExAcc *>(parts + blocks);
     int *mode = reinterpret_cast<int *>(acc + 1);

@@ -575,7 +575,7 @@ int tgo_valu_probe(int blocks, int iters, tgo_stream stream) {
     if (blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 20))
         return fail(TGO_EINVAL, "blocks and iters must be in 1..2^20");
     uint32_t *sink = nullptr;
-    int rc = workspace(256, (void **)&sink);
+    int rc = workspace(256, (void **)&sink, (hipStream_t)stream);
     if (rc) return rc;
     hipLaunchKernelGGL(tgo_valu_probe_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, sink, iters, 7u);
     TGO_HIP(hipGetLastError());

@@ -374,7 +374,7 @@ int launch_memory(const Rates &r, const tgo_task *d_tasks, const int64_t *d_mem,
     const uint64_t most = r.one_dma ? MEM_MAX_BLOCKS_ONE : MEM_MAX_BLOCKS_TWO;
     const uint32_t blocks = (uint32_t)(want < most ? want : most);
     Partial *parts = nullptr;
-    int rc = workspace(sizeof(Partial) * blocks, (void **)&parts);
+    int rc = workspace(sizeof(Partial) * blocks, (void **)&parts, st);
     if (rc) return rc;
     const uint64_t c = (uint64_t)cap;
     const dim3 g(blocks);

@@ -473,7 +473,7 @@ int launch_rounds(const Rates &r, const tgo_task *d_tasks, int T, int R, int64_t
     const uint64_t want = (count + RD_THREADS - 1) / RD_THREADS;
     const uint32_t blocks = (uint32_t)(want < RD_MAX_BLOCKS ? want : RD_MAX_BLOCKS);
     Partial *parts = nullptr;
-    int rc = workspace(sizeof(Partial) * blocks, (void **)&parts);
+    int rc = workspace(sizeof(Partial) * blocks, (void **)&parts, st);
     if (rc) return rc;
     const bool one = r.one_dma != 0;
     const uint32_t c32 = (uint32_t)count, t32 = (uint32_t)tf;

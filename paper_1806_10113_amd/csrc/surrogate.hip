@@ -1298,7 +1298,7 @@ int tgo_random_search(const tgo_model *model, const tgo_task *d_tasks, const int
     const int64_t per = (samples + 63) / 64 * 64;
     char *ws = nullptr;
     const size_t need = (size_t)G * (4 + 16 + 8 + 8) + 1024;
-    rc = workspace(need, (void **)&ws);
+    rc = workspace(need, (void **)&ws, st);
     if (rc) return rc;
     int32_t *status = (int32_t *)ws;
     int64_t *hns = (int64_t *)(ws + ((4 * (size_t)G + 255) & ~size_t(255)));

@@ -25,11 +25,11 @@ int hip_fail(hipError_t e, const char *what);
 // Validate a model and derive the kernel constants.
 int make_rates(const tgo_model *m, Rates *r);
 
-// Per-device workspace owned by the library, grown on demand and kept until
-// the process ends.  Not safe for overlapping calls on different streams of
-// one device that both need it (each call serialises through a mutex and the
-// buffer is stream-ordered per call).
-int workspace(size_t bytes, void **ptr);
+// Device workspace owned by the library, one per (device, stream), grown on
+// demand (a growth waits for the stream's earlier work) and kept until the
+// process ends.  Calls on different streams get different buffers, so they
+// may overlap; calls on one stream are ordered by the stream.
+int workspace(size_t bytes, void **ptr, hipStream_t st);
 
 constexpr uint64_t factorial(int n) { return n <= 1 ? 1ull : (uint64_t)n * factorial(n - 1); }
 

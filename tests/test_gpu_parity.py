@@ -184,6 +184,33 @@ def test_exhaustive_grid_sizes_agree(dev, monkeypatch):
     monkeypatch.delenv("TGO_EXHAUSTIVE_BLOCKS", raising=False)
 
 
+def test_exhaustive_concurrent_streams(dev):
+    """Calls in flight on two streams at once do not share scratch memory:
+    each gets the oracle's per-ordering times and summary (two groups, both
+    DMA schemes, several calls queued per stream before any sync)."""
+    import torch
+    from paper_1806_10113_amd import tgo
+    b = W.batch_groups(2, 9, 9, seed=13)
+    ga, gb = b.group(0), b.group(1)
+    refs = {(k, m): cmodel.exhaustive(g, m, per_order=True)
+            for k, g in (("a", ga), ("b", gb)) for m in (M.DEFAULT, M.Model(4, 3, 3, 1))}
+    sa, sb = torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)
+    ta, tb = to_dev(ga, dev), to_dev(gb, dev)
+    torch.cuda.synchronize()
+    outs = []
+    for m in (M.DEFAULT, M.Model(4, 3, 3, 1)):
+        for _ in range(3):
+            with torch.cuda.stream(sa):
+                outs.append(("a", m, tgo.exhaustive(ta, tmodel(m), per_order=True, stream=sa)))
+            with torch.cuda.stream(sb):
+                outs.append(("b", m, tgo.exhaustive(tb, tmodel(m), per_order=True, stream=sb)))
+    torch.cuda.synchronize()
+    for k, m, (summ, po) in outs:
+        ref = refs[(k, m)]
+        assert np.array_equal(po.cpu().numpy(), ref["times"]), (k, m)
+        check_summary(tgo.read_summary(summ), ref, 9)
+
+
 def test_exhaustive_64bit_path(dev):
     from paper_1806_10113_amd import tgo
     rng = np.random.default_rng(103)
