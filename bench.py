@@ -35,10 +35,10 @@ HBM_PEAK_GBS = 8000.0
 # VALU lane-ops per ordering issued by exhaustive_kernel<u32, M=4> on this
 # workload: SQ_INSTS_VALU per launch x 64 lanes / 12! (rocprofv3 counter run
 # recorded in profiles/exhaustive_n12_counters.txt).
-VALU_LANE_OPS_PER_ORDERING = 257.29
+VALU_LANE_OPS_PER_ORDERING = 258.30
 # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, each scaled by
 # what the counter reads for a 256 MiB device copy (same profile file).
-TRAFFIC_BYTES_PER_LAUNCH = 1_970_156
+TRAFFIC_BYTES_PER_LAUNCH = 2_887_660
 
 
 def parse():

@@ -374,11 +374,14 @@ static uint32_t resident_blocks(const void *kern, size_t shm) {
 // at once.  A subtree's cost varies with its DtH events, so blocks finish at
 // different times: one resident round leaves SIMDs idle at the end, many
 // short blocks let the dispatcher fill them.  Measured at N = 12 on MI355X
-// with 6 waves per SIMD (1,536 resident blocks): 8 rounds gave 3.06-3.11 ms
-// per launch against 3.82 ms for one round and 3.30 ms for 20 subtrees per
-// lane; beyond ~20 rounds the per-block work around the walk costs more than
-// it balances.  At 7 waves the grid is 8 x 1,792 = 14,336 blocks.
-constexpr uint32_t EX_ROUNDS = 8;
+// with 6 waves per SIMD (1,536 resident blocks) and block partials: 8 rounds
+// gave 3.06-3.11 ms per launch against 3.82 ms for one round and 3.30 ms for
+// 20 subtrees per lane.  With 7 waves (1,792 resident blocks) and the
+// accumulator atomics: 6 / 8 / 10 / 12 / 14 / 16 / 20 rounds took 2.85-2.87 /
+// 2.80 / 2.81-2.82 / 2.78-2.80 / 2.80-2.82 / 2.77-2.78 / 2.83 ms, and grids
+// that are not a multiple of the resident count were slower; 12 rounds,
+// 21,504 blocks.
+constexpr uint32_t EX_ROUNDS = 12;
 
 // Launch the 32-bit and 64-bit instantiations (the one that does not match
 // the group returns at once) and the finalize.  The grid is sized from the
