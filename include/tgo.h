@@ -145,6 +145,27 @@ int tgo_exhaustive(const tgo_model *model, const tgo_task *d_tasks, int n, int64
                    tgo_summary *d_summary, tgo_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * tgo_exhaustive_noalloc -- tgo_exhaustive for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, limits, errors and results as
+ * tgo_exhaustive; the caller still passes the tasks, the optional
+ * per-ordering buffer and the summary.  The call allocates nothing: its
+ * scratch (block partials, accumulator, time-path word) is a fixed
+ * per-device array of TGO_NOALLOC_SCRATCH_BYTES (2 MiB) that every device the
+ * library runs on holds until the process ends, and the launch grid is bounded
+ * so that the scratch always fits (the result does not depend on the grid).
+ * The scratch is re-initialised by the call's own kernels (no memset), so a
+ * call leaves nothing behind that the next one reads.  All calls on one device
+ * share that array: calls that overlap on one device (different streams, or
+ * threads) race and must be serialised by the caller.  The array's device
+ * address is looked up once per device, on the first call with that device
+ * current.
+ */
+#define TGO_NOALLOC_SCRATCH_BYTES (2u << 20)
+int tgo_exhaustive_noalloc(const tgo_model *model, const tgo_task *d_tasks, int n, int64_t *d_per_order,
+                           tgo_summary *d_summary, tgo_stream stream);
+
+/* ---------------------------------------------------------------------------
  * tgo_heuristic -- Algorithm 1 (Section 5.1) for a batch of groups.
  *   d_tasks/d_offs: CSR batch, group g = d_tasks[d_offs[g] .. d_offs[g+1]),
  *                   sizes 1..TGO_MAX_N.

@@ -127,6 +127,17 @@ int tgo_exhaustive(const tgo_model *model, const tgo_task *d_tasks, int n, int64
     return launch_exhaustive(r, d_tasks, n, d_per_order, d_summary, (hipStream_t)stream);
 }
 
+int tgo_exhaustive_noalloc(const tgo_model *model, const tgo_task *d_tasks, int n, int64_t *d_per_order,
+                           tgo_summary *d_summary, tgo_stream stream) {
+    Rates r;
+    int rc = make_rates(model, &r);
+    if (rc) return rc;
+    if (n < 1 || n > TGO_MAX_EXHAUSTIVE_N) return fail(TGO_EINVAL, "n must be in 1..13");
+    if (d_per_order && n > 12) return fail(TGO_EINVAL, "per-ordering output needs n <= 12");
+    if (!d_tasks || !d_summary) return fail(TGO_EINVAL, "NULL buffer");
+    return launch_exhaustive_noalloc(r, d_tasks, n, d_per_order, d_summary, (hipStream_t)stream);
+}
+
 int tgo_heuristic(const tgo_model *model, const tgo_task *d_tasks, const int32_t *d_offs,
                   int n_groups, uint8_t *d_orders, int64_t *d_ns, tgo_stream stream) {
     Rates r;

@@ -387,9 +387,16 @@ constexpr uint32_t EX_ROUNDS = 12;
 // the group returns at once) and the finalize.  The grid is sized from the
 // 32-bit kernel (the fast path), capped at one subtree per lane;
 // TGO_EXHAUSTIVE_BLOCKS overrides it for tuning experiments.
+// Scratch of one call: caller-provided (ptr, bytes), or the library's
+// per-(device, stream) workspace when ptr is NULL.
+struct ExScratch {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
 template <int M, bool STORE, int DMA>
 static int launch_pair(size_t shm32, size_t shm64, hipStream_t st, const tgo_task *t, int n,
-                       const Rates &r, uint32_t n_sub, int64_t *out, tgo_summary *d_out) {
+                       const Rates &r, uint32_t n_sub, int64_t *out, tgo_summary *d_out, ExScratch ws) {
     const void *k32 = reinterpret_cast<const void *>(&exhaustive_kernel<uint32_t, M, STORE, DMA>);
     const uint64_t want = ((uint64_t)n_sub + EX_THREADS - 1) / EX_THREADS;
     uint32_t blocks = resident_blocks(k32, shm32);
@@ -400,10 +407,21 @@ static int launch_pair(size_t shm32, size_t shm64, hipStream_t st, const tgo_tas
     }
     if ((uint64_t)blocks > want) blocks = (uint32_t)want;
     // workspace: the block partials (64-bit path), the 32-bit path's
-    // accumulator, then the group's time path
+    // accumulator, then the group's time path.  A fixed scratch bounds the
+    // grid instead (any grid gives the same result: lanes stride over the
+    // subtrees).
+    const size_t fixed = sizeof(ExAcc) + sizeof(Partial);
     Partial *parts = nullptr;
-    int rc = workspace(sizeof(Partial) * (blocks + 1) + sizeof(ExAcc), (void **)&parts, st);
-    if (rc) return rc;
+    if (ws.ptr) {
+        if (ws.bytes < fixed + sizeof(Partial))
+            return fail(TGO_ENOMEM, "scratch too small for one block");
+        const size_t fit = (ws.bytes - fixed) / sizeof(Partial);
+        if ((size_t)blocks > fit) blocks = (uint32_t)fit;
+        parts = reinterpret_cast<Partial *>(ws.ptr);
+    } else {
+        int rc = workspace(sizeof(Partial) * (blocks + 1) + sizeof(ExAcc), (void **)&parts, st);
+        if (rc) return rc;
+    }
     ExAcc *acc = reinterpret_cast<ExAcc *>(parts + blocks);
     int *mode = reinterpret_cast<int *>(acc + 1);
     hipLaunchKernelGGL(exhaustive_classify, dim3(1), dim3(64), 0, st, t, n, r, mode, acc);
@@ -421,23 +439,23 @@ static int launch_pair(size_t shm32, size_t shm64, hipStream_t st, const tgo_tas
 
 template <bool STORE, int DMA>
 static int launch_m(int m, size_t shm32, size_t shm64, hipStream_t st, const tgo_task *t, int n,
-                    const Rates &r, uint32_t n_sub, int64_t *out, tgo_summary *d_out) {
+                    const Rates &r, uint32_t n_sub, int64_t *out, tgo_summary *d_out, ExScratch ws) {
     switch (m) {
-        case 1: return launch_pair<1, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out);
-        case 2: return launch_pair<2, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out);
-        case 3: return launch_pair<3, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out);
-        case 4: return launch_pair<4, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out);
-        case 5: return launch_pair<5, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out);
+        case 1: return launch_pair<1, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out, ws);
+        case 2: return launch_pair<2, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out, ws);
+        case 3: return launch_pair<3, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out, ws);
+        case 4: return launch_pair<4, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out, ws);
+        case 5: return launch_pair<5, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out, ws);
         default:
             if constexpr (DMA == DMA_ONE)
-                return launch_pair<6, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out);
+                return launch_pair<6, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out, ws);
             else
-                return launch_pair<5, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out);
+                return launch_pair<5, STORE, DMA>(shm32, shm64, st, t, n, r, n_sub, out, d_out, ws);
     }
 }
 
-int launch_exhaustive(const Rates &r, const tgo_task *d_tasks, int n, int64_t *d_per_order,
-                      tgo_summary *d_out, hipStream_t st) {
+static int launch_exhaustive_ws(const Rates &r, const tgo_task *d_tasks, int n, int64_t *d_per_order,
+                                tgo_summary *d_out, hipStream_t st, ExScratch ws) {
     const bool one = r.one_dma != 0;
     const int m = choose_m(n, one);
     const uint64_t n_sub64 = factorial(n) / factorial(m);
@@ -446,11 +464,54 @@ int launch_exhaustive(const Rates &r, const tgo_task *d_tasks, int n, int64_t *d
     const size_t shm32 = ex_shm_bytes<uint32_t>(n, one);
     const size_t shm64 = ex_shm_bytes<uint64_t>(n, one);
     if (one) {
-        return d_per_order ? launch_m<true, DMA_ONE>(m, shm32, shm64, st, d_tasks, n, r, n_sub, d_per_order, d_out)
-                           : launch_m<false, DMA_ONE>(m, shm32, shm64, st, d_tasks, n, r, n_sub, nullptr, d_out);
+        return d_per_order
+                   ? launch_m<true, DMA_ONE>(m, shm32, shm64, st, d_tasks, n, r, n_sub, d_per_order, d_out, ws)
+                   : launch_m<false, DMA_ONE>(m, shm32, shm64, st, d_tasks, n, r, n_sub, nullptr, d_out, ws);
     }
-    return d_per_order ? launch_m<true, DMA_TWO>(m, shm32, shm64, st, d_tasks, n, r, n_sub, d_per_order, d_out)
-                       : launch_m<false, DMA_TWO>(m, shm32, shm64, st, d_tasks, n, r, n_sub, nullptr, d_out);
+    return d_per_order
+               ? launch_m<true, DMA_TWO>(m, shm32, shm64, st, d_tasks, n, r, n_sub, d_per_order, d_out, ws)
+               : launch_m<false, DMA_TWO>(m, shm32, shm64, st, d_tasks, n, r, n_sub, nullptr, d_out, ws);
+}
+
+int launch_exhaustive(const Rates &r, const tgo_task *d_tasks, int n, int64_t *d_per_order,
+                      tgo_summary *d_out, hipStream_t st) {
+    return launch_exhaustive_ws(r, d_tasks, n, d_per_order, d_out, st, ExScratch{});
+}
+
+// Fixed scratch of the allocation-free enumeration: block partials, the
+// 32-bit accumulator and the time-path word of one call.  Each device holds
+// its own copy for the life of the process.  On the host the array's name is
+// only a stand-in: its device address comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[TGO_NOALLOC_SCRATCH_BYTES];
+
+constexpr int EX_MAX_DEVICES = 64;
+
+static int scratch_address(void **ptr) {
+    static std::mutex mu;
+    static void *addr[EX_MAX_DEVICES] = {};
+    int dev = 0;
+    TGO_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= EX_MAX_DEVICES) return fail(TGO_EDEVICE, "device index above 63");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(TGO_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return TGO_OK;
+}
+
+int launch_exhaustive_noalloc(const Rates &r, const tgo_task *d_tasks, int n, int64_t *d_per_order,
+                              tgo_summary *d_out, hipStream_t st) {
+    ExScratch ws;
+    int rc = scratch_address(&ws.ptr);
+    if (rc) return rc;
+    ws.bytes = TGO_NOALLOC_SCRATCH_BYTES;
+    return launch_exhaustive_ws(r, d_tasks, n, d_per_order, d_out, st, ws);
 }
 
 }  // namespace tgo

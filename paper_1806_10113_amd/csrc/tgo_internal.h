@@ -44,6 +44,10 @@ struct Partial {
 
 int launch_exhaustive(const Rates &r, const tgo_task *d_tasks, int n, int64_t *d_per_order,
                       tgo_summary *d_out, hipStream_t st);
+// Same enumeration with its scratch in a fixed per-device array (no
+// allocation; the grid is bounded by the array's size).
+int launch_exhaustive_noalloc(const Rates &r, const tgo_task *d_tasks, int n, int64_t *d_per_order,
+                              tgo_summary *d_out, hipStream_t st);
 int launch_evaluate(const Rates &r, const tgo_task *d_tasks, int n, const uint8_t *d_orders,
                     int64_t m, int64_t *d_out, hipStream_t st);
 int launch_rounds(const Rates &r, const tgo_task *d_tasks, int T, int R, int64_t *d_per_order,

@@ -79,6 +79,8 @@ def lib():
         L.tgo_version.restype = i32
         L.tgo_evaluate.argtypes = [M, vp, i32, vp, i64, vp, vp]
         L.tgo_exhaustive.argtypes = [M, vp, i32, vp, vp, vp]
+        L.tgo_exhaustive_noalloc.argtypes = [M, vp, i32, vp, vp, vp]
+        L.tgo_exhaustive_noalloc.restype = i32
         L.tgo_heuristic.argtypes = [M, vp, vp, i32, vp, vp, vp]
         L.tgo_rounds.argtypes = [M, vp, i32, i32, vp, vp, vp, vp]
         L.tgo_exhaustive_mem.argtypes = [M, vp, vp, i32, i64, vp, vp, vp]
@@ -212,6 +214,28 @@ def exhaustive(tasks, model: Model = DEFAULT, per_order: bool = False, summary=N
                                 po.data_ptr() if po is not None else None, summary.data_ptr(),
                                 _stream(stream)), "tgo_exhaustive")
     return summary, po
+
+
+def exhaustive_noalloc(tasks, summary, per_order=None, model: Model = DEFAULT, stream=None):
+    """tgo_exhaustive_noalloc: the same enumeration with the library's fixed
+    per-device scratch (the call allocates nothing; the caller passes the
+    summary, uint8[136], and optionally the per-ordering int64[n!] buffer).
+    Calls that overlap on one device race on that scratch."""
+    import math
+    import torch
+    _dev_tensor(tasks, torch.int64, 3, "tasks")
+    _dev_tensor(summary, torch.uint8, None, "summary")
+    if summary.numel() < SUMMARY_DTYPE.itemsize:
+        raise ValueError("summary must hold 136 bytes")
+    n = tasks.shape[0]
+    if per_order is not None:
+        _dev_tensor(per_order, torch.int64, None, "per_order")
+        if per_order.numel() < math.factorial(n):
+            raise ValueError("per_order must hold n! entries")
+    _check(lib().tgo_exhaustive_noalloc(ctypes.byref(model._c()), tasks.data_ptr(), n,
+                                        per_order.data_ptr() if per_order is not None else None,
+                                        summary.data_ptr(), _stream(stream)), "tgo_exhaustive_noalloc")
+    return summary, per_order
 
 
 def predict(tasks, order, model: Model = DEFAULT) -> int:
