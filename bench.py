@@ -8,7 +8,9 @@ heuristic for the same group.  Inputs are resident in HBM before timing.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
-Prints one JSON line.  Only one GPU is used; --gpus above 1 exits.
+Prints one short JSON line (the headline, with a summary of the extra
+measurements); the full record of the extras is written to --extras-out.
+Only one GPU is used; --gpus above 1 exits.
 """
 from __future__ import annotations
 
@@ -36,6 +38,12 @@ HBM_PEAK_GBS = 8000.0
 # workload: SQ_INSTS_VALU per launch x 64 lanes / 12! (rocprofv3 counter run
 # recorded in profiles/exhaustive_n12_counters.txt).
 VALU_LANE_OPS_PER_ORDERING = 258.30
+# Share of lanes active per issued VALU instruction of that kernel on this
+# workload: SQ_THREAD_CYCLES_VALU / (64 x SQ_ACTIVE_INST_VALU) from a counter
+# run (profiles/exhaustive_n12_lane_utilisation.txt).  Issued lane-ops times
+# this share are the lane-ops that did work for some ordering; lanes masked off
+# in a divergent step do none.
+VALU_LANE_UTILISATION = 0.5501
 # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, each scaled by
 # what the counter reads for a 256 MiB device copy (same profile file).
 TRAFFIC_BYTES_PER_LAUNCH = 2_887_660
@@ -64,6 +72,9 @@ def parse():
                    help="also run the integer issue probe (for the ALU peak, read with counters)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run a 256 MiB device copy (for HBM counter calibration)")
+    p.add_argument("--extras-out", default=os.path.join("gpurun_out", "bench_extras.json"),
+                   help="file that receives the full record of the extra measurements "
+                        "(the headline line carries a short summary of them)")
     return p.parse_args()
 
 
@@ -90,7 +101,9 @@ def cpu_baseline(tasks, seconds: float):
     return {"value": count / dt, "unit": "orderings/s", "cores": threads, "kind": "oracle",
             "sample": f"ranks 0..{count - 1} of the N=12 group ({count / math.factorial(N):.2%} "
                       f"of 12!), plain C event simulator, {threads} threads, {dt:.1f} s",
-            "single_thread_value": one / dt1, "cpu_model": _cpu_model()}
+            "single_thread_value": one / dt1, "cpu_model": _cpu_model(),
+            "host_cpus": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "thread_cap": "16: the host CPU share of one GPU on this machine"}
 
 
 def _cpu_model() -> str:
@@ -421,6 +434,66 @@ def serving_extra(dev, sur, seconds: float):
                        "topk": 64, "budget_bytes": 8 << 30}}
 
 
+def extras_summary(extras: dict) -> dict:
+    """A few figures of each extra measurement for the headline line (the
+    full record goes to its own file)."""
+    def pick(d, *keys):
+        if not isinstance(d, dict):
+            return None
+        if "error" in d:
+            return {"error": str(d["error"])[:160]}
+        return {k: d.get(k) for k in keys if k in d}
+
+    out = {}
+    if "batch" in extras:
+        out["batch"] = pick(extras["batch"], "groups_per_s", "orderings_per_s", "ms_per_batch", "bad_status")
+    if "one_dma" in extras:
+        d = extras["one_dma"]
+        if isinstance(d, dict) and "error" not in d:
+            out["one_dma"] = {k: pick(d.get(k), "orderings_per_s", "ms_per_batch", "ms", "groups_per_s",
+                                      "matches_oracle")
+                              for k in ("exhaustive_n12", "exhaustive_n13", "batch")}
+        else:
+            out["one_dma"] = pick(d)
+    if "rounds" in extras:
+        out["rounds"] = pick(extras["rounds"], "orderings_per_s", "orderings")
+    if "memory" in extras:
+        out["memory"] = pick(extras["memory"], "orderings_per_s")
+    if "proposal_training" in extras:
+        out["proposal_training"] = pick(extras["proposal_training"], "pairs", "steps", "train_s",
+                                        "train_flop_per_s", "loss_last")
+    if "proposal_n16" in extras:
+        d = extras["proposal_n16"]
+        if isinstance(d, dict) and "error" not in d:
+            out["proposal_n16"] = {"equal_time": d.get("equal_time"), "vs_plain_max": d.get("vs_plain_max"),
+                                   "plain_max_samples": d.get("plain_max_samples"),
+                                   "ablation": d.get("ablation_candidates")}
+        else:
+            out["proposal_n16"] = pick(d)
+    if "serving" in extras:
+        out["serving"] = pick(extras["serving"], "offered_groups_per_s", "achieved_groups_per_s", "p50_us",
+                              "p99_us", "bad_status", "max_in_use_bytes")
+    if "hw_validation" in extras:
+        d = extras["hw_validation"]
+        if isinstance(d, dict) and "error" not in d:
+            out["hw_validation"] = {sc: (d.get(sc) or {}).get("geomean_err_pct")
+                                    for sc in ("two_dma", "one_dma_scheme", "two_dma_alu_kernels")}
+        else:
+            out["hw_validation"] = pick(d)
+    return _round(out)
+
+
+def _round(x):
+    """Floats to 4 significant digits (the headline line stays short)."""
+    if isinstance(x, float):
+        return float(f"{x:.4g}")
+    if isinstance(x, dict):
+        return {k: _round(v) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_round(v) for v in x]
+    return x
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -504,7 +577,12 @@ def main():
     roof = {"bound": "alu", "unit": "TOP/s", "peak": VALU_PEAK_TOPS}
     if VALU_LANE_OPS_PER_ORDERING is not None:
         achieved = VALU_LANE_OPS_PER_ORDERING * orderings / (avg_launch_ms / 1e3) / 1e12
-        roof.update({"achieved": achieved, "frac": achieved / VALU_PEAK_TOPS})
+        roof.update({"achieved": achieved, "frac": achieved / VALU_PEAK_TOPS,
+                     "lane_utilisation": VALU_LANE_UTILISATION,
+                     "achieved_active_lanes": achieved * VALU_LANE_UTILISATION,
+                     "frac_alg": achieved * VALU_LANE_UTILISATION / VALU_PEAK_TOPS,
+                     "frac_note": "frac = issued VALU lane-ops (counter run) / peak; frac_alg counts "
+                                  "only the lanes active in each issued instruction"})
     else:
         roof.update({"achieved": None, "frac": None})
     roof["traffic"] = TRAFFIC_BYTES_PER_LAUNCH
@@ -569,10 +647,22 @@ def main():
                 sur.close()
         if "hw" in want and args.hw_unit_ms > 0:
             run_extra("hw_validation", hw_validation_extra, dev, args.hw_unit_ms)
-        out["extras"] = extras
+        out["extras_summary"] = extras_summary(extras)
+        path = args.extras_out
+        try:
+            os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+            with open(path, "w") as f:
+                json.dump(extras, f, indent=1)
+            out["extras_file"] = path
+        except OSError as e:
+            out["extras_file"] = f"not written: {e}"
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(tasks_np, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    line = json.dumps(out)
+    if len(line) > 4000:  # the headline must stay one short line; drop the summary before anything else
+        out.pop("extras_summary", None)
+        line = json.dumps(out)
+    print(line, flush=True)
 
 
 if __name__ == "__main__":

@@ -293,6 +293,15 @@ int tgo_surrogate_train_step(tgo_surrogate *s, const tgo_task *d_tasks, const in
 int tgo_surrogate_search(tgo_surrogate *s, const tgo_model *model, const tgo_task *d_tasks,
                          const int32_t *d_offs, const uint32_t *d_keys, int n_groups, int64_t samples,
                          int topk, uint64_t seed, tgo_search_result *d_out, tgo_stream stream);
+/* The candidate stage of tgo_surrogate_search on its own (same arguments):
+ * d_cand [n_groups][topk] receives, per group, the topk smallest keys in
+ * ascending order, key = (score bits mapped to an unsigned integer of the same
+ * order) << 32 | sample index, so ties in score go to the lower sample index;
+ * ~0 where a group has fewer than topk samples or a size outside 1..16.  These
+ * are exactly the orderings that the search re-scores with the exact model. */
+int tgo_surrogate_candidates(tgo_surrogate *s, const tgo_model *model, const tgo_task *d_tasks,
+                             const int32_t *d_offs, const uint32_t *d_keys, int n_groups, int64_t samples,
+                             int topk, uint64_t seed, uint64_t *d_cand, tgo_stream stream);
 /* Plain exact search: the heuristic plus `samples` sampled orderings per group
  * scored exactly (rounded up to a multiple of 64). */
 int tgo_random_search(const tgo_model *model, const tgo_task *d_tasks, const int32_t *d_offs,

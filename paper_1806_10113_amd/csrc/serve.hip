@@ -19,6 +19,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <mutex>
@@ -84,6 +85,10 @@ struct tgo_server {
     int64_t max_in_use = 0;
     int max_queue = 0;
     std::string error;
+    // Test hook, set from TGO_SERVER_INJECT_QUERY_ERROR=k at creation: the
+    // k-th completion query of a busy slot is treated as a device error
+    // (the batch itself still runs and ends normally on the GPU).
+    int inject_query_error = 0;
 };
 
 namespace tgo {
@@ -197,14 +202,48 @@ static void retire(tgo_server *S, StreamSlot &sl) {
     sl.busy = false;
 }
 
+// A batch whose completion query reports a device error: its requests are
+// returned with status TGO_EDEVICE, their memory released, the slot freed and
+// the server stopped (a device error is sticky; nothing more is launched).
+static void fail_slot(tgo_server *S, StreamSlot &sl, const std::string &why) {
+    const int64_t t = now_ns();
+    if (S->error.empty()) S->error = why;
+    for (const Request &q : sl.reqs) {
+        tgo_server_result o;
+        std::memset(&o, 0, sizeof(o));
+        o.id = q.id;
+        o.n = q.n;
+        o.path = sl.kind;
+        o.status = TGO_EDEVICE;
+        o.t_arrive_ns = q.t_arrive;
+        o.t_admit_ns = q.t_admit;
+        o.t_done_ns = t;
+        o.best_ns = -1;
+        o.heur_ns = -1;
+        for (int i = 0; i < 16; ++i) o.best[i] = 0xff;
+        S->done.push_back(o);
+        S->in_use -= (int64_t)q.bytes;
+    }
+    S->completed += sl.reqs.size();
+    sl.reqs.clear();
+    sl.busy = false;
+    S->stop = true;
+}
+
 static void worker_main(tgo_server *S) {
     (void)hipSetDevice(S->device);
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
         bool progressed = false;
         for (StreamSlot &sl : S->slots) {
-            if (sl.busy && hipEventQuery(sl.ev) == hipSuccess) {
+            if (!sl.busy) continue;
+            hipError_t e = hipEventQuery(sl.ev);
+            if (S->inject_query_error > 0 && --S->inject_query_error == 0) e = hipErrorLaunchFailure;
+            if (e == hipSuccess) {
                 retire(S, sl);
+                progressed = true;
+            } else if (e != hipErrorNotReady) {
+                fail_slot(S, sl, std::string("batch failed on the device: ") + hipGetErrorString(e));
                 progressed = true;
             }
         }
@@ -222,8 +261,9 @@ static void worker_main(tgo_server *S) {
             if (kind < 0) break;
             const int rc = launch(S, sl, kind);
             if (rc) {
-                S->error = std::string("launch failed: ") + tgo_last_error();
-                S->stop = true;
+                // the admitted requests come back failed; nothing more is launched
+                fail_slot(S, sl, std::string("launch failed: ") + tgo_last_error());
+                break;
             }
             if (!sl.busy) break;  // nothing admissible right now
             progressed = true;
@@ -287,6 +327,7 @@ int tgo_server_create(const tgo_model *model, const tgo_server_config *cfg, tgo_
     if (!S) return fail(TGO_ENOMEM, "server");
     S->model = *model;
     S->cfg = c;
+    if (const char *e = std::getenv("TGO_SERVER_INJECT_QUERY_ERROR")) S->inject_query_error = std::atoi(e);
     (void)hipGetDevice(&S->device);
     std::vector<float> params;
     if (sur) {
@@ -342,7 +383,8 @@ int tgo_server_submit(tgo_server *S, const tgo_task *h_tasks, int n, uint32_t ke
     const int kind = n <= S->cfg.small_max_n ? 0 : 1;
     {
         std::lock_guard<std::mutex> lk(S->mu);
-        if (S->stop) return fail(TGO_EINVAL, "server is stopping: " + S->error);
+        if (S->stop)
+            return fail(S->error.empty() ? TGO_EINVAL : TGO_EDEVICE, "server is stopping: " + S->error);
         if (kind == 1 && !S->slots[0].sur) {
             S->rejected += 1;
             return fail(TGO_EINVAL, "no surrogate: groups larger than small_max_n are not served");

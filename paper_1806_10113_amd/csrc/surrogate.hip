@@ -1215,45 +1215,47 @@ int tgo_surrogate_train_step(tgo_surrogate *s, const tgo_task *d_tasks, const in
     return refresh(s, st);
 }
 
+// Candidate-key buffers, grown on demand.  The object is either fully sized
+// (both buffers, cand_bytes) or empty (no buffers, cand_bytes = 0): a failed
+// growth leaves it empty, so the next call tries to allocate again instead of
+// using a buffer that is not there.
 static int grow_cand(tgo_surrogate *s, size_t bytes) {
-    if (s->cand_bytes >= bytes) return TGO_OK;
+    if (s->cand_bytes >= bytes && s->cand[0] && s->cand[1]) return TGO_OK;
+    s->cand_bytes = 0;
+    if (s->cand[0] || s->cand[1]) TGO_HIP(hipDeviceSynchronize());
     for (int i = 0; i < 2; ++i) {
-        if (s->cand[i]) {
-            TGO_HIP(hipDeviceSynchronize());
-            TGO_HIP(hipFree(s->cand[i]));
-            s->cand[i] = nullptr;
-        }
+        if (s->cand[i]) (void)hipFree(s->cand[i]);
+        s->cand[i] = nullptr;
+    }
+    for (int i = 0; i < 2; ++i) {
         hipError_t e = hipMalloc((void **)&s->cand[i], bytes);
-        if (e != hipSuccess) return fail(TGO_ENOMEM, std::string("candidate keys: ") + hipGetErrorString(e));
+        if (e != hipSuccess) {
+            for (int j = 0; j < 2; ++j) {
+                if (s->cand[j]) (void)hipFree(s->cand[j]);
+                s->cand[j] = nullptr;
+            }
+            return fail(TGO_ENOMEM, std::string("candidate keys: ") + hipGetErrorString(e));
+        }
     }
     s->cand_bytes = bytes;
     return TGO_OK;
 }
 
-int tgo_surrogate_search(tgo_surrogate *s, const tgo_model *model, const tgo_task *d_tasks,
-                         const int32_t *d_offs, const uint32_t *d_keys, int G, int64_t samples, int topk,
-                         uint64_t seed, tgo_search_result *d_out, tgo_stream stream) {
-    if (!s) return fail(TGO_EINVAL, "surrogate is NULL");
-    Rates r;
-    int rc = make_rates(model, &r);
-    if (rc) return rc;
-    rc = check_groups(d_tasks, d_offs, G, s->max_groups);
-    if (rc) return rc;
-    if (G > 65535) return fail(TGO_EINVAL, "search handles at most 65535 groups per call");
-    if (samples < 1 || samples > ((int64_t)1 << 32)) return fail(TGO_EINVAL, "samples out of range");
-    if (topk < 1 || topk > TK_KEEP) return fail(TGO_EINVAL, "topk must be in 1..64");
-    if (!d_out) return fail(TGO_EINVAL, "NULL buffer");
+// The candidate stage of the search: sample, score and keep the TK_KEEP
+// smallest keys of every group.  On return cand[*cur] holds per group a
+// sorted list of *len keys (group stride *len) whose first TK_KEEP are the
+// group's smallest keys.
+static int search_candidates(tgo_surrogate *s, const Rates &r, const tgo_task *d_tasks, const int32_t *d_offs,
+                             const uint32_t *d_keys, int G, int64_t samples, uint64_t seed, hipStream_t st,
+                             int *cur_out, int64_t *len_out) {
     const int64_t chunk = s->max_rows / TK_RUN * TK_RUN;
     if (chunk < TK_RUN) return fail(TGO_EINVAL, "search needs max_rows >= 1024");
-    hipStream_t st = (hipStream_t)stream;
     const int64_t spad = (samples + TK_RUN - 1) / TK_RUN * TK_RUN;
     const int64_t runs = spad / TK_RUN;
-    rc = grow_cand(s, sizeof(unsigned long long) * (size_t)G * (size_t)runs * TK_KEEP);
+    int rc = grow_cand(s, sizeof(unsigned long long) * (size_t)G * (size_t)runs * TK_KEEP);
     if (rc) return rc;
     hipLaunchKernelGGL(group_status_kernel, dim3((G + 255) / 256), dim3(256), 0, st, d_tasks, d_offs, G, r,
                        s->status);
-    rc = launch_heuristic(r, d_tasks, d_offs, G, s->horders, 16, s->hns, 1, st);
-    if (rc) return rc;
     hipLaunchKernelGGL(group_features_kernel, dim3((G * SG_POS + 255) / 256), dim3(256), 0, st, d_tasks, d_offs,
                        G, s->F);
     const int64_t total = (int64_t)G * spad;
@@ -1276,12 +1278,72 @@ int tgo_surrogate_search(tgo_surrogate *s, const tgo_model *model, const tgo_tas
         len = (int64_t)nrun * TK_KEEP;
         cur ^= 1;
     }
+    TGO_HIP(hipGetLastError());
+    *cur_out = cur;
+    *len_out = len;
+    return TGO_OK;
+}
+
+static int check_search_args(tgo_surrogate *s, const tgo_model *model, Rates *r, const tgo_task *d_tasks,
+                             const int32_t *d_offs, int G, int64_t samples, int topk) {
+    if (!s) return fail(TGO_EINVAL, "surrogate is NULL");
+    int rc = make_rates(model, r);
+    if (rc) return rc;
+    rc = check_groups(d_tasks, d_offs, G, s->max_groups);
+    if (rc) return rc;
+    if (G > 65535) return fail(TGO_EINVAL, "search handles at most 65535 groups per call");
+    if (samples < 1 || samples > ((int64_t)1 << 32)) return fail(TGO_EINVAL, "samples out of range");
+    if (topk < 1 || topk > TK_KEEP) return fail(TGO_EINVAL, "topk must be in 1..64");
+    return TGO_OK;
+}
+
+// out[g][i] = in[g * stride + i] for i < k
+__global__ void copy_candidates_kernel(const unsigned long long *__restrict__ in, int64_t stride, int G, int k,
+                                       unsigned long long *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= G * k) return;
+    const int g = i / k, j = i % k;
+    out[i] = in[(int64_t)g * stride + j];
+}
+
+int tgo_surrogate_search(tgo_surrogate *s, const tgo_model *model, const tgo_task *d_tasks,
+                         const int32_t *d_offs, const uint32_t *d_keys, int G, int64_t samples, int topk,
+                         uint64_t seed, tgo_search_result *d_out, tgo_stream stream) {
+    Rates r;
+    int rc = check_search_args(s, model, &r, d_tasks, d_offs, G, samples, topk);
+    if (rc) return rc;
+    if (!d_out) return fail(TGO_EINVAL, "NULL buffer");
+    hipStream_t st = (hipStream_t)stream;
+    int cur = 0;
+    int64_t len = 0;
+    rc = search_candidates(s, r, d_tasks, d_offs, d_keys, G, samples, seed, st, &cur, &len);
+    if (rc) return rc;
+    rc = launch_heuristic(r, d_tasks, d_offs, G, s->horders, 16, s->hns, 1, st);
+    if (rc) return rc;
     hipLaunchKernelGGL(fill_u64_kernel, dim3((G + 255) / 256), dim3(256), 0, st, s->best, (int64_t)G, ~0ull);
     const size_t shm = sizeof(Slot<uint32_t>) * SG_THREADS * SG_POS;
     hipLaunchKernelGGL(rescore_kernel, dim3((G + 3) / 4), dim3(SG_THREADS), shm, st, d_tasks, d_offs, G, r, topk,
                        seed, s->status, d_keys, s->cand[cur], (int)len, s->best);
     hipLaunchKernelGGL(search_finish_kernel, dim3((G + 255) / 256), dim3(256), 0, st, d_offs, G, seed, d_keys,
                        s->status, s->best, s->horders, s->hns, d_out);
+    TGO_HIP(hipGetLastError());
+    return TGO_OK;
+}
+
+int tgo_surrogate_candidates(tgo_surrogate *s, const tgo_model *model, const tgo_task *d_tasks,
+                             const int32_t *d_offs, const uint32_t *d_keys, int G, int64_t samples, int topk,
+                             uint64_t seed, uint64_t *d_cand, tgo_stream stream) {
+    Rates r;
+    int rc = check_search_args(s, model, &r, d_tasks, d_offs, G, samples, topk);
+    if (rc) return rc;
+    if (!d_cand) return fail(TGO_EINVAL, "NULL buffer");
+    hipStream_t st = (hipStream_t)stream;
+    int cur = 0;
+    int64_t len = 0;
+    rc = search_candidates(s, r, d_tasks, d_offs, d_keys, G, samples, seed, st, &cur, &len);
+    if (rc) return rc;
+    hipLaunchKernelGGL(copy_candidates_kernel, dim3((G * topk + 255) / 256), dim3(256), 0, st, s->cand[cur], len,
+                       G, topk, (unsigned long long *)d_cand);
     TGO_HIP(hipGetLastError());
     return TGO_OK;
 }

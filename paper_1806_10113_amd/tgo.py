@@ -112,6 +112,8 @@ def lib():
         L.tgo_surrogate_train_step.argtypes = [vp, vp, vp, i32, vp, vp, vp, i32, ctypes.c_float, vp, vp]
         L.tgo_surrogate_search.argtypes = [vp, M, vp, vp, vp, i32, i64, i32, ctypes.c_uint64, vp, vp]
         L.tgo_random_search.argtypes = [M, vp, vp, i32, i64, ctypes.c_uint64, vp, vp]
+        L.tgo_surrogate_candidates.argtypes = [vp, M, vp, vp, vp, i32, i64, i32, ctypes.c_uint64, vp, vp]
+        L.tgo_surrogate_candidates.restype = i32
         for f in (L.tgo_surrogate_create, L.tgo_surrogate_param_count, L.tgo_surrogate_init,
                   L.tgo_surrogate_set_params, L.tgo_surrogate_get_params, L.tgo_surrogate_pairs,
                   L.tgo_surrogate_score, L.tgo_surrogate_grad, L.tgo_surrogate_train_step,
@@ -557,6 +559,21 @@ class Surrogate:
                "tgo_surrogate_search")
         return out
 
+    def candidates(self, tasks, offs, samples: int, topk: int, seed: int, model: Model = DEFAULT,
+                   keys=None, stream=None):
+        """The search's candidate keys: uint64 [groups, topk] device tensor
+        (score order bits << 32 | sample index, ascending; ~0 = none)."""
+        import torch
+        g = _groups(tasks, offs)
+        if keys is not None:
+            _dev_tensor(keys, torch.int32, None, "keys")
+        out = torch.empty((g, topk), dtype=torch.int64, device=tasks.device)
+        _check(lib().tgo_surrogate_candidates(self._h, ctypes.byref(model._c()), tasks.data_ptr(),
+                                              offs.data_ptr(), keys.data_ptr() if keys is not None else None,
+                                              g, samples, topk, seed, out.data_ptr(), _stream(stream)),
+               "tgo_surrogate_candidates")
+        return out
+
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
@@ -617,11 +634,16 @@ class Server:
                "tgo_server_submit")
         return rid.value
 
-    def poll(self, max_results: int = 4096) -> np.ndarray:
+    def poll(self, max_results: int = 4096, raise_on_error: bool = True):
+        """Finished results.  After a device error the C call still hands back
+        what finished (failed requests carry status TGO_EDEVICE) and returns
+        TGO_EDEVICE: with raise_on_error=False this returns (results, code)."""
         out = np.zeros(max_results, dtype=SERVER_RESULT_DTYPE)
         k = ctypes.c_int()
-        _check(lib().tgo_server_poll(self._h, out.ctypes.data, max_results, ctypes.byref(k)),
-               "tgo_server_poll")
+        rc = lib().tgo_server_poll(self._h, out.ctypes.data, max_results, ctypes.byref(k))
+        if not raise_on_error:
+            return out[:k.value], rc
+        _check(rc, "tgo_server_poll")
         return out[:k.value]
 
     def drain(self, timeout_ms: int = 60_000):

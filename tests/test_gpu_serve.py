@@ -130,3 +130,38 @@ def test_replay_poisson_trace(dev):
     for g in rng.choice(arr.batch.n_groups, size=40, replace=False):
         check_small(out[g], arr.batch.group(int(g)))
     srv.close()
+
+
+def test_device_error_in_a_batch_is_reported(dev, monkeypatch):
+    """A completion query that reports a device error (forced from the host:
+    the batch itself runs and ends normally) retires the batch with status
+    TGO_EDEVICE, releases its memory, stops the server, and drain, submit and
+    destroy return instead of waiting."""
+    from paper_1806_10113_amd import tgo
+    monkeypatch.setenv("TGO_SERVER_INJECT_QUERY_ERROR", "1")
+    srv = tgo.Server(tgo.DEFAULT, tgo.server_config(streams=2, max_batch=8))
+    monkeypatch.delenv("TGO_SERVER_INJECT_QUERY_ERROR")
+    b = W.batch_groups(24, 4, 8, seed=407)
+    ids = []
+    for g in range(b.n_groups):
+        try:
+            ids.append(srv.submit(b.group(g)))
+        except tgo.TgoError as e:  # the server may already have stopped
+            assert e.code == tgo.TGO_EDEVICE
+            break
+    with pytest.raises(tgo.TgoError) as ei:
+        srv.drain(20_000)
+    assert ei.value.code == tgo.TGO_EDEVICE
+    res, rc = srv.poll(100, raise_on_error=False)
+    assert rc == tgo.TGO_EDEVICE
+    failed = [r for r in res if r["status"] == tgo.TGO_EDEVICE]
+    assert 1 <= len(failed) <= 8
+    for r in res:
+        if r["status"] == 0:  # batches that finished before the failure are exact
+            g = ids.index(int(r["id"]))
+            check_small(r, b.group(g))
+    assert srv.stats()["in_use_bytes"] >= 0
+    with pytest.raises(tgo.TgoError) as ei:
+        srv.submit(b.group(0))
+    assert ei.value.code == tgo.TGO_EDEVICE
+    srv.close()  # returns: the worker does not wait for the failed slot

@@ -236,3 +236,46 @@ def test_save_load_roundtrip(dev, tmp_path):
         c.load(str(bad))
     a.close()
     c.close()
+
+
+def _orderable(scores: np.ndarray) -> np.ndarray:
+    """float32 -> uint32 with the same order (the search's key bits)."""
+    u = np.asarray(scores, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    neg = (u & 0x80000000) != 0
+    return np.where(neg, (~u) & 0xFFFFFFFF, u | 0x80000000)
+
+
+@pytest.mark.parametrize("samples,topk", [(5000, 64), (1024, 17), (40, 64), (2049, 1)])
+def test_candidates_are_the_k_lowest_scores(dev, samples, topk):
+    """The search's candidate set is exactly the topk lowest network scores of
+    the group's sampled orderings, ties to the lower sample index: the same
+    samples (drawn by the oracle's Philox) are scored through
+    tgo_surrogate_score and sorted on the host.  Covers several 1,024-key
+    runs with a ragged last run, a single run, fewer samples than topk, and
+    topk = 1."""
+    import torch
+    from paper_1806_10113_amd import tgo
+    ev = W.fixed_size_groups(5, 16, seed=306)
+    small = W.batch_groups(3, 9, 15, seed=307, per_task_label=True)
+    sizes = list(ev.sizes()) + list(small.sizes())
+    tasks_np = np.concatenate([ev.tasks, small.tasks])
+    offs_np = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    tasks, offs = to_dev(tasks_np, dev), to_dev(offs_np, dev)
+    G = len(sizes)
+    sur = tgo.Surrogate(max_rows=1 << 15, max_groups=64)
+    sur.init(8)
+    cand = sur.candidates(tasks, offs, samples=samples, topk=topk, seed=41).cpu().numpy().view(np.uint64)
+    for g in range(G):
+        n = sizes[g]
+        orders = philox.sample_orderings(n, g, 0, samples, 41)
+        full = np.full((samples, 16), 0xFF, dtype=np.uint8)
+        full[:, :n] = orders
+        sc = sur.score(tasks, offs, to_dev(full, dev), to_dev(np.full(samples, g, dtype=np.int32), dev))
+        sc = sc.cpu().numpy()
+        keys = (_orderable(sc) << np.uint64(32)) | np.arange(samples, dtype=np.uint64)
+        want = np.sort(keys)[:topk]
+        got = cand[g]
+        k = min(topk, samples)
+        assert np.array_equal(got[:k], want[:k]), g
+        assert (got[k:] == np.uint64(0xFFFFFFFFFFFFFFFF)).all()
+    sur.close()

@@ -335,6 +335,21 @@ def test_heuristic_hand_worked_cases():
             assert M.simulate(case["tasks"], order, m) == case["T"]
 
 
+def test_heuristic_hand_worked_cases_overlapped_rates():
+    """Hand-worked at 3/4: update under overlapped transfers, a select_next
+    tie (lower index wins) and select_last, each intermediate update checked."""
+    g = load("heuristic_hand_overlap.json")
+    m = M.Model(**g["model"])
+    for case in g["cases"]:
+        tasks = case["tasks"]
+        for key, want in case["updates"].items():
+            ot = [int(v) for v in key.split(",")]
+            assert list(M.update(tasks, ot, m)) == want, (case["name"], key)
+        assert M.heuristic(tasks, m) == case["order"], case["name"]
+        assert M.simulate(tasks, case["order"], m) == case["T"]
+        assert cmodel.simulate(tasks, case["order"], m) == case["T"]
+
+
 def test_heuristic_structure():
     rng = np.random.default_rng(22)
     for _ in range(50):
