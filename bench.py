@@ -64,6 +64,7 @@ def parse():
                         "(default all)")
     p.add_argument("--train-pairs", type=float, default=2e7,
                    help="exact (ordering, time) pairs used to train the proposal network")
+    p.add_argument("--train-batch", type=int, default=8192, help="pairs per training step")
     p.add_argument("--eval-groups", type=int, default=1024)
     p.add_argument("--serve-seconds", type=float, default=10.0)
     p.add_argument("--hw-unit-ms", type=float, default=10.0,
@@ -316,27 +317,38 @@ def train_surrogate(dev, pairs_total: float, seed: int = 1003, batch: int = 8192
     orders, gid, T, status = tgo.pairs(tasks, offs, per, seed=seed)
     torch.cuda.synchronize()
     t_pairs = time.perf_counter() - t0
-    sur = tgo.Surrogate(max_rows=1 << 18, max_groups=max(4096, groups))
+    sur = tgo.Surrogate(max_rows=max(1 << 16, batch), max_groups=max(4096, groups))
     sur.init(seed)
     P = orders.shape[0]
     steps = P // batch
+    # one shuffle of the whole set up front; every step then takes a
+    # contiguous slice (no per-step gathers)
     perm = torch.randperm(P, generator=torch.Generator().manual_seed(seed)).to(dev)
+    orders, gid, T = orders[perm].contiguous(), gid[perm].contiguous(), T[perm].contiguous()
+    torch.cuda.synchronize()
     loss = torch.empty(1, dtype=torch.float32, device=dev)
-    first = None
+    sur.train_step(tasks, offs, orders[:batch], gid[:batch], T[:batch], lr, loss=loss)
+    first = float(loss.cpu()[0])
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    for i in range(steps):
-        idx = perm[i * batch:(i + 1) * batch]
+    e0.record(stream)
+    for i in range(1, steps):
         rate = lr if i < steps * 2 // 3 else lr / 4
-        sur.train_step(tasks, offs, orders[idx].contiguous(), gid[idx].contiguous(), T[idx].contiguous(),
-                       rate, loss=loss)
-        if i == 0:
-            first = float(loss.cpu()[0])
+        sl = slice(i * batch, (i + 1) * batch)
+        sur.train_step(tasks, offs, orders[sl], gid[sl], T[sl], rate, loss=loss)
+    e1.record(stream)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    # forward 2 x 143,616 FLOP per row; backward: activation gradients of
+    # layers 3 and 2 (2 x 2 x 65,536) and the weight gradients (2 x 143,360)
+    flop_row = 2 * 143616 + 2 * 2 * 65536 + 2 * 143360
     return sur, {"pairs": int(P), "train_groups": groups, "steps": steps, "batch": batch,
                  "pairs_s": t_pairs, "train_s": t_train, "loss_first": first,
-                 "loss_last": float(loss.cpu()[0]),
-                 "train_flop_per_s": 3 * 2 * 143616 * P / t_train}
+                 "loss_last": float(loss.cpu()[0]), "us_per_step": 1e3 * ms / max(1, steps - 1),
+                 "train_flop_per_s": flop_row * batch * (steps - 1) / (ms / 1e3),
+                 "flop_per_row": flop_row}
 
 
 def surrogate_extra(dev, sur, n_groups: int):
@@ -356,7 +368,7 @@ def surrogate_extra(dev, sur, n_groups: int):
 
     res = {}
     sur_runs = {}
-    for S in (1 << 10, 1 << 12, 1 << 14, 1 << 16, 1 << 18):
+    for S in (1 << 10, 1 << 12, 1 << 14, 1 << 16, 1 << 18, 1_000_000):
         r, t = timed(lambda: sur.search(tasks, offs, samples=S, topk=64, seed=31))
         sur_runs[S] = (tgo.read_search(r), t)
     plain_runs = {}
@@ -460,7 +472,7 @@ def extras_summary(extras: dict) -> dict:
     if "memory" in extras:
         out["memory"] = pick(extras["memory"], "orderings_per_s")
     if "proposal_training" in extras:
-        out["proposal_training"] = pick(extras["proposal_training"], "pairs", "steps", "train_s",
+        out["proposal_training"] = pick(extras["proposal_training"], "pairs", "steps", "us_per_step",
                                         "train_flop_per_s", "loss_last")
     if "proposal_n16" in extras:
         d = extras["proposal_n16"]
@@ -636,7 +648,7 @@ def main():
             if name in want:
                 run_extra(name, fn, dev)
         if want & {"proposal", "serving"}:
-            trained = run_extra("proposal_training", lambda: train_surrogate(dev, args.train_pairs))
+            trained = run_extra("proposal_training", lambda: train_surrogate(dev, args.train_pairs, batch=args.train_batch))
             if trained is not None:
                 sur, tr = trained
                 extras["proposal_training"] = tr

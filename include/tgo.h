@@ -59,6 +59,7 @@ extern "C" {
 #define TGO_ROUNDS_MAX_PER_ORDER 479001600ull /* per-ordering output limit of tgo_rounds */
 #define TGO_MAX_MEM_N 12        /* largest group of tgo_exhaustive_mem (12! ranks) */
 #define TGO_MAX_CAPACITY (1ll << 62) /* largest device-memory capacity, bytes     */
+#define TGO_MAX_CKE_N 12        /* largest group of tgo_exhaustive_cke (12! ranks) */
 
 enum {
     TGO_OK = 0,
@@ -276,15 +277,34 @@ int tgo_surrogate_pairs(const tgo_model *model, const tgo_task *d_tasks, const i
 int tgo_surrogate_score(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *d_offs, int n_groups,
                         const uint8_t *d_orders, const int32_t *d_gid, int64_t rows, float *d_scores,
                         tgo_stream stream);
-/* Loss and gradient (d_grad: TGO_SURROGATE_PARAMS floats, may be NULL) on a
- * batch of pairs (rows a multiple of 64, <= max_rows). */
+/* Loss (mean squared error of the score against T / LB - 1) and its gradient
+ * (d_grad: TGO_SURROGATE_PARAMS floats in the parameter layout, may be NULL)
+ * on a batch of pairs: d_orders [rows][16], d_gid [rows], d_T [rows] (rows a
+ * multiple of 64, <= max_rows).  Inputs, weights, hidden activations and the
+ * back-propagated activation gradients are bf16, sums float32.  The batch's
+ * intermediate values are kept for tgo_surrogate_get_batch. */
 int tgo_surrogate_grad(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *d_offs, int n_groups,
                        const uint8_t *d_orders, const int32_t *d_gid, const int64_t *d_T, int rows,
                        float *d_grad, float *d_loss, tgo_stream stream);
-/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on a batch of pairs. */
+/* One training step: the gradient of tgo_surrogate_grad on the batch, then
+ * tgo_surrogate_adam_step with it (three kernel launches; d_loss receives the
+ * batch loss before the update). */
 int tgo_surrogate_train_step(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *d_offs,
                              int n_groups, const uint8_t *d_orders, const int32_t *d_gid,
                              const int64_t *d_T, int rows, float lr, float *d_loss, tgo_stream stream);
+/* One Adam step (Kingma and Ba: beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected
+ * moments, step count t starting at 1) of the float32 masters with a given
+ * gradient d_grad (TGO_SURROGATE_PARAMS floats); refreshes the bf16 copies. */
+int tgo_surrogate_adam_step(tgo_surrogate *s, const float *d_grad, float lr, tgo_stream stream);
+/* Adam state to the host: first and second moments (float[TGO_SURROGATE_PARAMS]
+ * each; either may be NULL) and the number of steps taken.  Synchronizes. */
+int tgo_surrogate_get_moments(tgo_surrogate *s, float *h_m, float *h_v, int64_t *h_step, tgo_stream stream);
+/* Values the last tgo_surrogate_grad computed for its first `rows` rows, to the
+ * host, row-major: what = 0 features [rows][48] (bf16 bits), 1..3 hidden
+ * activations h1..h3 [rows][256] (bf16 bits), 4 scores [rows] (float), 5..7
+ * gradients of the loss with respect to the pre-activations of layers 3, 2, 1
+ * [rows][256] (bf16 bits; zero where the ReLU is off).  Synchronizes. */
+int tgo_surrogate_get_batch(tgo_surrogate *s, int what, int64_t rows, void *h_out, tgo_stream stream);
 /* Surrogate-guided search: score `samples` sampled orderings per group, re-score
  * the `topk` (<= 64) best-scored exactly, return the best of those and the
  * heuristic ordering (ties to the heuristic).  d_keys (NULL: the group index)
@@ -439,6 +459,33 @@ int tgo_exhaustive_mem(const tgo_model *model, const tgo_task *d_tasks, const in
  * footprint outside [0, capacity], TGO_ERANGE for durations out of range. */
 int tgo_evaluate_mem(const tgo_model *model, const tgo_task *d_tasks, const int64_t *d_mem, int n,
                      int64_t capacity, const uint8_t *d_orders, int64_t m, int64_t *d_out, tgo_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * Concurrent kernels.  The paper's model runs one kernel at a time (Section
+ * 4.1, last paragraph); its NoReorder experiments use one command queue per
+ * kernel (Section 6.2), Section 3.2 says kernels from different queues overlap
+ * only while the device's resources last, and the conclusion leaves
+ * concurrent kernels to future work.  Reading: the device has `capacity`
+ * units of computing resources (1..2^30, e.g. its compute units); the kernel
+ * of task x holds d_units[x] of them (1..capacity) from its start to its end;
+ * kernels are dispatched in launch order, each once its HtD has ended, the
+ * kernel before it has started and its units fit beside the running kernels;
+ * a kernel takes its solo time.  Transfers are unchanged (either DMA scheme,
+ * overlap rates of the model).  Every kernel holding the whole capacity gives
+ * the results of tgo_exhaustive / tgo_evaluate.  64-bit time throughout.
+ *
+ * tgo_exhaustive_cke -- every ordering of n <= TGO_MAX_CKE_N tasks, summary as
+ *   tgo_exhaustive (optional per-ordering T by rank), plus Algorithm 1 with
+ *   `update` under the same rule in heur / heur_ns.  Device-side errors in the
+ *   summary status: TGO_ERANGE for a duration outside [0, 2^40), TGO_EINVAL
+ *   for a unit count outside 1..capacity.
+ * tgo_evaluate_cke -- T of m given orderings (rows of n bytes, n <= 16), or a
+ *   negative TGO_E* per row (TGO_EINVAL: not a permutation or bad units).
+ */
+int tgo_exhaustive_cke(const tgo_model *model, const tgo_task *d_tasks, const int32_t *d_units, int n,
+                       int32_t capacity, int64_t *d_per_order, tgo_summary *d_summary, tgo_stream stream);
+int tgo_evaluate_cke(const tgo_model *model, const tgo_task *d_tasks, const int32_t *d_units, int n,
+                     int32_t capacity, const uint8_t *d_orders, int64_t m, int64_t *d_out, tgo_stream stream);
 
 /* ---------------------------------------------------------------------------
  * Real execution on the device, to validate the model (Sections 4.2, 4.3):

@@ -68,6 +68,14 @@ def lib():
         L.oracle_mem_times.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]
+        L.oracle_cke_simulate.restype = ctypes.c_int64
+        L.oracle_cke_simulate.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int]
+        L.oracle_cke_times.restype = ctypes.c_int
+        L.oracle_cke_times.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -156,6 +164,32 @@ def mem_times(tasks, mem, capacity: int, model: Model = DEFAULT, lo: int = 0, hi
     hi = math.factorial(n) if hi is None else hi
     out = np.empty(hi - lo, dtype=np.int64)
     rc = lib().oracle_mem_times(t.ctypes.data, m.ctypes.data, n, int(capacity), model.q, model.p_htd,
+                                model.p_dth, model.dma_engines, lo, hi, threads or default_threads(),
+                                out.ctypes.data)
+    assert rc == 0
+    return out
+
+
+def cke_simulate(tasks, units, capacity: int, order, model: Model = DEFAULT) -> int:
+    """T of one ordering under the concurrent-kernel rule (C transcription of
+    oracle/cke.py)."""
+    t = _tasks(tasks)
+    u = np.ascontiguousarray(np.asarray(units, dtype=np.int32))
+    o = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    return int(lib().oracle_cke_simulate(t.ctypes.data, u.ctypes.data, len(t), int(capacity), o.ctypes.data,
+                                         model.q, model.p_htd, model.p_dth, model.dma_engines))
+
+
+def cke_times(tasks, units, capacity: int, model: Model = DEFAULT, lo: int = 0, hi: int | None = None,
+              threads: int | None = None) -> np.ndarray:
+    """T under the concurrent-kernel rule for the orderings of ranks [lo, hi)."""
+    import math
+    t = _tasks(tasks)
+    u = np.ascontiguousarray(np.asarray(units, dtype=np.int32))
+    n = len(t)
+    hi = math.factorial(n) if hi is None else hi
+    out = np.empty(hi - lo, dtype=np.int64)
+    rc = lib().oracle_cke_times(t.ctypes.data, u.ctypes.data, n, int(capacity), model.q, model.p_htd,
                                 model.p_dth, model.dma_engines, lo, hi, threads or default_threads(),
                                 out.ctypes.data)
     assert rc == 0

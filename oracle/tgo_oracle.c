@@ -503,3 +503,149 @@ int oracle_mem_times(const int64_t *tasks, const int64_t *mem, int n, int64_t ca
     free(th);
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Concurrent kernels (oracle/cke.py): kernel x holds units[x] of `cap` from
+ * its start to its end; kernels are dispatched in launch order when their HtD
+ * has ended and their units fit beside the running kernels; running kernels
+ * take their solo time.  Transfers as in oracle_simulate.  Returns T. */
+int64_t oracle_cke_simulate(const int64_t *tasks, const int *units, int n, int cap, const int *order, int q,
+                            int p_htd, int p_dth, int dma) {
+    int neng = dma == 2 ? 2 : 1; /* transfer engines: HtD, DtH (two) or one */
+    int qkind[2][2 * OMAXN], qtask[2][2 * OMAXN], qlen[2] = {0, 0}, qhead[2] = {0, 0};
+    int run_kind[2] = {-1, -1}, run_task[2] = {-1, -1};
+    int64_t left[2] = {0, 0}, rate[2], est[2];
+    int64_t kleft[OMAXN];
+    unsigned char krun[OMAXN], hdone[OMAXN], kdone[OMAXN];
+    memset(krun, 0, sizeof(krun));
+    memset(hdone, 0, sizeof(hdone));
+    memset(kdone, 0, sizeof(kdone));
+    for (int j = 0; j < n; ++j) {
+        if (dma == 2) {
+            qkind[0][qlen[0]] = K_HTD; qtask[0][qlen[0]++] = order[j];
+            qkind[1][qlen[1]] = K_DTH; qtask[1][qlen[1]++] = order[j];
+        } else {
+            qkind[0][qlen[0]] = K_HTD; qtask[0][qlen[0]++] = order[j];
+        }
+    }
+    if (dma != 2)
+        for (int j = 0; j < n; ++j) { qkind[0][qlen[0]] = K_DTH; qtask[0][qlen[0]++] = order[j]; }
+    int khead = 0, held = 0;
+    int64_t t = 0, total = 0;
+    for (;;) {
+        int changed = 1;
+        while (changed) {
+            changed = 0;
+            for (int e = 0; e < neng; ++e) {
+                if (run_kind[e] >= 0 && left[e] == 0) {
+                    if (run_kind[e] == K_HTD) hdone[run_task[e]] = 1;
+                    if (t > total) total = t;
+                    run_kind[e] = -1;
+                    changed = 1;
+                }
+            }
+            for (int x = 0; x < n; ++x) {
+                if (krun[x] && kleft[x] == 0) {
+                    krun[x] = 0;
+                    kdone[x] = 1;
+                    held -= units[x];
+                    if (t > total) total = t;
+                    changed = 1;
+                }
+            }
+            for (int e = 0; e < neng; ++e) {
+                if (run_kind[e] >= 0 || qhead[e] >= qlen[e]) continue;
+                int k = qkind[e][qhead[e]], x = qtask[e][qhead[e]];
+                if (k == K_DTH && !kdone[x]) continue;
+                qhead[e]++;
+                run_kind[e] = k;
+                run_task[e] = x;
+                left[e] = tasks[x * 3 + k] * q;
+                changed = 1;
+            }
+            while (khead < n && hdone[order[khead]] && held + units[order[khead]] <= cap) {
+                int x = order[khead++];
+                krun[x] = 1;
+                kleft[x] = tasks[x * 3 + K_KER];
+                held += units[x];
+                changed = 1;
+            }
+        }
+        int busy = 0, hbusy = 0, dbusy = 0;
+        for (int e = 0; e < neng; ++e) {
+            if (run_kind[e] < 0) continue;
+            busy = 1;
+            if (run_kind[e] == K_HTD) hbusy = 1;
+            if (run_kind[e] == K_DTH) dbusy = 1;
+        }
+        int64_t delta = INT64_MAX;
+        for (int x = 0; x < n; ++x)
+            if (krun[x]) {
+                busy = 1;
+                if (kleft[x] < delta) delta = kleft[x];
+            }
+        if (!busy) break;
+        for (int e = 0; e < neng; ++e) {
+            if (run_kind[e] < 0) continue;
+            rate[e] = hbusy && dbusy ? (run_kind[e] == K_HTD ? p_htd : p_dth) : q;
+            est[e] = ceil_div(left[e], rate[e]);
+            if (est[e] < delta) delta = est[e];
+        }
+        t += delta;
+        for (int e = 0; e < neng; ++e) {
+            if (run_kind[e] < 0) continue;
+            left[e] = est[e] == delta ? 0 : left[e] - rate[e] * delta;
+        }
+        for (int x = 0; x < n; ++x)
+            if (krun[x]) kleft[x] -= delta;
+    }
+    if (khead < n) return -1;
+    for (int e = 0; e < neng; ++e)
+        if (qhead[e] < qlen[e]) return -1;
+    return total;
+}
+
+typedef struct {
+    const int64_t *tasks;
+    const int *units;
+    int n, cap, q, p_htd, p_dth, dma;
+    uint64_t lo, hi, base;
+    int64_t *out;
+} cjob_t;
+
+static void *cke_worker(void *arg) {
+    cjob_t *j = (cjob_t *)arg;
+    int perm[OMAXN];
+    if (j->lo >= j->hi) return NULL;
+    decode_rank(j->n, j->lo, perm);
+    for (uint64_t rk = j->lo; rk < j->hi; ++rk) {
+        j->out[rk - j->base] = oracle_cke_simulate(j->tasks, j->units, j->n, j->cap, perm, j->q, j->p_htd,
+                                                   j->p_dth, j->dma);
+        next_perm(j->n, perm);
+    }
+    return NULL;
+}
+
+/* T under the concurrent-kernel rule for the orderings of ranks [lo, hi),
+ * out[rank - lo], on nthreads threads. */
+int oracle_cke_times(const int64_t *tasks, const int *units, int n, int cap, int q, int p_htd, int p_dth,
+                     int dma, uint64_t lo, uint64_t hi, int nthreads, int64_t *out) {
+    if (n < 1 || n > OMAXN || nthreads < 1 || hi < lo) return -1;
+    cjob_t *jobs = (cjob_t *)calloc((size_t)nthreads, sizeof(cjob_t));
+    pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    uint64_t count = hi - lo, per = (count + (uint64_t)nthreads - 1) / (uint64_t)nthreads;
+    for (int i = 0; i < nthreads; ++i) {
+        cjob_t *j = &jobs[i];
+        j->tasks = tasks; j->units = units; j->n = n; j->cap = cap;
+        j->q = q; j->p_htd = p_htd; j->p_dth = p_dth; j->dma = dma;
+        j->lo = lo + ((uint64_t)i * per < count ? (uint64_t)i * per : count);
+        j->hi = j->lo + per < hi ? j->lo + per : hi;
+        j->base = lo;
+        j->out = out;
+        pthread_create(&th[i], NULL, cke_worker, j);
+    }
+    for (int i = 0; i < nthreads; ++i) pthread_join(th[i], NULL);
+    free(jobs);
+    free(th);
+    return 0;
+}

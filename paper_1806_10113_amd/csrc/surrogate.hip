@@ -29,6 +29,7 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
 constexpr int SG_THREADS = 256;
+constexpr int GK = 32;  // K per MFMA instruction (16 x 16 x 32 bf16)
 
 // ------------------------------------------------------------- exact lanes
 // Exact evaluation of (group, ordering) items, one wave per group tile: the
@@ -255,243 +256,6 @@ __device__ __forceinline__ void row_input(const float *__restrict__ F, const int
     *okp = ok;
 }
 
-// Rows of the first-layer input (bf16 [rows][64]), see row_input; padding
-// rows are flagged in `valid`.
-__global__ void features_kernel(const float *__restrict__ F, const int32_t *__restrict__ offs,
-                                const uint32_t *__restrict__ gkeys,
-                                const uint8_t *__restrict__ orders, const int32_t *__restrict__ gid,
-                                int64_t row0, int64_t rows, int64_t spad, int64_t S, uint64_t seed,
-                                uint16_t *X, uint16_t *Xt, int64_t xt_rows, uint8_t *valid) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rows) return;
-    uint32_t w[SG_K0 / 2];
-    bool ok;
-    row_input(F, offs, gkeys, orders, gid, i, row0, spad, S, seed, w, &ok);
-    uint4 *dst = reinterpret_cast<uint4 *>(X + i * SG_K0);
-#pragma unroll
-    for (int c = 0; c < SG_K0 / 8; ++c) {
-        uint4 q;
-        q.x = w[4 * c];
-        q.y = w[4 * c + 1];
-        q.z = w[4 * c + 2];
-        q.w = w[4 * c + 3];
-        dst[c] = q;
-    }
-    if (Xt) {
-#pragma unroll
-        for (int c = 0; c < SG_K0 / 2; ++c) {
-            Xt[(int64_t)(2 * c) * xt_rows + i] = (uint16_t)w[c];
-            Xt[(int64_t)(2 * c + 1) * xt_rows + i] = (uint16_t)(w[c] >> 16);
-        }
-    }
-    if (valid) valid[i] = ok ? 1 : 0;
-}
-
-// ------------------------------------------------------------------- GEMM
-// C[M][N] = sum_k A[M][K] * B[N][K] (both K-contiguous, bf16), float32
-// accumulation on MFMA.  Block 256 threads, tile 64 x 64, K step 32; wave w
-// computes rows 16w..16w+15 against the 64 columns (four 16 x 16 tiles).
-// M, N multiples of 64, K a multiple of 32.
-//
-// Epilogue: v = acc (+ bias[n]); relu; multiply by (mask[m][n] > 0); then
-// store as bf16 [M][N] (Y), bf16 [N][M] (Yt) and/or float [M][N] (Cf).
-enum : int { EPI_BIAS = 1, EPI_RELU = 2, EPI_MASK = 4 };
-
-struct GemmOut {
-    uint16_t *Y;
-    uint16_t *Yt;
-    float *Cf;
-    const float *bias;
-    const uint16_t *mask;
-};
-
-constexpr int GT = 64, GK = 32, GPAD = 8;
-
-// With SPLITK the K range is cut into gridDim.z pieces and each block adds its
-// partial product into out.Cf (float atomics; Cf must start at zero).
-template <int EPI, bool SPLITK = false>
-__global__ __launch_bounds__(256) void gemm_nt_kernel(const uint16_t *__restrict__ A,
-                                                      const uint16_t *__restrict__ B, int M, int N, int K,
-                                                      GemmOut out) {
-    __shared__ __align__(16) uint16_t As[GT][GK + GPAD];
-    __shared__ __align__(16) uint16_t Bs[GT][GK + GPAD];
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-    const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
-    f32x4 acc[4];
-    for (int c = 0; c < 4; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int lr = tid >> 2, lk = (tid & 3) * 8;
-    int kbeg = 0, kend = K;
-    if constexpr (SPLITK) {
-        const int per = K / gridDim.z;  // a multiple of GK (checked by the launcher)
-        kbeg = blockIdx.z * per;
-        kend = kbeg + per;
-    }
-    for (int k0 = kbeg; k0 < kend; k0 += GK) {
-        const uint4 a = *reinterpret_cast<const uint4 *>(A + (int64_t)(m0 + lr) * K + k0 + lk);
-        const uint4 b = *reinterpret_cast<const uint4 *>(B + (int64_t)(n0 + lr) * K + k0 + lk);
-        __syncthreads();
-        *reinterpret_cast<uint4 *>(&As[lr][lk]) = a;
-        *reinterpret_cast<uint4 *>(&Bs[lr][lk]) = b;
-        __syncthreads();
-        const bf16x8 fa = *reinterpret_cast<const bf16x8 *>(&As[w * 16 + (l & 15)][(l >> 4) * 8]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const bf16x8 fb = *reinterpret_cast<const bf16x8 *>(&Bs[c * 16 + (l & 15)][(l >> 4) * 8]);
-            acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa, fb, acc[c], 0, 0, 0);
-        }
-    }
-    // lane l holds C[16w + 4(l/16) + i][16c + l%16], i = 0..3
-    if constexpr (SPLITK) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int col = n0 + c * 16 + (l & 15);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                atomicAdd(&out.Cf[(int64_t)(m0 + w * 16 + (l >> 4) * 4 + i) * N + col], acc[c][i]);
-        }
-        return;
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const int col = n0 + c * 16 + (l & 15);
-        const float bb = (EPI & EPI_BIAS) ? out.bias[col] : 0.f;
-        uint16_t yv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = m0 + w * 16 + (l >> 4) * 4 + i;
-            float vv = acc[c][i] + bb;
-            if (EPI & EPI_RELU) vv = vv > 0.f ? vv : 0.f;
-            if (EPI & EPI_MASK) vv = bf2f(out.mask[(int64_t)row * N + col]) > 0.f ? vv : 0.f;
-            if (out.Cf) out.Cf[(int64_t)row * N + col] = vv;
-            yv[i] = f2bf(vv);
-            if (out.Y) out.Y[(int64_t)row * N + col] = yv[i];
-        }
-        if (out.Yt) {
-            const int row0 = m0 + w * 16 + (l >> 4) * 4;
-            uint2 q;
-            q.x = yv[0] | ((uint32_t)yv[1] << 16);
-            q.y = yv[2] | ((uint32_t)yv[3] << 16);
-            *reinterpret_cast<uint2 *>(out.Yt + (int64_t)col * M + row0) = q;
-        }
-    }
-}
-
-// Large-M variant for the forward passes: block tile 128 x 128, wave w owns
-// the 64 x 64 quadrant (w/2, w%2) as 4 x 4 MFMA tiles, so every K step issues
-// 16 MFMAs per wave between two barriers; the next K slice is fetched into
-// registers while the current one is multiplied.  M, N multiples of 128.
-constexpr int BT2 = 128;
-
-__device__ __forceinline__ void epilogue_store(const GemmOut &out, int EPI, int M, int N, int row0, int col,
-                                               const f32x4 &acc) {
-    const float bb = (EPI & EPI_BIAS) ? out.bias[col] : 0.f;
-    uint16_t yv[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int row = row0 + i;
-        float vv = acc[i] + bb;
-        if (EPI & EPI_RELU) vv = vv > 0.f ? vv : 0.f;
-        if (EPI & EPI_MASK) vv = bf2f(out.mask[(int64_t)row * N + col]) > 0.f ? vv : 0.f;
-        if (out.Cf) out.Cf[(int64_t)row * N + col] = vv;
-        yv[i] = f2bf(vv);
-        if (out.Y) out.Y[(int64_t)row * N + col] = yv[i];
-    }
-    if (out.Yt) {
-        uint2 q;
-        q.x = yv[0] | ((uint32_t)yv[1] << 16);
-        q.y = yv[2] | ((uint32_t)yv[3] << 16);
-        *reinterpret_cast<uint2 *>(out.Yt + (int64_t)col * M + row0) = q;
-    }
-}
-
-template <int EPI>
-__global__ __launch_bounds__(256) void gemm_nt_big_kernel(const uint16_t *__restrict__ A,
-                                                          const uint16_t *__restrict__ B, int M, int N, int K,
-                                                          GemmOut out) {
-    __shared__ __align__(16) uint16_t As[BT2][GK + GPAD];
-    __shared__ __align__(16) uint16_t Bs[BT2][GK + GPAD];
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-    const int m0 = blockIdx.y * BT2, n0 = blockIdx.x * BT2;
-    const int wr = (w >> 1) * 64, wc = (w & 1) * 64;
-    f32x4 acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // each thread moves rows (tid / 4) and (tid / 4 + 64), 8 bf16 at column (tid % 4) * 8
-    const int lr = tid >> 2, lk = (tid & 3) * 8;
-    const uint16_t *a0 = A + (int64_t)(m0 + lr) * K + lk, *a1 = a0 + (int64_t)64 * K;
-    const uint16_t *b0 = B + (int64_t)(n0 + lr) * K + lk, *b1 = b0 + (int64_t)64 * K;
-    uint4 ra0 = *reinterpret_cast<const uint4 *>(a0), ra1 = *reinterpret_cast<const uint4 *>(a1);
-    uint4 rb0 = *reinterpret_cast<const uint4 *>(b0), rb1 = *reinterpret_cast<const uint4 *>(b1);
-    for (int k0 = 0; k0 < K; k0 += GK) {
-        __syncthreads();
-        *reinterpret_cast<uint4 *>(&As[lr][lk]) = ra0;
-        *reinterpret_cast<uint4 *>(&As[lr + 64][lk]) = ra1;
-        *reinterpret_cast<uint4 *>(&Bs[lr][lk]) = rb0;
-        *reinterpret_cast<uint4 *>(&Bs[lr + 64][lk]) = rb1;
-        __syncthreads();
-        if (k0 + GK < K) {
-            ra0 = *reinterpret_cast<const uint4 *>(a0 + k0 + GK);
-            ra1 = *reinterpret_cast<const uint4 *>(a1 + k0 + GK);
-            rb0 = *reinterpret_cast<const uint4 *>(b0 + k0 + GK);
-            rb1 = *reinterpret_cast<const uint4 *>(b1 + k0 + GK);
-        }
-        bf16x8 fa[4], fb[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            fa[t] = *reinterpret_cast<const bf16x8 *>(&As[wr + t * 16 + (l & 15)][(l >> 4) * 8]);
-            fb[t] = *reinterpret_cast<const bf16x8 *>(&Bs[wc + t * 16 + (l & 15)][(l >> 4) * 8]);
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-            epilogue_store(out, EPI, M, N, m0 + wr + a * 16 + (l >> 4) * 4, n0 + wc + b * 16 + (l & 15),
-                           acc[a][b]);
-}
-
-// float C[M][N] += A B^T with the K range split over blocks (weight gradients:
-// M, N <= 256 and K = batch rows)
-static void gemm_splitk(const uint16_t *A, const uint16_t *B, int M, int N, int K, float *C, hipStream_t st) {
-    int ks = 1;
-    while (ks < 64 && (M / GT) * (N / GT) * ks < 512 && K % (2 * ks * GK) == 0) ks *= 2;
-    GemmOut o{};
-    o.Cf = C;
-    hipLaunchKernelGGL((gemm_nt_kernel<0, true>), dim3(N / GT, M / GT, ks), dim3(256), 0, st, A, B, M, N, K, o);
-}
-
-template <int EPI>
-static void gemm(const uint16_t *A, const uint16_t *B, int M, int N, int K, const GemmOut &o,
-                 hipStream_t st) {
-    if (M % BT2 == 0 && N % BT2 == 0 && M >= 4096)
-        hipLaunchKernelGGL(gemm_nt_big_kernel<EPI>, dim3(N / BT2, M / BT2), dim3(256), 0, st, A, B, M, N, K, o);
-    else
-        hipLaunchKernelGGL(gemm_nt_kernel<EPI>, dim3(N / GT, M / GT), dim3(256), 0, st, A, B, M, N, K, o);
-}
-
-// ----------------------------------------------------------- head, loss
-
-// score[i] = h3[i] . w4 + b4 (one wave per row); invalid rows get +inf
-__global__ void head_kernel(const uint16_t *__restrict__ H3, const float *__restrict__ w4,
-                            const float *__restrict__ b4, int64_t rows, const uint8_t *__restrict__ valid,
-                            float *score) {
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int l = threadIdx.x & 63;
-    if (row >= rows) return;
-    const uint2 q = *reinterpret_cast<const uint2 *>(H3 + row * SG_H + l * 4);
-    float s = bf2f((uint16_t)q.x) * w4[l * 4] + bf2f((uint16_t)(q.x >> 16)) * w4[l * 4 + 1] +
-              bf2f((uint16_t)q.y) * w4[l * 4 + 2] + bf2f((uint16_t)(q.y >> 16)) * w4[l * 4 + 3];
-    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
-    if (l == 0) score[row] = (valid && !valid[row]) ? INFINITY : s + b4[0];
-}
-
 // float -> uint32 with the same order (top-k keys compare as integers)
 __device__ __forceinline__ uint32_t orderable(float f) {
     const uint32_t u = __float_as_uint(f);
@@ -651,126 +415,554 @@ __global__ __launch_bounds__(FM_THREADS) void mlp_fused_kernel(const float *__re
     }
 }
 
-// targets y = T / LB - 1 (LB: largest machine lower bound of the group)
-__global__ void target_kernel(const tgo_task *__restrict__ tasks, const int32_t *__restrict__ offs,
-                              const int32_t *__restrict__ gid, const int64_t *__restrict__ T, int rows,
-                              float *y) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rows) return;
-    const int g = gid[i];
-    const tgo_task *t = tasks + offs[g];
-    const int n = offs[g + 1] - offs[g];
-    int64_t sh = 0, sk = 0, sd = 0, mh = INT64_MAX, md = INT64_MAX, mkd = INT64_MAX, mhk = INT64_MAX;
-    for (int x = 0; x < n; ++x) {
-        const int64_t h = t[x].htd_ns, k = t[x].kern_ns, d = t[x].dth_ns;
-        sh += h; sk += k; sd += d;
-        mh = h < mh ? h : mh;
-        md = d < md ? d : md;
-        mkd = k + d < mkd ? k + d : mkd;
-        mhk = h + k < mhk ? h + k : mhk;
-    }
-    int64_t lb = sh + mkd;
-    lb = mh + sk + md > lb ? mh + sk + md : lb;
-    lb = mhk + sd > lb ? mhk + sd : lb;
-    lb = lb < 1 ? 1 : lb;
-    y[i] = (float)((double)T[i] / (double)lb - 1.0);
+// ---------------------------------------------------------------- training
+// One training step is three kernels:
+//   train_fwd_bwd_kernel  32 rows per block: features, the three hidden layers
+//                         and the head on MFMA with the activations in LDS,
+//                         the loss gradient, and back-propagation through
+//                         layers 3 and 2, all without leaving the block.  It
+//                         stores the bf16 activations and activation gradients
+//                         transposed ([feature][row]) for the weight gradients,
+//                         and per-block sums for the bias, head and loss terms.
+//   train_wgrad_kernel    weight gradients G^T A of the three layers as one
+//                         split-K launch (64 x 64 output tiles), plus the
+//                         per-chunk sums of the per-block vectors; partials
+//                         per K chunk, no atomics (the sum order is fixed).
+//   train_update_kernel   sums the K-chunk partials into the gradient and
+//                         (optionally) applies Adam and refreshes the bf16
+//                         weight copies.
+// Every wave keeps the B operands of its 32 output columns of a whole layer
+// in registers (64 VGPRs for K = 256), loaded one layer ahead, so the MFMA
+// loop reads only LDS.
+constexpr int TR_WAVES = 8;
+constexpr int TR_THREADS = 64 * TR_WAVES;   // wave w owns output columns 32w .. 32w+31
+constexpr int TR_RT = 2;                    // row tiles of 16
+constexpr int TR_ROWS = 16 * TR_RT;         // rows per block (one thread per (row, position): 32 x 16)
+constexpr int TR_LD = SG_H + 8;             // LDS pitch (bf16) of a 256-wide activation
+constexpr int TR_LD0 = SG_K0 + 8;           // LDS pitch of the 64-wide input
+// per-block vector: sums over the block's rows of the bias gradients of
+// layers 1..3, the head weight and bias gradients, and the loss
+constexpr int TR_V_B1 = 0, TR_V_B2 = 256, TR_V_B3 = 512, TR_V_W4 = 768, TR_V_B4 = 1024, TR_V_LOSS = 1025;
+constexpr int TR_VLEN = 1026, TR_VSTRIDE = 1028;
+constexpr int WG_TILES = 36;                // 16 (layer 3) + 16 (layer 2) + 4 (layer 1) tiles of 64 x 64
+constexpr int WG_VEC_BLOCKS = (TR_VLEN + 255) / 256;
+constexpr int WG_KS_MAX = 64;               // K chunks (partials) at most
+constexpr int WG_KC = 512;                  // rows per K chunk (more for larger batches)
+constexpr int WG_STEPS = 4;                 // K steps per wave loaded at once (4 waves x 4 x 32 = 512 rows)
+constexpr int WG_TILE = 64 * 64;
+static_assert(TR_ROWS * SG_POS == TR_THREADS, "one thread per (row, position)");
+
+// Block barrier that waits only for this wave's LDS accesses: __syncthreads()
+// also waits for every outstanding global load and store, which would drain
+// the next layer's weight loads and the activation stores at each layer.  The
+// kernel below never reads global memory that it writes, so only LDS needs
+// ordering here.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// dscore = 2 (score - y) / rows;  loss = mean (score - y)^2 (atomic sum)
-__global__ void loss_kernel(const float *__restrict__ score, const float *__restrict__ y, int rows,
-                            float *dscore, float *loss) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    float e = 0.f;
-    if (i < rows) {
-        const float d = score[i] - y[i];
-        dscore[i] = 2.f * d / (float)rows;
-        e = d * d / (float)rows;
-    }
-    for (int m = 32; m >= 1; m >>= 1) e += __shfl_xor(e, m);
-    if ((threadIdx.x & 63) == 0) atomicAdd(loss, e);
-}
-
-// dh3 = dscore w4 * (h3 > 0), bf16 [rows][256] and [256][rows] (one wave per row)
-__global__ void head_bwd_kernel(const uint16_t *__restrict__ H3, const float *__restrict__ w4,
-                                const float *__restrict__ dscore, int rows, uint16_t *dH, uint16_t *dHt) {
-    const int row = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    const int l = threadIdx.x & 63;
-    if (row >= rows) return;
-    const float ds = dscore[row];
-    for (int j = 0; j < 4; ++j) {
-        const int c = l * 4 + j;
-        const float h = bf2f(H3[(int64_t)row * SG_H + c]);
-        const uint16_t g = f2bf(h > 0.f ? ds * w4[c] : 0.f);
-        dH[(int64_t)row * SG_H + c] = g;
-        dHt[(int64_t)c * rows + row] = g;
-    }
-}
-
-// grad w4[c] = sum_i dscore_i h3[i][c] from the transposed activations (block
-// c < 256), grad b4 = sum_i dscore_i (block 256)
-__global__ void head_wgrad_kernel(const uint16_t *__restrict__ H3t, const float *__restrict__ dscore, int rows,
-                                  float *gw4, float *gb4) {
-    const int c = blockIdx.x;
-    float acc = 0.f;
-    for (int i = threadIdx.x; i < rows; i += blockDim.x)
-        acc += dscore[i] * (c < SG_H ? bf2f(H3t[(int64_t)c * rows + i]) : 1.f);
-    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
-    __shared__ float red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const float t = red[0] + red[1] + red[2] + red[3];
-        if (c < SG_H) gw4[c] = t;
-        else gb4[0] = t;
-    }
-}
-
-// bias gradient: gb[c] = sum_i Gt[c][i] (rows of the transposed gradient)
-__global__ void colsum_kernel(const uint16_t *__restrict__ Gt, int rows, float *gb) {
-    const int c = blockIdx.x;
-    float s = 0.f;
-    for (int i = threadIdx.x; i < rows; i += blockDim.x) s += bf2f(Gt[(int64_t)c * rows + i]);
-    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
-    __shared__ float red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) gb[c] = red[0] + red[1] + red[2] + red[3];
-}
-
-// first-layer weight gradient arrives as [256][64] (padded input); keep the 48 real columns
-__global__ void pack_w1_grad_kernel(const float *__restrict__ g64, float *g48) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= SG_H * SG_FEAT) return;
-    const int o = i / SG_FEAT, c = i % SG_FEAT;
-    g48[i] = g64[o * SG_K0 + c];
-}
-
-// Adam on the float32 masters, then refresh the bf16 working copies
-// (W [out][in] and Wt [in][out]; the first layer padded to 64 inputs).
-struct AdamArgs {
-    float lr, beta1, beta2, eps, c1, c2;  // c1 = 1 - beta1^t, c2 = 1 - beta2^t
+template <int K>
+struct WRegs {
+    bf16x8 v[K / GK][2];
 };
 
-__global__ void adam_kernel(float *p, const float *__restrict__ g, float *m, float *v, int count,
-                            AdamArgs a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    const float gi = g[i];
-    const float mi = a.beta1 * m[i] + (1.f - a.beta1) * gi;
-    const float vi = a.beta2 * v[i] + (1.f - a.beta2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    p[i] -= a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+// W: bf16 [256][K] output-major.  Wave w takes the B operands of output
+// columns 32w + 16b + (l % 16), b = 0, 1, for every K step.
+template <int K>
+__device__ __forceinline__ void wload(WRegs<K> &t, const uint16_t *__restrict__ W, int w, int l) {
+    const uint16_t *base = W + (int64_t)(32 * w + (l & 15)) * K + (l >> 4) * 8;
+#pragma unroll
+    for (int s = 0; s < K / GK; ++s)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) t.v[s][b] = *reinterpret_cast<const bf16x8 *>(base + (int64_t)16 * b * K + GK * s);
 }
 
-__global__ void refresh_bf16_kernel(const float *__restrict__ p, uint16_t *W1, uint16_t *W1t, uint16_t *W2,
-                                    uint16_t *W2t, uint16_t *W3, uint16_t *W3t) {
+// acc[a][b] = A[16a .. 16a+15][0..K) x W[cols of tile b][0..K)^T; lane l ends
+// with rows 16a + 4(l/16) + i, column 32w + 16b + l%16.
+template <int K, int LD>
+__device__ __forceinline__ void wmma(const uint16_t (*A)[LD], const WRegs<K> &t, int l, f32x4 (&acc)[TR_RT][2]) {
+#pragma unroll
+    for (int a = 0; a < TR_RT; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < K / GK; ++s) {
+        bf16x8 fa[TR_RT];
+#pragma unroll
+        for (int a = 0; a < TR_RT; ++a)
+            fa[a] = *reinterpret_cast<const bf16x8 *>(&A[16 * a + (l & 15)][GK * s + (l >> 4) * 8]);
+#pragma unroll
+        for (int a = 0; a < TR_RT; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], t.v[s][b], acc[a][b], 0, 0, 0);
+    }
+}
+
+// Transposed store of an LDS activation block: dst[c][r0 + r] = S[r][c] for
+// c < width, r < TR_ROWS (8 rows = 16 bytes per store).
+template <int LD>
+__device__ __forceinline__ void store_t(const uint16_t (*S)[LD], int width, uint16_t *dst, int64_t ld, int r0,
+                                        int tid) {
+    const int chunks = width * (TR_ROWS / 8);
+    for (int q = tid; q < chunks; q += TR_THREADS) {
+        const int c = q / (TR_ROWS / 8), r = (q % (TR_ROWS / 8)) * 8;
+        uint4 v;
+        v.x = S[r][c] | ((uint32_t)S[r + 1][c] << 16);
+        v.y = S[r + 2][c] | ((uint32_t)S[r + 3][c] << 16);
+        v.z = S[r + 4][c] | ((uint32_t)S[r + 5][c] << 16);
+        v.w = S[r + 6][c] | ((uint32_t)S[r + 7][c] << 16);
+        *reinterpret_cast<uint4 *>(dst + (int64_t)c * ld + r0 + r) = v;
+    }
+}
+
+// The four values a lane holds for (row tile a, column col) are rows
+// 16a + 4(l/16) + 0..3 of that column: one 8-byte store into the transposed
+// layout dst[col][row].
+__device__ __forceinline__ void store4_t(uint16_t *dst, int64_t ld, int col, int row0, const uint16_t (&v)[4]) {
+    uint2 q;
+    q.x = v[0] | ((uint32_t)v[1] << 16);
+    q.y = v[2] | ((uint32_t)v[3] << 16);
+    *reinterpret_cast<uint2 *>(dst + (int64_t)col * ld + row0) = q;
+}
+
+// Sum over the rows a lane holds (4 per row tile) and over the lanes that
+// share its column (l, l ^ 16, l ^ 32, l ^ 48); lanes l < 16 end with the
+// column total.
+__device__ __forceinline__ float col_total(float v) {
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+}
+
+// Forward and backward of the rows [32 blockIdx.x, +32).  Rows >= `rows`
+// carry zero features and zero loss gradient.  inv_rows = 1 / rows.
+__global__ __launch_bounds__(TR_THREADS) void train_fwd_bwd_kernel(
+    const tgo_task *__restrict__ tasks, const int32_t *__restrict__ offs, const uint8_t *__restrict__ orders,
+    const int32_t *__restrict__ gid, const int64_t *__restrict__ T, int rows, float inv_rows,
+    const uint16_t *__restrict__ W1, const uint16_t *__restrict__ W2, const uint16_t *__restrict__ W3,
+    const uint16_t *__restrict__ W2t, const uint16_t *__restrict__ W3t, const float *__restrict__ p, int64_t ld,
+    uint16_t *Xt, uint16_t *H1t, uint16_t *H2t, uint16_t *G3t, uint16_t *G2t, uint16_t *G1t, float *vec,
+    uint16_t *H3keep, float *score_keep) {
+    __shared__ __align__(16) uint16_t Xs[TR_ROWS][TR_LD0];
+    __shared__ __align__(16) uint16_t H1s[TR_ROWS][TR_LD];
+    __shared__ __align__(16) uint16_t H2s[TR_ROWS][TR_LD];
+    __shared__ __align__(16) uint16_t G3s[TR_ROWS][TR_LD];
+    __shared__ float part[TR_WAVES][TR_ROWS];
+    __shared__ float ys[TR_ROWS], dss[TR_ROWS];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int r0 = blockIdx.x * TR_ROWS;
+    float *vb = vec + (int64_t)blockIdx.x * TR_VSTRIDE;
+
+    WRegs<SG_K0> w1r;
+    wload(w1r, W1, w, l);
+    WRegs<SG_H> w2r;
+    wload(w2r, W2, w, l);
+
+    // features of (row, position); the target of each row
+    {
+        const int rr = tid >> 4, pos = tid & 15;
+        const int i = r0 + rr;
+        uint16_t f0 = 0, f1 = 0, f2 = 0;
+        if (i < rows) {
+            const int g = gid[i];
+            const int b = offs[g], n = offs[g + 1] - b;
+            const int x = orders[(int64_t)i * SG_POS + pos];
+            if (pos < n && x < n) {
+                const tgo_task t = tasks[b + x];
+                f0 = f2bf(feature_value(t.htd_ns));
+                f1 = f2bf(feature_value(t.kern_ns));
+                f2 = f2bf(feature_value(t.dth_ns));
+            }
+            if (pos == 0) {
+                // y = T / LB - 1, LB the largest machine lower bound of the group
+                int64_t sh = 0, sk = 0, sd = 0, mh = INT64_MAX, md = INT64_MAX, mkd = INT64_MAX, mhk = INT64_MAX;
+                for (int xx = 0; xx < n; ++xx) {
+                    const tgo_task t = tasks[b + xx];
+                    sh += t.htd_ns;
+                    sk += t.kern_ns;
+                    sd += t.dth_ns;
+                    mh = t.htd_ns < mh ? t.htd_ns : mh;
+                    md = t.dth_ns < md ? t.dth_ns : md;
+                    mkd = t.kern_ns + t.dth_ns < mkd ? t.kern_ns + t.dth_ns : mkd;
+                    mhk = t.htd_ns + t.kern_ns < mhk ? t.htd_ns + t.kern_ns : mhk;
+                }
+                int64_t lb = sh + mkd;
+                lb = mh + sk + md > lb ? mh + sk + md : lb;
+                lb = mhk + sd > lb ? mhk + sd : lb;
+                lb = lb < 1 ? 1 : lb;
+                ys[rr] = (float)((double)T[i] / (double)lb - 1.0);
+            }
+        } else if (pos == 0) {
+            ys[rr] = 0.f;
+        }
+        Xs[rr][3 * pos] = f0;
+        Xs[rr][3 * pos + 1] = f1;
+        Xs[rr][3 * pos + 2] = f2;
+        Xs[rr][SG_FEAT + pos] = 0;
+    }
+    lds_barrier();
+    store_t(Xs, SG_K0, Xt, ld, r0, tid);
+
+    f32x4 acc[TR_RT][2];
+    // layer 1 -> H1s
+    wmma<SG_K0, TR_LD0>(Xs, w1r, l, acc);
+    WRegs<SG_H> w3r;
+    wload(w3r, W3, w, l);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int col = 32 * w + 16 * b + (l & 15);
+        const float bb = p[SG_OFF_B1 + col];
+#pragma unroll
+        for (int a = 0; a < TR_RT; ++a) {
+            uint16_t hv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float v = acc[a][b][i] + bb;
+                hv[i] = f2bf(v > 0.f ? v : 0.f);
+                H1s[16 * a + 4 * (l >> 4) + i][col] = hv[i];
+            }
+            store4_t(H1t, ld, col, r0 + 16 * a + 4 * (l >> 4), hv);
+        }
+    }
+    lds_barrier();
+    // layer 2 -> H2s
+    wmma<SG_H, TR_LD>(H1s, w2r, l, acc);
+    WRegs<SG_H> w3tr;
+    wload(w3tr, W3t, w, l);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int col = 32 * w + 16 * b + (l & 15);
+        const float bb = p[SG_OFF_B2 + col];
+#pragma unroll
+        for (int a = 0; a < TR_RT; ++a) {
+            uint16_t hv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float v = acc[a][b][i] + bb;
+                hv[i] = f2bf(v > 0.f ? v : 0.f);
+                H2s[16 * a + 4 * (l >> 4) + i][col] = hv[i];
+            }
+            store4_t(H2t, ld, col, r0 + 16 * a + 4 * (l >> 4), hv);
+        }
+    }
+    lds_barrier();
+    // layer 3, kept in registers as bf16, and the head's per-wave row sums
+    wmma<SG_H, TR_LD>(H2s, w3r, l, acc);
+    WRegs<SG_H> w2tr;
+    wload(w2tr, W2t, w, l);
+    uint16_t h3[TR_RT][2][4];
+    float w4c[2];
+    {
+        float sum[TR_RT][4];
+#pragma unroll
+        for (int a = 0; a < TR_RT; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sum[a][i] = 0.f;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int col = 32 * w + 16 * b + (l & 15);
+            const float bb = p[SG_OFF_B3 + col];
+            w4c[b] = p[SG_OFF_W4 + col];
+#pragma unroll
+            for (int a = 0; a < TR_RT; ++a)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float v = acc[a][b][i] + bb;
+                    h3[a][b][i] = f2bf(v > 0.f ? v : 0.f);
+                    sum[a][i] += bf2f(h3[a][b][i]) * w4c[b];
+                    if (H3keep) {
+                        const int row = r0 + 16 * a + 4 * (l >> 4) + i;
+                        if (row < rows) H3keep[(int64_t)row * SG_H + col] = h3[a][b][i];
+                    }
+                }
+        }
+#pragma unroll
+        for (int a = 0; a < TR_RT; ++a)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float v = sum[a][i];
+                for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m);
+                if ((l & 15) == 0) part[w][16 * a + 4 * (l >> 4) + i] = v;
+            }
+    }
+    lds_barrier();
+    // scores, loss gradient and loss (wave 0)
+    if (w == 0) {
+        float e = 0.f, dsum = 0.f;
+        if (l < TR_ROWS) {
+            const int i = r0 + l;
+            float s = p[SG_OFF_B4];
+#pragma unroll
+            for (int v = 0; v < TR_WAVES; ++v) s += part[v][l];
+            float ds = 0.f;
+            if (i < rows) {
+                const float d = s - ys[l];
+                ds = 2.f * d * inv_rows;
+                e = d * d * inv_rows;
+                if (score_keep) score_keep[i] = s;
+            }
+            dss[l] = ds;
+            dsum = ds;
+        }
+        for (int m = 32; m >= 1; m >>= 1) {
+            e += __shfl_xor(e, m);
+            dsum += __shfl_xor(dsum, m);
+        }
+        if (l == 0) {
+            vb[TR_V_LOSS] = e;
+            vb[TR_V_B4] = dsum;
+        }
+    }
+    lds_barrier();
+    // G3 = dL/dz3 = ds w4 where h3 > 0, into G3s; head and layer-3 bias sums
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int col = 32 * w + 16 * b + (l & 15);
+        float gw4 = 0.f, gb3 = 0.f;
+#pragma unroll
+        for (int a = 0; a < TR_RT; ++a) {
+            uint16_t gv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * a + 4 * (l >> 4) + i;
+                const float ds = dss[row];
+                const float h = bf2f(h3[a][b][i]);
+                const uint16_t g = h > 0.f ? f2bf(ds * w4c[b]) : (uint16_t)0;
+                gv[i] = g;
+                G3s[row][col] = g;
+                gw4 += ds * h;
+                gb3 += bf2f(g);
+            }
+            store4_t(G3t, ld, col, r0 + 16 * a + 4 * (l >> 4), gv);
+        }
+        gw4 = col_total(gw4);
+        gb3 = col_total(gb3);
+        if (l < 16) {
+            vb[TR_V_W4 + col] = gw4;
+            vb[TR_V_B3 + col] = gb3;
+        }
+    }
+    lds_barrier();
+    // G2 = (G3 W3) where h2 > 0, over H2s
+    wmma<SG_H, TR_LD>(G3s, w3tr, l, acc);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int col = 32 * w + 16 * b + (l & 15);
+        float gb = 0.f;
+#pragma unroll
+        for (int a = 0; a < TR_RT; ++a) {
+            uint16_t gv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * a + 4 * (l >> 4) + i;
+                const uint16_t g = bf2f(H2s[row][col]) > 0.f ? f2bf(acc[a][b][i]) : (uint16_t)0;
+                gv[i] = g;
+                H2s[row][col] = g;
+                gb += bf2f(g);
+            }
+            store4_t(G2t, ld, col, r0 + 16 * a + 4 * (l >> 4), gv);
+        }
+        gb = col_total(gb);
+        if (l < 16) vb[TR_V_B2 + col] = gb;
+    }
+    lds_barrier();
+    // G1 = (G2 W2) where h1 > 0, over H1s
+    wmma<SG_H, TR_LD>(H2s, w2tr, l, acc);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int col = 32 * w + 16 * b + (l & 15);
+        float gb = 0.f;
+#pragma unroll
+        for (int a = 0; a < TR_RT; ++a) {
+            uint16_t gv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * a + 4 * (l >> 4) + i;
+                const uint16_t g = bf2f(H1s[row][col]) > 0.f ? f2bf(acc[a][b][i]) : (uint16_t)0;
+                gv[i] = g;
+                H1s[row][col] = g;
+                gb += bf2f(g);
+            }
+            store4_t(G1t, ld, col, r0 + 16 * a + 4 * (l >> 4), gv);
+        }
+        gb = col_total(gb);
+        if (l < 16) vb[TR_V_B1 + col] = gb;
+    }
+}
+
+// Weight gradients dW[o][i] = sum over rows of G[r][o] A[r][i] for the three
+// layers (A = X, h1, h2; G = dL/dz1..3), one 64 x 64 output tile and one K
+// chunk of kc rows per block: blockIdx.x = tile (0..15 layer 3, 16..31 layer
+// 2, 32..35 layer 1) or WG_TILES + j for the per-block vectors (entries
+// 256j .. 256j+255 summed over the chunk's row blocks); blockIdx.y = chunk.
+// The four waves take interleaved K steps straight from global memory (both
+// operands are K-contiguous) and add their tiles in LDS at the end.
+__global__ __launch_bounds__(256) void train_wgrad_kernel(
+    const uint16_t *__restrict__ Xt, const uint16_t *__restrict__ H1t, const uint16_t *__restrict__ H2t,
+    const uint16_t *__restrict__ G1t, const uint16_t *__restrict__ G2t, const uint16_t *__restrict__ G3t,
+    int64_t ld, int rows, int kc, const float *__restrict__ vec, float *wpart, float *vpart) {
+    const int tile = blockIdx.x, chunk = blockIdx.y;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int k0 = chunk * kc, k1 = min(rows, k0 + kc);
+    if (tile >= WG_TILES) {
+        const int j = (tile - WG_TILES) * 256 + tid;
+        if (j < TR_VLEN) {
+            float s = 0.f;
+            for (int blk = k0 / TR_ROWS; blk < (k1 + TR_ROWS - 1) / TR_ROWS; ++blk) s += vec[(int64_t)blk * TR_VSTRIDE + j];
+            vpart[(int64_t)chunk * TR_VSTRIDE + j] = s;
+        }
+        return;
+    }
+    __shared__ float red[3][64][65];  // waves 1..3 hand their tiles to wave 0
+    const uint16_t *A, *B;
+    int tm, tn;
+    if (tile < 16) {
+        A = G3t; B = H2t; tm = tile >> 2; tn = tile & 3;
+    } else if (tile < 32) {
+        A = G2t; B = H1t; tm = (tile - 16) >> 2; tn = (tile - 16) & 3;
+    } else {
+        A = G1t; B = Xt; tm = tile - 32; tn = 0;
+    }
+    const uint16_t *Ab = A + (int64_t)(64 * tm + (l & 15)) * ld + (l >> 4) * 8;
+    const uint16_t *Bb = B + (int64_t)(64 * tn + (l & 15)) * ld + (l >> 4) * 8;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // batches of WG_STEPS K steps per wave (steps w, w + 4, ...): every load of
+    // a batch is issued before its first MFMA
+    for (int kb = k0 + GK * w; kb < k1; kb += 4 * GK * WG_STEPS) {
+        bf16x8 fa[WG_STEPS][4], fb[WG_STEPS][4];
+#pragma unroll
+        for (int q = 0; q < WG_STEPS; ++q) {
+            const int k = kb + 4 * GK * q;
+            if (k < k1) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    fa[q][t] = *reinterpret_cast<const bf16x8 *>(Ab + (int64_t)16 * t * ld + k);
+                    fb[q][t] = *reinterpret_cast<const bf16x8 *>(Bb + (int64_t)16 * t * ld + k);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < WG_STEPS; ++q) {
+            if (kb + 4 * GK * q < k1) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[q][a], fb[q][b], acc[a][b], 0, 0, 0);
+            }
+        }
+    }
+    if (w > 0) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) red[w - 1][16 * a + 4 * (l >> 4) + i][16 * b + (l & 15)] = acc[a][b][i];
+    }
+    __syncthreads();
+    if (w == 0) {
+        float *out = wpart + ((int64_t)chunk * WG_TILES + tile) * WG_TILE;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * a + 4 * (l >> 4) + i, c = 16 * b + (l & 15);
+                    out[r * 64 + c] = acc[a][b][i] + red[0][r][c] + red[1][r][c] + red[2][r][c];
+                }
+    }
+}
+
+// Adam on the float32 masters (bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t)
+// (omb1 = 1 - beta1 and omb2 = 1 - beta2 are rounded from double on the host:
+// 1 - 0.999f in float32 would be 1.3e-5 off 0.001)
+struct AdamArgs {
+    float lr, beta1, beta2, eps, c1, c2, omb1, omb2;
+};
+
+// mode 0: gradient only (sum the chunk partials into g);
+// mode 1: that, then Adam and the bf16 copies; mode 2: Adam on the given
+// gradient gin.  Block 0 also writes the loss (modes 0, 1).
+__global__ void train_update_kernel(int mode, const float *__restrict__ wpart, const float *__restrict__ vpart,
+                                    int ks, const float *__restrict__ gin, float *p, float *g, float *m, float *v,
+                                    AdamArgs a, float *loss, uint16_t *W1, uint16_t *W2, uint16_t *W2t,
+                                    uint16_t *W3, uint16_t *W3t) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (mode != 2 && i == 0) {
+        float s = 0.f;
+        for (int c = 0; c < ks; ++c) s += vpart[(int64_t)c * TR_VSTRIDE + TR_V_LOSS];
+        *loss = s;
+    }
+    if (i >= SG_NPARAM) return;
+    float gi;
+    if (mode == 2) {
+        gi = gin[i];
+    } else {
+        int64_t widx = -1;  // offset in a chunk's tile partials, or -1 for a vector entry
+        int vidx = 0;
+        if (i < SG_OFF_B1) {
+            const int o = i / SG_FEAT, c = i % SG_FEAT;
+            widx = (int64_t)(32 + o / 64) * WG_TILE + (o % 64) * 64 + c;
+        } else if (i < SG_OFF_W2) {
+            vidx = TR_V_B1 + (i - SG_OFF_B1);
+        } else if (i < SG_OFF_B2) {
+            const int j = i - SG_OFF_W2, o = j / SG_H, c = j % SG_H;
+            widx = (int64_t)(16 + (o / 64) * 4 + c / 64) * WG_TILE + (o % 64) * 64 + c % 64;
+        } else if (i < SG_OFF_W3) {
+            vidx = TR_V_B2 + (i - SG_OFF_B2);
+        } else if (i < SG_OFF_B3) {
+            const int j = i - SG_OFF_W3, o = j / SG_H, c = j % SG_H;
+            widx = (int64_t)((o / 64) * 4 + c / 64) * WG_TILE + (o % 64) * 64 + c % 64;
+        } else if (i < SG_OFF_W4) {
+            vidx = TR_V_B3 + (i - SG_OFF_B3);
+        } else if (i < SG_OFF_B4) {
+            vidx = TR_V_W4 + (i - SG_OFF_W4);
+        } else {
+            vidx = TR_V_B4;
+        }
+        float s = 0.f;
+        if (widx >= 0) {
+            for (int c = 0; c < ks; ++c) s += wpart[(int64_t)c * WG_TILES * WG_TILE + widx];
+        } else {
+            for (int c = 0; c < ks; ++c) s += vpart[(int64_t)c * TR_VSTRIDE + vidx];
+        }
+        gi = s;
+        g[i] = gi;
+    }
+    if (mode == 0) return;
+    const float mi = a.beta1 * m[i] + a.omb1 * gi;
+    const float vi = a.beta2 * v[i] + a.omb2 * (gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+    p[i] = pi;
+    const uint16_t bb = f2bf(pi);
+    if (i < SG_OFF_B1) {
+        W1[(i / SG_FEAT) * SG_K0 + i % SG_FEAT] = bb;
+    } else if (i >= SG_OFF_W2 && i < SG_OFF_B2) {
+        const int j = i - SG_OFF_W2;
+        W2[j] = bb;
+        W2t[(j % SG_H) * SG_H + j / SG_H] = bb;
+    } else if (i >= SG_OFF_W3 && i < SG_OFF_B3) {
+        const int j = i - SG_OFF_W3;
+        W3[j] = bb;
+        W3t[(j % SG_H) * SG_H + j / SG_H] = bb;
+    }
+}
+
+__global__ void refresh_bf16_kernel(const float *__restrict__ p, uint16_t *W1, uint16_t *W2, uint16_t *W2t,
+                                    uint16_t *W3, uint16_t *W3t) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < SG_H * SG_K0) {
         const int o = i / SG_K0, c = i % SG_K0;
-        const uint16_t b = c < SG_FEAT ? f2bf(p[SG_OFF_W1 + o * SG_FEAT + c]) : (uint16_t)0;
-        W1[o * SG_K0 + c] = b;
-        W1t[c * SG_H + o] = b;
+        W1[o * SG_K0 + c] = c < SG_FEAT ? f2bf(p[SG_OFF_W1 + o * SG_FEAT + c]) : (uint16_t)0;
     }
     if (i < SG_H * SG_H) {
         const int o = i / SG_H, c = i % SG_H;
@@ -895,15 +1087,19 @@ struct tgo_surrogate {
     int64_t max_rows = 0;
     int64_t step = 0;
     void *mem = nullptr;
-    // parameters
-    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr, *gw1 = nullptr;
-    uint16_t *W1 = nullptr, *W1t = nullptr, *W2 = nullptr, *W2t = nullptr, *W3 = nullptr, *W3t = nullptr;
-    // activations (rows x width)
-    uint16_t *X = nullptr, *Xt = nullptr, *H1 = nullptr, *H1t = nullptr, *H2 = nullptr, *H2t = nullptr;
-    uint16_t *H3 = nullptr, *H3t = nullptr, *D3 = nullptr, *D3t = nullptr, *D2 = nullptr, *D2t = nullptr;
-    uint16_t *D1 = nullptr, *D1t = nullptr;
-    float *score = nullptr, *y = nullptr, *dscore = nullptr, *F = nullptr;
-    uint8_t *valid = nullptr;
+    // parameters: float32 masters, gradient, Adam moments; bf16 working copies
+    // W [out][in] (W1 padded to 64 inputs) and, for back-propagation, W^T
+    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    uint16_t *W1 = nullptr, *W2 = nullptr, *W2t = nullptr, *W3 = nullptr, *W3t = nullptr;
+    // training batch, transposed [feature][row] with row pitch max_rows
+    uint16_t *Xt = nullptr, *H1t = nullptr, *H2t = nullptr, *G1t = nullptr, *G2t = nullptr, *G3t = nullptr;
+    // kept by tgo_surrogate_grad for inspection: h3 [row][256] and scores
+    uint16_t *H3 = nullptr;
+    float *score = nullptr;
+    int64_t kept_rows = 0;
+    // per-block vectors and per-chunk partial sums of a training step
+    float *vec = nullptr, *wpart = nullptr, *vpart = nullptr;
+    float *F = nullptr;
     int max_groups = 0;
     int32_t *status = nullptr;
     uint8_t *horders = nullptr;
@@ -917,22 +1113,51 @@ namespace tgo {
 
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-static int sur_forward(tgo_surrogate *s, int64_t rows, bool keep_t, hipStream_t st) {
-    // rows is a multiple of 64; X holds the first-layer input
-    GemmOut o{};
-    o.bias = s->p + SG_OFF_B1;
-    o.Y = s->H1;
-    o.Yt = keep_t ? s->H1t : nullptr;
-    gemm<EPI_BIAS | EPI_RELU>(s->X, s->W1, (int)rows, SG_H, SG_K0, o, st);
-    o.bias = s->p + SG_OFF_B2;
-    o.Y = s->H2;
-    o.Yt = keep_t ? s->H2t : nullptr;
-    gemm<EPI_BIAS | EPI_RELU>(s->H1, s->W2, (int)rows, SG_H, SG_H, o, st);
-    o.bias = s->p + SG_OFF_B3;
-    o.Y = s->H3;
-    o.Yt = keep_t ? s->H3t : nullptr;
-    gemm<EPI_BIAS | EPI_RELU>(s->H2, s->W3, (int)rows, SG_H, SG_H, o, st);
+// K chunks of the weight-gradient launch: at most WG_KS_MAX, each a whole
+// number of row blocks.
+static void wgrad_chunks(int rows, int *ks, int *kc) {
+    int k = (rows + WG_KC - 1) / WG_KC;
+    k = k < 1 ? 1 : (k > WG_KS_MAX ? WG_KS_MAX : k);
+    int c = ((rows + k - 1) / k + TR_ROWS - 1) / TR_ROWS * TR_ROWS;
+    *kc = c;
+    *ks = (rows + c - 1) / c;
+}
+
+// Forward + backward and the weight-gradient partials of one batch; returns
+// the number of K chunks.
+static int train_pass(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *d_offs, const uint8_t *d_orders,
+                      const int32_t *d_gid, const int64_t *d_T, int rows, bool keep, int *ks_out, hipStream_t st) {
+    const int blocks = (rows + TR_ROWS - 1) / TR_ROWS;
+    hipLaunchKernelGGL(train_fwd_bwd_kernel, dim3(blocks), dim3(TR_THREADS), 0, st, d_tasks, d_offs, d_orders, d_gid,
+                       d_T, rows, 1.0f / (float)rows, s->W1, s->W2, s->W3, s->W2t, s->W3t, s->p, s->max_rows, s->Xt,
+                       s->H1t, s->H2t, s->G3t, s->G2t, s->G1t, s->vec, keep ? s->H3 : (uint16_t *)nullptr,
+                       keep ? s->score : (float *)nullptr);
+    int ks = 0, kc = 0;
+    wgrad_chunks(rows, &ks, &kc);
+    hipLaunchKernelGGL(train_wgrad_kernel, dim3(WG_TILES + WG_VEC_BLOCKS, ks), dim3(256), 0, st, s->Xt, s->H1t,
+                       s->H2t, s->G1t, s->G2t, s->G3t, s->max_rows, rows, kc, s->vec, s->wpart, s->vpart);
+    TGO_HIP(hipGetLastError());
+    *ks_out = ks;
     return TGO_OK;
+}
+
+static AdamArgs adam_args(int64_t step, float lr) {
+    AdamArgs a;
+    a.lr = lr;
+    a.beta1 = 0.9f;
+    a.beta2 = 0.999f;
+    a.eps = 1e-8f;
+    a.c1 = (float)(1.0 - std::pow(0.9, (double)step));
+    a.c2 = (float)(1.0 - std::pow(0.999, (double)step));
+    a.omb1 = (float)(1.0 - 0.9);
+    a.omb2 = (float)(1.0 - 0.999);
+    return a;
+}
+
+static void launch_update(tgo_surrogate *s, int mode, int ks, const float *gin, const AdamArgs &a, float *loss,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(train_update_kernel, dim3((SG_NPARAM + 255) / 256), dim3(256), 0, st, mode, s->wpart,
+                       s->vpart, ks, gin, s->p, s->g, s->m, s->v, a, loss, s->W1, s->W2, s->W2t, s->W3, s->W3t);
 }
 
 }  // namespace tgo
@@ -953,21 +1178,19 @@ int tgo_surrogate_create(int64_t max_rows, int max_groups, tgo_surrogate **out) 
     s->max_groups = max_groups;
     (void)hipGetDevice(&s->device);
     const size_t R = (size_t)max_rows;
+    const size_t blocks = (R + TR_ROWS - 1) / TR_ROWS;
     std::vector<std::pair<void **, size_t>> parts = {
         {(void **)&s->p, 4 * SG_NPARAM}, {(void **)&s->g, 4 * SG_NPARAM}, {(void **)&s->m, 4 * SG_NPARAM},
-        {(void **)&s->v, 4 * SG_NPARAM}, {(void **)&s->gw1, 4 * SG_H * SG_K0},
-        {(void **)&s->W1, 2 * SG_H * SG_K0}, {(void **)&s->W1t, 2 * SG_H * SG_K0},
-        {(void **)&s->W2, 2 * SG_H * SG_H}, {(void **)&s->W2t, 2 * SG_H * SG_H},
+        {(void **)&s->v, 4 * SG_NPARAM},
+        {(void **)&s->W1, 2 * SG_H * SG_K0}, {(void **)&s->W2, 2 * SG_H * SG_H}, {(void **)&s->W2t, 2 * SG_H * SG_H},
         {(void **)&s->W3, 2 * SG_H * SG_H}, {(void **)&s->W3t, 2 * SG_H * SG_H},
-        {(void **)&s->X, 2 * R * SG_K0}, {(void **)&s->Xt, 2 * R * SG_K0},
-        {(void **)&s->H1, 2 * R * SG_H}, {(void **)&s->H1t, 2 * R * SG_H},
-        {(void **)&s->H2, 2 * R * SG_H}, {(void **)&s->H2t, 2 * R * SG_H},
-        {(void **)&s->H3, 2 * R * SG_H}, {(void **)&s->H3t, 2 * R * SG_H},
-        {(void **)&s->D3, 2 * R * SG_H}, {(void **)&s->D3t, 2 * R * SG_H},
-        {(void **)&s->D2, 2 * R * SG_H}, {(void **)&s->D2t, 2 * R * SG_H},
-        {(void **)&s->D1, 2 * R * SG_H}, {(void **)&s->D1t, 2 * R * SG_H},
-        {(void **)&s->score, 4 * R}, {(void **)&s->y, 4 * R}, {(void **)&s->dscore, 4 * R},
-        {(void **)&s->valid, R}, {(void **)&s->F, 4 * (size_t)max_groups * SG_POS * 3},
+        {(void **)&s->Xt, 2 * R * SG_K0}, {(void **)&s->H1t, 2 * R * SG_H}, {(void **)&s->H2t, 2 * R * SG_H},
+        {(void **)&s->G1t, 2 * R * SG_H}, {(void **)&s->G2t, 2 * R * SG_H}, {(void **)&s->G3t, 2 * R * SG_H},
+        {(void **)&s->H3, 2 * R * SG_H}, {(void **)&s->score, 4 * R},
+        {(void **)&s->vec, 4 * blocks * TR_VSTRIDE},
+        {(void **)&s->wpart, 4 * (size_t)WG_KS_MAX * WG_TILES * WG_TILE},
+        {(void **)&s->vpart, 4 * (size_t)WG_KS_MAX * TR_VSTRIDE},
+        {(void **)&s->F, 4 * (size_t)max_groups * SG_POS * 3},
         {(void **)&s->status, 4 * (size_t)max_groups}, {(void **)&s->horders, 16 * (size_t)max_groups},
         {(void **)&s->hns, 8 * (size_t)max_groups}, {(void **)&s->best, 8 * (size_t)max_groups},
         {(void **)&s->keys, 8 * R},
@@ -999,7 +1222,7 @@ void tgo_surrogate_destroy(tgo_surrogate *s) {
 
 static int refresh(tgo_surrogate *s, hipStream_t st) {
     hipLaunchKernelGGL(refresh_bf16_kernel, dim3((SG_H * SG_H + 255) / 256), dim3(256), 0, st, s->p, s->W1,
-                       s->W1t, s->W2, s->W2t, s->W3, s->W3t);
+                       s->W2, s->W2t, s->W3, s->W3t);
     TGO_HIP(hipGetLastError());
     return TGO_OK;
 }
@@ -1099,22 +1322,6 @@ int tgo_surrogate_pairs(const tgo_model *model, const tgo_task *d_tasks, const i
     return TGO_OK;
 }
 
-// features of given orderings into X (rows padded to a multiple of 64 with zero rows)
-static int given_features(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *d_offs, int G,
-                          const uint8_t *d_orders, const int32_t *d_gid, int64_t rows, bool with_t,
-                          hipStream_t st) {
-    hipLaunchKernelGGL(group_features_kernel, dim3((G * SG_POS + 255) / 256), dim3(256), 0, st, d_tasks, d_offs,
-                       G, s->F);
-    const int64_t pad = (rows + 63) / 64 * 64;
-    if (pad > rows) TGO_HIP(hipMemsetAsync(s->X + rows * SG_K0, 0, 2 * (pad - rows) * SG_K0, st));
-    hipLaunchKernelGGL(features_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, s->F, d_offs,
-                       (const uint32_t *)nullptr, d_orders, d_gid, (int64_t)0, rows, (int64_t)1, (int64_t)1,
-                       (uint64_t)0, s->X,
-                       with_t ? s->Xt : (uint16_t *)nullptr, rows, (uint8_t *)nullptr);
-    TGO_HIP(hipGetLastError());
-    return TGO_OK;
-}
-
 int tgo_surrogate_score(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *d_offs, int G,
                         const uint8_t *d_orders, const int32_t *d_gid, int64_t rows, float *d_scores,
                         tgo_stream stream) {
@@ -1133,52 +1340,6 @@ int tgo_surrogate_score(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t
     return TGO_OK;
 }
 
-// forward + backward on a batch of pairs; gradient (float [NPARAM]) into s->g, loss into d_loss
-static int sur_grad(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *d_offs, int G,
-                    const uint8_t *d_orders, const int32_t *d_gid, const int64_t *d_T, int rows,
-                    float *d_loss, hipStream_t st) {
-    int rc = given_features(s, d_tasks, d_offs, G, d_orders, d_gid, rows, true, st);
-    if (rc) return rc;
-    rc = sur_forward(s, rows, true, st);
-    if (rc) return rc;
-    hipLaunchKernelGGL(head_kernel, dim3((unsigned)((rows * 64 + 255) / 256)), dim3(256), 0, st, s->H3,
-                       s->p + SG_OFF_W4, s->p + SG_OFF_B4, (int64_t)rows, (const uint8_t *)nullptr, s->score);
-    hipLaunchKernelGGL(target_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, d_tasks, d_offs, d_gid, d_T,
-                       rows, s->y);
-    TGO_HIP(hipMemsetAsync(d_loss, 0, 4, st));
-    TGO_HIP(hipMemsetAsync(s->g, 0, 4 * SG_NPARAM, st));
-    hipLaunchKernelGGL(loss_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, s->score, s->y, rows, s->dscore,
-                       d_loss);
-    hipLaunchKernelGGL(head_bwd_kernel, dim3((unsigned)((rows * 64 + 255) / 256)), dim3(256), 0, st, s->H3,
-                       s->p + SG_OFF_W4, s->dscore, rows, s->D3, s->D3t);
-    hipLaunchKernelGGL(head_wgrad_kernel, dim3(SG_H + 1), dim3(256), 0, st, s->H3t, s->dscore, rows,
-                       s->g + SG_OFF_W4, s->g + SG_OFF_B4);
-    // layer 3: grad W3 = D3^T H2 ; grad b3 = colsum ; D2 = (D3 W3) * (H2 > 0)
-    gemm_splitk(s->D3t, s->H2t, SG_H, SG_H, rows, s->g + SG_OFF_W3, st);
-    hipLaunchKernelGGL(colsum_kernel, dim3(SG_H), dim3(256), 0, st, s->D3t, rows, s->g + SG_OFF_B3);
-    GemmOut o{};
-    o.Y = s->D2;
-    o.Yt = s->D2t;
-    o.mask = s->H2;
-    gemm<EPI_MASK>(s->D3, s->W3t, rows, SG_H, SG_H, o, st);
-    // layer 2
-    gemm_splitk(s->D2t, s->H1t, SG_H, SG_H, rows, s->g + SG_OFF_W2, st);
-    hipLaunchKernelGGL(colsum_kernel, dim3(SG_H), dim3(256), 0, st, s->D2t, rows, s->g + SG_OFF_B2);
-    o = GemmOut{};
-    o.Y = s->D1;
-    o.Yt = s->D1t;
-    o.mask = s->H1;
-    gemm<EPI_MASK>(s->D2, s->W2t, rows, SG_H, SG_H, o, st);
-    // layer 1: grad W1 = D1^T X
-    TGO_HIP(hipMemsetAsync(s->gw1, 0, 4 * SG_H * SG_K0, st));
-    gemm_splitk(s->D1t, s->Xt, SG_H, SG_K0, rows, s->gw1, st);
-    hipLaunchKernelGGL(colsum_kernel, dim3(SG_H), dim3(256), 0, st, s->D1t, rows, s->g + SG_OFF_B1);
-    hipLaunchKernelGGL(pack_w1_grad_kernel, dim3((SG_H * SG_FEAT + 255) / 256), dim3(256), 0, st, s->gw1,
-                       s->g + SG_OFF_W1);
-    TGO_HIP(hipGetLastError());
-    return TGO_OK;
-}
-
 int tgo_surrogate_grad(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *d_offs, int G,
                        const uint8_t *d_orders, const int32_t *d_gid, const int64_t *d_T, int rows,
                        float *d_grad, float *d_loss, tgo_stream stream) {
@@ -1188,8 +1349,12 @@ int tgo_surrogate_grad(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t 
     if (rows < 64 || rows > s->max_rows || rows % 64 || !d_orders || !d_gid || !d_T || !d_loss)
         return fail(TGO_EINVAL, "rows must be a multiple of 64 up to max_rows; no NULL buffers");
     hipStream_t st = (hipStream_t)stream;
-    rc = sur_grad(s, d_tasks, d_offs, G, d_orders, d_gid, d_T, rows, d_loss, st);
+    int ks = 0;
+    rc = train_pass(s, d_tasks, d_offs, d_orders, d_gid, d_T, rows, true, &ks, st);
     if (rc) return rc;
+    s->kept_rows = rows;
+    launch_update(s, 0, ks, nullptr, adam_args(1, 0.f), d_loss, st);
+    TGO_HIP(hipGetLastError());
     if (d_grad) TGO_HIP(hipMemcpyAsync(d_grad, s->g, 4 * SG_NPARAM, hipMemcpyDeviceToDevice, st));
     return TGO_OK;
 }
@@ -1197,22 +1362,63 @@ int tgo_surrogate_grad(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t 
 int tgo_surrogate_train_step(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *d_offs, int G,
                              const uint8_t *d_orders, const int32_t *d_gid, const int64_t *d_T, int rows,
                              float lr, float *d_loss, tgo_stream stream) {
-    int rc = tgo_surrogate_grad(s, d_tasks, d_offs, G, d_orders, d_gid, d_T, rows, nullptr, d_loss, stream);
+    if (!s) return fail(TGO_EINVAL, "surrogate is NULL");
+    int rc = check_groups(d_tasks, d_offs, G, s->max_groups);
     if (rc) return rc;
+    if (rows < 64 || rows > s->max_rows || rows % 64 || !d_orders || !d_gid || !d_T || !d_loss)
+        return fail(TGO_EINVAL, "rows must be a multiple of 64 up to max_rows; no NULL buffers");
     if (!(lr > 0.f)) return fail(TGO_EINVAL, "lr must be > 0");
     hipStream_t st = (hipStream_t)stream;
+    int ks = 0;
+    rc = train_pass(s, d_tasks, d_offs, d_orders, d_gid, d_T, rows, false, &ks, st);
+    if (rc) return rc;
     s->step += 1;
-    AdamArgs a;
-    a.lr = lr;
-    a.beta1 = 0.9f;
-    a.beta2 = 0.999f;
-    a.eps = 1e-8f;
-    a.c1 = (float)(1.0 - std::pow(0.9, (double)s->step));
-    a.c2 = (float)(1.0 - std::pow(0.999, (double)s->step));
-    hipLaunchKernelGGL(adam_kernel, dim3((SG_NPARAM + 255) / 256), dim3(256), 0, st, s->p, s->g, s->m, s->v,
-                       SG_NPARAM, a);
+    launch_update(s, 1, ks, nullptr, adam_args(s->step, lr), d_loss, st);
     TGO_HIP(hipGetLastError());
-    return refresh(s, st);
+    return TGO_OK;
+}
+
+int tgo_surrogate_adam_step(tgo_surrogate *s, const float *d_grad, float lr, tgo_stream stream) {
+    if (!s || !d_grad) return fail(TGO_EINVAL, "NULL argument");
+    if (!(lr > 0.f)) return fail(TGO_EINVAL, "lr must be > 0");
+    s->step += 1;
+    launch_update(s, 2, 0, d_grad, adam_args(s->step, lr), nullptr, (hipStream_t)stream);
+    TGO_HIP(hipGetLastError());
+    return TGO_OK;
+}
+
+int tgo_surrogate_get_moments(tgo_surrogate *s, float *h_m, float *h_v, int64_t *h_step, tgo_stream stream) {
+    if (!s) return fail(TGO_EINVAL, "surrogate is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    if (h_m) TGO_HIP(hipMemcpyAsync(h_m, s->m, 4 * SG_NPARAM, hipMemcpyDeviceToHost, st));
+    if (h_v) TGO_HIP(hipMemcpyAsync(h_v, s->v, 4 * SG_NPARAM, hipMemcpyDeviceToHost, st));
+    TGO_HIP(hipStreamSynchronize(st));
+    if (h_step) *h_step = s->step;
+    return TGO_OK;
+}
+
+int tgo_surrogate_get_batch(tgo_surrogate *s, int what, int64_t rows, void *h_out, tgo_stream stream) {
+    if (!s || !h_out) return fail(TGO_EINVAL, "NULL argument");
+    if (what < 0 || what > 7) return fail(TGO_EINVAL, "what must be in 0..7");
+    if (rows < 1 || rows > s->kept_rows) return fail(TGO_EINVAL, "rows must be in 1..rows of the last tgo_surrogate_grad");
+    hipStream_t st = (hipStream_t)stream;
+    if (what == 3 || what == 4) {
+        const size_t b = what == 3 ? 2 * (size_t)rows * SG_H : 4 * (size_t)rows;
+        TGO_HIP(hipMemcpyAsync(h_out, what == 3 ? (void *)s->H3 : (void *)s->score, b, hipMemcpyDeviceToHost, st));
+        TGO_HIP(hipStreamSynchronize(st));
+        return TGO_OK;
+    }
+    const uint16_t *src = what == 0 ? s->Xt : what == 1 ? s->H1t : what == 2 ? s->H2t
+                        : what == 5 ? s->G3t : what == 6 ? s->G2t : s->G1t;
+    const int width = what == 0 ? SG_K0 : SG_H, keep = what == 0 ? SG_FEAT : SG_H;
+    std::vector<uint16_t> t((size_t)width * rows);
+    TGO_HIP(hipMemcpy2DAsync(t.data(), 2 * (size_t)rows, src, 2 * (size_t)s->max_rows, 2 * (size_t)rows, width,
+                             hipMemcpyDeviceToHost, st));
+    TGO_HIP(hipStreamSynchronize(st));
+    uint16_t *o = (uint16_t *)h_out;
+    for (int64_t r = 0; r < rows; ++r)
+        for (int c = 0; c < keep; ++c) o[r * keep + c] = t[(size_t)c * rows + r];
+    return TGO_OK;
 }
 
 // Candidate-key buffers, grown on demand.  The object is either fully sized

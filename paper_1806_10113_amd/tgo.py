@@ -114,6 +114,16 @@ def lib():
         L.tgo_random_search.argtypes = [M, vp, vp, i32, i64, ctypes.c_uint64, vp, vp]
         L.tgo_surrogate_candidates.argtypes = [vp, M, vp, vp, vp, i32, i64, i32, ctypes.c_uint64, vp, vp]
         L.tgo_surrogate_candidates.restype = i32
+        L.tgo_exhaustive_cke.argtypes = [M, vp, vp, i32, i32, vp, vp, vp]
+        L.tgo_exhaustive_cke.restype = i32
+        L.tgo_evaluate_cke.argtypes = [M, vp, vp, i32, i32, vp, i64, vp, vp]
+        L.tgo_evaluate_cke.restype = i32
+        L.tgo_surrogate_adam_step.argtypes = [vp, vp, ctypes.c_float, vp]
+        L.tgo_surrogate_adam_step.restype = i32
+        L.tgo_surrogate_get_moments.argtypes = [vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
+        L.tgo_surrogate_get_moments.restype = i32
+        L.tgo_surrogate_get_batch.argtypes = [vp, i32, i64, vp, vp]
+        L.tgo_surrogate_get_batch.restype = i32
         for f in (L.tgo_surrogate_create, L.tgo_surrogate_param_count, L.tgo_surrogate_init,
                   L.tgo_surrogate_set_params, L.tgo_surrogate_get_params, L.tgo_surrogate_pairs,
                   L.tgo_surrogate_score, L.tgo_surrogate_grad, L.tgo_surrogate_train_step,
@@ -238,6 +248,45 @@ def exhaustive_noalloc(tasks, summary, per_order=None, model: Model = DEFAULT, s
                                         per_order.data_ptr() if per_order is not None else None,
                                         summary.data_ptr(), _stream(stream)), "tgo_exhaustive_noalloc")
     return summary, per_order
+
+
+def exhaustive_cke(tasks, units, capacity: int, model: Model = DEFAULT, per_order: bool = False, summary=None,
+                   stream=None):
+    """Every ordering with concurrent kernels: task x's kernel holds units[x]
+    (int32 [n] device tensor) of ``capacity`` while it runs.  Returns (summary
+    uint8[136] device tensor with Algorithm 1 under the same rule in heur /
+    heur_ns, per-ordering int64 device tensor or None)."""
+    import math
+    import torch
+    _dev_tensor(tasks, torch.int64, 3, "tasks")
+    _dev_tensor(units, torch.int32, None, "units")
+    n = tasks.shape[0]
+    if units.numel() != n:
+        raise ValueError("one unit count per task")
+    po = torch.empty(math.factorial(n), dtype=torch.int64, device=tasks.device) if per_order else None
+    if summary is None:
+        summary = torch.empty(SUMMARY_DTYPE.itemsize, dtype=torch.uint8, device=tasks.device)
+    _check(lib().tgo_exhaustive_cke(ctypes.byref(model._c()), tasks.data_ptr(), units.data_ptr(), n, capacity,
+                                    po.data_ptr() if po is not None else None, summary.data_ptr(),
+                                    _stream(stream)), "tgo_exhaustive_cke")
+    return summary, po
+
+
+def evaluate_cke(tasks, units, capacity: int, orders, model: Model = DEFAULT, out=None, stream=None):
+    """T (int64) of each row of ``orders`` (uint8 [m, n]) with concurrent kernels."""
+    import torch
+    _dev_tensor(tasks, torch.int64, 3, "tasks")
+    _dev_tensor(units, torch.int32, None, "units")
+    _dev_tensor(orders, torch.uint8, None, "orders")
+    n = tasks.shape[0]
+    if orders.dim() != 2 or orders.shape[1] != n or units.numel() != n:
+        raise ValueError("orders must be [m, n] and units [n]")
+    m = orders.shape[0]
+    if out is None:
+        out = torch.empty(m, dtype=torch.int64, device=tasks.device)
+    _check(lib().tgo_evaluate_cke(ctypes.byref(model._c()), tasks.data_ptr(), units.data_ptr(), n, capacity,
+                                  orders.data_ptr(), m, out.data_ptr(), _stream(stream)), "tgo_evaluate_cke")
+    return out
 
 
 def predict(tasks, order, model: Model = DEFAULT) -> int:
@@ -545,6 +594,40 @@ class Surrogate:
                                               lr, loss.data_ptr(), _stream(stream)),
                "tgo_surrogate_train_step")
         return loss
+
+    def adam_step(self, grad, lr: float, stream=None):
+        """One Adam step of the masters with a given float32 device gradient."""
+        import torch
+        _dev_tensor(grad, torch.float32, None, "grad")
+        if grad.numel() != SURROGATE_PARAMS:
+            raise ValueError("grad must hold every parameter")
+        _check(lib().tgo_surrogate_adam_step(self._h, grad.data_ptr(), lr, _stream(stream)),
+               "tgo_surrogate_adam_step")
+
+    def moments(self):
+        """(m, v, step): Adam's moments as float32 host arrays and the step count."""
+        m = np.empty(SURROGATE_PARAMS, dtype=np.float32)
+        v = np.empty(SURROGATE_PARAMS, dtype=np.float32)
+        t = ctypes.c_int64()
+        _check(lib().tgo_surrogate_get_moments(self._h, m.ctypes.data, v.ctypes.data, ctypes.byref(t), None),
+               "tgo_surrogate_get_moments")
+        return m, v, t.value
+
+    BATCH_FEATURES, BATCH_H1, BATCH_H2, BATCH_H3, BATCH_SCORE, BATCH_G3, BATCH_G2, BATCH_G1 = range(8)
+
+    def batch_values(self, what: int, rows: int) -> np.ndarray:
+        """A stored value of the last grad() batch, row-major: bf16 values as
+        float64 (features [rows, 48], h1..h3 and the gradients G3, G2, G1
+        [rows, 256]) or the float32 scores [rows]."""
+        if what == self.BATCH_SCORE:
+            out = np.empty(rows, dtype=np.float32)
+        else:
+            out = np.empty((rows, 48 if what == self.BATCH_FEATURES else 256), dtype=np.uint16)
+        _check(lib().tgo_surrogate_get_batch(self._h, what, rows, out.ctypes.data, None),
+               "tgo_surrogate_get_batch")
+        if what == self.BATCH_SCORE:
+            return out
+        return (out.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
     def search(self, tasks, offs, samples: int, topk: int, seed: int, model: Model = DEFAULT,
                keys=None, stream=None):

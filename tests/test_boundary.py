@@ -87,6 +87,14 @@ def test_host_argument_errors(L):
     for n, cap, m in ((0, 10, 1), (17, 10, 1), (4, 0, 1), (4, 10, -1), (4, 10, (1 << 40) + 1)):
         assert L.tgo_evaluate_mem(ctypes.byref(good), fake, fake, n, cap, fake, m, fake, None) == tgo.TGO_EINVAL
     assert L.tgo_evaluate_mem(ctypes.byref(good), fake, None, 4, 10, fake, 5, fake, None) == tgo.TGO_EINVAL
+    # concurrent kernels: n in 1..12 (evaluate 1..16), capacity in 1..2^30, buffers present
+    for n, cap in ((0, 4), (13, 4), (4, 0), (4, (1 << 30) + 1)):
+        assert L.tgo_exhaustive_cke(ctypes.byref(good), fake, fake, n, cap, None, fake, None) == tgo.TGO_EINVAL
+    assert L.tgo_exhaustive_cke(ctypes.byref(good), fake, None, 4, 4, None, fake, None) == tgo.TGO_EINVAL
+    assert L.tgo_exhaustive_cke(None, fake, fake, 4, 4, None, fake, None) == tgo.TGO_EINVAL
+    for n, cap, m in ((0, 4, 1), (17, 4, 1), (4, 0, 1), (4, 4, -1)):
+        assert L.tgo_evaluate_cke(ctypes.byref(good), fake, fake, n, cap, fake, m, fake, None) == tgo.TGO_EINVAL
+    assert L.tgo_evaluate_cke(ctypes.byref(good), fake, None, 4, 4, fake, 3, fake, None) == tgo.TGO_EINVAL
     # the integer issue probe: 1..2^20 blocks and iterations
     for blocks, iters in ((0, 1), (1, 0), ((1 << 20) + 1, 1), (1, (1 << 20) + 1)):
         assert L.tgo_valu_probe(blocks, iters, None) == tgo.TGO_EINVAL

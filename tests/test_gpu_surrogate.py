@@ -5,6 +5,11 @@ and the gain of the trained network over random candidates."""
 import numpy as np
 import pytest
 
+import os
+import sys
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
 from oracle import cmodel
 from oracle import mlp
 from oracle import model as M
@@ -84,34 +89,154 @@ def test_scores_against_float64_oracle(dev):
     sur.close()
 
 
-def test_gradients_against_float64_oracle(dev):
+def _grad_case(dev, rows_groups, per, seed_groups, seed_pairs, seed_net):
     import torch
     from paper_1806_10113_amd import tgo
-    b = W.batch_groups(32, 8, 16, seed=302, per_task_label=True)
+    b = W.batch_groups(rows_groups, 8, 16, seed=seed_groups, per_task_label=True)
     tasks, offs = to_dev(b.tasks, dev), to_dev(b.offs, dev)
-    orders, gid, T, _ = tgo.pairs(tasks, offs, 64, seed=13)  # 2048 rows
-    sur = tgo.Surrogate(max_rows=4096, max_groups=64)
-    flat = setup_net(2)
+    orders, gid, T, _ = tgo.pairs(tasks, offs, per, seed=seed_pairs)
+    sur = tgo.Surrogate(max_rows=8192, max_groups=4096)
+    flat = setup_net(seed_net)
     sur.set_params(flat)
     grad, loss = sur.grad(tasks, offs, orders, gid, T)
-    grad = grad.cpu().numpy().astype(np.float64)
-    params = [(mlp.round_bf16(Wt), bb) for Wt, bb in mlp.unflatten(flat)]
-    params[-1] = mlp.unflatten(flat)[-1]
-    on, og = orders.cpu().numpy(), gid.cpu().numpy()
-    X = mlp.round_bf16(oracle_features(b, on, og))
-    y = np.array([mlp.target(b.group(g), t) for g, t in zip(og, T.cpu().numpy())])
-    want = mlp.flatten(mlp.backward(params, X, y, round_hidden=mlp.round_bf16))
-    assert abs(float(loss.cpu()[0]) - mlp.loss(params, X, y)) <= 2e-2 * mlp.loss(params, X, y) + 1e-6
-    # per block: relative L2 error and direction
+    return sur, b, flat, orders.cpu().numpy(), gid.cpu().numpy(), T.cpu().numpy(), grad.cpu().numpy(), \
+        float(loss.cpu()[0])
+
+
+@pytest.mark.parametrize("groups,per", [(32, 64), (4, 64), (96, 64)])
+def test_gradients_stage_by_stage(dev, groups, per):
+    """Every stage of the device's forward and backward pass, element by
+    element, against the oracle's definition of that stage on the device's
+    own stage inputs (bounds in tests/mlp_stage.py): features, h1, h2, h3,
+    scores, the three activation gradients, every weight and bias gradient
+    and the loss.  Batches of 256 (8 row blocks), 2,048 and 6,144 rows."""
+    import mlp_stage as S
+    sur, b, flat, on, og, Tn, grad, loss = _grad_case(dev, groups, per, 302, 13, 2)
+    rows = len(og)
+    P = mlp.unflatten(flat)
+    W1, b1 = mlp.round_bf16(P[0][0]), P[0][1]
+    W2, b2 = mlp.round_bf16(P[1][0]), P[1][1]
+    W3, b3 = mlp.round_bf16(P[2][0]), P[2][1]
+    w4, b4 = P[3][0][0], P[3][1][0]
+    X = sur.batch_values(sur.BATCH_FEATURES, rows)
+    H1 = sur.batch_values(sur.BATCH_H1, rows)
+    H2 = sur.batch_values(sur.BATCH_H2, rows)
+    H3 = sur.batch_values(sur.BATCH_H3, rows)
+    sc = sur.batch_values(sur.BATCH_SCORE, rows).astype(np.float64)
+    G3 = sur.batch_values(sur.BATCH_G3, rows)
+    G2 = sur.batch_values(sur.BATCH_G2, rows)
+    G1 = sur.batch_values(sur.BATCH_G1, rows)
+    # features: one float32 then one bf16 rounding of the float64 value
+    Xo = oracle_features(b, on, og)
+    S.check("features", X, Xo, (S.U + 2 * S.F32) * np.abs(Xo))
+    # forward stages on the device's own inputs
+    e, sa = S.layer_stage(X, W1, b1, 48)
+    S.check("h1", H1, e, S.act_bound(e, sa, 48))
+    e, sa = S.layer_stage(H1, W2, b2, 256)
+    S.check("h2", H2, e, S.act_bound(e, sa, 256))
+    e, sa = S.layer_stage(H2, W3, b3, 256)
+    S.check("h3", H3, e, S.act_bound(e, sa, 256))
+    e = H3 @ w4 + b4
+    S.check("score", sc, e, S.sum_bound(np.abs(H3) @ np.abs(w4) + abs(b4), 256))
+    # loss gradient on the device's scores; targets y = T / LB - 1 (float32 on the device)
+    y = np.array([mlp.target(b.group(g), t) for g, t in zip(og, Tn)])
+    ds = 2.0 * (sc - y) / rows
+    dds = 2.0 / rows * 6 * S.F32 * (np.abs(sc) + np.abs(y))
+    e = (H3 > 0) * (ds[:, None] * w4[None, :])
+    S.check("G3", G3, e, (S.U + 2 * S.F32) * np.abs(e) + (H3 > 0) * (dds[:, None] * np.abs(w4)[None, :]) * (1 + S.U)
+            + 1e-45)
+    e, sa = S.back_stage(G3, W3, H2 > 0)
+    S.check("G2", G2, e, S.act_bound(e, sa, 256))
+    e, sa = S.back_stage(G2, W2, H1 > 0)
+    S.check("G1", G1, e, S.act_bound(e, sa, 256))
+    # gradients: float32 sums over the batch of the device's stored values
+    want, bnd = [], []
+    for G, A in ((G1, X), (G2, H1), (G3, H2)):
+        e, sa = S.wgrad_stage(G, A)
+        want.append((e, G.sum(axis=0)))
+        bnd.append((S.sum_bound(sa, rows), S.sum_bound(np.abs(G).sum(axis=0), rows)))
+    e4 = (ds[:, None] * H3).sum(axis=0)
+    bnd4 = S.sum_bound(np.abs(ds) @ np.abs(H3), rows) + dds @ np.abs(H3)
+    want.append((e4[None, :], np.array([ds.sum()])))
+    bnd.append((bnd4[None, :], np.array([S.sum_bound(np.abs(ds).sum(), rows) + dds.sum()])))
+    S.check("gradient", grad, mlp.flatten(want), mlp.flatten(bnd))
+    lo = np.mean((sc - y) ** 2)
+    assert abs(loss - lo) <= S.sum_bound(np.sum((sc - y) ** 2) / rows, rows) + 8 * S.F32 * lo + 1e-12
+    # and, as a whole, the device gradient follows the float64 network (no
+    # bf16 anywhere but the weights and inputs): direction and size per block
+    params = [(mlp.round_bf16(Wt), bb) for Wt, bb in P]
+    params[-1] = P[-1]
+    full = mlp.flatten(mlp.backward(params, mlp.round_bf16(Xo), y, round_hidden=mlp.round_bf16))
     off = 0
     for fi, fo in zip(mlp.LAYERS[:-1], mlp.LAYERS[1:]):
         for size in (fo * fi, fo):
-            a, w = grad[off:off + size], want[off:off + size]
+            a, wv = grad[off:off + size].astype(np.float64), full[off:off + size]
             off += size
-            rel = np.linalg.norm(a - w) / max(np.linalg.norm(w), 1e-12)
-            cos = float(a @ w) / max(np.linalg.norm(a) * np.linalg.norm(w), 1e-30)
+            rel = np.linalg.norm(a - wv) / max(np.linalg.norm(wv), 1e-12)
+            cos = float(a @ wv) / max(np.linalg.norm(a) * np.linalg.norm(wv), 1e-30)
             assert rel < 0.05 and cos > 0.998, (fi, fo, size, rel, cos)
     sur.close()
+
+
+def test_adam_step_against_oracle(dev):
+    """tgo_surrogate_adam_step against the oracle's Adam (float64) from the
+    device's own previous state, three steps, element by element: m and v
+    within 2^-22 of their terms, the parameters within 2^-23 of themselves
+    plus 2^-20 of the update (float32 evaluation of the same formula)."""
+    import torch
+    from paper_1806_10113_amd import tgo
+    sur = tgo.Surrogate(max_rows=1024, max_groups=16)
+    flat = setup_net(3)
+    sur.set_params(flat)
+    rng = np.random.default_rng(5)
+    N = tgo.SURROGATE_PARAMS
+    p_prev = sur.get_params().astype(np.float64)
+    m_prev, v_prev, t0 = sur.moments()
+    assert t0 == 0 and not m_prev.any() and not v_prev.any()
+    m_prev, v_prev = m_prev.astype(np.float64), v_prev.astype(np.float64)
+    for t, lr in ((1, 1e-3), (2, 3e-4), (3, 1e-3)):
+        g = (rng.normal(size=N) * 10.0 ** rng.uniform(-6, 0, size=N)).astype(np.float32)
+        g[::97] = 0.0
+        sur.adam_step(torch.as_tensor(g).to(dev), lr)
+        p_dev = sur.get_params().astype(np.float64)
+        m_dev, v_dev, step = sur.moments()
+        assert step == t
+        lr32 = float(np.float32(lr))
+        p_or, m_or, v_or = mlp.adam_step(p_prev, g.astype(np.float64), m_prev, v_prev, t, lr32)
+        assert (np.abs(m_dev - m_or) <= 2.0 ** -22 * (0.9 * np.abs(m_prev) + 0.1 * np.abs(g)) + 1e-45).all()
+        assert (np.abs(v_dev - v_or) <= 2.0 ** -22 * (0.999 * v_prev + 0.001 * g.astype(np.float64) ** 2)
+                + 1e-45).all()
+        upd = np.abs(p_or - p_prev)
+        assert (np.abs(p_dev - p_or) <= 2.0 ** -23 * np.abs(p_or) + 2.0 ** -20 * upd + 1e-45).all()
+        # the first step moves every parameter with a nonzero gradient by lr (Adam's closed form)
+        if t == 1:
+            nz = g != 0
+            assert np.allclose(upd[nz], lr32 * np.abs(g[nz]) / (np.abs(g[nz]) + 1e-8), rtol=1e-5)
+            assert (p_dev[~nz] == p_prev[~nz]).all()
+        p_prev, m_prev, v_prev = p_dev, m_dev.astype(np.float64), v_dev.astype(np.float64)
+    sur.close()
+
+
+def test_train_step_is_grad_then_adam(dev):
+    """train_step on a batch gives bit for bit the parameters of grad() on the
+    same batch followed by adam_step with that gradient."""
+    from paper_1806_10113_amd import tgo
+    b = W.batch_groups(24, 8, 16, seed=310, per_task_label=True)
+    tasks, offs = to_dev(b.tasks, dev), to_dev(b.offs, dev)
+    orders, gid, T, _ = tgo.pairs(tasks, offs, 128, seed=15)
+    flat = setup_net(4)
+    a = tgo.Surrogate(max_rows=4096, max_groups=64)
+    c = tgo.Surrogate(max_rows=4096, max_groups=64)
+    a.set_params(flat)
+    c.set_params(flat)
+    for step in range(3):
+        la = a.train_step(tasks, offs, orders, gid, T, lr=1e-3)
+        g, lc = c.grad(tasks, offs, orders, gid, T)
+        c.adam_step(g, 1e-3)
+        assert float(la.cpu()[0]) == float(lc.cpu()[0])
+        assert np.array_equal(a.get_params(), c.get_params()), step
+    a.close()
+    c.close()
 
 
 def trained(dev, steps=600, seed=5, groups=256):

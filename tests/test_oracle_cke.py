@@ -136,3 +136,20 @@ def test_argument_checks():
         cke.simulate([(1, 1, 1)], [3], 2, [0])
     with pytest.raises(ValueError):
         cke.simulate([(1, 1, 1)], [1, 1], 2, [0])
+
+
+def test_c_transcription_matches():
+    from oracle import cmodel
+    cmodel.build()
+    rng = np.random.default_rng(36)
+    for m in MODELS:
+        for _ in range(30):
+            n = int(rng.integers(1, 7))
+            tasks = rand_group(rng, n)
+            C = int(rng.integers(1, 9))
+            units = [int(v) for v in rng.integers(1, C + 1, size=n)]
+            order = list(rng.permutation(n))
+            assert cmodel.cke_simulate(tasks, units, C, order, m) == cke.simulate(tasks, units, C, order, m)
+        tasks = rand_group(rng, 5, 0, 30)
+        units = [1, 2, 3, 2, 1]
+        assert list(cmodel.cke_times(tasks, units, 3, m)) == cke.all_times(tasks, units, 3, m)

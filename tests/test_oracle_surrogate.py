@@ -2,9 +2,11 @@
 the ordering sampler, the float64 network (finite differences, hand cases),
 Adam's first step in closed form, and the target's lower bound."""
 import itertools
+import os
 import math
 
 import numpy as np
+import pytest
 
 from oracle import mlp
 from oracle import model as M
@@ -129,3 +131,43 @@ def test_bf16_rounding():
     # 8 significant bits: 1 + 2^-8 is a tie -> even (1.0); 1 + 3*2^-8 -> 1 + 2^-6;
     # 1 + 2^-9 rounds down
     assert list(out) == [1.0, 1.0, 1.0 + 2 ** -6, -2.5, 1.0]
+
+
+def test_stage_bounds_catch_planted_mistakes():
+    """The stage bounds of the GPU gradient test have teeth: a weight
+    gradient missing one 64-row tile of a 2,048-row batch, a transposed
+    operand, a dropped mask, a bias left out and a one-position shift of the
+    features are each far outside them (mistakes planted in the oracle's own
+    stage values; the unaltered values, rounded to bf16 where the device
+    rounds, pass)."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import mlp_stage as S
+    rng = np.random.default_rng(7)
+    params = mlp.init_params(rng)
+    W1, b1 = mlp.round_bf16(params[0][0]), rng.normal(size=256) * 0.1
+    W2 = mlp.round_bf16(params[1][0])
+    rows = 2048
+    X = mlp.round_bf16(rng.uniform(0, 1, size=(rows, 48)))
+    e, sa = S.layer_stage(X, W1, b1, 48)
+    H1 = mlp.round_bf16(e)
+    S.check("h1", H1, e, S.act_bound(e, sa, 48))
+    with pytest.raises(AssertionError):
+        S.check("h1 without bias", mlp.round_bf16(np.maximum(X @ W1.T, 0)), e, S.act_bound(e, sa, 48))
+    Xs = np.roll(X, 3, axis=1)
+    with pytest.raises(AssertionError):
+        e2, sa2 = S.layer_stage(Xs, W1, b1, 48)
+        S.check("h1 shifted features", mlp.round_bf16(e2), e, S.act_bound(e, sa, 48))
+    G2 = mlp.round_bf16(rng.normal(size=(rows, 256)) * 1e-3 * (rng.uniform(size=(rows, 256)) > 0.5))
+    e, sa = S.back_stage(G2, W2, H1 > 0)
+    S.check("G1", mlp.round_bf16(e), e, S.act_bound(e, sa, 256))
+    with pytest.raises(AssertionError):
+        S.check("G1 without mask", mlp.round_bf16(G2 @ W2), e, S.act_bound(e, sa, 256))
+    with pytest.raises(AssertionError):
+        S.check("G1 transposed weights", mlp.round_bf16((G2 @ W2.T) * (H1 > 0)), e, S.act_bound(e, sa, 256))
+    G1 = mlp.round_bf16(e)
+    e, sa = S.wgrad_stage(G1, X)
+    S.check("dW1", e.astype(np.float32), e, S.sum_bound(sa, rows))
+    dropped = G1[64:].T @ X[64:]
+    with pytest.raises(AssertionError):
+        S.check("dW1 without the first row tile", dropped, e, S.sum_bound(sa, rows))
