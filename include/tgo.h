@@ -36,7 +36,7 @@
  *   - Functions are reentrant; a handle (plan, surrogate, server) must not be
  *     used from two threads at once.
  *   - Scratch memory: tgo_exhaustive, tgo_exhaustive_mem, tgo_rounds,
- *     tgo_random_search and tgo_valu_probe use device scratch owned by the
+ *     tgo_random_search and tgo_surrogate_pairs use device scratch owned by the
  *     library, one buffer per (device, stream), grown on demand (a growth
  *     waits for that stream's earlier work and allocates) and kept until the
  *     process ends.  Calls on different streams may therefore overlap; calls
@@ -107,6 +107,10 @@ typedef struct {
     int64_t heur_ns;                   /*  0xff / -1 when not computed)           */
 } tgo_summary;
 
+/* Error reporting for every call below (no passage of the paper: library
+ * plumbing).  tgo_strerror: a static text for a TGO_E* code.  tgo_last_error:
+ * the detail of the last failing call on this thread (valid until the next
+ * call on the thread).  tgo_version: the ABI version, 1. */
 const char *tgo_strerror(int code);
 const char *tgo_last_error(void);
 int tgo_version(void);
@@ -190,8 +194,14 @@ int tgo_heuristic(const tgo_model *model, const tgo_task *d_tasks, const int32_t
  * The paper's runtime reorders the task group that its proxy thread finds
  * waiting (Section 6.2); a batch holds many such groups.
  *
- * tgo_plan_create  -- device workspace for up to max_groups groups (allocated
- *                     here, freed by tgo_plan_destroy) and a capture stream.
+ * tgo_plan_create  -- device workspace for up to max_groups groups of at most
+ *                     max_n (1..12) tasks (allocated here, freed by
+ *                     tgo_plan_destroy) and a capture stream.  mem_budget (0:
+ *                     the default of 64 MiB beyond the per-group records)
+ *                     bounds the plan's device memory: it sets how many
+ *                     tiles a group on the 64-bit time path is split into;
+ *                     TGO_ENOMEM if even one per group does not fit.  Groups
+ *                     larger than max_n get status TGO_EINVAL.
  * tgo_plan_autotune-- times candidate work decompositions (positions
  *                     enumerated per lane by group size, subtrees per lane per
  *                     tile, persistent grid size) on the given batch and keeps
@@ -200,15 +210,16 @@ int tgo_heuristic(const tgo_model *model, const tgo_task *d_tasks, const int32_t
  * tgo_batch        -- for every group g of the CSR batch (tasks
  *                     d_tasks[d_offs[g] .. d_offs[g+1])), writes d_out[g]: the
  *                     full-enumeration summary plus the heuristic ordering
- *                     (heur, heur_ns).  Group sizes 1..12; a group whose
- *                     predicted times could reach 2^31 ns gets status
- *                     TGO_ERANGE (use tgo_exhaustive for it).  The launch
+ *                     (heur, heur_ns).  Group sizes 1..12.  Groups whose
+ *                     times could reach 2^31 ns are enumerated with 64-bit
+ *                     time in the same launch sequence (a second persistent
+ *                     kernel, per-tile partial summaries).  The launch
  *                     sequence is captured once into a HIP graph and replayed
  *                     while (d_tasks, d_offs, n_groups, d_out) stay the same.
  *                     Calls on one plan must not overlap on different streams.
  */
 typedef struct tgo_plan tgo_plan;
-int tgo_plan_create(const tgo_model *model, int max_groups, tgo_plan **out);
+int tgo_plan_create(const tgo_model *model, int max_groups, int max_n, size_t mem_budget, tgo_plan **out);
 int tgo_plan_autotune(tgo_plan *plan, const tgo_task *d_tasks, const int32_t *d_offs, int n_groups,
                       tgo_summary *d_out, tgo_stream stream);
 int tgo_plan_describe(const tgo_plan *plan, char *buf, size_t len);
@@ -236,9 +247,10 @@ void tgo_plan_destroy(tgo_plan *plan);
  * hi32(x (i + 1)) and keeping x = lo32(x (i + 1)), x reloaded from the next
  * word every four draws.
  *
- * Search and pair generation use the 32-bit time path: a group whose times
- * could reach 2^31 ns gets status TGO_ERANGE.  All buffers below are device
- * memory; the surrogate owns max_rows rows of activations.
+ * Search and pair generation evaluate orderings exactly with 32-bit time
+ * where a group's times stay below 2^31 ns and with 64-bit time otherwise
+ * (durations must lie in [0, 2^40): TGO_ERANGE outside).  All buffers below
+ * are device memory; the surrogate owns max_rows rows of activations.
  */
 #define TGO_SURROGATE_PARAMS 144385
 
@@ -331,18 +343,25 @@ int tgo_random_search(const tgo_model *model, const tgo_task *d_tasks, const int
 /* ---------------------------------------------------------------------------
  * Serving: a continuous-batching request loop.  The paper's proxy thread polls
  * a buffer of offloaded tasks, forms a task group, reorders and submits it
- * (Section 6.2); here requests (one task group each) arrive at any time and a
- * scheduler thread keeps up to `streams` batches in flight on their own HIP
- * streams.  A free stream takes the waiting requests of one size class, oldest
- * first, as far as the device-memory budget allows; requests that arrive
- * while others run are admitted as soon as a stream and memory free up.
+ * (Section 6.2); here requests (one task group each) arrive at any time.  The
+ * task tables of admitted requests wait on the device, in one ring of task
+ * rows per size class; a request is admitted when its rows fit in its ring,
+ * and the rings get what the memory budget leaves after the server's own
+ * device memory (plans, network workspaces, result buffers), so admission is
+ * by memory and the device memory the server holds never exceeds
+ * budget_bytes (tgo_server_create fails with TGO_ENOMEM if the budget cannot
+ * hold one request per class).  A scheduler thread keeps up to `streams`
+ * batches in flight on their own HIP streams: a free stream takes the oldest
+ * admitted requests of one size class and launches them straight from the
+ * ring; requests that arrive while others run are admitted as soon as rows
+ * free up, and launched as soon as a stream does.
  * Groups with n <= small_max_n are enumerated in full (tgo_batch; answer =
  * the best ordering, with the heuristic's time beside it); larger groups use
  * the learned proposal (tgo_surrogate_search with the request's key as its
  * sampling key, so a request's answer is the same alone and in any mix).
  */
 typedef struct {
-    int64_t budget_bytes;   /* device memory that admitted requests may hold   */
+    int64_t budget_bytes;   /* device memory the server may hold in all         */
     int32_t streams;        /* batches in flight (1..8)                        */
     int32_t max_batch;      /* groups per exhaustive batch (1..4096)           */
     int32_t max_batch_large;/* groups per surrogate batch (1..4096)            */
@@ -365,7 +384,12 @@ typedef struct {
 
 typedef struct {
     uint64_t submitted, completed, batches, rejected;
-    int64_t in_use_bytes, max_in_use_bytes, queued, max_queued;
+    int64_t in_use_bytes, max_in_use_bytes;  /* device memory held: base + ring rows */
+    int64_t queued, max_queued;              /* requests not yet launched            */
+    int64_t base_bytes;                      /* the server's own buffers, plans,
+                                                network workspaces                  */
+    int64_t ring_rows[2];                    /* queue capacity (task rows) per class */
+    int64_t budget_bytes;
 } tgo_server_stats;
 
 typedef struct tgo_server tgo_server;
@@ -566,12 +590,6 @@ int tgo_hw_run_proxy(tgo_hw *hw, const tgo_model *model, const tgo_hw_task *h_ta
  * Section 4.2.1.  h_times[4] = HtD start, HtD end, DtH start, DtH end (ns).
  * Blocking. */
 int tgo_hw_overlap(tgo_hw *hw, int64_t htd_bytes, int64_t dth_bytes, int64_t dth_delay_ns, int64_t *h_times);
-/* Integer issue probe for the ALU roofline: `blocks` blocks of 256 threads,
- * each thread running eight independent chains of 32-bit shift-and-add for
- * iters x 16 steps (2 VALU instructions per step and chain, no memory
- * traffic).  Its counter run gives the 32-bit VALU instructions a CU issues
- * per clock.  Enqueued on `stream`. */
-int tgo_valu_probe(int blocks, int iters, tgo_stream stream);
 /* Least-squares line y = slope * x + intercept over n >= 2 points (host); the
  * kernel model T = eta * m + gamma of Eq. 1, and transfer time against size. */
 int tgo_fit_line(const double *h_x, const double *h_y, int n, double *slope, double *intercept);
@@ -583,7 +601,11 @@ int tgo_fit_line(const double *h_x, const double *h_y, int n, double *slope, dou
  * without overlap are skipped (TGO_EINVAL if none overlaps). */
 int tgo_fit_overlap(const int64_t *h_times, const int64_t *h_solo, int n, double *rho_htd, double *rho_dth);
 
-/* Host helpers: lexicographic rank <-> ordering (index arithmetic only). */
+/* Host helpers for the search space of Section 1 (the n! launch orderings of a
+ * group, which every enumeration call ranks lexicographically, rank 0 = the
+ * identity): tgo_rank gives the rank of a permutation h_order of 0..n-1
+ * (TGO_EINVAL if it is not one, n outside 1..16), tgo_unrank the ordering of
+ * a rank (TGO_ERANGE for rank >= n!).  Index arithmetic only, no device. */
 int tgo_rank(int n, const uint8_t *h_order, uint64_t *rank);
 int tgo_unrank(int n, uint64_t rank, uint8_t *h_order);
 

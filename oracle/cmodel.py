@@ -14,7 +14,9 @@ from .model import Model, DEFAULT
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "tgo_oracle.c")
-LIB = os.path.join(HERE, "libtgo_oracle.so")
+# TGO_ORACLE_LIB names another build of the same source (the sanitizer test
+# loads an AddressSanitizer / UBSan build this way); it is used as it is.
+LIB = os.environ.get("TGO_ORACLE_LIB") or os.path.join(HERE, "libtgo_oracle.so")
 
 
 class OracleSummary(ctypes.Structure):
@@ -38,7 +40,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if not os.environ.get("TGO_ORACLE_LIB") and (
+                not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC)):
             build()
         L = ctypes.CDLL(LIB)
         L.oracle_simulate.restype = ctypes.c_int64

@@ -40,26 +40,6 @@ __global__ __launch_bounds__(256) void tgo_hw_fma_kernel(float *x, int64_t n, in
     }
 }
 
-// Integer issue probe: eight independent shift-and-add chains per lane, no
-// memory traffic; the counter run of it shows how many 32-bit VALU
-// instructions a CU issues per clock.
-__global__ __launch_bounds__(256) void tgo_valu_probe_kernel(uint32_t *out, int iters, uint32_t s) {
-    uint32_t a[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) a[j] = threadIdx.x ^ (uint32_t)j;
-    for (int i = 0; i < iters; ++i) {
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) a[j] = (a[j] >> 1) + s;
-        s = s * 3u + 1u;
-    }
-    uint32_t r = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) r += a[j];
-    if (r == 0x9e3779b9u) out[0] = r;  // practically never: keeps the chains live
-}
-
 // One thread waits until `ticks` of the constant-rate wall clock have passed
 // (bounded by max_polls reads of the clock).
 __global__ void tgo_hw_delay_kernel(int64_t ticks, int64_t max_polls) {
@@ -568,17 +548,6 @@ int tgo_hw_overlap(tgo_hw *hw, int64_t htd_bytes, int64_t dth_bytes, int64_t dth
     h_times[1] = ns_between(hw->t0, hw->ev[1]);
     h_times[2] = ns_between(hw->t0, hw->ev[4]);
     h_times[3] = ns_between(hw->t0, hw->ev[5]);
-    return TGO_OK;
-}
-
-int tgo_valu_probe(int blocks, int iters, tgo_stream stream) {
-    if (blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 20))
-        return fail(TGO_EINVAL, "blocks and iters must be in 1..2^20");
-    uint32_t *sink = nullptr;
-    int rc = workspace(256, (void **)&sink, (hipStream_t)stream);
-    if (rc) return rc;
-    hipLaunchKernelGGL(tgo_valu_probe_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, sink, iters, 7u);
-    TGO_HIP(hipGetLastError());
     return TGO_OK;
 }
 

@@ -2,17 +2,26 @@
 //
 // The paper's runtime has a host proxy thread that polls a buffer of
 // offloaded tasks, forms the task group, reorders it with the heuristic and
-// submits it (Section 6.2).  Here many such groups arrive as requests.  A
-// scheduler thread keeps up to `streams` batches in flight, each on its own
-// HIP stream: whenever a stream is free it takes the waiting requests of one
-// size class that fit the device-memory budget, copies their task tables into
-// the stream's device-resident queue buffers and launches the batch; finished
-// batches are retired by polling their events, which frees their slots and
-// memory for requests that arrived meanwhile.  Small groups (n <= small_max_n)
-// are enumerated exhaustively with a fixed-shape batch (graph replay); larger
-// groups go through the learned proposal, keyed by the request's key (its id
-// unless the caller gives one) so that a request's answer does not depend on
-// what it was batched with.
+// submits it (Section 6.2).  Here many such groups arrive as requests, and the
+// waiting groups live on the device:
+//   * two device-resident queues, one per size class (n <= small_max_n:
+//     enumerated in full; larger: the learned proposal), each a ring of task
+//     rows in HBM.  A request is admitted when its rows fit in its ring; the
+//     rings are sized so that the server's own device memory (batch plans,
+//     network workspaces, result buffers) plus both rings stay within the
+//     memory budget, so admission is by memory.  Admitted rows are copied to
+//     the ring by an upload stream;
+//   * a scheduler thread keeps up to `streams` batches in flight, each on a
+//     HIP stream of its own: a free stream takes the oldest admitted requests
+//     of one class that lie back to back in their ring (up to the class's
+//     batch size) and launches the batch straight from the ring (the batch
+//     kernels read the ring through per-group row offsets), after the uploads
+//     it depends on; finished batches are retired by polling their events,
+//     which frees their ring rows for requests that arrived meanwhile.
+// Small groups run a fixed-shape batch (padded with empty groups, so its
+// captured graph is replayed); large groups are sampled with the request's
+// key (its id unless the caller gives one), so a request's answer does not
+// depend on what it was batched with.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,26 +50,36 @@ struct Request {
     uint64_t id = 0;
     uint32_t key = 0;
     int n = 0;
+    int cls = 0;           // 0 = full enumeration, 1 = learned proposal
     tgo_task tasks[TGO_MAX_N];
     int64_t t_arrive = 0, t_admit = 0;
-    size_t bytes = 0;
+    int64_t pos = 0;       // ring position of its first row (monotonic)
+    bool launched = false, done = false;
+};
+
+// Device-resident queue of one size class: task rows of admitted requests.
+// Positions grow monotonically; row p lives at p % cap.  A request never wraps
+// (if it does not fit before the end, the rows up to the end are skipped and
+// count as held until the ring's head passes them).
+struct Ring {
+    tgo_task *d = nullptr;   // device rows
+    tgo_task *h = nullptr;   // pinned staging mirror
+    int64_t cap = 0;         // rows
+    int64_t head = 0, tail = 0;
+    std::deque<Request *> q;  // admitted requests in ring order
 };
 
 struct StreamSlot {
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
     bool busy = false;
-    int kind = 0;  // 0 = exhaustive batch, 1 = surrogate search
-    std::vector<Request> reqs;
+    int kind = 0;
+    std::vector<Request *> reqs;
     tgo_plan *plan = nullptr;
     tgo_surrogate *sur = nullptr;
-    // device queue buffers
-    tgo_task *d_tasks = nullptr;
     int32_t *d_offs = nullptr;
     uint32_t *d_keys = nullptr;
     unsigned char *d_out = nullptr;
-    // pinned host mirrors
-    tgo_task *h_tasks = nullptr;
     int32_t *h_offs = nullptr;
     uint32_t *h_keys = nullptr;
     unsigned char *h_out = nullptr;
@@ -73,17 +92,21 @@ struct tgo_server {
     tgo_server_config cfg;
     int device = 0;
     std::vector<StreamSlot> slots;
+    Ring ring[2];
+    hipStream_t up = nullptr;     // uploads into the rings
+    hipEvent_t up_ev = nullptr;   // after the last upload
+    bool up_pending = false;
     std::mutex mu;
     std::condition_variable cv;
-    std::deque<Request> pending[2];
+    std::deque<Request *> arrivals[2];  // submitted, not yet admitted
     std::vector<tgo_server_result> done;
     std::thread worker;
     bool stop = false;
-    int64_t in_use = 0;
+    int64_t base_bytes = 0;       // device memory the server holds for itself
+    int64_t in_use = 0, max_in_use = 0;
     uint64_t next_id = 1;
     uint64_t submitted = 0, completed = 0, batches = 0, rejected = 0;
-    int64_t max_in_use = 0;
-    int max_queue = 0;
+    int64_t max_queue = 0;
     std::string error;
     // Test hook, set from TGO_SERVER_INJECT_QUERY_ERROR=k at creation: the
     // k-th completion query of a busy slot is treated as a device error
@@ -93,13 +116,119 @@ struct tgo_server {
 
 namespace tgo {
 
-static size_t request_bytes(const tgo_server_config &c, int n) {
-    // what a request holds in the stream queue buffers while in flight
-    const bool small = n <= c.small_max_n;
-    size_t b = sizeof(tgo_task) * TGO_MAX_N + sizeof(int32_t) + sizeof(uint32_t);
-    b += small ? sizeof(tgo_summary) : sizeof(tgo_search_result);
-    if (!small) b += (size_t)((c.samples + 1023) / 1024) * 64 * 8 * 2;  // candidate keys
-    return b;
+constexpr int64_t RING_MAX_ROWS = int64_t(1) << 22;  // 96 MiB of rows per class at most
+
+static size_t result_bytes(int kind) { return kind == 0 ? sizeof(tgo_summary) : sizeof(tgo_search_result); }
+
+static int64_t ring_held(const Ring &r) { return r.tail - r.head; }
+
+// Bytes of device memory held now: the server's own, plus the ring rows held.
+static int64_t held_bytes(const tgo_server *S) {
+    return S->base_bytes + (int64_t)sizeof(tgo_task) * (ring_held(S->ring[0]) + ring_held(S->ring[1]));
+}
+
+// Admit arrivals whose rows fit in their ring (called with the lock held).
+static int admit(tgo_server *S) {
+    for (int c = 0; c < 2; ++c) {
+        Ring &R = S->ring[c];
+        int64_t first = -1, last = -1;  // physical rows to upload, [first, last)
+        auto flush = [&]() -> int {
+            if (first < 0) return 0;
+            TGO_HIP(hipMemcpyAsync(R.d + first, R.h + first, sizeof(tgo_task) * (size_t)(last - first),
+                                   hipMemcpyHostToDevice, S->up));
+            S->up_pending = true;
+            first = last = -1;
+            return 0;
+        };
+        while (!S->arrivals[c].empty()) {
+            Request *q = S->arrivals[c].front();
+            int64_t pos = R.tail;
+            const int64_t off = pos % R.cap;
+            if (off + q->n > R.cap) pos += R.cap - off;  // skip to the start of the ring
+            if (pos + q->n - R.head > R.cap) break;     // no room: wait for memory
+            if (pos != R.tail) {
+                const int rc = flush();
+                if (rc) return rc;
+            }
+            const int64_t phys = pos % R.cap;
+            std::memcpy(R.h + phys, q->tasks, sizeof(tgo_task) * (size_t)q->n);
+            if (first < 0) first = phys;
+            last = phys + q->n;
+            q->pos = pos;
+            q->t_admit = now_ns();
+            R.tail = pos + q->n;
+            R.q.push_back(q);
+            S->arrivals[c].pop_front();
+        }
+        const int rc = flush();
+        if (rc) return rc;
+    }
+    if (S->up_pending) {
+        TGO_HIP(hipEventRecord(S->up_ev, S->up));
+        S->up_pending = false;
+    }
+    S->in_use = held_bytes(S);
+    S->max_in_use = std::max(S->max_in_use, S->in_use);
+    return 0;
+}
+
+// Launch the oldest admitted, unlaunched requests of class `kind` that lie
+// back to back in the ring, on slot sl (called with the lock held).
+static int launch(tgo_server *S, StreamSlot &sl, int kind) {
+    const tgo_server_config &c = S->cfg;
+    Ring &R = S->ring[kind];
+    const int cap = kind == 0 ? c.max_batch : c.max_batch_large;
+    sl.reqs.clear();
+    int64_t expect = -1;
+    for (Request *q : R.q) {
+        if (q->launched) continue;
+        if ((int)sl.reqs.size() >= cap) break;
+        const int64_t phys = q->pos % R.cap;
+        if (expect >= 0 && phys != expect) break;  // wrapped: the next batch takes it
+        sl.reqs.push_back(q);
+        expect = phys + q->n;
+    }
+    if (sl.reqs.empty()) return 0;
+    for (Request *q : sl.reqs) q->launched = true;
+    // row offsets into the ring; the exhaustive batch is padded with empty
+    // groups to its fixed shape so that its captured graph is replayed
+    const int ng = kind == 0 ? c.max_batch : (int)sl.reqs.size();
+    int32_t off = (int32_t)(sl.reqs[0]->pos % R.cap);
+    for (int g = 0; g < ng; ++g) {
+        sl.h_offs[g] = off;
+        if (g < (int)sl.reqs.size()) {
+            off += sl.reqs[g]->n;
+            sl.h_keys[g] = sl.reqs[g]->key;
+        } else {
+            sl.h_keys[g] = 0;
+        }
+    }
+    sl.h_offs[ng] = off;
+    sl.kind = kind;
+    hipStream_t st = sl.st;
+    TGO_HIP(hipStreamWaitEvent(st, S->up_ev, 0));
+    TGO_HIP(hipMemcpyAsync(sl.d_offs, sl.h_offs, sizeof(int32_t) * (ng + 1), hipMemcpyHostToDevice, st));
+    int rc;
+    if (kind == 0) {
+        rc = tgo_batch(sl.plan, R.d, sl.d_offs, ng, (tgo_summary *)sl.d_out, st);
+    } else {
+        TGO_HIP(hipMemcpyAsync(sl.d_keys, sl.h_keys, sizeof(uint32_t) * ng, hipMemcpyHostToDevice, st));
+        rc = tgo_surrogate_search(sl.sur, &S->model, R.d, sl.d_offs, sl.d_keys, ng, c.samples, c.topk, c.seed,
+                                  (tgo_search_result *)sl.d_out, st);
+    }
+    if (rc) return rc;
+    TGO_HIP(hipMemcpyAsync(sl.h_out, sl.d_out, result_bytes(kind) * sl.reqs.size(), hipMemcpyDeviceToHost, st));
+    TGO_HIP(hipEventRecord(sl.ev, st));
+    sl.busy = true;
+    S->batches += 1;
+    return 0;
+}
+
+// Requests submitted and not yet launched: submitted - completed - in flight.
+static int64_t queued_now(const tgo_server *S) {
+    int64_t inflight = 0;
+    for (const StreamSlot &sl : S->slots) inflight += sl.busy ? (int64_t)sl.reqs.size() : 0;
+    return (int64_t)(S->submitted - S->completed) - inflight;
 }
 
 static void fill_result(tgo_server_result &o, const Request &q, int kind, const unsigned char *raw, int64_t t_done) {
@@ -132,101 +261,60 @@ static void fill_result(tgo_server_result &o, const Request &q, int kind, const 
     }
 }
 
-// Launch one batch of `kind` on slot k from the pending queue (called with the lock held).
-static int launch(tgo_server *S, StreamSlot &sl, int kind) {
-    const tgo_server_config &c = S->cfg;
-    std::deque<Request> &q = S->pending[kind];
-    sl.reqs.clear();
-    const int cap = kind == 0 ? c.max_batch : c.max_batch_large;
-    while (!q.empty() && (int)sl.reqs.size() < cap) {
-        Request &r = q.front();
-        if (S->in_use + (int64_t)r.bytes > c.budget_bytes && !sl.reqs.empty()) break;
-        if (S->in_use + (int64_t)r.bytes > c.budget_bytes && S->in_use > 0) break;  // wait for memory
-        r.t_admit = now_ns();
-        S->in_use += (int64_t)r.bytes;
-        sl.reqs.push_back(r);
-        q.pop_front();
+// Requests done: free their ring rows from the head on (ring order).
+static void release(tgo_server *S, int kind) {
+    Ring &R = S->ring[kind];
+    while (!R.q.empty() && R.q.front()->done) {
+        Request *q = R.q.front();
+        R.q.pop_front();
+        R.head = R.q.empty() ? R.tail : R.q.front()->pos;
+        delete q;
     }
-    if (sl.reqs.empty()) return 0;
-    S->max_in_use = std::max(S->max_in_use, S->in_use);
-    // host staging: groups back to back; the exhaustive batch is padded with
-    // empty groups to its fixed shape so its captured graph is replayed
-    int off = 0;
-    sl.h_offs[0] = 0;
-    const int ng = kind == 0 ? c.max_batch : (int)sl.reqs.size();
-    for (int g = 0; g < ng; ++g) {
-        if (g < (int)sl.reqs.size()) {
-            const Request &r = sl.reqs[g];
-            std::memcpy(sl.h_tasks + off, r.tasks, sizeof(tgo_task) * r.n);
-            off += r.n;
-            sl.h_keys[g] = r.key;
-        } else {
-            sl.h_keys[g] = 0;
-        }
-        sl.h_offs[g + 1] = off;
-    }
-    sl.kind = kind;
-    hipStream_t st = sl.st;
-    TGO_HIP(hipMemcpyAsync(sl.d_tasks, sl.h_tasks, sizeof(tgo_task) * std::max(off, 1), hipMemcpyHostToDevice, st));
-    TGO_HIP(hipMemcpyAsync(sl.d_offs, sl.h_offs, sizeof(int32_t) * (ng + 1), hipMemcpyHostToDevice, st));
-    int rc;
-    size_t out_bytes;
-    if (kind == 0) {
-        rc = tgo_batch(sl.plan, sl.d_tasks, sl.d_offs, ng, (tgo_summary *)sl.d_out, st);
-        out_bytes = sizeof(tgo_summary) * sl.reqs.size();
-    } else {
-        TGO_HIP(hipMemcpyAsync(sl.d_keys, sl.h_keys, sizeof(uint32_t) * ng, hipMemcpyHostToDevice, st));
-        rc = tgo_surrogate_search(sl.sur, &S->model, sl.d_tasks, sl.d_offs, sl.d_keys, ng, c.samples, c.topk,
-                                  c.seed, (tgo_search_result *)sl.d_out, st);
-        out_bytes = sizeof(tgo_search_result) * sl.reqs.size();
-    }
-    if (rc) return rc;
-    TGO_HIP(hipMemcpyAsync(sl.h_out, sl.d_out, out_bytes, hipMemcpyDeviceToHost, st));
-    TGO_HIP(hipEventRecord(sl.ev, st));
-    sl.busy = true;
-    S->batches += 1;
-    return 0;
+    S->in_use = held_bytes(S);
 }
 
 static void retire(tgo_server *S, StreamSlot &sl) {
     const int64_t t = now_ns();
-    const size_t rb = sl.kind == 0 ? sizeof(tgo_summary) : sizeof(tgo_search_result);
+    const size_t rb = result_bytes(sl.kind);
     for (size_t i = 0; i < sl.reqs.size(); ++i) {
         tgo_server_result o;
-        fill_result(o, sl.reqs[i], sl.kind, sl.h_out + i * rb, t);
+        fill_result(o, *sl.reqs[i], sl.kind, sl.h_out + i * rb, t);
         S->done.push_back(o);
-        S->in_use -= (int64_t)sl.reqs[i].bytes;
+        sl.reqs[i]->done = true;
     }
     S->completed += sl.reqs.size();
     sl.reqs.clear();
     sl.busy = false;
+    release(S, sl.kind);
 }
 
-// A batch whose completion query reports a device error: its requests are
-// returned with status TGO_EDEVICE, their memory released, the slot freed and
-// the server stopped (a device error is sticky; nothing more is launched).
+// A batch whose completion query reports a device error, or that could not be
+// launched: its requests come back with status TGO_EDEVICE, their rows are
+// released, the slot is freed and the server stops (a device error is sticky;
+// nothing more is launched).
 static void fail_slot(tgo_server *S, StreamSlot &sl, const std::string &why) {
     const int64_t t = now_ns();
     if (S->error.empty()) S->error = why;
-    for (const Request &q : sl.reqs) {
+    for (Request *q : sl.reqs) {
         tgo_server_result o;
         std::memset(&o, 0, sizeof(o));
-        o.id = q.id;
-        o.n = q.n;
+        o.id = q->id;
+        o.n = q->n;
         o.path = sl.kind;
         o.status = TGO_EDEVICE;
-        o.t_arrive_ns = q.t_arrive;
-        o.t_admit_ns = q.t_admit;
+        o.t_arrive_ns = q->t_arrive;
+        o.t_admit_ns = q->t_admit;
         o.t_done_ns = t;
         o.best_ns = -1;
         o.heur_ns = -1;
         for (int i = 0; i < 16; ++i) o.best[i] = 0xff;
         S->done.push_back(o);
-        S->in_use -= (int64_t)q.bytes;
+        q->done = true;
     }
     S->completed += sl.reqs.size();
     sl.reqs.clear();
     sl.busy = false;
+    release(S, sl.kind);
     S->stop = true;
 }
 
@@ -247,25 +335,32 @@ static void worker_main(tgo_server *S) {
                 progressed = true;
             }
         }
+        if (!S->stop) {
+            if (admit(S)) {
+                S->error = std::string("admission failed: ") + tgo_last_error();
+                S->stop = true;
+            }
+        }
         for (StreamSlot &sl : S->slots) {
-            if (sl.busy) continue;
-            // the class whose oldest request has waited longest goes first
+            if (S->stop || sl.busy) continue;
+            // the class whose oldest unlaunched request arrived first goes first
             int kind = -1;
             int64_t oldest = INT64_MAX;
-            for (int k = 0; k < 2; ++k)
-                if (!S->pending[k].empty() && S->pending[k].front().t_arrive < oldest &&
-                    (k == 0 || sl.sur)) {
-                    oldest = S->pending[k].front().t_arrive;
-                    kind = k;
-                }
+            for (int k = 0; k < 2; ++k) {
+                if (k == 1 && !sl.sur) continue;
+                for (Request *q : S->ring[k].q)
+                    if (!q->launched) {
+                        if (q->t_arrive < oldest) { oldest = q->t_arrive; kind = k; }
+                        break;
+                    }
+            }
             if (kind < 0) break;
             const int rc = launch(S, sl, kind);
             if (rc) {
-                // the admitted requests come back failed; nothing more is launched
                 fail_slot(S, sl, std::string("launch failed: ") + tgo_last_error());
                 break;
             }
-            if (!sl.busy) break;  // nothing admissible right now
+            if (!sl.busy) break;
             progressed = true;
         }
         if (S->stop) {
@@ -289,6 +384,21 @@ static void worker_main(tgo_server *S) {
     S->cv.notify_all();
 }
 
+static void free_slot(StreamSlot &sl) {
+    if (sl.st) (void)hipStreamSynchronize(sl.st);
+    if (sl.plan) tgo_plan_destroy(sl.plan);
+    if (sl.sur) tgo_surrogate_destroy(sl.sur);
+    if (sl.d_offs) (void)hipFree(sl.d_offs);
+    if (sl.d_keys) (void)hipFree(sl.d_keys);
+    if (sl.d_out) (void)hipFree(sl.d_out);
+    if (sl.h_offs) (void)hipHostFree(sl.h_offs);
+    if (sl.h_keys) (void)hipHostFree(sl.h_keys);
+    if (sl.h_out) (void)hipHostFree(sl.h_out);
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+    if (sl.st) (void)hipStreamDestroy(sl.st);
+    sl = StreamSlot();
+}
+
 }  // namespace tgo
 
 using namespace tgo;
@@ -306,6 +416,30 @@ void tgo_server_config_default(tgo_server_config *c) {
     c->pad = 0;
     c->samples = 8192;
     c->seed = 4;
+}
+
+void tgo_server_destroy(tgo_server *S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        for (int c = 0; c < 2; ++c) {
+            for (Request *q : S->arrivals[c]) delete q;
+            S->arrivals[c].clear();
+        }
+    }
+    S->cv.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    for (StreamSlot &sl : S->slots) free_slot(sl);
+    if (S->up) (void)hipStreamSynchronize(S->up);
+    for (int c = 0; c < 2; ++c) {
+        for (Request *q : S->ring[c].q) delete q;
+        if (S->ring[c].d) (void)hipFree(S->ring[c].d);
+        if (S->ring[c].h) (void)hipHostFree(S->ring[c].h);
+    }
+    if (S->up_ev) (void)hipEventDestroy(S->up_ev);
+    if (S->up) (void)hipStreamDestroy(S->up);
+    delete S;
 }
 
 int tgo_server_create(const tgo_model *model, const tgo_server_config *cfg, tgo_surrogate *sur,
@@ -340,14 +474,13 @@ int tgo_server_create(const tgo_model *model, const tgo_server_config *cfg, tgo_
     }
     S->slots.resize(c.streams);
     const int gmax = std::max(c.max_batch, c.max_batch_large);
+    int64_t base = 0;
     for (StreamSlot &sl : S->slots) {
         hipError_t e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMalloc(&sl.d_tasks, sizeof(tgo_task) * TGO_MAX_N * gmax);
         if (e == hipSuccess) e = hipMalloc(&sl.d_offs, sizeof(int32_t) * (gmax + 1));
         if (e == hipSuccess) e = hipMalloc(&sl.d_keys, sizeof(uint32_t) * gmax);
         if (e == hipSuccess) e = hipMalloc(&sl.d_out, sizeof(tgo_summary) * gmax);
-        if (e == hipSuccess) e = hipHostMalloc(&sl.h_tasks, sizeof(tgo_task) * TGO_MAX_N * gmax);
         if (e == hipSuccess) e = hipHostMalloc(&sl.h_offs, sizeof(int32_t) * (gmax + 1));
         if (e == hipSuccess) e = hipHostMalloc(&sl.h_keys, sizeof(uint32_t) * gmax);
         if (e == hipSuccess) e = hipHostMalloc(&sl.h_out, sizeof(tgo_summary) * gmax);
@@ -355,18 +488,51 @@ int tgo_server_create(const tgo_model *model, const tgo_server_config *cfg, tgo_
             tgo_server_destroy(S);
             return hip_fail(e, "server slot");
         }
-        rc = tgo_plan_create(model, c.max_batch, &sl.plan);
+        base += (int64_t)(sizeof(int32_t) * (gmax + 1) + sizeof(uint32_t) * gmax + sizeof(tgo_summary) * gmax);
+        rc = tgo_plan_create(model, c.max_batch, c.small_max_n, 0, &sl.plan);
+        if (!rc) base += (int64_t)plan_device_bytes(sl.plan);
         if (!rc && sur) {
             const int64_t rows = std::max<int64_t>(4096, std::min<int64_t>((int64_t)1 << 16,
                                                    (c.samples + 4095) / 4096 * 4096));
             rc = tgo_surrogate_create(rows, c.max_batch_large, &sl.sur);
             if (!rc) rc = tgo_surrogate_set_params(sl.sur, params.data(), sl.st);
+            if (!rc) rc = surrogate_reserve(sl.sur, c.max_batch_large, c.samples);
+            if (!rc) base += (int64_t)surrogate_device_bytes(sl.sur);
         }
         if (rc) {
             tgo_server_destroy(S);
             return rc;
         }
     }
+    // rings: whatever the budget leaves beyond the server's own memory, split
+    // between the classes in proportion to their largest request, at most
+    // RING_MAX_ROWS rows each; each must hold at least one request of its class
+    S->base_bytes = base;
+    const int64_t left_rows = (c.budget_bytes - base) / (int64_t)sizeof(tgo_task);
+    const int64_t want[2] = {c.small_max_n, sur ? TGO_MAX_N : 0};
+    if (left_rows < want[0] + want[1]) {
+        tgo_server_destroy(S);
+        return fail(TGO_ENOMEM, "budget below the server's own device memory (" + std::to_string(base) +
+                                    " bytes) plus one request per class");
+    }
+    for (int k = 0; k < 2; ++k) {
+        Ring &R = S->ring[k];
+        R.cap = want[k] ? std::min<int64_t>(RING_MAX_ROWS, left_rows * want[k] / (want[0] + want[1])) : 1;
+        hipError_t e = hipMalloc(&R.d, sizeof(tgo_task) * (size_t)R.cap);
+        if (e == hipSuccess) e = hipHostMalloc(&R.h, sizeof(tgo_task) * (size_t)R.cap);
+        if (e != hipSuccess) {
+            tgo_server_destroy(S);
+            return fail(TGO_ENOMEM, std::string("server ring: ") + hipGetErrorString(e));
+        }
+    }
+    hipError_t e = hipStreamCreateWithFlags(&S->up, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->up_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(S->up_ev, S->up);
+    if (e != hipSuccess) {
+        tgo_server_destroy(S);
+        return hip_fail(e, "server upload stream");
+    }
+    S->in_use = S->max_in_use = base;
     S->worker = std::thread(worker_main, S);
     *out = S;
     return TGO_OK;
@@ -375,32 +541,33 @@ int tgo_server_create(const tgo_model *model, const tgo_server_config *cfg, tgo_
 int tgo_server_submit(tgo_server *S, const tgo_task *h_tasks, int n, uint32_t key, uint64_t *id) {
     if (!S || !h_tasks) return fail(TGO_EINVAL, "NULL argument");
     if (n < 1 || n > TGO_MAX_N) return fail(TGO_EINVAL, "n must be in 1..16");
-    Request r;
-    r.n = n;
-    std::memcpy(r.tasks, h_tasks, sizeof(tgo_task) * n);
-    r.t_arrive = now_ns();
-    r.bytes = request_bytes(S->cfg, n);
     const int kind = n <= S->cfg.small_max_n ? 0 : 1;
+    Request *r = new (std::nothrow) Request();
+    if (!r) return fail(TGO_ENOMEM, "request");
+    r->n = n;
+    r->cls = kind;
+    std::memcpy(r->tasks, h_tasks, sizeof(tgo_task) * n);
+    r->t_arrive = now_ns();
+    uint64_t rid = 0;
     {
         std::lock_guard<std::mutex> lk(S->mu);
-        if (S->stop)
+        if (S->stop) {
+            delete r;
             return fail(S->error.empty() ? TGO_EINVAL : TGO_EDEVICE, "server is stopping: " + S->error);
+        }
         if (kind == 1 && !S->slots[0].sur) {
             S->rejected += 1;
+            delete r;
             return fail(TGO_EINVAL, "no surrogate: groups larger than small_max_n are not served");
         }
-        if ((int64_t)r.bytes > S->cfg.budget_bytes) {
-            S->rejected += 1;
-            return fail(TGO_ENOMEM, "request larger than the whole memory budget");
-        }
-        r.id = S->next_id++;
-        r.key = key ? key : (uint32_t)r.id;
-        S->pending[kind].push_back(r);
+        r->id = rid = S->next_id++;
+        r->key = key ? key : (uint32_t)r->id;
+        S->arrivals[kind].push_back(r);
         S->submitted += 1;
-        S->max_queue = std::max(S->max_queue, (int)(S->pending[0].size() + S->pending[1].size()));
+        S->max_queue = std::max(S->max_queue, queued_now(S));
     }
     S->cv.notify_all();
-    if (id) *id = r.id;
+    if (id) *id = rid;
     return TGO_OK;
 }
 
@@ -436,8 +603,12 @@ int tgo_server_get_stats(tgo_server *S, tgo_server_stats *st) {
     st->rejected = S->rejected;
     st->in_use_bytes = S->in_use;
     st->max_in_use_bytes = S->max_in_use;
-    st->queued = (int64_t)(S->pending[0].size() + S->pending[1].size());
+    st->queued = queued_now(S);
     st->max_queued = S->max_queue;
+    st->base_bytes = S->base_bytes;
+    st->ring_rows[0] = S->ring[0].cap;
+    st->ring_rows[1] = S->ring[1].cap;
+    st->budget_bytes = S->cfg.budget_bytes;
     return TGO_OK;
 }
 
@@ -474,34 +645,6 @@ int tgo_server_replay(tgo_server *S, const tgo_task *h_tasks, const int32_t *h_o
         if (idx < (uint64_t)n_requests) h_out[idx] = res[i];
     }
     return got == n_requests ? TGO_OK : fail(TGO_ERANGE, "missing results");
-}
-
-void tgo_server_destroy(tgo_server *S) {
-    if (!S) return;
-    {
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->stop = true;
-        S->pending[0].clear();
-        S->pending[1].clear();
-    }
-    S->cv.notify_all();
-    if (S->worker.joinable()) S->worker.join();
-    for (StreamSlot &sl : S->slots) {
-        if (sl.st) hipStreamSynchronize(sl.st);
-        if (sl.plan) tgo_plan_destroy(sl.plan);
-        if (sl.sur) tgo_surrogate_destroy(sl.sur);
-        if (sl.d_tasks) hipFree(sl.d_tasks);
-        if (sl.d_offs) hipFree(sl.d_offs);
-        if (sl.d_keys) hipFree(sl.d_keys);
-        if (sl.d_out) hipFree(sl.d_out);
-        if (sl.h_tasks) hipHostFree(sl.h_tasks);
-        if (sl.h_offs) hipHostFree(sl.h_offs);
-        if (sl.h_keys) hipHostFree(sl.h_keys);
-        if (sl.h_out) hipHostFree(sl.h_out);
-        if (sl.ev) hipEventDestroy(sl.ev);
-        if (sl.st) hipStreamDestroy(sl.st);
-    }
-    delete S;
 }
 
 }  // extern "C"

@@ -19,6 +19,7 @@
 #include <string>
 #include <vector>
 
+#include "enum_dev.h"
 #include "surrogate_dev.h"
 #include "tables_dev.h"
 #include "tgo_internal.h"
@@ -34,157 +35,208 @@ constexpr int GK = 32;  // K per MFMA instruction (16 x 16 x 32 bf16)
 // ------------------------------------------------------------- exact lanes
 // Exact evaluation of (group, ordering) items, one wave per group tile: the
 // wave loads the group's task table into its own LDS area and each lane
-// evaluates one ordering with the 32-bit window code.
+// evaluates one ordering with the window code.  A group runs the 32-bit time
+// path when its times stay below 2^31 ns (group mode 0) and the 64-bit path
+// otherwise (mode 1); every kernel below exists in both widths and takes the
+// groups of its own mode.
 
+template <typename TT>
 struct WaveTables {
-    Quad<uint32_t> H[4][MAXN];
-    DRec<uint32_t> D[4][MAXN];
+    Quad<TT> H[4][MAXN];
+    DRec<TT> D[4][MAXN];
 };
 
-__device__ __forceinline__ uint32_t eval_perm(uint64_t perm, int n, const View<uint32_t, 1, SG_THREADS> &v,
-                                              const Rates &r) {
-    Lane<uint32_t> st = lane_init<uint32_t>();
+template <typename TT, int NT>
+__device__ __forceinline__ TT eval_perm(uint64_t perm, int n, const View<TT, 1, NT> &v, const Rates &r) {
+    Lane<TT> st = lane_init<TT>();
     for (int j = 0; j < n; ++j) window(st, j, (uint32_t)((perm >> (4 * j)) & 15u), v, r);
     return tail(st, r);
 }
 
-__device__ __forceinline__ void load_group(WaveTables &wt, int w, int lane, const tgo_task *t, int n,
+template <typename TT>
+__device__ __forceinline__ void load_group(WaveTables<TT> &wt, int w, int lane, const tgo_task *t, int n,
                                            const Rates &r) {
-    if (lane < n) table_entry<uint32_t>(t[lane], r, &wt.H[w][lane], &wt.D[w][lane]);
+    if (lane < n) table_entry<TT>(t[lane], r, &wt.H[w][lane], &wt.D[w][lane]);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// status per group: 0, or a TGO_E* code (size out of range, or outside the
-// 32-bit time path which the search kernels use)
+template <typename TT>
+constexpr int mode_of() { return sizeof(TT) == 4 ? 0 : 1; }
+
+// dynamic LDS of the exact-lane kernels: the per-lane kernel queue
+// (the 64-bit kernels run blocks of 128 lanes: their queue stays at 32 KB)
+template <typename TT>
+constexpr int lane_threads() { return sizeof(TT) == 4 ? SG_THREADS : SG_THREADS / 2; }
+template <typename TT>
+constexpr size_t lane_queue_bytes() { return sizeof(Slot<TT>) * lane_threads<TT>() * SG_POS; }
+
+// per group: 0 (32-bit path), 1 (64-bit path) or a TGO_E* code (size out of
+// range, a duration outside [0, 2^40))
 __global__ void group_status_kernel(const tgo_task *__restrict__ tasks, const int32_t *__restrict__ offs,
-                                    int G, Rates r, int32_t *status) {
+                                    int G, Rates r, int32_t *mode, int32_t *status) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= G) return;
     const int n = offs[g + 1] - offs[g];
-    int st = 0;
-    if (n < 1 || n > SG_POS) st = TGO_EINVAL;
-    else st = classify_group(tasks + offs[g], n, r) == 0 ? 0 : TGO_ERANGE;
-    status[g] = st;
+    const int c = (n < 1 || n > SG_POS) ? TGO_EINVAL : classify_group(tasks + offs[g], n, r);
+    if (mode) mode[g] = c;
+    if (status) status[g] = c < 0 ? c : 0;
 }
 
 // Training pairs: per group `per` sampled orderings (per is a multiple of 64)
-// and their exact T.
-__global__ __launch_bounds__(SG_THREADS) void pairs_kernel(const tgo_task *__restrict__ tasks,
+// and their exact T.  The 32-bit instantiation also fills the rows of groups
+// with an error status.
+template <typename TT, int NT = lane_threads<TT>()>
+__global__ __launch_bounds__(NT) void pairs_kernel(const tgo_task *__restrict__ tasks,
                                                            const int32_t *__restrict__ offs, int G,
                                                            Rates r, int64_t per, uint64_t seed,
-                                                           const int32_t *__restrict__ status,
+                                                           const int32_t *__restrict__ mode,
                                                            uint8_t *orders, int32_t *gid, int64_t *T) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ WaveTables wt;
+    __shared__ WaveTables<TT> wt;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    View<uint32_t, 1, SG_THREADS> v;
+    View<TT, 1, NT> v;
     v.H = wt.H[w];
     v.D = wt.D[w];
-    v.Q = reinterpret_cast<Slot<uint32_t> *>(smem) + threadIdx.x;
+    v.Q = reinterpret_cast<Slot<TT> *>(smem) + threadIdx.x;
     const int64_t tiles_per_group = per / 64;
     const int64_t total = tiles_per_group * G;
-    const int64_t wstride = (int64_t)gridDim.x * (SG_THREADS / 64);
-    for (int64_t tile = (int64_t)blockIdx.x * (SG_THREADS / 64) + w; tile < total; tile += wstride) {
+    const int64_t wstride = (int64_t)gridDim.x * (NT / 64);
+    for (int64_t tile = (int64_t)blockIdx.x * (NT / 64) + w; tile < total; tile += wstride) {
         const int g = (int)(tile / tiles_per_group);
+        const int md = mode[g];
+        if (md >= 0 && md != mode_of<TT>()) continue;
         const int64_t s = (tile % tiles_per_group) * 64 + lane;
         const int64_t row = (int64_t)g * per + s;
         const int n = offs[g + 1] - offs[g];
         uint8_t *o = orders + row * SG_POS;
-        gid[row] = g;
-        if (status[g] != 0) {
-            T[row] = status[g];
-            for (int p = 0; p < SG_POS; ++p) o[p] = 0xff;
+        if (md < 0) {
+            if constexpr (sizeof(TT) == 4) {
+                gid[row] = g;
+                T[row] = md;
+                for (int p = 0; p < SG_POS; ++p) o[p] = 0xff;
+            }
             continue;
         }
+        gid[row] = g;
         load_group(wt, w, lane, tasks + offs[g], n, r);
         const uint64_t perm = sample_ordering(n, (uint32_t)g, (uint64_t)s, seed);
-        T[row] = (int64_t)eval_perm(perm, n, v, r);
+        T[row] = (int64_t)eval_perm<TT, NT>(perm, n, v, r);
         for (int p = 0; p < SG_POS; ++p) o[p] = p < n ? (uint8_t)((perm >> (4 * p)) & 15u) : 0xff;
         __builtin_amdgcn_wave_barrier();
     }
 }
 
-// Plain exact search: `per` sampled orderings per group (a multiple of 64),
-// keep the smallest (T << 32 | sample).
+// Best (T, sample) of a group, for the groups of the 64-bit path (T may need
+// more than 32 bits, so it is not packed with the sample into one key).
+struct BestPair {
+    uint64_t t;  // ~0: none
+    uint64_t s;
+};
+
+__device__ __forceinline__ void pair_min(uint64_t &t, uint64_t &s, uint64_t t2, uint64_t s2) {
+    if (t2 < t || (t2 == t && s2 < s)) { t = t2; s = s2; }
+}
+
+// Plain exact search: `per` sampled orderings per group (a multiple of 64).
 // Each wave takes chunks of `chunk` consecutive 64-sample tiles of one group,
 // so the group's table is loaded and the wave's minimum published once per
-// chunk; wave-uniform values are kept in scalar registers.
+// chunk; wave-uniform values are kept in scalar registers.  32-bit path: the
+// smallest (T << 32 | sample) per group by one 64-bit atomic per chunk.
+// 64-bit path: chunk c of group g writes its (T, sample) to wpart[g][c]
+// (chunks of wchunk tiles, at most RS_WIDE_CHUNKS per group).
+constexpr int RS_WIDE_CHUNKS = 256;
 
-__global__ __launch_bounds__(SG_THREADS) void random_search_kernel(const tgo_task *__restrict__ tasks,
+template <typename TT, int NT = lane_threads<TT>()>
+__global__ __launch_bounds__(NT) void random_search_kernel(const tgo_task *__restrict__ tasks,
                                                                    const int32_t *__restrict__ offs,
                                                                    int G, Rates r, int64_t per,
                                                                    uint64_t seed, int64_t chunk_tiles,
-                                                                   const int32_t *__restrict__ status,
-                                                                   unsigned long long *best) {
+                                                                   const int32_t *__restrict__ mode,
+                                                                   unsigned long long *best, BestPair *wpart) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ WaveTables wt;
+    __shared__ WaveTables<TT> wt;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    View<uint32_t, 1, SG_THREADS> v;
+    View<TT, 1, NT> v;
     v.H = wt.H[w];
     v.D = wt.D[w];
-    v.Q = reinterpret_cast<Slot<uint32_t> *>(smem) + threadIdx.x;
+    v.Q = reinterpret_cast<Slot<TT> *>(smem) + threadIdx.x;
     const int64_t tiles_per_group = per / 64;
     const int64_t chunks_per_group = (tiles_per_group + chunk_tiles - 1) / chunk_tiles;
     const int64_t total = chunks_per_group * G;
-    const int64_t wstride = (int64_t)gridDim.x * (SG_THREADS / 64);
-    for (int64_t chunk = (int64_t)blockIdx.x * (SG_THREADS / 64) + w; chunk < total; chunk += wstride) {
+    const int64_t wstride = (int64_t)gridDim.x * (NT / 64);
+    for (int64_t chunk = (int64_t)blockIdx.x * (NT / 64) + w; chunk < total; chunk += wstride) {
         const int g = (int)(chunk / chunks_per_group);
-        if (status[g] != 0) continue;
+        if (mode[g] != mode_of<TT>()) continue;
         const int n = offs[g + 1] - offs[g];
         load_group(wt, w, lane, tasks + offs[g], n, r);
         const int64_t t0 = (chunk % chunks_per_group) * chunk_tiles;
         const int64_t t1 = t0 + chunk_tiles < tiles_per_group ? t0 + chunk_tiles : tiles_per_group;
-        unsigned long long key = ~0ull;
+        uint64_t bt = ~0ull, bs = ~0ull;
         for (int64_t tile = t0; tile < t1; ++tile) {
             const int64_t s = tile * 64 + lane;
             const uint64_t perm = sample_ordering(n, (uint32_t)g, (uint64_t)s, seed);
-            const unsigned long long k = ((unsigned long long)eval_perm(perm, n, v, r) << 32) | (uint64_t)s;
-            key = k < key ? k : key;
+            pair_min(bt, bs, (uint64_t)eval_perm<TT, NT>(perm, n, v, r), (uint64_t)s);
         }
         for (int m = 32; m >= 1; m >>= 1) {
-            const unsigned long long o = __shfl_xor(key, m);
-            key = o < key ? o : key;
+            const uint64_t t2 = shfl_xor64(bt, m), s2 = shfl_xor64(bs, m);
+            pair_min(bt, bs, t2, s2);
         }
-        if (lane == 0) atomicMin(&best[g], key);
+        if (lane == 0) {
+            if constexpr (sizeof(TT) == 4) {
+                atomicMin(&best[g], (unsigned long long)((bt << 32) | bs));
+            } else {
+                BestPair bp;
+                bp.t = bt;
+                bp.s = bs;
+                wpart[(int64_t)g * RS_WIDE_CHUNKS + chunk % chunks_per_group] = bp;
+            }
+        }
         __builtin_amdgcn_wave_barrier();
     }
 }
 
 // Exact re-score of the k best-scored candidates of every group (k <= 64,
-// one wave per group): keys hold the sample index in the low 32 bits.
-__global__ __launch_bounds__(SG_THREADS) void rescore_kernel(const tgo_task *__restrict__ tasks,
+// one wave per group): keys hold the sample index in the low 32 bits.  The
+// group's best (T, sample) goes to out[g] (T = ~0: no candidate).
+template <typename TT, int NT = lane_threads<TT>()>
+__global__ __launch_bounds__(NT) void rescore_kernel(const tgo_task *__restrict__ tasks,
                                                              const int32_t *__restrict__ offs, int G,
                                                              Rates r, int k, uint64_t seed,
-                                                             const int32_t *__restrict__ status,
+                                                             const int32_t *__restrict__ mode,
                                                              const uint32_t *__restrict__ gkeys,
                                                              const unsigned long long *__restrict__ keys,
-                                                             int key_stride,
-                                                             unsigned long long *best) {
+                                                             int key_stride, BestPair *out) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ WaveTables wt;
+    __shared__ WaveTables<TT> wt;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    View<uint32_t, 1, SG_THREADS> v;
+    View<TT, 1, NT> v;
     v.H = wt.H[w];
     v.D = wt.D[w];
-    v.Q = reinterpret_cast<Slot<uint32_t> *>(smem) + threadIdx.x;
-    for (int g = blockIdx.x * (SG_THREADS / 64) + w; g < G; g += gridDim.x * (SG_THREADS / 64)) {
-        if (status[g] != 0) continue;
+    v.Q = reinterpret_cast<Slot<TT> *>(smem) + threadIdx.x;
+    for (int g = blockIdx.x * (NT / 64) + w; g < G; g += gridDim.x * (NT / 64)) {
+        const int md = mode[g];
+        if (md >= 0 && md != mode_of<TT>()) continue;
+        if (md < 0) {
+            if (sizeof(TT) == 4 && lane == 0) out[g] = BestPair{~0ull, ~0ull};
+            continue;
+        }
         const int n = offs[g + 1] - offs[g];
         load_group(wt, w, lane, tasks + offs[g], n, r);
-        unsigned long long key = ~0ull;
+        uint64_t bt = ~0ull, bs = ~0ull;
         const unsigned long long kk = lane < k ? keys[(int64_t)g * key_stride + lane] : ~0ull;
         if (kk != ~0ull) {
             const uint64_t s = kk & 0xffffffffull;
             const uint64_t perm = sample_ordering(n, gkeys ? gkeys[g] : (uint32_t)g, s, seed);
-            key = ((unsigned long long)eval_perm(perm, n, v, r) << 32) | s;
+            bt = (uint64_t)eval_perm<TT, NT>(perm, n, v, r);
+            bs = s;
         }
         for (int m = 32; m >= 1; m >>= 1) {
-            const unsigned long long o = __shfl_xor(key, m);
-            key = o < key ? o : key;
+            const uint64_t t2 = shfl_xor64(bt, m), s2 = shfl_xor64(bs, m);
+            pair_min(bt, bs, t2, s2);
         }
-        if (lane == 0) best[g] = key;
+        if (lane == 0) out[g] = BestPair{bt, bs};
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -1036,22 +1088,46 @@ __global__ void fill_u64_kernel(unsigned long long *p, int64_t n, unsigned long 
 }
 
 // results: best of candidates (exact) and the heuristic
+// Results: best of candidates (exact) and the heuristic.  The candidates'
+// best (T, sample) of group g comes from pairs[g] (re-score), or, for the
+// plain search, from the packed key best[g] (32-bit path) or the chunk
+// partials wpart[g][0 .. wchunks) (64-bit path).
 __global__ void search_finish_kernel(const int32_t *__restrict__ offs, int G, uint64_t seed,
                                      const uint32_t *__restrict__ gkeys,
-                                     const int32_t *__restrict__ status,
+                                     const int32_t *__restrict__ mode,
+                                     const BestPair *__restrict__ pairs,
                                      const unsigned long long *__restrict__ best,
+                                     const BestPair *__restrict__ wpart, int wchunks,
                                      const uint8_t *__restrict__ horders, const int64_t *__restrict__ hns,
                                      tgo_search_result *out) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= G) return;
     tgo_search_result r;
     const int n = offs[g + 1] - offs[g];
+    const int md = mode[g];
     r.n = n;
-    r.status = status[g];
+    r.status = md < 0 ? md : 0;
     r.pad = 0;
     for (int i = 0; i < 16; ++i) r.best[i] = 0xff;
     r.heur_ns = hns[g];
-    if (r.status != 0 || best[g] == ~0ull) {
+    uint64_t ct = ~0ull, cs = ~0ull;
+    if (md >= 0) {
+        if (pairs) {
+            ct = pairs[g].t;
+            cs = pairs[g].s;
+        } else if (md == 0) {
+            if (best[g] != ~0ull) {
+                ct = best[g] >> 32;
+                cs = best[g] & 0xffffffffull;
+            }
+        } else {
+            for (int c = 0; c < wchunks; ++c) {
+                const BestPair q = wpart[(int64_t)g * RS_WIDE_CHUNKS + c];
+                pair_min(ct, cs, q.t, q.s);
+            }
+        }
+    }
+    if (r.status != 0 || ct == ~0ull) {
         r.best_ns = r.status != 0 ? r.status : r.heur_ns;
         r.cand_best_ns = -1;
         r.best_sample = 0;
@@ -1061,8 +1137,7 @@ __global__ void search_finish_kernel(const int32_t *__restrict__ offs, int G, ui
         out[g] = r;
         return;
     }
-    const int64_t cT = (int64_t)(best[g] >> 32);
-    const uint64_t cs = best[g] & 0xffffffffull;
+    const int64_t cT = (int64_t)ct;
     r.cand_best_ns = cT;
     r.best_sample = cs;
     if (r.heur_ns >= 0 && r.heur_ns <= cT) {
@@ -1104,9 +1179,11 @@ struct tgo_surrogate {
     int32_t *status = nullptr;
     uint8_t *horders = nullptr;
     int64_t *hns = nullptr;
-    unsigned long long *best = nullptr, *keys = nullptr;
+    tgo::BestPair *best = nullptr;
+    unsigned long long *keys = nullptr;
     unsigned long long *cand[2] = {nullptr, nullptr};
     size_t cand_bytes = 0;
+    size_t bytes = 0;  // the main allocation
 };
 
 namespace tgo {
@@ -1192,11 +1269,12 @@ int tgo_surrogate_create(int64_t max_rows, int max_groups, tgo_surrogate **out) 
         {(void **)&s->vpart, 4 * (size_t)WG_KS_MAX * TR_VSTRIDE},
         {(void **)&s->F, 4 * (size_t)max_groups * SG_POS * 3},
         {(void **)&s->status, 4 * (size_t)max_groups}, {(void **)&s->horders, 16 * (size_t)max_groups},
-        {(void **)&s->hns, 8 * (size_t)max_groups}, {(void **)&s->best, 8 * (size_t)max_groups},
+        {(void **)&s->hns, 8 * (size_t)max_groups}, {(void **)&s->best, sizeof(BestPair) * (size_t)max_groups},
         {(void **)&s->keys, 8 * R},
     };
     size_t total = 0;
     for (auto &pt : parts) total += align256(pt.second);
+    s->bytes = total;
     hipError_t e = hipMalloc(&s->mem, total);
     if (e != hipSuccess) {
         delete s;
@@ -1213,10 +1291,10 @@ int tgo_surrogate_create(int64_t max_rows, int max_groups, tgo_surrogate **out) 
 
 void tgo_surrogate_destroy(tgo_surrogate *s) {
     if (!s) return;
-    hipDeviceSynchronize();
-    hipFree(s->mem);
-    if (s->cand[0]) hipFree(s->cand[0]);
-    if (s->cand[1]) hipFree(s->cand[1]);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(s->mem);
+    if (s->cand[0]) (void)hipFree(s->cand[0]);
+    if (s->cand[1]) (void)hipFree(s->cand[1]);
     delete s;
 }
 
@@ -1311,13 +1389,18 @@ int tgo_surrogate_pairs(const tgo_model *model, const tgo_task *d_tasks, const i
     if (per_group < 64 || per_group % 64) return fail(TGO_EINVAL, "per_group must be a positive multiple of 64");
     if (!d_status || !d_orders || !d_gid || !d_T) return fail(TGO_EINVAL, "NULL buffer");
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(group_status_kernel, dim3((G + 255) / 256), dim3(256), 0, st, d_tasks, d_offs, G, r,
+    int32_t *mode = nullptr;
+    rc = workspace(4 * (size_t)G, (void **)&mode, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(group_status_kernel, dim3((G + 255) / 256), dim3(256), 0, st, d_tasks, d_offs, G, r, mode,
                        d_status);
-    const size_t shm = sizeof(Slot<uint32_t>) * SG_THREADS * SG_POS;
     const int64_t tiles = per_group / 64 * G;
     const int blocks = (int)std::min<int64_t>((tiles + 3) / 4, 8192);
-    hipLaunchKernelGGL(pairs_kernel, dim3(blocks), dim3(SG_THREADS), shm, st, d_tasks, d_offs, G, r, per_group,
-                       seed, d_status, d_orders, d_gid, d_T);
+    hipLaunchKernelGGL(pairs_kernel<uint32_t>, dim3(blocks), dim3(SG_THREADS), lane_queue_bytes<uint32_t>(), st,
+                       d_tasks, d_offs, G, r, per_group, seed, mode, d_orders, d_gid, d_T);
+    // groups on the 64-bit time path (the blocks skip every other group)
+    hipLaunchKernelGGL(pairs_kernel<uint64_t>, dim3(2 * blocks), dim3(lane_threads<uint64_t>()), lane_queue_bytes<uint64_t>(), st,
+                       d_tasks, d_offs, G, r, per_group, seed, mode, d_orders, d_gid, d_T);
     TGO_HIP(hipGetLastError());
     return TGO_OK;
 }
@@ -1421,6 +1504,12 @@ int tgo_surrogate_get_batch(tgo_surrogate *s, int what, int64_t rows, void *h_ou
     return TGO_OK;
 }
 
+}  // extern "C"
+
+size_t tgo::surrogate_device_bytes(const tgo_surrogate *s) { return s ? s->bytes + 2 * s->cand_bytes : 0; }
+
+extern "C" {
+
 // Candidate-key buffers, grown on demand.  The object is either fully sized
 // (both buffers, cand_bytes) or empty (no buffers, cand_bytes = 0): a failed
 // growth leaves it empty, so the next call tries to allocate again instead of
@@ -1447,6 +1536,17 @@ static int grow_cand(tgo_surrogate *s, size_t bytes) {
     return TGO_OK;
 }
 
+}  // extern "C"
+
+// Size the candidate buffers for searches of up to G groups of `samples`
+// draws each, so that such searches allocate nothing more.
+int tgo::surrogate_reserve(tgo_surrogate *s, int G, int64_t samples) {
+    const int64_t runs = (samples + TK_RUN - 1) / TK_RUN;
+    return grow_cand(s, sizeof(unsigned long long) * (size_t)G * (size_t)runs * TK_KEEP);
+}
+
+extern "C" {
+
 // The candidate stage of the search: sample, score and keep the TK_KEEP
 // smallest keys of every group.  On return cand[*cur] holds per group a
 // sorted list of *len keys (group stride *len) whose first TK_KEEP are the
@@ -1461,7 +1561,7 @@ static int search_candidates(tgo_surrogate *s, const Rates &r, const tgo_task *d
     int rc = grow_cand(s, sizeof(unsigned long long) * (size_t)G * (size_t)runs * TK_KEEP);
     if (rc) return rc;
     hipLaunchKernelGGL(group_status_kernel, dim3((G + 255) / 256), dim3(256), 0, st, d_tasks, d_offs, G, r,
-                       s->status);
+                       s->status, (int32_t *)nullptr);
     hipLaunchKernelGGL(group_features_kernel, dim3((G * SG_POS + 255) / 256), dim3(256), 0, st, d_tasks, d_offs,
                        G, s->F);
     const int64_t total = (int64_t)G * spad;
@@ -1526,12 +1626,13 @@ int tgo_surrogate_search(tgo_surrogate *s, const tgo_model *model, const tgo_tas
     if (rc) return rc;
     rc = launch_heuristic(r, d_tasks, d_offs, G, s->horders, 16, s->hns, 1, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(fill_u64_kernel, dim3((G + 255) / 256), dim3(256), 0, st, s->best, (int64_t)G, ~0ull);
-    const size_t shm = sizeof(Slot<uint32_t>) * SG_THREADS * SG_POS;
-    hipLaunchKernelGGL(rescore_kernel, dim3((G + 3) / 4), dim3(SG_THREADS), shm, st, d_tasks, d_offs, G, r, topk,
-                       seed, s->status, d_keys, s->cand[cur], (int)len, s->best);
+    hipLaunchKernelGGL(rescore_kernel<uint32_t>, dim3((G + 3) / 4), dim3(SG_THREADS), lane_queue_bytes<uint32_t>(), st,
+                       d_tasks, d_offs, G, r, topk, seed, s->status, d_keys, s->cand[cur], (int)len, s->best);
+    hipLaunchKernelGGL(rescore_kernel<uint64_t>, dim3((G + 1) / 2), dim3(lane_threads<uint64_t>()), lane_queue_bytes<uint64_t>(), st,
+                       d_tasks, d_offs, G, r, topk, seed, s->status, d_keys, s->cand[cur], (int)len, s->best);
     hipLaunchKernelGGL(search_finish_kernel, dim3((G + 255) / 256), dim3(256), 0, st, d_offs, G, seed, d_keys,
-                       s->status, s->best, s->horders, s->hns, d_out);
+                       s->status, s->best, (const unsigned long long *)nullptr, (const BestPair *)nullptr, 0,
+                       s->horders, s->hns, d_out);
     TGO_HIP(hipGetLastError());
     return TGO_OK;
 }
@@ -1565,29 +1666,43 @@ int tgo_random_search(const tgo_model *model, const tgo_task *d_tasks, const int
     hipStream_t st = (hipStream_t)stream;
     const int64_t per = (samples + 63) / 64 * 64;
     char *ws = nullptr;
-    const size_t need = (size_t)G * (4 + 16 + 8 + 8) + 1024;
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t need = al(4 * (size_t)G) + al(8 * (size_t)G) + al(8 * (size_t)G) + al(16 * (size_t)G) +
+                        sizeof(BestPair) * RS_WIDE_CHUNKS * (size_t)G;
     rc = workspace(need, (void **)&ws, st);
     if (rc) return rc;
-    int32_t *status = (int32_t *)ws;
-    int64_t *hns = (int64_t *)(ws + ((4 * (size_t)G + 255) & ~size_t(255)));
-    unsigned long long *best = (unsigned long long *)((char *)hns + ((8 * (size_t)G + 255) & ~size_t(255)));
-    uint8_t *horders = (uint8_t *)((char *)best + ((8 * (size_t)G + 255) & ~size_t(255)));
-    hipLaunchKernelGGL(group_status_kernel, dim3((G + 255) / 256), dim3(256), 0, st, d_tasks, d_offs, G, r, status);
+    int32_t *mode = (int32_t *)ws;
+    int64_t *hns = (int64_t *)(ws + al(4 * (size_t)G));
+    unsigned long long *best = (unsigned long long *)((char *)hns + al(8 * (size_t)G));
+    uint8_t *horders = (uint8_t *)((char *)best + al(8 * (size_t)G));
+    BestPair *wpart = (BestPair *)(horders + al(16 * (size_t)G));
+    hipLaunchKernelGGL(group_status_kernel, dim3((G + 255) / 256), dim3(256), 0, st, d_tasks, d_offs, G, r, mode,
+                       (int32_t *)nullptr);
     rc = launch_heuristic(r, d_tasks, d_offs, G, horders, 16, hns, 1, st);
     if (rc) return rc;
     hipLaunchKernelGGL(fill_u64_kernel, dim3((G + 255) / 256), dim3(256), 0, st, best, (int64_t)G, ~0ull);
+    int wchunks = 0;
     if (per > 0) {
-        const size_t shm = sizeof(Slot<uint32_t>) * SG_THREADS * SG_POS;
         // chunks of up to 64 tiles, while keeping at least ~64k wave tasks
-        const int64_t tiles = per / 64 * G;
+        const int64_t tpg = per / 64;
+        const int64_t tiles = tpg * G;
         const int64_t chunk_tiles = std::max<int64_t>(1, std::min<int64_t>(64, tiles >> 16));
-        const int64_t chunks = (per / 64 + chunk_tiles - 1) / chunk_tiles * G;
+        const int64_t chunks = (tpg + chunk_tiles - 1) / chunk_tiles * G;
         const int blocks = (int)std::min<int64_t>((chunks + 3) / 4, 16384);
-        hipLaunchKernelGGL(random_search_kernel, dim3(blocks), dim3(SG_THREADS), shm, st, d_tasks, d_offs, G, r,
-                           per, seed, chunk_tiles, status, best);
+        hipLaunchKernelGGL(random_search_kernel<uint32_t>, dim3(blocks), dim3(SG_THREADS),
+                           lane_queue_bytes<uint32_t>(), st, d_tasks, d_offs, G, r, per, seed, chunk_tiles, mode,
+                           best, wpart);
+        // groups on the 64-bit time path: at most RS_WIDE_CHUNKS chunks each
+        const int64_t wct = std::max<int64_t>(chunk_tiles, (tpg + RS_WIDE_CHUNKS - 1) / RS_WIDE_CHUNKS);
+        wchunks = (int)((tpg + wct - 1) / wct);
+        const int wblocks = (int)std::min<int64_t>(((int64_t)wchunks * G + 1) / 2, 16384);
+        hipLaunchKernelGGL(random_search_kernel<uint64_t>, dim3(wblocks), dim3(lane_threads<uint64_t>()),
+                           lane_queue_bytes<uint64_t>(), st, d_tasks, d_offs, G, r, per, seed, wct, mode, best,
+                           wpart);
     }
     hipLaunchKernelGGL(search_finish_kernel, dim3((G + 255) / 256), dim3(256), 0, st, d_offs, G, seed,
-                       (const uint32_t *)nullptr, status, best, horders, hns, d_out);
+                       (const uint32_t *)nullptr, mode, (const BestPair *)nullptr, best, wpart, wchunks, horders,
+                       hns, d_out);
     TGO_HIP(hipGetLastError());
     return TGO_OK;
 }

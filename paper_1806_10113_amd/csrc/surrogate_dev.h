@@ -85,9 +85,11 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
-// log1p(x / 1 us) / log1p(20 ms / 1 us)
+// log1p(x / 1 us) / log1p(20 ms / 1 us), in float32 (a few ulp of the exact
+// value; the network sees it rounded to bf16)
 __device__ __forceinline__ float feature_value(int64_t x_ns) {
-    return (float)(log1p((double)x_ns / 1000.0) / log1p(20000.0));
+    constexpr float INV_SCALE = (float)(1.0 / 9.90353755128617);  // 1 / log1p(20000)
+    return log1pf((float)x_ns * 1e-3f) * INV_SCALE;
 }
 
 }  // namespace tgo

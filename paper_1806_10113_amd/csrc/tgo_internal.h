@@ -60,6 +60,10 @@ int launch_memory(const Rates &r, const tgo_task *d_tasks, const int64_t *d_mem,
                   int64_t *d_per_order, tgo_summary *d_out, hipStream_t st);
 int launch_memory_evaluate(const Rates &r, const tgo_task *d_tasks, const int64_t *d_mem, int n, int64_t cap,
                            const uint8_t *d_orders, int64_t m, int64_t *d_out, hipStream_t st);
+// Device bytes owned by a plan / a surrogate (for the server's memory budget).
+size_t plan_device_bytes(const tgo_plan *p);
+size_t surrogate_device_bytes(const tgo_surrogate *s);
+int surrogate_reserve(tgo_surrogate *s, int max_groups, int64_t samples);
 int launch_heuristic(const Rates &r, const tgo_task *d_tasks, const int32_t *d_offs, int n_groups,
                      uint8_t *d_orders, int order_stride, int64_t *d_ns, int ns_stride,
                      hipStream_t st);

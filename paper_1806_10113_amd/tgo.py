@@ -13,7 +13,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libtgo.so")
+# TGO_LIB names another build of the same sources (the host-sanitizer test
+# loads one this way); by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("TGO_LIB") or os.path.join(_PKG, "libtgo.so")
 
 TGO_OK, TGO_EINVAL, TGO_ERANGE, TGO_ENOMEM, TGO_EDEVICE = 0, -1, -2, -3, -4
 MAX_N = 16
@@ -95,7 +97,7 @@ def lib():
         L.tgo_surrogate_load.restype = i32
         L.tgo_rank.argtypes = [i32, vp, ctypes.POINTER(ctypes.c_uint64)]
         L.tgo_unrank.argtypes = [i32, ctypes.c_uint64, vp]
-        L.tgo_plan_create.argtypes = [M, i32, ctypes.POINTER(vp)]
+        L.tgo_plan_create.argtypes = [M, i32, i32, ctypes.c_size_t, ctypes.POINTER(vp)]
         L.tgo_plan_autotune.argtypes = [vp, vp, vp, i32, vp, vp]
         L.tgo_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
         L.tgo_batch.argtypes = [vp, vp, vp, i32, vp, vp]
@@ -151,8 +153,6 @@ def lib():
         L.tgo_hw_run_rounds.restype = i32
         L.tgo_hw_run_mem.argtypes = [vp, vp, i32, vp, vp, i64, i32, ctypes.POINTER(ctypes.c_int64), vp]
         L.tgo_hw_run_mem.restype = i32
-        L.tgo_valu_probe.argtypes = [i32, i32, vp]
-        L.tgo_valu_probe.restype = i32
         L.tgo_hw_run_proxy.argtypes = [vp, M, vp, vp, i32, i32, ctypes.POINTER(ctypes.c_int64), vp, vp, vp]
         L.tgo_hw_run_proxy.restype = i32
         L.tgo_fit_line.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -368,8 +368,21 @@ def evaluate_mem(tasks, mem, capacity: int, orders, model: Model = DEFAULT, out=
 
 
 def valu_probe(blocks: int, iters: int, stream=None):
-    """Launch the integer issue probe (tgo_valu_probe)."""
-    _check(lib().tgo_valu_probe(int(blocks), int(iters), _stream(stream)), "tgo_valu_probe")
+    """Launch the integer issue probe of the calibration library
+    (libtgo_probe.so, tgo_probe_valu): a measurement of the device for the
+    ALU roofline, not part of the model."""
+    import torch
+    path = os.path.join(_PKG, "libtgo_probe.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run python -m paper_1806_10113_amd.build")
+    P = ctypes.CDLL(path)
+    P.tgo_probe_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    P.tgo_probe_valu.restype = ctypes.c_int
+    sink = torch.zeros(4, dtype=torch.int32, device="cuda")
+    rc = P.tgo_probe_valu(int(blocks), int(iters), sink.data_ptr(), _stream(stream))
+    if rc != 0:
+        raise TgoError(rc, "tgo_probe_valu", "bad argument" if rc == -1 else "launch error")
+    return sink
 
 
 def read_groups(groups) -> list:
@@ -416,12 +429,12 @@ def heuristic(tasks, offs, model: Model = DEFAULT, stream=None):
 class Plan:
     """Batched enumeration plan (device workspace, captured graph, tuned decomposition)."""
 
-    def __init__(self, model: Model = DEFAULT, max_groups: int = 4096):
+    def __init__(self, model: Model = DEFAULT, max_groups: int = 4096, max_n: int = 12, mem_budget: int = 0):
         self._h = ctypes.c_void_p()
         self.model = model
         self.max_groups = max_groups
-        _check(lib().tgo_plan_create(ctypes.byref(model._c()), max_groups, ctypes.byref(self._h)),
-               "tgo_plan_create")
+        _check(lib().tgo_plan_create(ctypes.byref(model._c()), max_groups, max_n, mem_budget,
+                                     ctypes.byref(self._h)), "tgo_plan_create")
 
     def close(self):
         if self._h:
@@ -677,7 +690,9 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
                 ("in_use_bytes", ctypes.c_int64), ("max_in_use_bytes", ctypes.c_int64),
-                ("queued", ctypes.c_int64), ("max_queued", ctypes.c_int64)]
+                ("queued", ctypes.c_int64), ("max_queued", ctypes.c_int64),
+                ("base_bytes", ctypes.c_int64), ("ring_rows", ctypes.c_int64 * 2),
+                ("budget_bytes", ctypes.c_int64)]
 
 
 def server_config(**kw) -> ServerConfig:
@@ -735,7 +750,9 @@ class Server:
     def stats(self) -> dict:
         s = ServerStats()
         _check(lib().tgo_server_get_stats(self._h, ctypes.byref(s)), "tgo_server_get_stats")
-        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+        d = {k: getattr(s, k) for k, _ in ServerStats._fields_}
+        d["ring_rows"] = list(d["ring_rows"])
+        return d
 
     def replay(self, tasks, offs, arrival_ns, timeout_ms: int = 600_000) -> np.ndarray:
         t = np.ascontiguousarray(np.asarray(tasks, dtype=np.int64).reshape(-1, 3))

@@ -135,6 +135,24 @@ def poisson_arrivals(rate_per_s: float = 20_000.0, duration_s: float = 1.0, n_lo
     return Arrivals(t, b)
 
 
+def poisson_stream(rate_per_s: float, duration_s: float, pool: Batch, seed: int) -> Arrivals:
+    """Exponential gaps with mean 1/rate; request i carries pool group idx[i],
+    idx uniform over the pool (with replacement).  The gaps are drawn first,
+    then the indices, from one PCG64(seed) stream.  Drawing from a fixed pool
+    keeps high-rate streams cheap to build."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n_req = int(rate_per_s * duration_s)
+    gaps = rng.exponential(1e9 / rate_per_s, size=n_req)
+    t = np.cumsum(gaps).astype(np.int64)
+    idx = rng.integers(0, pool.n_groups, size=n_req)
+    sizes = pool.sizes()[idx].astype(np.int64)
+    offs = np.zeros(n_req + 1, dtype=np.int64)
+    np.cumsum(sizes, out=offs[1:])
+    rows = np.repeat(pool.offs[:-1][idx].astype(np.int64) - offs[:-1], sizes) + np.arange(offs[-1])
+    labels = pool.labels[rows] if len(pool.labels) == len(pool.tasks) else pool.labels[idx]
+    return Arrivals(t, Batch(pool.tasks[rows], offs.astype(np.int32), labels))
+
+
 # The paper's synthetic tasks T0..T7 in fractions of the 10 ms unit (Table of
 # synthetic tasks), and the five 4-task benchmarks BK0..BK100 (Table of
 # synthetic benchmarks).

@@ -95,9 +95,6 @@ def test_host_argument_errors(L):
     for n, cap, m in ((0, 4, 1), (17, 4, 1), (4, 0, 1), (4, 4, -1)):
         assert L.tgo_evaluate_cke(ctypes.byref(good), fake, fake, n, cap, fake, m, fake, None) == tgo.TGO_EINVAL
     assert L.tgo_evaluate_cke(ctypes.byref(good), fake, None, 4, 4, fake, 3, fake, None) == tgo.TGO_EINVAL
-    # the integer issue probe: 1..2^20 blocks and iterations
-    for blocks, iters in ((0, 1), (1, 0), ((1 << 20) + 1, 1), (1, (1 << 20) + 1)):
-        assert L.tgo_valu_probe(blocks, iters, None) == tgo.TGO_EINVAL
 
 
 def test_rank_unrank_match_lexicographic_order():
@@ -117,3 +114,21 @@ def test_rank_unrank_match_lexicographic_order():
         tgo.unrank(5, math.factorial(5))
     with pytest.raises(tgo.TgoError):
         tgo.rank([0, 0, 1])
+
+
+def test_calibration_library_is_separate():
+    """The integer issue probe lives in libtgo_probe.so (include/tgo_probe.h),
+    outside the product library, and rejects bad arguments on the host."""
+    from paper_1806_10113_amd import tgo
+    L = tgo.lib()
+    assert not hasattr(L, "tgo_valu_probe") and not hasattr(L, "tgo_probe_valu")
+    path = os.path.join(os.path.dirname(tgo.LIB_PATH), "libtgo_probe.so")
+    P = ctypes.CDLL(path)
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "tgo_probe.h")).read(), flags=re.S)
+    for name in re.findall(r"\b(tgo_[a-z0-9_]+)\s*\(", text):
+        assert hasattr(P, name), name
+    P.tgo_probe_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    fake = ctypes.c_void_p(16)
+    for blocks, iters in ((0, 1), (1, 0), ((1 << 20) + 1, 1), (1, (1 << 20) + 1)):
+        assert P.tgo_probe_valu(blocks, iters, fake, None) == -1
+    assert P.tgo_probe_valu(1, 1, None, None) == -1

@@ -200,3 +200,33 @@ def test_edge_cases(dev):
         got = tgo.evaluate_mem(to_dev(tk, dev), to_dev(mem, dev), cap,
                                to_dev([[0, 1], [1, 0]], dev, np.uint8)).cpu().numpy()
         assert (got == code).all()
+
+
+def _stored():
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "memory_n12_summaries.json")))
+
+
+@pytest.mark.parametrize("case", ["dma2_cap1", "dma2_cap0.6", "dma2_cap0.4", "dma2_cap0.25", "dma2_cap0",
+                                  "dma1_cap1", "dma1_cap0.6", "dma1_cap0.4", "dma1_cap0.25", "dma1_cap0"])
+def test_n12_full_size_against_stored_oracle(dev, case):
+    """The N = 12 group under the memory limit at five capacities and both
+    launch schemes: every field of the summary over all 12! orderings, and
+    Algorithm 1 under the limit, equal the oracle's stored values
+    (tests/golden/memory_n12_summaries.json, written by make_golden.py from
+    the oracle alone)."""
+    g = _stored()
+    c = g["cases"][case]
+    tasks = np.array(g["tasks_ns"], dtype=np.int64)
+    mem = np.array(g["mem_bytes"], dtype=np.int64)
+    assert np.array_equal(tasks, W.single_group_mixed(12, seed=1))
+    assert np.array_equal(mem, W.footprints(tasks))
+    m = M.Model(**c["model"])
+    s, _ = run(dev, tasks, mem, c["capacity"], m, per_order=False)
+    assert s["status"] == 0 and s["count"] == c["count"]
+    for k in ("min_ns", "argmin_rank", "max_ns", "argmax_rank"):
+        assert s[k] == c[k], k
+    assert s["sum"] == int(c["sum"]) and s["fingerprint"] == int(c["fingerprint"])
+    assert s["heur"] == c["heuristic"] and s["heur_ns"] == c["heuristic_ns"]

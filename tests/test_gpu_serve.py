@@ -1,6 +1,6 @@
 """GPU checks of the continuous-batching server: every answer exact against
-the oracle, the same alone and in a mix, admission within the memory budget,
-and a real-time replay of a Poisson trace."""
+the oracle, the same alone and in a mix, admission within the memory budget
+(queue rings that wrap), and a real-time replay of a Poisson trace."""
 import numpy as np
 import pytest
 
@@ -101,21 +101,90 @@ def test_same_alone_and_in_mix_small_and_large(dev):
     sur.close()
 
 
+TASK_BYTES = 24  # one task row: three int64 durations
+
+
 def test_budget_admission(dev):
+    """The budget covers the server's own device memory plus the queue rings:
+    with room for about three requests' rows beyond its own memory, later
+    requests wait for rows to free up, the device memory held never exceeds
+    the budget, and every answer is exact (the small ring wraps many times)."""
     from paper_1806_10113_amd import tgo
-    # a budget of about three small requests forces waiting for memory
-    cfg = tgo.server_config(streams=4, max_batch=16, budget_bytes=3 * 700)
-    b = W.batch_groups(40, 4, 8, seed=405)
+    probe = tgo.Server(tgo.DEFAULT, tgo.server_config(streams=4, max_batch=16))
+    base = probe.stats()["base_bytes"]
+    probe.close()
+    assert base > 0
+    budget = base + 3 * 8 * TASK_BYTES
+    cfg = tgo.server_config(streams=4, max_batch=16, budget_bytes=budget)
+    b = W.batch_groups(60, 4, 8, seed=405)
     srv = tgo.Server(tgo.DEFAULT, cfg)
+    st0 = srv.stats()
+    assert st0["base_bytes"] == base and st0["ring_rows"][0] == 24
+    assert st0["budget_bytes"] == budget
     ids = [srv.submit(b.group(g)) for g in range(b.n_groups)]
     srv.drain()
     res = by_id(srv.poll(100))
     st = srv.stats()
-    assert st["max_in_use_bytes"] <= 3 * 700
-    assert st["batches"] >= b.n_groups // 3
+    assert base < st["max_in_use_bytes"] <= budget
+    assert st["in_use_bytes"] == base  # everything released
+    assert st["batches"] >= b.n_groups // 6
+    assert st["max_queued"] > 3
     for g, i in enumerate(ids):
         check_small(res[i], b.group(g))
     srv.close()
+
+
+def test_budget_below_own_memory_is_refused(dev):
+    from paper_1806_10113_amd import tgo
+    probe = tgo.Server(tgo.DEFAULT, tgo.server_config(streams=2, max_batch=16))
+    base = probe.stats()["base_bytes"]
+    probe.close()
+    for budget in (1000, base, base + 9 * TASK_BYTES):  # small_max_n = 10 rows do not fit
+        with pytest.raises(tgo.TgoError) as ei:
+            tgo.Server(tgo.DEFAULT, tgo.server_config(streams=2, max_batch=16, budget_bytes=budget))
+        assert ei.value.code == tgo.TGO_ENOMEM
+    srv = tgo.Server(tgo.DEFAULT, tgo.server_config(streams=2, max_batch=16,
+                                                    budget_bytes=base + 10 * TASK_BYTES))
+    grp = W.batch_groups(1, 10, 10, seed=409).group(0)
+    ids = [srv.submit(grp) for _ in range(3)]  # one at a time through a 10-row ring
+    srv.drain()
+    res = by_id(srv.poll(10))
+    for i in ids:
+        check_small(res[i], grp)
+    srv.close()
+
+
+def test_large_class_ring_wraps(dev):
+    """Both classes through small rings: large requests (learned proposal)
+    wrap their ring and still score exactly what they report."""
+    from paper_1806_10113_amd import tgo
+    sur = tgo.Surrogate(max_rows=1 << 13, max_groups=8)
+    sur.init(11)
+    cfg = tgo.server_config(streams=2, max_batch=8, max_batch_large=4, samples=2048, topk=16)
+    probe = tgo.Server(tgo.DEFAULT, cfg, sur)
+    base = probe.stats()["base_bytes"]
+    probe.close()
+    cfg.budget_bytes = base + 3 * (10 + 16) * TASK_BYTES  # rings of 30 and 48 rows
+    srv = tgo.Server(tgo.DEFAULT, cfg, sur)
+    assert srv.stats()["ring_rows"] == [30, 48]
+    mix = W.batch_groups(40, 6, 16, seed=410, per_task_label=True)
+    ids = [srv.submit(mix.group(g)) for g in range(mix.n_groups)]
+    srv.drain()
+    res = by_id(srv.poll(100))
+    st = srv.stats()
+    assert st["max_in_use_bytes"] <= cfg.budget_bytes
+    for g, i in enumerate(ids):
+        grp = mix.group(g)
+        n = len(grp)
+        r = res[i]
+        assert r["status"] == 0
+        assert r["best_ns"] == cmodel.simulate(grp, [int(v) for v in r["best"][:n]], M.DEFAULT)
+        if n <= 10:
+            check_small(r, grp)
+        else:
+            assert r["path"] == 1 and r["best_ns"] <= r["heur_ns"]
+    srv.close()
+    sur.close()
 
 
 def test_replay_poisson_trace(dev):

@@ -128,7 +128,9 @@ def test_gradients_stage_by_stage(dev, groups, per):
     G1 = sur.batch_values(sur.BATCH_G1, rows)
     # features: one float32 then one bf16 rounding of the float64 value
     Xo = oracle_features(b, on, og)
-    S.check("features", X, Xo, (S.U + 2 * S.F32) * np.abs(Xo))
+    # float32 evaluation on the device (conversion, scaling, log1pf, 1/scale:
+    # a few ulp), then one bf16 rounding
+    S.check("features", X, Xo, (S.U + 16 * S.F32) * np.abs(Xo))
     # forward stages on the device's own inputs
     e, sa = S.layer_stage(X, W1, b1, 48)
     S.check("h1", H1, e, S.act_bound(e, sa, 48))
@@ -403,4 +405,59 @@ def test_candidates_are_the_k_lowest_scores(dev, samples, topk):
         k = min(topk, samples)
         assert np.array_equal(got[:k], want[:k]), g
         assert (got[k:] == np.uint64(0xFFFFFFFFFFFFFFFF)).all()
+    sur.close()
+
+
+def _wide_batch(seed):
+    """Groups on the 64-bit time path (durations up to 2^38 ns) between
+    ordinary ones."""
+    rng = np.random.default_rng(seed)
+    groups = []
+    for i in range(12):
+        n = int(rng.integers(6, 17))
+        hi = (1 << 38) if i % 2 == 0 else 3_000_000
+        groups.append(rng.integers(1, hi, size=(n, 3)).astype(np.int64))
+    tasks = np.concatenate(groups)
+    offs = np.cumsum([0] + [len(g) for g in groups]).astype(np.int32)
+    return groups, tasks, offs
+
+
+def test_64bit_time_path_in_pairs_and_searches(dev):
+    """Groups whose times pass 2^31 ns: exact pairs, the plain search (best
+    sample and time against the oracle's evaluation of every sample) and the
+    learned-proposal search (exact re-score of its own candidates)."""
+    from paper_1806_10113_amd import tgo
+    groups, tasks_np, offs_np = _wide_batch(320)
+    tasks, offs = to_dev(tasks_np, dev), to_dev(offs_np, dev)
+    orders, gid, T, status = tgo.pairs(tasks, offs, 64, seed=18)
+    assert (status.cpu().numpy() == 0).all()
+    on, Tn = orders.cpu().numpy(), T.cpu().numpy()
+    for g, grp in enumerate(groups):
+        n = len(grp)
+        rows = slice(g * 64, (g + 1) * 64)
+        assert np.array_equal(Tn[rows], cmodel.eval_orders(grp, on[rows, :n], M.DEFAULT)), g
+    assert Tn.max() > (1 << 40)
+    res = tgo.read_search(tgo.random_search(tasks, offs, samples=3000, seed=25))
+    for g, grp in enumerate(groups):
+        n = len(grp)
+        smp = philox.sample_orderings(n, g, 0, 3008, 25)  # rounded up to 64-sample tiles
+        Ts = cmodel.eval_orders(grp, smp, M.DEFAULT)
+        s = int(np.argmin(Ts))
+        assert res[g]["status"] == 0
+        assert res[g]["cand_best_ns"] == Ts[s] and res[g]["best_sample"] == s, g
+        h = M.simulate(grp, M.heuristic(grp, M.DEFAULT), M.DEFAULT)
+        assert res[g]["heur_ns"] == h and res[g]["best_ns"] == min(int(Ts[s]), h)
+    sur = tgo.Surrogate(max_rows=1 << 14, max_groups=64)
+    sur.init(12)
+    out = tgo.read_search(sur.search(tasks, offs, samples=2048, topk=16, seed=26))
+    cand = sur.candidates(tasks, offs, samples=2048, topk=16, seed=26).cpu().numpy().view(np.uint64)
+    for g, grp in enumerate(groups):
+        n = len(grp)
+        smp = [int(k) & 0xFFFFFFFF for k in cand[g]]
+        perms = np.array([philox.sample_ordering(n, g, s, 26) for s in smp], dtype=np.uint8)
+        Ts = cmodel.eval_orders(grp, perms, M.DEFAULT)
+        i = min(range(len(smp)), key=lambda j: (int(Ts[j]), smp[j]))
+        r = out[g]
+        assert r["status"] == 0 and r["cand_best_ns"] == Ts[i] and r["best_sample"] == smp[i], g
+        assert r["best_ns"] == cmodel.simulate(grp, r["best"], M.DEFAULT)
     sur.close()
