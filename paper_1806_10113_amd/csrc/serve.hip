@@ -146,11 +146,11 @@ static int admit(tgo_server *S) {
             const int64_t off = pos % R.cap;
             if (off + q->n > R.cap) pos += R.cap - off;  // skip to the start of the ring
             if (pos + q->n - R.head > R.cap) break;     // no room: wait for memory
-            if (pos != R.tail) {
+            const int64_t phys = pos % R.cap;
+            if (first >= 0 && phys != last) {  // not right behind the rows staged so far
                 const int rc = flush();
                 if (rc) return rc;
             }
-            const int64_t phys = pos % R.cap;
             std::memcpy(R.h + phys, q->tasks, sizeof(tgo_task) * (size_t)q->n);
             if (first < 0) first = phys;
             last = phys + q->n;

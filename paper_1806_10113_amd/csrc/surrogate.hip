@@ -469,9 +469,9 @@ __global__ __launch_bounds__(FM_THREADS) void mlp_fused_kernel(const float *__re
 
 // ---------------------------------------------------------------- training
 // One training step is three kernels:
-//   train_fwd_bwd_kernel  32 rows per block: features, the three hidden layers
-//                         and the head on MFMA with the activations in LDS,
-//                         the loss gradient, and back-propagation through
+//   train_fwd_bwd_kernel  128 rows per block: features, the three hidden
+//                         layers and the head on MFMA with the activations in
+//                         LDS, the loss gradient, and back-propagation through
 //                         layers 3 and 2, all without leaving the block.  It
 //                         stores the bf16 activations and activation gradients
 //                         transposed ([feature][row]) for the weight gradients,
@@ -484,12 +484,18 @@ __global__ __launch_bounds__(FM_THREADS) void mlp_fused_kernel(const float *__re
 //                         (optionally) applies Adam and refreshes the bf16
 //                         weight copies.
 // Every wave keeps the B operands of its 32 output columns of a whole layer
-// in registers (64 VGPRs for K = 256), loaded one layer ahead, so the MFMA
-// loop reads only LDS.
+// in registers (64 VGPRs for K = 256), the next layer's loaded while the
+// current one runs, so the MFMA loop reads only LDS.  Every weight a CU
+// fetches serves the block's 128 rows (the weights are the kernel's largest
+// memory stream).  Two LDS activation buffers of 128 rows suffice: the ReLU
+// masks of layers 1 and 2, needed again by the backward pass, stay in
+// registers as bits, because a lane owns the same (row, column) elements in
+// every layer.
 constexpr int TR_WAVES = 8;
 constexpr int TR_THREADS = 64 * TR_WAVES;   // wave w owns output columns 32w .. 32w+31
-constexpr int TR_RT = 2;                    // row tiles of 16
-constexpr int TR_ROWS = 16 * TR_RT;         // rows per block (one thread per (row, position): 32 x 16)
+constexpr int TR_RT = 8;                    // row tiles of 16
+constexpr int TR_ROWS = 16 * TR_RT;         // rows per block
+constexpr int TR_HALF = TR_RT / 2;          // row tiles per MFMA pass (two passes per layer)
 constexpr int TR_LD = SG_H + 8;             // LDS pitch (bf16) of a 256-wide activation
 constexpr int TR_LD0 = SG_K0 + 8;           // LDS pitch of the 64-wide input
 // per-block vector: sums over the block's rows of the bias gradients of
@@ -499,10 +505,11 @@ constexpr int TR_VLEN = 1026, TR_VSTRIDE = 1028;
 constexpr int WG_TILES = 36;                // 16 (layer 3) + 16 (layer 2) + 4 (layer 1) tiles of 64 x 64
 constexpr int WG_VEC_BLOCKS = (TR_VLEN + 255) / 256;
 constexpr int WG_KS_MAX = 64;               // K chunks (partials) at most
-constexpr int WG_KC = 512;                  // rows per K chunk (more for larger batches)
-constexpr int WG_STEPS = 4;                 // K steps per wave loaded at once (4 waves x 4 x 32 = 512 rows)
+constexpr int WG_KC = 1024;                 // rows per K chunk (more for larger batches): 256 per wave
+constexpr int WG_DEPTH = 4;                 // K steps whose loads a wave has in flight
 constexpr int WG_TILE = 64 * 64;
-static_assert(TR_ROWS * SG_POS == TR_THREADS, "one thread per (row, position)");
+static_assert(TR_ROWS * SG_POS % TR_THREADS == 0, "features: whole passes of one thread per (row, position)");
+static_assert(2 * TR_HALF * 2 * 4 == 64, "a lane's ReLU mask bits fill one 64-bit word");
 
 // Block barrier that waits only for this wave's LDS accesses: __syncthreads()
 // also waits for every outstanding global load and store, which would drain
@@ -512,6 +519,11 @@ static_assert(TR_ROWS * SG_POS == TR_THREADS, "one thread per (row, position)");
 __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
+
+// Keeps the compiler from moving memory accesses across this point (no
+// instruction): the next layer's weight loads stay behind the current layer,
+// so that at most two layers' weights are live in registers.
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
 
 template <int K>
 struct WRegs {
@@ -529,22 +541,23 @@ __device__ __forceinline__ void wload(WRegs<K> &t, const uint16_t *__restrict__ 
         for (int b = 0; b < 2; ++b) t.v[s][b] = *reinterpret_cast<const bf16x8 *>(base + (int64_t)16 * b * K + GK * s);
 }
 
-// acc[a][b] = A[16a .. 16a+15][0..K) x W[cols of tile b][0..K)^T; lane l ends
-// with rows 16a + 4(l/16) + i, column 32w + 16b + l%16.
-template <int K, int LD>
-__device__ __forceinline__ void wmma(const uint16_t (*A)[LD], const WRegs<K> &t, int l, f32x4 (&acc)[TR_RT][2]) {
+// acc[a][b] = A[16(a0 + a) .. +15][0..K) x W[cols of tile b][0..K)^T; lane l
+// ends with rows 16(a0 + a) + 4(l/16) + i, column 32w + 16b + l%16.
+template <int K, int LD, int RA>
+__device__ __forceinline__ void wmma_rows(const uint16_t (*A)[LD], int a0, const WRegs<K> &t, int l,
+                                          f32x4 (&acc)[RA][2]) {
 #pragma unroll
-    for (int a = 0; a < TR_RT; ++a)
+    for (int a = 0; a < RA; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < K / GK; ++s) {
-        bf16x8 fa[TR_RT];
+        bf16x8 fa[RA];
 #pragma unroll
-        for (int a = 0; a < TR_RT; ++a)
-            fa[a] = *reinterpret_cast<const bf16x8 *>(&A[16 * a + (l & 15)][GK * s + (l >> 4) * 8]);
+        for (int a = 0; a < RA; ++a)
+            fa[a] = *reinterpret_cast<const bf16x8 *>(&A[16 * (a0 + a) + (l & 15)][GK * s + (l >> 4) * 8]);
 #pragma unroll
-        for (int a = 0; a < TR_RT; ++a)
+        for (int a = 0; a < RA; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], t.v[s][b], acc[a][b], 0, 0, 0);
@@ -552,13 +565,15 @@ __device__ __forceinline__ void wmma(const uint16_t (*A)[LD], const WRegs<K> &t,
 }
 
 // Transposed store of an LDS activation block: dst[c][r0 + r] = S[r][c] for
-// c < width, r < TR_ROWS (8 rows = 16 bytes per store).
+// c < width, r < TR_ROWS, r0 + r < ld (8 rows = 16 bytes per store; ld is a
+// multiple of 64, so a store of 8 rows is all inside or all outside).
 template <int LD>
 __device__ __forceinline__ void store_t(const uint16_t (*S)[LD], int width, uint16_t *dst, int64_t ld, int r0,
                                         int tid) {
     const int chunks = width * (TR_ROWS / 8);
     for (int q = tid; q < chunks; q += TR_THREADS) {
         const int c = q / (TR_ROWS / 8), r = (q % (TR_ROWS / 8)) * 8;
+        if (r0 + r >= ld) continue;
         uint4 v;
         v.x = S[r][c] | ((uint32_t)S[r + 1][c] << 16);
         v.y = S[r + 2][c] | ((uint32_t)S[r + 3][c] << 16);
@@ -570,8 +585,9 @@ __device__ __forceinline__ void store_t(const uint16_t (*S)[LD], int width, uint
 
 // The four values a lane holds for (row tile a, column col) are rows
 // 16a + 4(l/16) + 0..3 of that column: one 8-byte store into the transposed
-// layout dst[col][row].
+// layout dst[col][row], skipped past the ld rows the layout holds.
 __device__ __forceinline__ void store4_t(uint16_t *dst, int64_t ld, int col, int row0, const uint16_t (&v)[4]) {
+    if (row0 >= ld) return;
     uint2 q;
     q.x = v[0] | ((uint32_t)v[1] << 16);
     q.y = v[2] | ((uint32_t)v[3] << 16);
@@ -587,8 +603,10 @@ __device__ __forceinline__ float col_total(float v) {
     return v;
 }
 
-// Forward and backward of the rows [32 blockIdx.x, +32).  Rows >= `rows`
+// Forward and backward of the rows [128 blockIdx.x, +128).  Rows >= `rows`
 // carry zero features and zero loss gradient.  inv_rows = 1 / rows.
+// LDS: bufA holds h1, then h3 and, in place, dL/dz3; bufB holds the input
+// features, then h2, then dL/dz2.
 __global__ __launch_bounds__(TR_THREADS) void train_fwd_bwd_kernel(
     const tgo_task *__restrict__ tasks, const int32_t *__restrict__ offs, const uint8_t *__restrict__ orders,
     const int32_t *__restrict__ gid, const int64_t *__restrict__ T, int rows, float inv_rows,
@@ -596,57 +614,85 @@ __global__ __launch_bounds__(TR_THREADS) void train_fwd_bwd_kernel(
     const uint16_t *__restrict__ W2t, const uint16_t *__restrict__ W3t, const float *__restrict__ p, int64_t ld,
     uint16_t *Xt, uint16_t *H1t, uint16_t *H2t, uint16_t *G3t, uint16_t *G2t, uint16_t *G1t, float *vec,
     uint16_t *H3keep, float *score_keep) {
-    __shared__ __align__(16) uint16_t Xs[TR_ROWS][TR_LD0];
-    __shared__ __align__(16) uint16_t H1s[TR_ROWS][TR_LD];
-    __shared__ __align__(16) uint16_t H2s[TR_ROWS][TR_LD];
-    __shared__ __align__(16) uint16_t G3s[TR_ROWS][TR_LD];
+    __shared__ __align__(16) uint16_t bufA[TR_ROWS][TR_LD];
+    __shared__ __align__(16) uint16_t bufB[TR_ROWS][TR_LD];
     __shared__ float part[TR_WAVES][TR_ROWS];
     __shared__ float ys[TR_ROWS], dss[TR_ROWS];
+    uint16_t (*Xs)[TR_LD0] = reinterpret_cast<uint16_t (*)[TR_LD0]>(&bufB[0][0]);
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int r0 = blockIdx.x * TR_ROWS;
     float *vb = vec + (int64_t)blockIdx.x * TR_VSTRIDE;
+    // the row a lane's element (pass h, row tile a, value i) belongs to, and
+    // the bit of that element in the lane's ReLU masks
+#define TR_ROW(h, a, i) (16 * ((h) * TR_HALF + (a)) + 4 * (l >> 4) + (i))
+#define TR_BIT(h, a, b, i) ((((h) * TR_HALF + (a)) * 2 + (b)) * 4 + (i))
 
     WRegs<SG_K0> w1r;
     wload(w1r, W1, w, l);
     WRegs<SG_H> w2r;
     wload(w2r, W2, w, l);
+    // biases and head weights of this lane's two columns
+    float bias1[2], bias2[2], bias3[2], w4c[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int col = 32 * w + 16 * b + (l & 15);
+        bias1[b] = p[SG_OFF_B1 + col];
+        bias2[b] = p[SG_OFF_B2 + col];
+        bias3[b] = p[SG_OFF_B3 + col];
+        w4c[b] = p[SG_OFF_W4 + col];
+    }
+    const float bias4 = p[SG_OFF_B4];
 
-    // features of (row, position); the target of each row
-    {
-        const int rr = tid >> 4, pos = tid & 15;
+    // features of (row, position) and the target of each row, 32 rows per
+    // pass.  The 16 lanes of a row also hold the group's tasks (lane x: task
+    // x) for the target's lower bound, reduced across the row's lanes: every
+    // global load of a row is issued at one of three dependent levels
+    // (row -> group -> tasks)
+#pragma unroll
+    for (int it = 0; it < TR_ROWS * SG_POS / TR_THREADS; ++it) {
+        const int rr = 32 * it + (tid >> 4), pos = tid & 15;
         const int i = r0 + rr;
+        const bool live = i < rows;
+        const int g = live ? gid[i] : 0;
+        const int x = live ? orders[(int64_t)i * SG_POS + pos] : 0;
+        const int64_t Ti = live && pos == 0 ? T[i] : 0;
+        const int b = live ? offs[g] : 0;
+        const int n = live ? offs[g + 1] - b : 0;
         uint16_t f0 = 0, f1 = 0, f2 = 0;
-        if (i < rows) {
-            const int g = gid[i];
-            const int b = offs[g], n = offs[g + 1] - b;
-            const int x = orders[(int64_t)i * SG_POS + pos];
-            if (pos < n && x < n) {
-                const tgo_task t = tasks[b + x];
-                f0 = f2bf(feature_value(t.htd_ns));
-                f1 = f2bf(feature_value(t.kern_ns));
-                f2 = f2bf(feature_value(t.dth_ns));
-            }
-            if (pos == 0) {
-                // y = T / LB - 1, LB the largest machine lower bound of the group
-                int64_t sh = 0, sk = 0, sd = 0, mh = INT64_MAX, md = INT64_MAX, mkd = INT64_MAX, mhk = INT64_MAX;
-                for (int xx = 0; xx < n; ++xx) {
-                    const tgo_task t = tasks[b + xx];
-                    sh += t.htd_ns;
-                    sk += t.kern_ns;
-                    sd += t.dth_ns;
-                    mh = t.htd_ns < mh ? t.htd_ns : mh;
-                    md = t.dth_ns < md ? t.dth_ns : md;
-                    mkd = t.kern_ns + t.dth_ns < mkd ? t.kern_ns + t.dth_ns : mkd;
-                    mhk = t.htd_ns + t.kern_ns < mhk ? t.htd_ns + t.kern_ns : mhk;
-                }
-                int64_t lb = sh + mkd;
-                lb = mh + sk + md > lb ? mh + sk + md : lb;
-                lb = mhk + sd > lb ? mhk + sd : lb;
-                lb = lb < 1 ? 1 : lb;
-                ys[rr] = (float)((double)T[i] / (double)lb - 1.0);
-            }
-        } else if (pos == 0) {
-            ys[rr] = 0.f;
+        if (pos < n && x < n) {
+            const tgo_task t = tasks[b + x];
+            f0 = f2bf(feature_value(t.htd_ns));
+            f1 = f2bf(feature_value(t.kern_ns));
+            f2 = f2bf(feature_value(t.dth_ns));
+        }
+        // y = T / LB - 1, LB the largest machine lower bound of the group
+        int64_t sh = 0, sk = 0, sd = 0, mh = INT64_MAX, md = INT64_MAX, mkd = INT64_MAX, mhk = INT64_MAX;
+        if (pos < n) {
+            const tgo_task t = tasks[b + pos];
+            sh = t.htd_ns;
+            sk = t.kern_ns;
+            sd = t.dth_ns;
+            mh = t.htd_ns;
+            md = t.dth_ns;
+            mkd = t.kern_ns + t.dth_ns;
+            mhk = t.htd_ns + t.kern_ns;
+        }
+#pragma unroll
+        for (int m = 1; m < 16; m <<= 1) {
+            sh += shfl_xor64(sh, m);
+            sk += shfl_xor64(sk, m);
+            sd += shfl_xor64(sd, m);
+            mh = min(mh, shfl_xor64(mh, m));
+            md = min(md, shfl_xor64(md, m));
+            mkd = min(mkd, shfl_xor64(mkd, m));
+            mhk = min(mhk, shfl_xor64(mhk, m));
+        }
+        if (pos == 0) {
+            int64_t lb = sh + mkd;
+            lb = mh + sk + md > lb ? mh + sk + md : lb;
+            lb = mhk + sd > lb ? mhk + sd : lb;
+            lb = lb < 1 ? 1 : lb;
+            ys[rr] = live ? (float)((double)Ti / (double)lb - 1.0) : 0.f;
         }
         Xs[rr][3 * pos] = f0;
         Xs[rr][3 * pos + 1] = f1;
@@ -656,106 +702,113 @@ __global__ __launch_bounds__(TR_THREADS) void train_fwd_bwd_kernel(
     lds_barrier();
     store_t(Xs, SG_K0, Xt, ld, r0, tid);
 
-    f32x4 acc[TR_RT][2];
-    // layer 1 -> H1s
-    wmma<SG_K0, TR_LD0>(Xs, w1r, l, acc);
-    WRegs<SG_H> w3r;
-    wload(w3r, W3, w, l);
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const int col = 32 * w + 16 * b + (l & 15);
-        const float bb = p[SG_OFF_B1 + col];
-#pragma unroll
-        for (int a = 0; a < TR_RT; ++a) {
-            uint16_t hv[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float v = acc[a][b][i] + bb;
-                hv[i] = f2bf(v > 0.f ? v : 0.f);
-                H1s[16 * a + 4 * (l >> 4) + i][col] = hv[i];
-            }
-            store4_t(H1t, ld, col, r0 + 16 * a + 4 * (l >> 4), hv);
-        }
-    }
-    lds_barrier();
-    // layer 2 -> H2s
-    wmma<SG_H, TR_LD>(H1s, w2r, l, acc);
-    WRegs<SG_H> w3tr;
-    wload(w3tr, W3t, w, l);
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const int col = 32 * w + 16 * b + (l & 15);
-        const float bb = p[SG_OFF_B2 + col];
-#pragma unroll
-        for (int a = 0; a < TR_RT; ++a) {
-            uint16_t hv[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float v = acc[a][b][i] + bb;
-                hv[i] = f2bf(v > 0.f ? v : 0.f);
-                H2s[16 * a + 4 * (l >> 4) + i][col] = hv[i];
-            }
-            store4_t(H2t, ld, col, r0 + 16 * a + 4 * (l >> 4), hv);
-        }
-    }
-    lds_barrier();
-    // layer 3, kept in registers as bf16, and the head's per-wave row sums
-    wmma<SG_H, TR_LD>(H2s, w3r, l, acc);
-    WRegs<SG_H> w2tr;
-    wload(w2tr, W2t, w, l);
-    uint16_t h3[TR_RT][2][4];
-    float w4c[2];
-    {
-        float sum[TR_RT][4];
-#pragma unroll
-        for (int a = 0; a < TR_RT; ++a)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) sum[a][i] = 0.f;
+    uint64_t m1 = 0, m2 = 0;  // ReLU masks of layers 1 and 2 (bit TR_BIT: h > 0)
+    // layer 1: Xs -> bufA
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+        f32x4 acc[TR_HALF][2];
+        wmma_rows<SG_K0, TR_LD0, TR_HALF>(Xs, h * TR_HALF, w1r, l, acc);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const int col = 32 * w + 16 * b + (l & 15);
-            const float bb = p[SG_OFF_B3 + col];
-            w4c[b] = p[SG_OFF_W4 + col];
 #pragma unroll
-            for (int a = 0; a < TR_RT; ++a)
+            for (int a = 0; a < TR_HALF; ++a) {
+                uint16_t hv[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const float v = acc[a][b][i] + bb;
-                    h3[a][b][i] = f2bf(v > 0.f ? v : 0.f);
-                    sum[a][i] += bf2f(h3[a][b][i]) * w4c[b];
+                    const float v = acc[a][b][i] + bias1[b];
+                    hv[i] = f2bf(v > 0.f ? v : 0.f);
+                    bufA[TR_ROW(h, a, i)][col] = hv[i];
+                    m1 |= (uint64_t)(hv[i] != 0) << TR_BIT(h, a, b, i);
+                }
+                store4_t(H1t, ld, col, r0 + TR_ROW(h, a, 0), hv);
+            }
+        }
+    }
+    compiler_fence();  // the next layer's weights load only once this layer is done
+    WRegs<SG_H> w3r;
+    wload(w3r, W3, w, l);
+    lds_barrier();
+    // layer 2: bufA -> bufB (the input features are no longer read)
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+        f32x4 acc[TR_HALF][2];
+        wmma_rows<SG_H, TR_LD, TR_HALF>(bufA, h * TR_HALF, w2r, l, acc);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int col = 32 * w + 16 * b + (l & 15);
+#pragma unroll
+            for (int a = 0; a < TR_HALF; ++a) {
+                uint16_t hv[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float v = acc[a][b][i] + bias2[b];
+                    hv[i] = f2bf(v > 0.f ? v : 0.f);
+                    bufB[TR_ROW(h, a, i)][col] = hv[i];
+                    m2 |= (uint64_t)(hv[i] != 0) << TR_BIT(h, a, b, i);
+                }
+                store4_t(H2t, ld, col, r0 + TR_ROW(h, a, 0), hv);
+            }
+        }
+    }
+    compiler_fence();  // the next layer's weights load only once this layer is done
+    WRegs<SG_H> w3tr;
+    wload(w3tr, W3t, w, l);
+    lds_barrier();
+    // layer 3: bufB -> bufA (h1 is no longer read: its mask is in m1), and
+    // the head's per-wave row sums
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+        f32x4 acc[TR_HALF][2];
+        wmma_rows<SG_H, TR_LD, TR_HALF>(bufB, h * TR_HALF, w3r, l, acc);
+#pragma unroll
+        for (int a = 0; a < TR_HALF; ++a) {
+            float sum[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int col = 32 * w + 16 * b + (l & 15);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float v = acc[a][b][i] + bias3[b];
+                    const uint16_t hq = f2bf(v > 0.f ? v : 0.f);
+                    bufA[TR_ROW(h, a, i)][col] = hq;
+                    sum[i] += bf2f(hq) * w4c[b];
                     if (H3keep) {
-                        const int row = r0 + 16 * a + 4 * (l >> 4) + i;
-                        if (row < rows) H3keep[(int64_t)row * SG_H + col] = h3[a][b][i];
+                        const int row = r0 + TR_ROW(h, a, i);
+                        if (row < rows) H3keep[(int64_t)row * SG_H + col] = hq;
                     }
                 }
-        }
-#pragma unroll
-        for (int a = 0; a < TR_RT; ++a)
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                float v = sum[a][i];
+                float v = sum[i];
                 for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m);
-                if ((l & 15) == 0) part[w][16 * a + 4 * (l >> 4) + i] = v;
+                if ((l & 15) == 0) part[w][TR_ROW(h, a, i)] = v;
             }
+        }
     }
+    compiler_fence();  // the next layer's weights load only once this layer is done
+    WRegs<SG_H> w2tr;
+    wload(w2tr, W2t, w, l);
     lds_barrier();
-    // scores, loss gradient and loss (wave 0)
+    // scores, loss gradient and loss (wave 0: rows l and l + 64)
     if (w == 0) {
         float e = 0.f, dsum = 0.f;
-        if (l < TR_ROWS) {
-            const int i = r0 + l;
-            float s = p[SG_OFF_B4];
 #pragma unroll
-            for (int v = 0; v < TR_WAVES; ++v) s += part[v][l];
+        for (int q = 0; q < TR_ROWS / 64; ++q) {
+            const int row = l + 64 * q, i = r0 + row;
+            float sc = bias4;
+#pragma unroll
+            for (int v = 0; v < TR_WAVES; ++v) sc += part[v][row];
             float ds = 0.f;
             if (i < rows) {
-                const float d = s - ys[l];
+                const float d = sc - ys[row];
                 ds = 2.f * d * inv_rows;
-                e = d * d * inv_rows;
-                if (score_keep) score_keep[i] = s;
+                e += d * d * inv_rows;
+                if (score_keep) score_keep[i] = sc;
             }
-            dss[l] = ds;
-            dsum = ds;
+            dss[row] = ds;
+            dsum += ds;
         }
         for (int m = 32; m >= 1; m >>= 1) {
             e += __shfl_xor(e, m);
@@ -767,27 +820,29 @@ __global__ __launch_bounds__(TR_THREADS) void train_fwd_bwd_kernel(
         }
     }
     lds_barrier();
-    // G3 = dL/dz3 = ds w4 where h3 > 0, into G3s; head and layer-3 bias sums
+    // dL/dz3 = ds w4 where h3 > 0, in place of h3 in bufA; head and layer-3 bias sums
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
         const int col = 32 * w + 16 * b + (l & 15);
         float gw4 = 0.f, gb3 = 0.f;
 #pragma unroll
-        for (int a = 0; a < TR_RT; ++a) {
-            uint16_t gv[4];
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = 16 * a + 4 * (l >> 4) + i;
-                const float ds = dss[row];
-                const float h = bf2f(h3[a][b][i]);
-                const uint16_t g = h > 0.f ? f2bf(ds * w4c[b]) : (uint16_t)0;
-                gv[i] = g;
-                G3s[row][col] = g;
-                gw4 += ds * h;
-                gb3 += bf2f(g);
+            for (int a = 0; a < TR_HALF; ++a) {
+                uint16_t gv[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = TR_ROW(h, a, i);
+                    const float ds = dss[row];
+                    const float hf = bf2f(bufA[row][col]);
+                    const uint16_t g = hf > 0.f ? f2bf(ds * w4c[b]) : (uint16_t)0;
+                    gv[i] = g;
+                    bufA[row][col] = g;
+                    gw4 += ds * hf;
+                    gb3 += bf2f(g);
+                }
+                store4_t(G3t, ld, col, r0 + TR_ROW(h, a, 0), gv);
             }
-            store4_t(G3t, ld, col, r0 + 16 * a + 4 * (l >> 4), gv);
-        }
         gw4 = col_total(gw4);
         gb3 = col_total(gb3);
         if (l < 16) {
@@ -796,73 +851,114 @@ __global__ __launch_bounds__(TR_THREADS) void train_fwd_bwd_kernel(
         }
     }
     lds_barrier();
-    // G2 = (G3 W3) where h2 > 0, over H2s
-    wmma<SG_H, TR_LD>(G3s, w3tr, l, acc);
+    // dL/dz2 = (dL/dz3 W3) where h2 > 0: bufA -> bufB (h2 is no longer read)
+    {
+        float gb[2] = {0.f, 0.f};
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+            f32x4 acc[TR_HALF][2];
+            wmma_rows<SG_H, TR_LD, TR_HALF>(bufA, h * TR_HALF, w3tr, l, acc);
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const int col = 32 * w + 16 * b + (l & 15);
-        float gb = 0.f;
+            for (int b = 0; b < 2; ++b) {
+                const int col = 32 * w + 16 * b + (l & 15);
 #pragma unroll
-        for (int a = 0; a < TR_RT; ++a) {
-            uint16_t gv[4];
+                for (int a = 0; a < TR_HALF; ++a) {
+                    uint16_t gv[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = 16 * a + 4 * (l >> 4) + i;
-                const uint16_t g = bf2f(H2s[row][col]) > 0.f ? f2bf(acc[a][b][i]) : (uint16_t)0;
-                gv[i] = g;
-                H2s[row][col] = g;
-                gb += bf2f(g);
+                    for (int i = 0; i < 4; ++i) {
+                        const uint16_t g = (m2 >> TR_BIT(h, a, b, i)) & 1 ? f2bf(acc[a][b][i]) : (uint16_t)0;
+                        gv[i] = g;
+                        bufB[TR_ROW(h, a, i)][col] = g;
+                        gb[b] += bf2f(g);
+                    }
+                    store4_t(G2t, ld, col, r0 + TR_ROW(h, a, 0), gv);
+                }
             }
-            store4_t(G2t, ld, col, r0 + 16 * a + 4 * (l >> 4), gv);
         }
-        gb = col_total(gb);
-        if (l < 16) vb[TR_V_B2 + col] = gb;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const float t = col_total(gb[b]);
+            if (l < 16) vb[TR_V_B2 + 32 * w + 16 * b + l] = t;
+        }
     }
     lds_barrier();
-    // G1 = (G2 W2) where h1 > 0, over H1s
-    wmma<SG_H, TR_LD>(H2s, w2tr, l, acc);
+    // dL/dz1 = (dL/dz2 W2) where h1 > 0, from bufB; stored only
+    {
+        float gb[2] = {0.f, 0.f};
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+            f32x4 acc[TR_HALF][2];
+            wmma_rows<SG_H, TR_LD, TR_HALF>(bufB, h * TR_HALF, w2tr, l, acc);
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const int col = 32 * w + 16 * b + (l & 15);
-        float gb = 0.f;
+            for (int b = 0; b < 2; ++b) {
+                const int col = 32 * w + 16 * b + (l & 15);
 #pragma unroll
-        for (int a = 0; a < TR_RT; ++a) {
-            uint16_t gv[4];
+                for (int a = 0; a < TR_HALF; ++a) {
+                    uint16_t gv[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = 16 * a + 4 * (l >> 4) + i;
-                const uint16_t g = bf2f(H1s[row][col]) > 0.f ? f2bf(acc[a][b][i]) : (uint16_t)0;
-                gv[i] = g;
-                H1s[row][col] = g;
-                gb += bf2f(g);
+                    for (int i = 0; i < 4; ++i) {
+                        const uint16_t g = (m1 >> TR_BIT(h, a, b, i)) & 1 ? f2bf(acc[a][b][i]) : (uint16_t)0;
+                        gv[i] = g;
+                        gb[b] += bf2f(g);
+                    }
+                    store4_t(G1t, ld, col, r0 + TR_ROW(h, a, 0), gv);
+                }
             }
-            store4_t(G1t, ld, col, r0 + 16 * a + 4 * (l >> 4), gv);
         }
-        gb = col_total(gb);
-        if (l < 16) vb[TR_V_B1 + col] = gb;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const float t = col_total(gb[b]);
+            if (l < 16) vb[TR_V_B1 + 32 * w + 16 * b + l] = t;
+        }
     }
+#undef TR_ROW
+#undef TR_BIT
+}
+
+// src[0] + src[stride] + ... + src[(ks - 1) stride], added in that order, with
+// the loads issued eight at a time.
+__device__ __forceinline__ float chunk_sum(const float *__restrict__ src, int64_t stride, int ks) {
+    float s = 0.f;
+    int c = 0;
+    for (; c + 8 <= ks; c += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(c + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; c < ks; ++c) s += src[(int64_t)c * stride];
+    return s;
 }
 
 // Weight gradients dW[o][i] = sum over rows of G[r][o] A[r][i] for the three
 // layers (A = X, h1, h2; G = dL/dz1..3), one 64 x 64 output tile and one K
 // chunk of kc rows per block: blockIdx.x = tile (0..15 layer 3, 16..31 layer
 // 2, 32..35 layer 1) or WG_TILES + j for the per-block vectors (entries
-// 256j .. 256j+255 summed over the chunk's row blocks); blockIdx.y = chunk.
-// The four waves take interleaved K steps straight from global memory (both
-// operands are K-contiguous) and add their tiles in LDS at the end.
+// 256j .. 256j+255 summed over the chunk's row blocks).  Work items (chunk,
+// tile) map to blocks so that every item of a chunk runs on one XCD: blocks
+// are handed to the 8 XCDs in turn (block b to XCD b % 8), and XCD x takes
+// the chunks x, x + 8, ...  The chunk's rows of the six activation arrays are
+// then fetched into that XCD's L2 once and read from there by its 41 items.
+// The four waves take a quarter of the chunk each, straight from global
+// memory (both operands are K-contiguous), and add their tiles in LDS at the
+// end.
 __global__ __launch_bounds__(256) void train_wgrad_kernel(
     const uint16_t *__restrict__ Xt, const uint16_t *__restrict__ H1t, const uint16_t *__restrict__ H2t,
     const uint16_t *__restrict__ G1t, const uint16_t *__restrict__ G2t, const uint16_t *__restrict__ G3t,
     int64_t ld, int rows, int kc, const float *__restrict__ vec, float *wpart, float *vpart) {
-    const int tile = blockIdx.x, chunk = blockIdx.y;
+    constexpr int ITEMS = WG_TILES + WG_VEC_BLOCKS;
+    const int xcd = blockIdx.x % 8, j = blockIdx.x / 8;
+    const int chunk = xcd + 8 * (j / ITEMS), tile = j % ITEMS;
+    const int ks = (rows + kc - 1) / kc;
+    if (chunk >= ks) return;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int k0 = chunk * kc, k1 = min(rows, k0 + kc);
     if (tile >= WG_TILES) {
-        const int j = (tile - WG_TILES) * 256 + tid;
-        if (j < TR_VLEN) {
-            float s = 0.f;
-            for (int blk = k0 / TR_ROWS; blk < (k1 + TR_ROWS - 1) / TR_ROWS; ++blk) s += vec[(int64_t)blk * TR_VSTRIDE + j];
-            vpart[(int64_t)chunk * TR_VSTRIDE + j] = s;
+        const int e = (tile - WG_TILES) * 256 + tid;
+        if (e < TR_VLEN) {
+            const int b0 = k0 / TR_ROWS, b1 = (k1 + TR_ROWS - 1) / TR_ROWS;
+            vpart[(int64_t)chunk * TR_VSTRIDE + e] = chunk_sum(vec + (int64_t)b0 * TR_VSTRIDE + e, TR_VSTRIDE, b1 - b0);
         }
         return;
     }
@@ -883,29 +979,43 @@ __global__ __launch_bounds__(256) void train_wgrad_kernel(
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // batches of WG_STEPS K steps per wave (steps w, w + 4, ...): every load of
-    // a batch is issued before its first MFMA
-    for (int kb = k0 + GK * w; kb < k1; kb += 4 * GK * WG_STEPS) {
-        bf16x8 fa[WG_STEPS][4], fb[WG_STEPS][4];
+    // wave w takes the contiguous quarter [kw0, kw1) of the chunk, 32 rows
+    // per K step, with the loads of the next WG_DEPTH - 1 steps in flight
+    // while a step's MFMAs run.  A last partial step reads rows up to the next
+    // multiple of 32, which the forward kernel wrote (zero gradients) and
+    // which lie below ld.
+    const int kq = kc / 4;
+    const int kw0 = k0 + w * kq, kw1 = min(k1, kw0 + kq);
+    const int steps = kw1 > kw0 ? (kw1 - kw0 + GK - 1) / GK : 0;
+    bf16x8 fa[WG_DEPTH][4], fb[WG_DEPTH][4];
 #pragma unroll
-        for (int q = 0; q < WG_STEPS; ++q) {
-            const int k = kb + 4 * GK * q;
-            if (k < k1) {
+    for (int q = 0; q < WG_DEPTH; ++q) {
+        if (q < steps) {
+            const int k = kw0 + GK * q;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    fa[q][t] = *reinterpret_cast<const bf16x8 *>(Ab + (int64_t)16 * t * ld + k);
-                    fb[q][t] = *reinterpret_cast<const bf16x8 *>(Bb + (int64_t)16 * t * ld + k);
-                }
+            for (int t = 0; t < 4; ++t) {
+                fa[q][t] = *reinterpret_cast<const bf16x8 *>(Ab + (int64_t)16 * t * ld + k);
+                fb[q][t] = *reinterpret_cast<const bf16x8 *>(Bb + (int64_t)16 * t * ld + k);
             }
         }
+    }
+    for (int s0 = 0; s0 < steps; s0 += WG_DEPTH) {
 #pragma unroll
-        for (int q = 0; q < WG_STEPS; ++q) {
-            if (kb + 4 * GK * q < k1) {
+        for (int q = 0; q < WG_DEPTH; ++q) {
+            if (s0 + q < steps) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
                         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[q][a], fb[q][b], acc[a][b], 0, 0, 0);
+                if (s0 + q + WG_DEPTH < steps) {
+                    const int k = kw0 + GK * (s0 + q + WG_DEPTH);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        fa[q][t] = *reinterpret_cast<const bf16x8 *>(Ab + (int64_t)16 * t * ld + k);
+                        fb[q][t] = *reinterpret_cast<const bf16x8 *>(Bb + (int64_t)16 * t * ld + k);
+                    }
+                }
             }
         }
     }
@@ -947,11 +1057,7 @@ __global__ void train_update_kernel(int mode, const float *__restrict__ wpart, c
                                     AdamArgs a, float *loss, uint16_t *W1, uint16_t *W2, uint16_t *W2t,
                                     uint16_t *W3, uint16_t *W3t) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (mode != 2 && i == 0) {
-        float s = 0.f;
-        for (int c = 0; c < ks; ++c) s += vpart[(int64_t)c * TR_VSTRIDE + TR_V_LOSS];
-        *loss = s;
-    }
+    if (mode != 2 && i == 0) *loss = chunk_sum(vpart + TR_V_LOSS, TR_VSTRIDE, ks);
     if (i >= SG_NPARAM) return;
     float gi;
     if (mode == 2) {
@@ -979,13 +1085,9 @@ __global__ void train_update_kernel(int mode, const float *__restrict__ wpart, c
         } else {
             vidx = TR_V_B4;
         }
-        float s = 0.f;
-        if (widx >= 0) {
-            for (int c = 0; c < ks; ++c) s += wpart[(int64_t)c * WG_TILES * WG_TILE + widx];
-        } else {
-            for (int c = 0; c < ks; ++c) s += vpart[(int64_t)c * TR_VSTRIDE + vidx];
-        }
-        gi = s;
+        const float *src = widx >= 0 ? wpart + widx : vpart + vidx;
+        const int64_t stride = widx >= 0 ? (int64_t)WG_TILES * WG_TILE : (int64_t)TR_VSTRIDE;
+        gi = chunk_sum(src, stride, ks);
         g[i] = gi;
     }
     if (mode == 0) return;
@@ -1157,9 +1259,17 @@ __global__ void search_finish_kernel(const int32_t *__restrict__ offs, int G, ui
 
 // ------------------------------------------------------------------- host
 
+// Leading dimension of the transposed activation arrays ([feature][row]):
+// max_rows plus 2,176 elements (4 KiB + 256 B per feature row), so that the
+// rows a wave touches in one access, whose stride would otherwise be a power
+// of two (e.g. 128 KiB at 65,536 rows), spread over the L2 and HBM channels
+// instead of landing on one.
+constexpr int64_t TR_LD_PAD = 2176;
+
 struct tgo_surrogate {
     int device = 0;
     int64_t max_rows = 0;
+    int64_t ldt = 0;  // max_rows + TR_LD_PAD
     int64_t step = 0;
     void *mem = nullptr;
     // parameters: float32 masters, gradient, Adam moments; bf16 working copies
@@ -1206,13 +1316,14 @@ static int train_pass(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t *
                       const int32_t *d_gid, const int64_t *d_T, int rows, bool keep, int *ks_out, hipStream_t st) {
     const int blocks = (rows + TR_ROWS - 1) / TR_ROWS;
     hipLaunchKernelGGL(train_fwd_bwd_kernel, dim3(blocks), dim3(TR_THREADS), 0, st, d_tasks, d_offs, d_orders, d_gid,
-                       d_T, rows, 1.0f / (float)rows, s->W1, s->W2, s->W3, s->W2t, s->W3t, s->p, s->max_rows, s->Xt,
+                       d_T, rows, 1.0f / (float)rows, s->W1, s->W2, s->W3, s->W2t, s->W3t, s->p, s->ldt, s->Xt,
                        s->H1t, s->H2t, s->G3t, s->G2t, s->G1t, s->vec, keep ? s->H3 : (uint16_t *)nullptr,
                        keep ? s->score : (float *)nullptr);
     int ks = 0, kc = 0;
     wgrad_chunks(rows, &ks, &kc);
-    hipLaunchKernelGGL(train_wgrad_kernel, dim3(WG_TILES + WG_VEC_BLOCKS, ks), dim3(256), 0, st, s->Xt, s->H1t,
-                       s->H2t, s->G1t, s->G2t, s->G3t, s->max_rows, rows, kc, s->vec, s->wpart, s->vpart);
+    hipLaunchKernelGGL(train_wgrad_kernel, dim3((WG_TILES + WG_VEC_BLOCKS) * 8 * ((ks + 7) / 8)), dim3(256), 0, st,
+                       s->Xt, s->H1t,
+                       s->H2t, s->G1t, s->G2t, s->G3t, s->ldt, rows, kc, s->vec, s->wpart, s->vpart);
     TGO_HIP(hipGetLastError());
     *ks_out = ks;
     return TGO_OK;
@@ -1252,17 +1363,18 @@ int tgo_surrogate_create(int64_t max_rows, int max_groups, tgo_surrogate **out) 
     tgo_surrogate *s = new (std::nothrow) tgo_surrogate();
     if (!s) return fail(TGO_ENOMEM, "surrogate");
     s->max_rows = max_rows;
+    s->ldt = max_rows + TR_LD_PAD;
     s->max_groups = max_groups;
     (void)hipGetDevice(&s->device);
-    const size_t R = (size_t)max_rows;
+    const size_t R = (size_t)max_rows, LT = (size_t)s->ldt;
     const size_t blocks = (R + TR_ROWS - 1) / TR_ROWS;
     std::vector<std::pair<void **, size_t>> parts = {
         {(void **)&s->p, 4 * SG_NPARAM}, {(void **)&s->g, 4 * SG_NPARAM}, {(void **)&s->m, 4 * SG_NPARAM},
         {(void **)&s->v, 4 * SG_NPARAM},
         {(void **)&s->W1, 2 * SG_H * SG_K0}, {(void **)&s->W2, 2 * SG_H * SG_H}, {(void **)&s->W2t, 2 * SG_H * SG_H},
         {(void **)&s->W3, 2 * SG_H * SG_H}, {(void **)&s->W3t, 2 * SG_H * SG_H},
-        {(void **)&s->Xt, 2 * R * SG_K0}, {(void **)&s->H1t, 2 * R * SG_H}, {(void **)&s->H2t, 2 * R * SG_H},
-        {(void **)&s->G1t, 2 * R * SG_H}, {(void **)&s->G2t, 2 * R * SG_H}, {(void **)&s->G3t, 2 * R * SG_H},
+        {(void **)&s->Xt, 2 * LT * SG_K0}, {(void **)&s->H1t, 2 * LT * SG_H}, {(void **)&s->H2t, 2 * LT * SG_H},
+        {(void **)&s->G1t, 2 * LT * SG_H}, {(void **)&s->G2t, 2 * LT * SG_H}, {(void **)&s->G3t, 2 * LT * SG_H},
         {(void **)&s->H3, 2 * R * SG_H}, {(void **)&s->score, 4 * R},
         {(void **)&s->vec, 4 * blocks * TR_VSTRIDE},
         {(void **)&s->wpart, 4 * (size_t)WG_KS_MAX * WG_TILES * WG_TILE},
@@ -1495,7 +1607,7 @@ int tgo_surrogate_get_batch(tgo_surrogate *s, int what, int64_t rows, void *h_ou
                         : what == 5 ? s->G3t : what == 6 ? s->G2t : s->G1t;
     const int width = what == 0 ? SG_K0 : SG_H, keep = what == 0 ? SG_FEAT : SG_H;
     std::vector<uint16_t> t((size_t)width * rows);
-    TGO_HIP(hipMemcpy2DAsync(t.data(), 2 * (size_t)rows, src, 2 * (size_t)s->max_rows, 2 * (size_t)rows, width,
+    TGO_HIP(hipMemcpy2DAsync(t.data(), 2 * (size_t)rows, src, 2 * (size_t)s->ldt, 2 * (size_t)rows, width,
                              hipMemcpyDeviceToHost, st));
     TGO_HIP(hipStreamSynchronize(st));
     uint16_t *o = (uint16_t *)h_out;

@@ -342,6 +342,26 @@ def test_exhaustive_n13_largest_group(dev):
     assert (got >= s["min_ns"]).all() and (got <= s["max_ns"]).all()
 
 
+@pytest.mark.parametrize("key,dma", [("mixed_n13_seed7", 2), ("mixed_n13_seed1_one_dma", 1)])
+def test_exhaustive_n13_against_stored_oracle(dev, key, dma):
+    """The general N = 13 groups (6 DK + 7 DT, seeds 7 and 1): all
+    6,227,020,800 orderings in one call, every summary field against the
+    oracle's stored full enumeration (tests/golden/make_golden.py), and
+    Algorithm 1's ordering and time."""
+    from paper_1806_10113_amd import tgo
+    g = json.load(open(os.path.join(GOLDEN, "single_group_summaries.json")))[key]
+    seed = 7 if dma == 2 else 1
+    tasks = W.single_group_mixed(13, seed)
+    assert tasks.tolist() == g["tasks_ns"]
+    m = M.Model(g["model"]["q"], g["model"]["p_htd"], g["model"]["p_dth"], g["model"]["dma_engines"])
+    assert m.dma_engines == dma
+    s = tgo.read_summary(tgo.exhaustive(to_dev(tasks, dev), tmodel(m))[0])
+    check_summary(s, g, 13)
+    orders, ns = tgo.heuristic(to_dev(tasks, dev), to_dev(np.array([0, 13], dtype=np.int32), dev), tmodel(m))
+    assert list(orders.cpu().numpy()[0, :13]) == g["heuristic"]
+    assert int(ns.cpu().numpy()[0]) == g["heuristic_ns"]
+
+
 def test_predict_host_buffers(dev):
     """tgo_predict: one ordering from host memory, computed on the device."""
     from paper_1806_10113_amd import tgo
