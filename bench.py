@@ -64,7 +64,12 @@ def parse():
                         "(default all)")
     p.add_argument("--train-pairs", type=float, default=2e7,
                    help="exact (ordering, time) pairs used to train the proposal network")
-    p.add_argument("--train-batch", type=int, default=8192, help="pairs per training step")
+    p.add_argument("--train-batch", type=int, default=65536,
+                   help="pairs per training step (the forward/backward kernel takes 128 rows per block, "
+                        "so 32,768 or more fill the 256 CUs)")
+    p.add_argument("--train-lr", type=float, default=1e-3, help="Adam learning rate (a quarter of it in the "
+                                                                 "last third of the steps)")
+    p.add_argument("--train-epochs", type=int, default=3, help="passes over the training pairs")
     p.add_argument("--eval-groups", type=int, default=1024)
     p.add_argument("--serve-seconds", type=float, default=10.0)
     p.add_argument("--hw-unit-ms", type=float, default=10.0,
@@ -305,8 +310,10 @@ def hw_validation_extra(dev, unit_ms: float):
     return out
 
 
-def train_surrogate(dev, pairs_total: float, seed: int = 1003, batch: int = 8192, lr: float = 1e-3):
-    """Train the proposal network on exact pairs from groups of N in [8, 16]."""
+def train_surrogate(dev, pairs_total: float, seed: int = 1003, batch: int = 8192, lr: float = 1e-3,
+                    epochs: int = 1):
+    """Train the proposal network on exact pairs from groups of N in [8, 16]
+    (`epochs` passes over the pairs, each in its own shuffled order)."""
     import torch
     from paper_1806_10113_amd import tgo, workloads as W
     per = 1024
@@ -320,12 +327,18 @@ def train_surrogate(dev, pairs_total: float, seed: int = 1003, batch: int = 8192
     sur = tgo.Surrogate(max_rows=max(1 << 16, batch), max_groups=max(4096, groups))
     sur.init(seed)
     P = orders.shape[0]
-    steps = P // batch
-    # one shuffle of the whole set up front; every step then takes a
-    # contiguous slice (no per-step gathers)
-    perm = torch.randperm(P, generator=torch.Generator().manual_seed(seed)).to(dev)
-    orders, gid, T = orders[perm].contiguous(), gid[perm].contiguous(), T[perm].contiguous()
+    per_epoch = P // batch
+    steps = per_epoch * epochs
+    # one shuffle of the whole set per epoch, up front; every step then takes
+    # a contiguous slice (no per-step gathers)
+    gen = torch.Generator().manual_seed(seed)
+    shuffled = []
+    for _ in range(epochs):
+        perm = torch.randperm(P, generator=gen).to(dev)
+        shuffled.append((orders[perm].contiguous(), gid[perm].contiguous(), T[perm].contiguous()))
+    del orders, gid, T
     torch.cuda.synchronize()
+    orders, gid, T = shuffled[0]
     loss = torch.empty(1, dtype=torch.float32, device=dev)
     sur.train_step(tasks, offs, orders[:batch], gid[:batch], T[:batch], lr, loss=loss)
     first = float(loss.cpu()[0])
@@ -335,7 +348,8 @@ def train_surrogate(dev, pairs_total: float, seed: int = 1003, batch: int = 8192
     e0.record(stream)
     for i in range(1, steps):
         rate = lr if i < steps * 2 // 3 else lr / 4
-        sl = slice(i * batch, (i + 1) * batch)
+        orders, gid, T = shuffled[i // per_epoch]
+        sl = slice((i % per_epoch) * batch, (i % per_epoch + 1) * batch)
         sur.train_step(tasks, offs, orders[sl], gid[sl], T[sl], rate, loss=loss)
     e1.record(stream)
     torch.cuda.synchronize()
@@ -344,7 +358,9 @@ def train_surrogate(dev, pairs_total: float, seed: int = 1003, batch: int = 8192
     # forward 2 x 143,616 FLOP per row; backward: activation gradients of
     # layers 3 and 2 (2 x 2 x 65,536) and the weight gradients (2 x 143,360)
     flop_row = 2 * 143616 + 2 * 2 * 65536 + 2 * 143360
-    return sur, {"pairs": int(P), "train_groups": groups, "steps": steps, "batch": batch,
+    del shuffled
+    return sur, {"pairs": int(P), "train_groups": groups, "steps": steps, "batch": batch, "epochs": epochs,
+                 "lr": lr,
                  "pairs_s": t_pairs, "train_s": t_train, "loss_first": first,
                  "loss_last": float(loss.cpu()[0]), "us_per_step": 1e3 * ms / max(1, steps - 1),
                  "train_flop_per_s": flop_row * batch * (steps - 1) / (ms / 1e3),
@@ -414,7 +430,7 @@ def surrogate_extra(dev, sur, n_groups: int):
 
 
 SERVE_CFG = {"streams": 4, "max_batch": 256, "max_batch_large": 64, "samples": 4096, "topk": 64,
-             "budget_bytes": 8 << 30}
+             "budget_bytes": 8 << 30, "window_us": 300}
 SERVE_P99_TARGET_US = 5000.0  # the latency at which serving capacity is stated
 
 
@@ -458,26 +474,28 @@ def serving_extra(dev, sur, seconds: float):
            "latency_window": f"arrivals after the first {warm_s:g} s of a {seconds:g} s trace",
            "config": dict(SERVE_CFG)}
     # capacity: offered load doubled until the server falls behind (achieved
-    # below 95 % of offered) or p99 passes the target
+    # below 95 % of offered)
     pool = W.batch_groups(50_000, 4, 16, seed=5, per_task_label=True)
-    sweep, capacity = [], None
+    sweep, capacity, sustained = [], None, None
     rate = 20_000.0
-    while rate <= 1_280_000.0:
+    while rate <= 640_000.0:
         a = W.poisson_stream(rate, 1.5, pool, seed=6)
         r = {"offered_groups_per_s": rate, **_serve_run(sur, a, 0.5)}
         sweep.append(r)
-        ok = r["achieved_groups_per_s"] >= 0.95 * rate and r["p99_us"] <= SERVE_P99_TARGET_US \
-            and r["bad_status"] == 0
-        if ok:
-            capacity = r["achieved_groups_per_s"]
-        else:
+        keeps_up = r["achieved_groups_per_s"] >= 0.95 * rate and r["bad_status"] == 0
+        if not keeps_up:
             break
+        sustained = r["achieved_groups_per_s"]
+        if r["p99_us"] <= SERVE_P99_TARGET_US:
+            capacity = r["achieved_groups_per_s"]
         rate *= 2
     res["capacity_sweep"] = sweep
     res["capacity_groups_per_s"] = capacity
-    res["capacity_rule"] = (f"largest offered load (doubling from 20,000/s, 1.5 s traces, latency "
-                            f"over arrivals after 0.5 s) served at >= 95 % of the offered rate with "
-                            f"p99 <= {SERVE_P99_TARGET_US:g} us")
+    res["sustained_groups_per_s"] = sustained
+    res["capacity_rule"] = (f"offered load doubled from 20,000/s (1.5 s traces, latency over arrivals "
+                            f"after 0.5 s) until the server falls below 95 % of it: capacity = the largest "
+                            f"load served with p99 <= {SERVE_P99_TARGET_US:g} us, sustained = the largest "
+                            f"load served at any latency")
     # a budget that binds: the server's own memory plus 512 task rows
     tight = res["base_bytes"] + 512 * 24
     a = W.poisson_stream(20_000.0, 2.0, pool, seed=8)
@@ -523,7 +541,7 @@ def extras_summary(extras: dict) -> dict:
             out["proposal_n16"] = pick(d)
     if "serving" in extras:
         out["serving"] = pick(extras["serving"], "offered_groups_per_s", "achieved_groups_per_s", "p50_us",
-                              "p99_us", "bad_status", "capacity_groups_per_s")
+                              "p99_us", "bad_status", "capacity_groups_per_s", "sustained_groups_per_s")
     if "hw_validation" in extras:
         d = extras["hw_validation"]
         if isinstance(d, dict) and "error" not in d:
@@ -669,8 +687,11 @@ def main():
                 extras[name] = {"error": "skipped after a device error in an earlier extra"}
                 return None
             try:
+                t0 = time.perf_counter()
                 r = fn(*a)
                 extras[name] = r
+                print(json.dumps({"extra_done": name, "s": round(time.perf_counter() - t0, 1)}), file=sys.stderr,
+                      flush=True)
                 return r
             except Exception as e:  # noqa: BLE001 - reported, not swallowed
                 msg = f"{type(e).__name__}: {e}"
@@ -687,7 +708,8 @@ def main():
             if name in want:
                 run_extra(name, fn, dev)
         if want & {"proposal", "serving"}:
-            trained = run_extra("proposal_training", lambda: train_surrogate(dev, args.train_pairs, batch=args.train_batch))
+            trained = run_extra("proposal_training", lambda: train_surrogate(dev, args.train_pairs, batch=args.train_batch,
+                                                                             lr=args.train_lr, epochs=args.train_epochs))
             if trained is not None:
                 sur, tr = trained
                 extras["proposal_training"] = tr

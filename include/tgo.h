@@ -367,7 +367,11 @@ typedef struct {
     int32_t max_batch_large;/* groups per surrogate batch (1..4096)            */
     int32_t small_max_n;    /* exhaustive up to this size (1..12)              */
     int32_t topk;           /* exact re-scores per large group (1..64)         */
-    int32_t pad;
+    int32_t window_us;      /* while another batch is in flight, a free stream
+                               waits up to this long (microseconds, measured
+                               from the oldest waiting request's arrival) for
+                               its batch to fill before launching it; 0 =
+                               launch at once (0..100000)                       */
     int64_t samples;        /* scored samples per large group                  */
     uint64_t seed;          /* sampling seed                                   */
 } tgo_server_config;

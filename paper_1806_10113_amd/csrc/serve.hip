@@ -67,6 +67,7 @@ struct Ring {
     int64_t cap = 0;         // rows
     int64_t head = 0, tail = 0;
     std::deque<Request *> q;  // admitted requests in ring order
+    int64_t waiting = 0;      // of those, not launched yet
 };
 
 struct StreamSlot {
@@ -158,6 +159,7 @@ static int admit(tgo_server *S) {
             q->t_admit = now_ns();
             R.tail = pos + q->n;
             R.q.push_back(q);
+            R.waiting += 1;
             S->arrivals[c].pop_front();
         }
         const int rc = flush();
@@ -190,6 +192,7 @@ static int launch(tgo_server *S, StreamSlot &sl, int kind) {
     }
     if (sl.reqs.empty()) return 0;
     for (Request *q : sl.reqs) q->launched = true;
+    R.waiting -= (int64_t)sl.reqs.size();
     // row offsets into the ring; the exhaustive batch is padded with empty
     // groups to its fixed shape so that its captured graph is replayed
     const int ng = kind == 0 ? c.max_batch : (int)sl.reqs.size();
@@ -355,6 +358,15 @@ static void worker_main(tgo_server *S) {
                     }
             }
             if (kind < 0) break;
+            // with another batch in flight, give a small batch up to
+            // window_us (from its oldest request's arrival) to fill
+            const int cap = kind == 0 ? S->cfg.max_batch : S->cfg.max_batch_large;
+            if (S->cfg.window_us > 0 && S->ring[kind].waiting < cap &&
+                now_ns() - oldest < (int64_t)S->cfg.window_us * 1000) {
+                bool other_busy = false;
+                for (const StreamSlot &o : S->slots) other_busy |= o.busy;
+                if (other_busy) break;
+            }
             const int rc = launch(S, sl, kind);
             if (rc) {
                 fail_slot(S, sl, std::string("launch failed: ") + tgo_last_error());
@@ -413,7 +425,7 @@ void tgo_server_config_default(tgo_server_config *c) {
     c->max_batch_large = 64;
     c->small_max_n = 10;
     c->topk = 64;
-    c->pad = 0;
+    c->window_us = 0;
     c->samples = 8192;
     c->seed = 4;
 }
@@ -457,6 +469,7 @@ int tgo_server_create(const tgo_model *model, const tgo_server_config *cfg, tgo_
     if (c.topk < 1 || c.topk > 64 || c.samples < 1 || c.samples > ((int64_t)1 << 32))
         return fail(TGO_EINVAL, "bad search parameters");
     if (c.budget_bytes <= 0) return fail(TGO_EINVAL, "budget must be positive");
+    if (c.window_us < 0 || c.window_us > 100000) return fail(TGO_EINVAL, "window_us must be in 0..100000");
     tgo_server *S = new (std::nothrow) tgo_server();
     if (!S) return fail(TGO_ENOMEM, "server");
     S->model = *model;

@@ -502,12 +502,13 @@ constexpr int TR_LD0 = SG_K0 + 8;           // LDS pitch of the 64-wide input
 // layers 1..3, the head weight and bias gradients, and the loss
 constexpr int TR_V_B1 = 0, TR_V_B2 = 256, TR_V_B3 = 512, TR_V_W4 = 768, TR_V_B4 = 1024, TR_V_LOSS = 1025;
 constexpr int TR_VLEN = 1026, TR_VSTRIDE = 1028;
-constexpr int WG_TILES = 36;                // 16 (layer 3) + 16 (layer 2) + 4 (layer 1) tiles of 64 x 64
+constexpr int WG_BT = 128;                  // weight-gradient output tile: 128 x 128 (layer 1: 128 x 64)
+constexpr int WG_TILES = 10;                // 4 (layer 3) + 4 (layer 2) + 2 (layer 1)
+constexpr int WG_BK = 64;                   // rows (K) per LDS stage
+constexpr int WG_LDK = WG_BK + 8;           // LDS pitch (bf16) of a staged operand row
 constexpr int WG_VEC_BLOCKS = (TR_VLEN + 255) / 256;
 constexpr int WG_KS_MAX = 64;               // K chunks (partials) at most
-constexpr int WG_KC = 1024;                 // rows per K chunk (more for larger batches): 256 per wave
-constexpr int WG_DEPTH = 4;                 // K steps whose loads a wave has in flight
-constexpr int WG_TILE = 64 * 64;
+constexpr int WG_KC = 1024;                 // rows per K chunk (more for larger batches)
 static_assert(TR_ROWS * SG_POS % TR_THREADS == 0, "features: whole passes of one thread per (row, position)");
 static_assert(2 * TR_HALF * 2 * 4 == 64, "a lane's ReLU mask bits fill one 64-bit word");
 
@@ -931,18 +932,63 @@ __device__ __forceinline__ float chunk_sum(const float *__restrict__ src, int64_
     return s;
 }
 
+// One LDS stage of the weight-gradient kernel: rows cr + 32q (q < 4) of the
+// G and A feature blocks, 8 K values from k on, one 16-byte load each (A rows
+// at or past na are zero).  The staging arrays use a native vector type: with
+// HIP's uint4 (a struct) the compiler kept them in scratch memory.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void wg_fetch(u32x4 (&rg)[4], u32x4 (&ra)[4], const uint16_t *gsrc, const uint16_t *asrc,
+                                         int64_t ld, int64_t k, int cr, int na) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        rg[q] = *reinterpret_cast<const u32x4 *>(gsrc + (int64_t)32 * q * ld + k);
+        ra[q] = 32 * q + cr < na ? *reinterpret_cast<const u32x4 *>(asrc + (int64_t)32 * q * ld + k) : u32x4{0, 0, 0, 0};
+    }
+}
+__device__ __forceinline__ void wg_stash(const u32x4 (&rg)[4], const u32x4 (&ra)[4], uint16_t (*sg)[WG_LDK],
+                                         uint16_t (*sa)[WG_LDK], int cr, int ck) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        *reinterpret_cast<u32x4 *>(&sg[32 * q + cr][ck]) = rg[q];
+        *reinterpret_cast<u32x4 *>(&sa[32 * q + cr][ck]) = ra[q];
+    }
+}
+
+// The MFMAs of one LDS stage: this wave's 64 x 64 quarter (rows 64 wo.., columns
+// 64 wi..) over the stage's 64 K values.
+__device__ __forceinline__ void wg_mma(f32x4 (&acc)[4][4], const uint16_t (*sg)[WG_LDK], const uint16_t (*sa)[WG_LDK],
+                                       int wo, int wi, int l) {
+#pragma unroll
+    for (int kk = 0; kk < WG_BK / GK; ++kk) {
+        bf16x8 fg[4], fa[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            fg[x] = *reinterpret_cast<const bf16x8 *>(&sg[64 * wo + 16 * x + (l & 15)][GK * kk + (l >> 4) * 8]);
+            fa[x] = *reinterpret_cast<const bf16x8 *>(&sa[64 * wi + 16 * x + (l & 15)][GK * kk + (l >> 4) * 8]);
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+                acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fg[x], fa[y], acc[x][y], 0, 0, 0);
+    }
+}
+
 // Weight gradients dW[o][i] = sum over rows of G[r][o] A[r][i] for the three
-// layers (A = X, h1, h2; G = dL/dz1..3), one 64 x 64 output tile and one K
-// chunk of kc rows per block: blockIdx.x = tile (0..15 layer 3, 16..31 layer
-// 2, 32..35 layer 1) or WG_TILES + j for the per-block vectors (entries
-// 256j .. 256j+255 summed over the chunk's row blocks).  Work items (chunk,
-// tile) map to blocks so that every item of a chunk runs on one XCD: blocks
-// are handed to the 8 XCDs in turn (block b to XCD b % 8), and XCD x takes
-// the chunks x, x + 8, ...  The chunk's rows of the six activation arrays are
-// then fetched into that XCD's L2 once and read from there by its 41 items.
-// The four waves take a quarter of the chunk each, straight from global
-// memory (both operands are K-contiguous), and add their tiles in LDS at the
-// end.
+// layers (A = X, h1, h2; G = dL/dz1..3), one 128 x 128 output tile (layer 1:
+// 128 x 64) and one K chunk of kc rows per block, written as a partial in
+// parameter order (wpart[chunk][parameter]); blockIdx maps to tile 0..3
+// (layer 3), 4..7 (layer 2), 8..9 (layer 1) or WG_TILES + j for the
+// per-block vectors (entries 256j .. 256j+255 summed over the chunk's row
+// blocks into the bias, head and loss entries).  Work items (chunk, tile) map
+// to blocks so that every item of a chunk runs on one XCD: blocks are handed
+// to the 8 XCDs in turn (block b to XCD b % 8), and XCD x takes the chunks
+// x, x + 8, ...; the chunk's rows of the six activation arrays are then
+// fetched into that XCD's L2 once.
+// Both operands are K-contiguous in HBM ([feature][row]); a stage of 64 rows
+// of both is copied into LDS with whole 128-byte lines per feature (double
+// buffered, with the loads two stages ahead in flight), and each of the four
+// waves computes a 64 x 64 quarter of the tile from LDS.
 __global__ __launch_bounds__(256) void train_wgrad_kernel(
     const uint16_t *__restrict__ Xt, const uint16_t *__restrict__ H1t, const uint16_t *__restrict__ H2t,
     const uint16_t *__restrict__ G1t, const uint16_t *__restrict__ G2t, const uint16_t *__restrict__ G3t,
@@ -954,92 +1000,83 @@ __global__ __launch_bounds__(256) void train_wgrad_kernel(
     if (chunk >= ks) return;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int k0 = chunk * kc, k1 = min(rows, k0 + kc);
+    float *wp = wpart + (int64_t)chunk * SG_NPARAM;
     if (tile >= WG_TILES) {
         const int e = (tile - WG_TILES) * 256 + tid;
         if (e < TR_VLEN) {
             const int b0 = k0 / TR_ROWS, b1 = (k1 + TR_ROWS - 1) / TR_ROWS;
-            vpart[(int64_t)chunk * TR_VSTRIDE + e] = chunk_sum(vec + (int64_t)b0 * TR_VSTRIDE + e, TR_VSTRIDE, b1 - b0);
+            const float v = chunk_sum(vec + (int64_t)b0 * TR_VSTRIDE + e, TR_VSTRIDE, b1 - b0);
+            if (e == TR_V_LOSS) vpart[chunk] = v;
+            else if (e == TR_V_B4) wp[SG_OFF_B4] = v;
+            else if (e >= TR_V_W4) wp[SG_OFF_W4 + (e - TR_V_W4)] = v;
+            else if (e >= TR_V_B3) wp[SG_OFF_B3 + (e - TR_V_B3)] = v;
+            else if (e >= TR_V_B2) wp[SG_OFF_B2 + (e - TR_V_B2)] = v;
+            else wp[SG_OFF_B1 + (e - TR_V_B1)] = v;
         }
         return;
     }
-    __shared__ float red[3][64][65];  // waves 1..3 hand their tiles to wave 0
-    const uint16_t *A, *B;
-    int tm, tn;
-    if (tile < 16) {
-        A = G3t; B = H2t; tm = tile >> 2; tn = tile & 3;
-    } else if (tile < 32) {
-        A = G2t; B = H1t; tm = (tile - 16) >> 2; tn = (tile - 16) & 3;
+    __shared__ __align__(16) uint16_t sG[2][WG_BT][WG_LDK];
+    __shared__ __align__(16) uint16_t sA[2][WG_BT][WG_LDK];
+    const uint16_t *G, *A;
+    int tm, tn, na;  // output rows 128 tm.., columns 128 tn.., na columns in the tile
+    if (tile < 4) {
+        G = G3t; A = H2t; tm = tile >> 1; tn = tile & 1; na = WG_BT;
+    } else if (tile < 8) {
+        G = G2t; A = H1t; tm = (tile - 4) >> 1; tn = (tile - 4) & 1; na = WG_BT;
     } else {
-        A = G1t; B = Xt; tm = tile - 32; tn = 0;
+        G = G1t; A = Xt; tm = tile - 8; tn = 0; na = SG_K0;
     }
-    const uint16_t *Ab = A + (int64_t)(64 * tm + (l & 15)) * ld + (l >> 4) * 8;
-    const uint16_t *Bb = B + (int64_t)(64 * tn + (l & 15)) * ld + (l >> 4) * 8;
+    // copy of one stage: 128 feature rows x 64 K of each operand, 16 bytes per
+    // thread and step; thread t takes feature row t/8 + 32s, K offset 8 (t%8)
+    const int cr = tid >> 3, ck = (tid & 7) * 8;
+    const uint16_t *gsrc = G + (int64_t)(WG_BT * tm + cr) * ld + ck;
+    const uint16_t *asrc = A + (int64_t)(WG_BT * tn + cr) * ld + ck;
+    const int nstage = (k1 - k0 + WG_BK - 1) / WG_BK;
+    u32x4 rg[4], ra[4];
+    const int wo = w >> 1, wi = w & 1;  // this wave's 64 x 64 quarter
+    const bool active = 64 * wi < na;
     f32x4 acc[4][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // wave w takes the contiguous quarter [kw0, kw1) of the chunk, 32 rows
-    // per K step, with the loads of the next WG_DEPTH - 1 steps in flight
-    // while a step's MFMAs run.  A last partial step reads rows up to the next
-    // multiple of 32, which the forward kernel wrote (zero gradients) and
-    // which lie below ld.
-    const int kq = kc / 4;
-    const int kw0 = k0 + w * kq, kw1 = min(k1, kw0 + kq);
-    const int steps = kw1 > kw0 ? (kw1 - kw0 + GK - 1) / GK : 0;
-    bf16x8 fa[WG_DEPTH][4], fb[WG_DEPTH][4];
-#pragma unroll
-    for (int q = 0; q < WG_DEPTH; ++q) {
-        if (q < steps) {
-            const int k = kw0 + GK * q;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                fa[q][t] = *reinterpret_cast<const bf16x8 *>(Ab + (int64_t)16 * t * ld + k);
-                fb[q][t] = *reinterpret_cast<const bf16x8 *>(Bb + (int64_t)16 * t * ld + k);
-            }
-        }
-    }
-    for (int s0 = 0; s0 < steps; s0 += WG_DEPTH) {
-#pragma unroll
-        for (int q = 0; q < WG_DEPTH; ++q) {
-            if (s0 + q < steps) {
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[q][a], fb[q][b], acc[a][b], 0, 0, 0);
-                if (s0 + q + WG_DEPTH < steps) {
-                    const int k = kw0 + GK * (s0 + q + WG_DEPTH);
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        fa[q][t] = *reinterpret_cast<const bf16x8 *>(Ab + (int64_t)16 * t * ld + k);
-                        fb[q][t] = *reinterpret_cast<const bf16x8 *>(Bb + (int64_t)16 * t * ld + k);
-                    }
-                }
-            }
-        }
-    }
-    if (w > 0) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) red[w - 1][16 * a + 4 * (l >> 4) + i][16 * b + (l & 15)] = acc[a][b][i];
-    }
+        for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // a last partial stage reads rows up to the next multiple of 64, which
+    // the forward kernel wrote (zero gradients) and which lie below ld.
+    // Two register sets alternate: the loads of stage s + 2 are issued before
+    // the MFMAs of stage s, and land in LDS after those of stage s + 1.
+    u32x4 rg2[4], ra2[4];
+    wg_fetch(rg, ra, gsrc, asrc, ld, k0, cr, na);
+    wg_stash(rg, ra, sG[0], sA[0], cr, ck);
+    if (1 < nstage) wg_fetch(rg2, ra2, gsrc, asrc, ld, k0 + WG_BK, cr, na);
     __syncthreads();
-    if (w == 0) {
-        float *out = wpart + ((int64_t)chunk * WG_TILES + tile) * WG_TILE;
+    for (int st = 0; st < nstage; st += 2) {
+        if (st + 2 < nstage) wg_fetch(rg, ra, gsrc, asrc, ld, k0 + (int64_t)(st + 2) * WG_BK, cr, na);
+        if (active) wg_mma(acc, sG[0], sA[0], wo, wi, l);
+        if (st + 1 < nstage) wg_stash(rg2, ra2, sG[1], sA[1], cr, ck);
+        __syncthreads();
+        if (st + 1 >= nstage) break;
+        if (st + 3 < nstage) wg_fetch(rg2, ra2, gsrc, asrc, ld, k0 + (int64_t)(st + 3) * WG_BK, cr, na);
+        if (active) wg_mma(acc, sG[1], sA[1], wo, wi, l);
+        if (st + 2 < nstage) wg_stash(rg, ra, sG[0], sA[0], cr, ck);
+        __syncthreads();
+    }
+    if (!active) return;
+    // lane l holds rows 4(l/16) + i, column l%16 of each 16 x 16 sub-tile
+    float *dst = wp + (tile < 4 ? SG_OFF_W3 : tile < 8 ? SG_OFF_W2 : SG_OFF_W1);
+    const int pitch = tile < 8 ? SG_H : SG_FEAT;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+    for (int x = 0; x < 4; ++x)
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
+        for (int y = 0; y < 4; ++y) {
+            const int c = WG_BT * tn + 64 * wi + 16 * y + (l & 15);
+            if (c < pitch) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const int r = 16 * a + 4 * (l >> 4) + i, c = 16 * b + (l & 15);
-                    out[r * 64 + c] = acc[a][b][i] + red[0][r][c] + red[1][r][c] + red[2][r][c];
+                    const int o = WG_BT * tm + 64 * wo + 16 * x + 4 * (l >> 4) + i;
+                    dst[o * pitch + c] = acc[x][y][i];
                 }
-    }
+            }
+        }
 }
 
 // Adam on the float32 masters (bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t)
@@ -1057,37 +1094,13 @@ __global__ void train_update_kernel(int mode, const float *__restrict__ wpart, c
                                     AdamArgs a, float *loss, uint16_t *W1, uint16_t *W2, uint16_t *W2t,
                                     uint16_t *W3, uint16_t *W3t) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (mode != 2 && i == 0) *loss = chunk_sum(vpart + TR_V_LOSS, TR_VSTRIDE, ks);
+    if (mode != 2 && i == 0) *loss = chunk_sum(vpart, 1, ks);
     if (i >= SG_NPARAM) return;
     float gi;
     if (mode == 2) {
         gi = gin[i];
     } else {
-        int64_t widx = -1;  // offset in a chunk's tile partials, or -1 for a vector entry
-        int vidx = 0;
-        if (i < SG_OFF_B1) {
-            const int o = i / SG_FEAT, c = i % SG_FEAT;
-            widx = (int64_t)(32 + o / 64) * WG_TILE + (o % 64) * 64 + c;
-        } else if (i < SG_OFF_W2) {
-            vidx = TR_V_B1 + (i - SG_OFF_B1);
-        } else if (i < SG_OFF_B2) {
-            const int j = i - SG_OFF_W2, o = j / SG_H, c = j % SG_H;
-            widx = (int64_t)(16 + (o / 64) * 4 + c / 64) * WG_TILE + (o % 64) * 64 + c % 64;
-        } else if (i < SG_OFF_W3) {
-            vidx = TR_V_B2 + (i - SG_OFF_B2);
-        } else if (i < SG_OFF_B3) {
-            const int j = i - SG_OFF_W3, o = j / SG_H, c = j % SG_H;
-            widx = (int64_t)((o / 64) * 4 + c / 64) * WG_TILE + (o % 64) * 64 + c % 64;
-        } else if (i < SG_OFF_W4) {
-            vidx = TR_V_B3 + (i - SG_OFF_B3);
-        } else if (i < SG_OFF_B4) {
-            vidx = TR_V_W4 + (i - SG_OFF_W4);
-        } else {
-            vidx = TR_V_B4;
-        }
-        const float *src = widx >= 0 ? wpart + widx : vpart + vidx;
-        const int64_t stride = widx >= 0 ? (int64_t)WG_TILES * WG_TILE : (int64_t)TR_VSTRIDE;
-        gi = chunk_sum(src, stride, ks);
+        gi = chunk_sum(wpart + i, SG_NPARAM, ks);
         g[i] = gi;
     }
     if (mode == 0) return;
@@ -1377,8 +1390,8 @@ int tgo_surrogate_create(int64_t max_rows, int max_groups, tgo_surrogate **out) 
         {(void **)&s->G1t, 2 * LT * SG_H}, {(void **)&s->G2t, 2 * LT * SG_H}, {(void **)&s->G3t, 2 * LT * SG_H},
         {(void **)&s->H3, 2 * R * SG_H}, {(void **)&s->score, 4 * R},
         {(void **)&s->vec, 4 * blocks * TR_VSTRIDE},
-        {(void **)&s->wpart, 4 * (size_t)WG_KS_MAX * WG_TILES * WG_TILE},
-        {(void **)&s->vpart, 4 * (size_t)WG_KS_MAX * TR_VSTRIDE},
+        {(void **)&s->wpart, 4 * (size_t)WG_KS_MAX * SG_NPARAM},
+        {(void **)&s->vpart, 4 * (size_t)WG_KS_MAX},
         {(void **)&s->F, 4 * (size_t)max_groups * SG_POS * 3},
         {(void **)&s->status, 4 * (size_t)max_groups}, {(void **)&s->horders, 16 * (size_t)max_groups},
         {(void **)&s->hns, 8 * (size_t)max_groups}, {(void **)&s->best, sizeof(BestPair) * (size_t)max_groups},

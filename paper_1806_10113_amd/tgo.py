@@ -674,7 +674,7 @@ class Surrogate:
 class ServerConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_int64), ("streams", ctypes.c_int32),
                 ("max_batch", ctypes.c_int32), ("max_batch_large", ctypes.c_int32),
-                ("small_max_n", ctypes.c_int32), ("topk", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("small_max_n", ctypes.c_int32), ("topk", ctypes.c_int32), ("window_us", ctypes.c_int32),
                 ("samples", ctypes.c_int64), ("seed", ctypes.c_uint64)]
 
 

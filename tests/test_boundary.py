@@ -97,6 +97,22 @@ def test_host_argument_errors(L):
     assert L.tgo_evaluate_cke(ctypes.byref(good), fake, None, 4, 4, fake, 3, fake, None) == tgo.TGO_EINVAL
 
 
+def test_server_config_errors(L):
+    """tgo_server_create checks its configuration before touching a device."""
+    from paper_1806_10113_amd import tgo
+    good = tgo.DEFAULT._c()
+    out = ctypes.c_void_p()
+    for field, bad in (("streams", 0), ("streams", 9), ("max_batch", 0), ("max_batch_large", 5000),
+                       ("small_max_n", 13), ("topk", 65), ("samples", 0), ("budget_bytes", 0),
+                       ("window_us", -1), ("window_us", 100001)):
+        c = tgo.server_config(**{field: bad})
+        assert L.tgo_server_create(ctypes.byref(good), ctypes.byref(c), None, ctypes.byref(out)) == tgo.TGO_EINVAL, field
+        assert not out.value
+    c = tgo.server_config()
+    assert c.window_us == 0 and c.streams == 4 and c.budget_bytes == 8 << 30
+    assert L.tgo_server_create(None, ctypes.byref(c), None, ctypes.byref(out)) == tgo.TGO_EINVAL
+
+
 def test_rank_unrank_match_lexicographic_order():
     from paper_1806_10113_amd import tgo
     for n in range(1, 7):
