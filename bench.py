@@ -44,6 +44,12 @@ VALU_LANE_OPS_PER_ORDERING = 258.30
 # this share are the lane-ops that did work for some ordering; lanes masked off
 # in a divergent step do none.
 VALU_LANE_UTILISATION = 0.5501
+# Integer operations the method needs per ordering of that workload, counted
+# by `python opcount.py` (a transcription of the window formulation and the
+# walk over the last four positions, each statement priced at its 32-bit ALU
+# operations, lanes counted on their own: 3.0 windows, 1.74 DtH events and
+# 0.62 rate changes per ordering).
+ALG_OPS_PER_ORDERING = 125.8
 # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, each scaled by
 # what the counter reads for a 256 MiB device copy (same profile file).
 TRAFFIC_BYTES_PER_LAUNCH = 2_887_660
@@ -650,8 +656,12 @@ def main():
                      "lane_utilisation": VALU_LANE_UTILISATION,
                      "achieved_active_lanes": achieved * VALU_LANE_UTILISATION,
                      "frac_alg": achieved * VALU_LANE_UTILISATION / VALU_PEAK_TOPS,
+                     "alg_ops_per_ordering": ALG_OPS_PER_ORDERING,
+                     "frac_alg_opcount": ALG_OPS_PER_ORDERING * orderings / (avg_launch_ms / 1e3) / 1e12
+                                         / VALU_PEAK_TOPS,
                      "frac_note": "frac = issued VALU lane-ops (counter run) / peak; frac_alg counts "
-                                  "only the lanes active in each issued instruction"})
+                                  "only the lanes active in each issued instruction; frac_alg_opcount = "
+                                  "the method's counted integer ops per ordering (opcount.py) / peak"})
     else:
         roof.update({"achieved": None, "frac": None})
     roof["traffic"] = TRAFFIC_BYTES_PER_LAUNCH
