@@ -66,7 +66,8 @@ def parse():
     p.add_argument("--no-extras", action="store_true",
                    help="skip the batched, learned-proposal and serving measurements")
     p.add_argument("--extras", default="all",
-                   help="comma-separated subset of: batch, one_dma, rounds, memory, proposal, serving, hw "
+                   help="comma-separated subset of: batch, one_dma, rounds, memory, proposal, serving, hw, "
+                        "train (the network's training alone; proposal and serving train it too) "
                         "(default all)")
     p.add_argument("--train-pairs", type=float, default=2e7,
                    help="exact (ordering, time) pairs used to train the proposal network")
@@ -717,7 +718,7 @@ def main():
                          ("memory", memory_extra)):
             if name in want:
                 run_extra(name, fn, dev)
-        if want & {"proposal", "serving"}:
+        if want & {"proposal", "serving", "train"}:
             trained = run_extra("proposal_training", lambda: train_surrogate(dev, args.train_pairs, batch=args.train_batch,
                                                                              lr=args.train_lr, epochs=args.train_epochs))
             if trained is not None:
