@@ -187,6 +187,31 @@ def test_large_class_ring_wraps(dev):
     sur.close()
 
 
+def test_batching_window_keeps_answers(dev):
+    """A batching window changes how requests are grouped into batches, not
+    their answers (exhaustive: exact; learned proposal: same sampling key)."""
+    from paper_1806_10113_amd import tgo
+    sur = tgo.Surrogate(max_rows=1 << 13, max_groups=32)
+    sur.init(13)
+    mix = W.batch_groups(60, 4, 16, seed=411, per_task_label=True)
+    res = []
+    for win in (0, 2000):
+        cfg = tgo.server_config(streams=2, max_batch=16, max_batch_large=8, samples=2048, topk=16, window_us=win)
+        srv = tgo.Server(tgo.DEFAULT, cfg, sur)
+        ids = [srv.submit(mix.group(g), key=1000 + g) for g in range(mix.n_groups)]
+        srv.drain()
+        r = by_id(srv.poll(100))
+        res.append([r[i] for i in ids])
+        srv.close()
+    for g, (a, b) in enumerate(zip(*res)):
+        for k in ("status", "path", "best_ns", "heur_ns"):
+            assert a[k] == b[k], (g, k)
+        assert bytes(a["best"]) == bytes(b["best"])
+        if a["path"] == 0:
+            check_small(a, mix.group(g))
+    sur.close()
+
+
 def test_replay_poisson_trace(dev):
     from paper_1806_10113_amd import tgo
     arr = W.poisson_arrivals(20_000.0, 0.1, 4, 10, seed=406)
