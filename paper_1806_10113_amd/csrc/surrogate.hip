@@ -521,6 +521,37 @@ __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// Read for the tasks of an empty group (then masked), so that the feature
+// loads need no branch.
+__device__ const tgo_task ZERO_TASK = {0, 0, 0};
+
+// A 64-bit value rotated right by R lanes within each row of 16 lanes (two
+// DPP moves).
+template <int R>
+__device__ __forceinline__ int64_t row_ror64(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, 0x120 + R, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), 0x120 + R, 0xF, 0xF, false);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+// Sum / minimum over the 16 lanes of a row, left in every lane of the row.
+__device__ __forceinline__ void row16_sum(int64_t &v) {
+    v += row_ror64<8>(v);
+    v += row_ror64<4>(v);
+    v += row_ror64<2>(v);
+    v += row_ror64<1>(v);
+}
+__device__ __forceinline__ void row16_min(int64_t &v) {
+    int64_t t = row_ror64<8>(v);
+    v = t < v ? t : v;
+    t = row_ror64<4>(v);
+    v = t < v ? t : v;
+    t = row_ror64<2>(v);
+    v = t < v ? t : v;
+    t = row_ror64<1>(v);
+    v = t < v ? t : v;
+}
+
 // Keeps the compiler from moving memory accesses across this point (no
 // instruction): the next layer's weight loads stay behind the current layer,
 // so that at most two layers' weights are live in registers.
@@ -566,15 +597,19 @@ __device__ __forceinline__ void wmma_rows(const uint16_t (*A)[LD], int a0, const
 }
 
 // Transposed store of an LDS activation block: dst[c][r0 + r] = S[r][c] for
-// c < width, r < TR_ROWS, r0 + r < ld (8 rows = 16 bytes per store; ld is a
-// multiple of 64, so a store of 8 rows is all inside or all outside).
-template <int LD>
-__device__ __forceinline__ void store_t(const uint16_t (*S)[LD], int width, uint16_t *dst, int64_t ld, int r0,
-                                        int tid) {
-    const int chunks = width * (TR_ROWS / 8);
-    for (int q = tid; q < chunks; q += TR_THREADS) {
+// c < WIDTH, r < TR_ROWS (8 rows = 16 bytes per store).  The transposed
+// arrays hold ld >= every row a block writes (see TR_LD_PAD), so no store
+// needs a bounds test; stores without branches and with a fixed count let
+// the compiler wait for exactly the loads it needs later, instead of for
+// every outstanding memory operation.
+template <int WIDTH, int LD>
+__device__ __forceinline__ void store_t(const uint16_t (*S)[LD], uint16_t *dst, int64_t ld, int r0, int tid) {
+    constexpr int chunks = WIDTH * (TR_ROWS / 8);
+    static_assert(chunks % TR_THREADS == 0, "whole passes");
+#pragma unroll
+    for (int qq = 0; qq < chunks / TR_THREADS; ++qq) {
+        const int q = tid + qq * TR_THREADS;
         const int c = q / (TR_ROWS / 8), r = (q % (TR_ROWS / 8)) * 8;
-        if (r0 + r >= ld) continue;
         uint4 v;
         v.x = S[r][c] | ((uint32_t)S[r + 1][c] << 16);
         v.y = S[r + 2][c] | ((uint32_t)S[r + 3][c] << 16);
@@ -586,9 +621,8 @@ __device__ __forceinline__ void store_t(const uint16_t (*S)[LD], int width, uint
 
 // The four values a lane holds for (row tile a, column col) are rows
 // 16a + 4(l/16) + 0..3 of that column: one 8-byte store into the transposed
-// layout dst[col][row], skipped past the ld rows the layout holds.
+// layout dst[col][row] (every row a block writes lies below ld).
 __device__ __forceinline__ void store4_t(uint16_t *dst, int64_t ld, int col, int row0, const uint16_t (&v)[4]) {
-    if (row0 >= ld) return;
     uint2 q;
     q.x = v[0] | ((uint32_t)v[1] << 16);
     q.y = v[2] | ((uint32_t)v[3] << 16);
@@ -628,10 +662,6 @@ __global__ __launch_bounds__(TR_THREADS) void train_fwd_bwd_kernel(
 #define TR_ROW(h, a, i) (16 * ((h) * TR_HALF + (a)) + 4 * (l >> 4) + (i))
 #define TR_BIT(h, a, b, i) ((((h) * TR_HALF + (a)) * 2 + (b)) * 4 + (i))
 
-    WRegs<SG_K0> w1r;
-    wload(w1r, W1, w, l);
-    WRegs<SG_H> w2r;
-    wload(w2r, W2, w, l);
     // biases and head weights of this lane's two columns
     float bias1[2], bias2[2], bias3[2], w4c[2];
 #pragma unroll
@@ -646,62 +676,82 @@ __global__ __launch_bounds__(TR_THREADS) void train_fwd_bwd_kernel(
 
     // features of (row, position) and the target of each row, 32 rows per
     // pass.  The 16 lanes of a row also hold the group's tasks (lane x: task
-    // x) for the target's lower bound, reduced across the row's lanes: every
-    // global load of a row is issued at one of three dependent levels
-    // (row -> group -> tasks)
+    // x) for the target's lower bound, reduced across the row's lanes.  The
+    // loads come at three dependent levels (row -> group -> tasks), each
+    // issued for all passes at once and without branches (indices clamped
+    // into range, results selected), so their latencies overlap.
+    constexpr int FP = TR_ROWS * SG_POS / TR_THREADS;  // passes
+    const int pos = tid & 15;
+    int gv[FP], xv[FP], bv[FP], nv[FP];
+    int64_t Tv[FP];
 #pragma unroll
-    for (int it = 0; it < TR_ROWS * SG_POS / TR_THREADS; ++it) {
-        const int rr = 32 * it + (tid >> 4), pos = tid & 15;
-        const int i = r0 + rr;
-        const bool live = i < rows;
-        const int g = live ? gid[i] : 0;
-        const int x = live ? orders[(int64_t)i * SG_POS + pos] : 0;
-        const int64_t Ti = live && pos == 0 ? T[i] : 0;
-        const int b = live ? offs[g] : 0;
-        const int n = live ? offs[g + 1] - b : 0;
-        uint16_t f0 = 0, f1 = 0, f2 = 0;
-        if (pos < n && x < n) {
-            const tgo_task t = tasks[b + x];
-            f0 = f2bf(feature_value(t.htd_ns));
-            f1 = f2bf(feature_value(t.kern_ns));
-            f2 = f2bf(feature_value(t.dth_ns));
-        }
+    for (int it = 0; it < FP; ++it) {
+        const int i = r0 + 32 * it + (tid >> 4);
+        const int ic = i < rows ? i : rows - 1;
+        gv[it] = gid[ic];
+        xv[it] = orders[(int64_t)ic * SG_POS + pos];
+        Tv[it] = T[ic];
+    }
+#pragma unroll
+    for (int it = 0; it < FP; ++it) {
+        bv[it] = offs[gv[it]];
+        nv[it] = offs[gv[it] + 1] - bv[it];
+    }
+    tgo_task tx[FP], tp[FP];
+#pragma unroll
+    for (int it = 0; it < FP; ++it) {
+        // an index past the group reads its first task (an empty group: a
+        // zero task), masked below
+        const int n = nv[it];
+        const tgo_task *g0 = n > 0 ? tasks + bv[it] : &ZERO_TASK;
+        tx[it] = g0[xv[it] < n ? xv[it] : 0];
+        tp[it] = g0[pos < n ? pos : 0];
+    }
+#pragma unroll
+    for (int it = 0; it < FP; ++it) {
+        const int rr = 32 * it + (tid >> 4);
+        const bool live = r0 + rr < rows;
+        const int n = live ? nv[it] : 0;
+        const bool has = pos < n && xv[it] < n;
+        const tgo_task t = tx[it];
+        const uint16_t f0 = has ? f2bf(feature_value(t.htd_ns)) : (uint16_t)0;
+        const uint16_t f1 = has ? f2bf(feature_value(t.kern_ns)) : (uint16_t)0;
+        const uint16_t f2 = has ? f2bf(feature_value(t.dth_ns)) : (uint16_t)0;
         // y = T / LB - 1, LB the largest machine lower bound of the group
-        int64_t sh = 0, sk = 0, sd = 0, mh = INT64_MAX, md = INT64_MAX, mkd = INT64_MAX, mhk = INT64_MAX;
-        if (pos < n) {
-            const tgo_task t = tasks[b + pos];
-            sh = t.htd_ns;
-            sk = t.kern_ns;
-            sd = t.dth_ns;
-            mh = t.htd_ns;
-            md = t.dth_ns;
-            mkd = t.kern_ns + t.dth_ns;
-            mhk = t.htd_ns + t.kern_ns;
-        }
-#pragma unroll
-        for (int m = 1; m < 16; m <<= 1) {
-            sh += shfl_xor64(sh, m);
-            sk += shfl_xor64(sk, m);
-            sd += shfl_xor64(sd, m);
-            mh = min(mh, shfl_xor64(mh, m));
-            md = min(md, shfl_xor64(md, m));
-            mkd = min(mkd, shfl_xor64(mkd, m));
-            mhk = min(mhk, shfl_xor64(mhk, m));
-        }
+        const bool own = pos < n;
+        const tgo_task u = tp[it];
+        int64_t sh = own ? u.htd_ns : 0, sk = own ? u.kern_ns : 0, sd = own ? u.dth_ns : 0;
+        int64_t mh = own ? u.htd_ns : INT64_MAX, md = own ? u.dth_ns : INT64_MAX;
+        int64_t mkd = own ? u.kern_ns + u.dth_ns : INT64_MAX, mhk = own ? u.htd_ns + u.kern_ns : INT64_MAX;
+        row16_sum(sh);
+        row16_sum(sk);
+        row16_sum(sd);
+        row16_min(mh);
+        row16_min(md);
+        row16_min(mkd);
+        row16_min(mhk);
         if (pos == 0) {
             int64_t lb = sh + mkd;
             lb = mh + sk + md > lb ? mh + sk + md : lb;
             lb = mhk + sd > lb ? mhk + sd : lb;
             lb = lb < 1 ? 1 : lb;
-            ys[rr] = live ? (float)((double)Ti / (double)lb - 1.0) : 0.f;
+            ys[rr] = live ? (float)((double)Tv[it] / (double)lb - 1.0) : 0.f;
         }
         Xs[rr][3 * pos] = f0;
         Xs[rr][3 * pos + 1] = f1;
         Xs[rr][3 * pos + 2] = f2;
         Xs[rr][SG_FEAT + pos] = 0;
     }
+    // the first two layers' weights are loaded once the features are built
+    // (vector memory returns in order: loads issued before the features'
+    // own would hold them up)
+    compiler_fence();
+    WRegs<SG_K0> w1r;
+    wload(w1r, W1, w, l);
+    WRegs<SG_H> w2r;
+    wload(w2r, W2, w, l);
     lds_barrier();
-    store_t(Xs, SG_K0, Xt, ld, r0, tid);
+    store_t<SG_K0>(Xs, Xt, ld, r0, tid);
 
     uint64_t m1 = 0, m2 = 0;  // ReLU masks of layers 1 and 2 (bit TR_BIT: h > 0)
     // layer 1: Xs -> bufA
@@ -1276,8 +1326,11 @@ __global__ void search_finish_kernel(const int32_t *__restrict__ offs, int G, ui
 // max_rows plus 2,176 elements (4 KiB + 256 B per feature row), so that the
 // rows a wave touches in one access, whose stride would otherwise be a power
 // of two (e.g. 128 KiB at 65,536 rows), spread over the L2 and HBM channels
-// instead of landing on one.
+// instead of landing on one.  The pad also covers the rows of the last
+// 128-row block past max_rows (max_rows is a multiple of 64), which the
+// forward kernel writes unconditionally.
 constexpr int64_t TR_LD_PAD = 2176;
+static_assert(TR_LD_PAD >= tgo::TR_ROWS - 64, "the last block's rows lie inside the transposed arrays");
 
 struct tgo_surrogate {
     int device = 0;

@@ -82,11 +82,13 @@ __device__ __forceinline__ uint64_t sample_ordering(int n, uint32_t g, uint64_t 
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
-// log1p(x / 1 us) / log1p(20 ms / 1 us), in float32 (a few ulp of the exact
-// value; the network sees it rounded to bf16)
+// log1p(x / 1 us) / log1p(20 ms / 1 us), in float32 as log2(1 + x) times
+// ln 2 / ln 20001 with the hardware base-2 logarithm (a few float32 ulp of
+// the exact value for durations of 100 ns and more; the network sees it
+// rounded to bf16)
 __device__ __forceinline__ float feature_value(int64_t x_ns) {
-    constexpr float INV_SCALE = (float)(1.0 / 9.90353755128617);  // 1 / log1p(20000)
-    return log1pf((float)x_ns * 1e-3f) * INV_SCALE;
+    constexpr float SCALE = (float)(0.69314718055994531 / 9.90353755128617);  // ln 2 / ln 20001
+    return __log2f(1.0f + (float)x_ns * 1e-3f) * SCALE;
 }
 
 }  // namespace tgo
