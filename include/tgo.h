@@ -207,6 +207,14 @@ int tgo_heuristic(const tgo_model *model, const tgo_task *d_tasks, const int32_t
  *                     tile, persistent grid size) on the given batch and keeps
  *                     the fastest.  Blocks until done; overwrites d_out.
  * tgo_plan_describe-- the chosen decomposition as a JSON object.
+ * tgo_plan_set_decomposition -- sets the decomposition that describe reports
+ *                     (m_by_n[n - 1]: positions enumerated per lane for group
+ *                     size n = 1..12, each in 1..min(n, 5); lane_mult: subtrees
+ *                     per lane in a tile, 1..64; blocks: persistent grid,
+ *                     1..65536), e.g. one a tuning run saved, so that a later
+ *                     process skips tgo_plan_autotune.  Results never depend
+ *                     on it.  TGO_EINVAL for a value out of range (the plan is
+ *                     then unchanged).
  * tgo_batch        -- for every group g of the CSR batch (tasks
  *                     d_tasks[d_offs[g] .. d_offs[g+1])), writes d_out[g]: the
  *                     full-enumeration summary plus the heuristic ordering
@@ -223,6 +231,7 @@ int tgo_plan_create(const tgo_model *model, int max_groups, int max_n, size_t me
 int tgo_plan_autotune(tgo_plan *plan, const tgo_task *d_tasks, const int32_t *d_offs, int n_groups,
                       tgo_summary *d_out, tgo_stream stream);
 int tgo_plan_describe(const tgo_plan *plan, char *buf, size_t len);
+int tgo_plan_set_decomposition(tgo_plan *plan, const int32_t *m_by_n, int lane_mult, int blocks);
 int tgo_batch(tgo_plan *plan, const tgo_task *d_tasks, const int32_t *d_offs, int n_groups,
               tgo_summary *d_out, tgo_stream stream);
 void tgo_plan_destroy(tgo_plan *plan);

@@ -699,6 +699,23 @@ int tgo_plan_autotune(tgo_plan *p, const tgo_task *d_tasks, const int32_t *d_off
     return TGO_OK;
 }
 
+int tgo_plan_set_decomposition(tgo_plan *p, const int32_t *m_by_n, int lane_mult, int blocks) {
+    if (!p || !m_by_n) return fail(TGO_EINVAL, "NULL argument");
+    if (lane_mult < 1 || lane_mult > 64) return fail(TGO_EINVAL, "lane_mult must be in 1..64");
+    if (blocks < 1 || blocks > 65536) return fail(TGO_EINVAL, "blocks must be in 1..65536");
+    BatchCfg c = p->cfg;
+    for (int n = 1; n <= BT_MAX_N; ++n) {
+        const int m = m_by_n[n - 1];
+        if (m < 1 || m > std::min(n, BT_MAX_M)) return fail(TGO_EINVAL, "m_by_n[n-1] must be in 1..min(n, 5)");
+        c.m[n] = (int8_t)m;
+    }
+    c.lane_mult = lane_mult;
+    c.blocks = blocks;
+    p->cfg = c;
+    drop_graph(p);
+    return TGO_OK;
+}
+
 int tgo_plan_describe(const tgo_plan *p, char *buf, size_t len) {
     if (!p || !buf || len == 0) return fail(TGO_EINVAL, "bad argument");
     std::string s = "{\"m_by_n\": [";

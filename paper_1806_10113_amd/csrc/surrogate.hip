@@ -477,9 +477,10 @@ __global__ __launch_bounds__(FM_THREADS) void mlp_fused_kernel(const float *__re
 //                         transposed ([feature][row]) for the weight gradients,
 //                         and per-block sums for the bias, head and loss terms.
 //   train_wgrad_kernel    weight gradients G^T A of the three layers as one
-//                         split-K launch (64 x 64 output tiles), plus the
-//                         per-chunk sums of the per-block vectors; partials
-//                         per K chunk, no atomics (the sum order is fixed).
+//                         split-K launch (128 x 128 output tiles staged
+//                         through LDS), plus the per-chunk sums of the
+//                         per-block vectors; partials per K chunk in
+//                         parameter order, no atomics (the sum order is fixed).
 //   train_update_kernel   sums the K-chunk partials into the gradient and
 //                         (optionally) applies Adam and refreshes the bf16
 //                         weight copies.

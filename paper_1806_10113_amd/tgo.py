@@ -100,6 +100,7 @@ def lib():
         L.tgo_plan_create.argtypes = [M, i32, i32, ctypes.c_size_t, ctypes.POINTER(vp)]
         L.tgo_plan_autotune.argtypes = [vp, vp, vp, i32, vp, vp]
         L.tgo_plan_describe.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+        L.tgo_plan_set_decomposition.argtypes = [vp, vp, i32, i32]
         L.tgo_batch.argtypes = [vp, vp, vp, i32, vp, vp]
         L.tgo_surrogate_create.argtypes = [i64, i32, ctypes.POINTER(vp)]
         L.tgo_surrogate_destroy.argtypes = [vp]
@@ -468,6 +469,15 @@ class Plan:
         buf = ctypes.create_string_buffer(1024)
         _check(lib().tgo_plan_describe(self._h, buf, 1024), "tgo_plan_describe")
         return json.loads(buf.value.decode())
+
+    def set_decomposition(self, desc: dict):
+        """Restore a decomposition that describe() reported (m_by_n, lane_mult,
+        blocks), e.g. saved from a tuning run, instead of tuning again."""
+        m = np.ascontiguousarray(np.asarray(desc["m_by_n"], dtype=np.int32))
+        if m.shape != (12,):
+            raise ValueError("m_by_n must hold 12 entries (group sizes 1..12)")
+        _check(lib().tgo_plan_set_decomposition(self._h, m.ctypes.data, int(desc["lane_mult"]),
+                                                int(desc["blocks"])), "tgo_plan_set_decomposition")
 
     def run(self, tasks, offs, out=None, stream=None):
         """Summaries (uint8 [G, 136] device tensor) for every group of the batch."""

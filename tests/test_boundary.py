@@ -113,6 +113,13 @@ def test_server_config_errors(L):
     assert L.tgo_server_create(None, ctypes.byref(c), None, ctypes.byref(out)) == tgo.TGO_EINVAL
 
 
+def test_plan_decomposition_null_arguments(L):
+    from paper_1806_10113_amd import tgo
+    m = (ctypes.c_int32 * 12)(*([1] * 12))
+    assert L.tgo_plan_set_decomposition(None, m, 1, 64) == tgo.TGO_EINVAL
+    assert L.tgo_plan_set_decomposition(ctypes.c_void_p(16), None, 1, 64) == tgo.TGO_EINVAL
+
+
 def test_rank_unrank_match_lexicographic_order():
     from paper_1806_10113_amd import tgo
     for n in range(1, 7):

@@ -87,8 +87,23 @@ def test_batch_uneven_4096_groups(dev):
     plan2 = tgo.Plan(tgo.DEFAULT, max_groups=4096)
     out2 = plan2.run(tasks, offs)
     assert bool((out2 == out).all())
+    # the tuned decomposition restored into a new plan (as a later process
+    # would from a saved description) is the same decomposition, same bytes
+    plan3 = tgo.Plan(tgo.DEFAULT, max_groups=4096)
+    plan3.set_decomposition(desc)
+    d3 = plan3.describe()
+    for k in ("m_by_n", "lane_mult", "blocks"):
+        assert d3[k] == desc[k], k
+    assert bool((plan3.run(tasks, offs) == out).all())
+    bad = dict(desc, m_by_n=[1] * 11 + [6])
+    with pytest.raises(tgo.TgoError):
+        plan3.set_decomposition(bad)
+    with pytest.raises(tgo.TgoError):
+        plan3.set_decomposition(dict(desc, blocks=0))
+    assert plan3.describe()["m_by_n"] == desc["m_by_n"]
     plan.close()
     plan2.close()
+    plan3.close()
 
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_4096_seed2.npz")
