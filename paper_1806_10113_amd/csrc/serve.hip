@@ -146,7 +146,11 @@ static int admit(tgo_server *S) {
             int64_t pos = R.tail;
             const int64_t off = pos % R.cap;
             if (off + q->n > R.cap) pos += R.cap - off;  // skip to the start of the ring
-            if (pos + q->n - R.head > R.cap) break;     // no room: wait for memory
+            if (R.q.empty()) {
+                R.head = pos;  // nothing is held: the rows skipped are free too
+            } else if (pos + q->n - R.head > R.cap) {
+                break;  // no room: wait for memory
+            }
             const int64_t phys = pos % R.cap;
             if (first >= 0 && phys != last) {  // not right behind the rows staged so far
                 const int rc = flush();

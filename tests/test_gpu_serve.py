@@ -154,6 +154,26 @@ def test_budget_below_own_memory_is_refused(dev):
     srv.close()
 
 
+def test_requests_larger_than_half_the_ring(dev):
+    """A ring of 12 rows and groups of 7..10 tasks: a request that does not fit
+    before the ring's end starts again at its beginning, and when nothing is
+    held the rows it skipped count as free (no request waits forever)."""
+    from paper_1806_10113_amd import tgo
+    probe = tgo.Server(tgo.DEFAULT, tgo.server_config(streams=2, max_batch=8))
+    base = probe.stats()["base_bytes"]
+    probe.close()
+    srv = tgo.Server(tgo.DEFAULT, tgo.server_config(streams=2, max_batch=8, budget_bytes=base + 12 * TASK_BYTES))
+    assert srv.stats()["ring_rows"][0] == 12
+    b = W.batch_groups(30, 7, 10, seed=412)
+    ids = [srv.submit(b.group(g)) for g in range(b.n_groups)]
+    srv.drain(30_000)
+    res = by_id(srv.poll(100))
+    for g, i in enumerate(ids):
+        check_small(res[i], b.group(g))
+    assert srv.stats()["max_in_use_bytes"] <= base + 12 * TASK_BYTES
+    srv.close()
+
+
 def test_large_class_ring_wraps(dev):
     """Both classes through small rings: large requests (learned proposal)
     wrap their ring and still score exactly what they report."""
