@@ -541,9 +541,15 @@ def extras_summary(extras: dict) -> dict:
     if "proposal_n16" in extras:
         d = extras["proposal_n16"]
         if isinstance(d, dict) and "error" not in d:
-            out["proposal_n16"] = {"equal_time": d.get("equal_time"), "vs_plain_max": d.get("vs_plain_max"),
-                                   "plain_max_samples": d.get("plain_max_samples"),
-                                   "ablation": d.get("ablation_candidates")}
+            # per sample count S: [gap % to the plain search at equal time,
+            # gap % to the largest plain search, speedup over it]
+            eq, mx = d.get("equal_time") or {}, d.get("vs_plain_max") or {}
+            out["proposal_n16"] = {
+                "per_S": {S: [round(eq[S]["gap_pct_vs_plain"], 3), round(mx[S]["gap_pct"], 3),
+                              round(mx[S]["speedup_groups_per_s"], 2)] for S in mx if S in eq},
+                "per_S_fields": "gap_pct_equal_time, gap_pct_vs_plain_max, speedup_vs_plain_max",
+                "plain_max_samples": d.get("plain_max_samples"),
+                "network_better_than_random": (d.get("ablation_candidates") or {}).get("network_better")}
         else:
             out["proposal_n16"] = pick(d)
     if "serving" in extras:

@@ -315,6 +315,38 @@ __device__ __forceinline__ uint32_t orderable(float f) {
 }
 
 // --------------------------------------------------------- fused inference
+// Wave-level sorting of 64-bit keys, lane i holding element i (64 lanes).
+__device__ __forceinline__ unsigned long long shfl64(unsigned long long v, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+    return ((unsigned long long)hi << 32) | lo;
+}
+// Bitonic sort network, ascending.
+__device__ __forceinline__ unsigned long long wave_sort64(unsigned long long v, int lane) {
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const unsigned long long o = shfl_xor64(v, j);
+            const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+            v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+        }
+    return v;
+}
+// The 64 smallest of two ascending lists a and b, ascending: min(a[i],
+// b[63 - i]) is a bitonic sequence holding them, which a half-cleaner
+// cascade sorts.
+__device__ __forceinline__ unsigned long long wave_merge_low64(unsigned long long a, unsigned long long b, int lane) {
+    const unsigned long long br = shfl64(b, 63 - lane);
+    unsigned long long v = a < br ? a : br;
+#pragma unroll
+    for (int j = 32; j > 0; j >>= 1) {
+        const unsigned long long o = shfl_xor64(v, j);
+        v = (lane & j) == 0 ? (o < v ? o : v) : (o > v ? o : v);
+    }
+    return v;
+}
+
 // One block scores 64 rows end to end: it builds their first-layer inputs in
 // LDS, runs the three hidden layers on MFMA with the activations kept in LDS
 // (rounded to bf16, as the layer-by-layer path stores them) and applies the
@@ -451,18 +483,21 @@ __global__ __launch_bounds__(FM_THREADS) void mlp_fused_kernel(const float *__re
             if ((l & 15) == 0) part[w][16 * a + 4 * (l >> 4) + i] = v;
         }
     __syncthreads();
-    if (tid < FM_ROWS) {
+    if (tid < FM_ROWS) {  // wave 0, one row per lane
         const int64_t i = base + tid;
-        if (i < rows) {
-            float sc = p[SG_OFF_B4];
+        float sc = p[SG_OFF_B4];
 #pragma unroll
-            for (int v = 0; v < FM_WAVES; ++v) sc += part[v][tid];
-            if (keys) {
-                const int64_t smp = (row0 + i) % spad;
-                keys[i] = okrow[tid] ? (((unsigned long long)orderable(sc) << 32) | (uint64_t)smp) : ~0ull;
-            } else {
-                score[i] = okrow[tid] ? sc : INFINITY;
-            }
+        for (int v = 0; v < FM_WAVES; ++v) sc += part[v][tid];
+        if (keys) {
+            // the block's 64 keys, sorted: the top-k passes take every 64
+            // consecutive keys as an ascending list (rows past the end are
+            // ~0, so the valid keys come first)
+            unsigned long long key = ~0ull;
+            if (i < rows && okrow[tid]) key = ((unsigned long long)orderable(sc) << 32) | (uint64_t)((row0 + i) % spad);
+            key = wave_sort64(key, tid);
+            if (i < rows) keys[i] = key;
+        } else if (i < rows) {
+            score[i] = okrow[tid] ? sc : INFINITY;
         }
     }
 }
@@ -1214,38 +1249,37 @@ __global__ void init_params_kernel(float *p, uint64_t seed) {
 
 // ------------------------------------------------------------------ top-k
 // Keys (orderable score bits << 32 | sample index) per group; each pass keeps
-// the 64 smallest of every run of 1024 keys (bitonic sort in LDS).
-
-
+// the 64 smallest of every run of 1024 keys.  A run is 16 ascending lists of
+// 64 keys (the scoring kernel sorts each block's 64 keys; a pass writes its
+// 64 ascending); the 8 waves of a block merge pairs of lists in a tree
+// (16 -> 8 -> 4 -> 2 -> 1), keeping the lower 64 at each merge.
 constexpr int TK_RUN = 1024;
-constexpr int TK_THREADS = 256;
+constexpr int TK_THREADS = 512;
 constexpr int TK_KEEP = 64;
+static_assert(TK_THREADS == 64 * (TK_RUN / 128), "one wave per pair of lists");
 
 // in: [G][len] keys (group stride in_stride); out: [G][ceil(len/TK_RUN)*64]
 __global__ __launch_bounds__(TK_THREADS) void topk_pass_kernel(const unsigned long long *__restrict__ in,
                                                          int64_t in_stride, int64_t len, int runs,
                                                          unsigned long long *out, int64_t out_stride) {
-    __shared__ unsigned long long s[TK_RUN];
+    __shared__ unsigned long long s[TK_RUN / 128][TK_KEEP];
     const int g = blockIdx.y, run = blockIdx.x;
-    const int64_t base = (int64_t)run * TK_RUN;
-    for (int i = threadIdx.x; i < TK_RUN; i += blockDim.x)
-        s[i] = base + i < len ? in[(int64_t)g * in_stride + base + i] : ~0ull;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const unsigned long long *src = in + (int64_t)g * in_stride;
+    const int64_t ia = (int64_t)run * TK_RUN + 128 * w + lane, ib = ia + 64;
+    const unsigned long long a = ia < len ? src[ia] : ~0ull;
+    const unsigned long long b = ib < len ? src[ib] : ~0ull;
+    unsigned long long v = wave_merge_low64(a, b, lane);
+    s[w][lane] = v;
     __syncthreads();
-    for (int k = 2; k <= TK_RUN; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < TK_RUN; i += blockDim.x) {
-                const int p = i ^ j;
-                if (p > i) {
-                    const bool up = (i & k) == 0;
-                    const unsigned long long a = s[i], b = s[p];
-                    if ((a > b) == up) { s[i] = b; s[p] = a; }
-                }
-            }
-            __syncthreads();
-        }
+#pragma unroll
+    for (int nl = TK_RUN / 256; nl >= 1; nl >>= 1) {
+        if (w < nl) v = wave_merge_low64(s[2 * w][lane], s[2 * w + 1][lane], lane);
+        __syncthreads();
+        if (w < nl) s[w][lane] = v;
+        __syncthreads();
     }
-    for (int i = threadIdx.x; i < TK_KEEP; i += blockDim.x)
-        out[(int64_t)g * out_stride + (int64_t)run * TK_KEEP + i] = s[i];
+    if (w == 0) out[(int64_t)g * out_stride + (int64_t)run * TK_KEEP + lane] = v;
 }
 
 __global__ void fill_u64_kernel(unsigned long long *p, int64_t n, unsigned long long v) {
