@@ -52,15 +52,16 @@ struct Ctx {
 };
 
 // Level with L positions left (position n - L is being chosen).  list holds
-// the remaining tasks in increasing order, one per nibble.
-template <typename TT, int L, bool STORE, int TS, int QS, int DMA>
-__device__ __forceinline__ void level(const Ctx &c, const View<TT, TS, QS> &v, const Lane<TT> &s,
+// the remaining tasks in increasing order, one per nibble.  LaneT is the
+// simulation state (Lane: event form, CLane: chain form).
+template <typename TT, int L, bool STORE, int TS, int QS, int DMA, typename LaneT>
+__device__ __forceinline__ void level(const Ctx &c, const View<TT, TS, QS> &v, const LaneT &s,
                                       uint32_t list, uint32_t l, Sub<TT> &u) {
     const int j = c.n - L;
 #pragma unroll 1
     for (int ci = 0; ci < L; ++ci) {
         const uint32_t x = (list >> (4 * ci)) & 15u;
-        Lane<TT> s2 = s;
+        LaneT s2 = s;
         window<DMA, (L > 1)>(s2, j, x, v, c.r);
         const uint32_t l2 = l + (uint32_t)ci * (uint32_t)fact_c(L - 1);
         if constexpr (L == 1) {
@@ -75,12 +76,12 @@ __device__ __forceinline__ void level(const Ctx &c, const View<TT, TS, QS> &v, c
 
 // Decode the prefix of subtree s (positions 0 .. n-M-1 of rank s*M!) and
 // simulate its windows.  Returns the remaining tasks, ascending, one per nibble.
-template <int DMA, typename TT, int TS, int QS>
-__device__ __forceinline__ uint64_t prefix(Lane<TT> &st, uint32_t s, int n, int m,
+template <int DMA, typename LaneT, typename TT, int TS, int QS>
+__device__ __forceinline__ uint64_t prefix(LaneT &st, uint32_t s, int n, int m,
                                            const View<TT, TS, QS> &v, const Rates &r) {
     uint64_t list = 0;
     for (int i = n - 1; i >= 0; --i) list = (list << 4) | (uint64_t)i;
-    st = lane_init<TT>();
+    lane_reset(st);
     const int plen = n - m;
     uint32_t rem = s;
     // block size of position i in subtree units: (n-1-i)!/m!

@@ -11,6 +11,7 @@
 
 #include <cstdlib>
 #include <mutex>
+#include <type_traits>
 
 #include "enum_dev.h"
 #include "tables_dev.h"
@@ -171,8 +172,10 @@ void exhaustive_kernel(const tgo_task *__restrict__ tasks, int n, Rates r, uint3
     Acc<TT> a;
     acc_init(a);
     const uint32_t stride = gridDim.x * blockDim.x;
+    // two DMA engines: the chain form; one engine: windows without DtH events
+    using LaneT = std::conditional_t<DMA == DMA_TWO, CLane<TT>, Lane<TT>>;
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_sub; s += stride) {
-        Lane<TT> st;
+        LaneT st;
         const uint64_t list = prefix<DMA>(st, s, n, M, v, r);
         const uint64_t r0 = (uint64_t)s * factorial(M);
         if constexpr (STORE) c.out_sub = out + r0;

@@ -23,6 +23,14 @@
 //     the end of HtD at position j and processes the DtH events inside it.
 //     The state at the start of window j depends only on positions < j, which
 //     lets an enumeration share the windows of a common prefix.
+//   * Chain form (CLane below): since every DtH that starts before the last
+//     HtD ends runs at the overlapped rate, its start and end follow from the
+//     previous DtH's end and its own kernel's end alone:
+//     S_j = max(E_{j-1}, K_j), E_j = S_j + ceil(q d_j / p_dth).  Window j
+//     appends DtH j to this chain once K_j is known, and a window only walks
+//     the DtHs that end inside it; a start from idle is handled in the same
+//     step as the completion before it, and a DtH that follows the previous
+//     one without a gap leaves the HtD estimate as it is.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -64,6 +72,14 @@ struct alignas(2 * sizeof(TT)) Slot {
     TT dp;  // its DtH while overlapped: ceil(q d / p_dth).  p_dth dp = q d + slack
             // with slack < p_dth <= q, so d and slack follow from p_dth dp
 };
+
+// Chain entry of DtH j: start and end while the HtD engine is busy.
+template <typename TT>
+struct alignas(2 * sizeof(TT)) Span {
+    TT s, e;
+};
+static_assert(sizeof(Span<uint32_t>) == sizeof(Slot<uint32_t>), "chain entries reuse the queue slots");
+static_assert(sizeof(Span<uint64_t>) == sizeof(Slot<uint64_t>), "chain entries reuse the queue slots");
 
 template <typename TT> struct Signed;
 template <> struct Signed<uint32_t> { using type = int32_t; };
@@ -111,6 +127,9 @@ struct View {
     __device__ __forceinline__ DRec<TT> d(uint32_t x) const { return D[x * TS]; }
     __device__ __forceinline__ Slot<TT> q(int j) const { return Q[j * QS]; }
     __device__ __forceinline__ void put(int j, Slot<TT> s) const { Q[j * QS] = s; }
+    // the same queue memory holding chain entries (start, end) of DtH j
+    __device__ __forceinline__ Span<TT> span(int j) const { return reinterpret_cast<const Span<TT> *>(Q)[j * QS]; }
+    __device__ __forceinline__ void put_span(int j, Span<TT> e) const { reinterpret_cast<Span<TT> *>(Q)[j * QS] = e; }
 };
 
 // Simulation state at the start of a window (an HtD about to start).
@@ -140,6 +159,9 @@ __device__ __forceinline__ Lane<TT> lane_init() {
     s.i = 0; s.drun = false;
     return s;
 }
+
+template <typename TT>
+__device__ __forceinline__ void lane_reset(Lane<TT> &s) { s = lane_init<TT>(); }
 
 // One DMA engine (Section 3.2, scheme for such devices): every HtD is queued
 // on the one transfer engine before every DtH, so the HtDs run back to back
@@ -252,6 +274,138 @@ __device__ __forceinline__ TT tail(const Lane<TT> &s, const Rates &r) {
         const TT pw = TT(r.p_d) * (s.dev - s.t);
         const TT ud = pw > s.slack ? pw - s.slack : TT(0);
         const TT dend = s.t + ceil_q(ud, r.q_log2) + (s.dpre - s.dthru);
+        T = tmax(T, dend);
+    }
+    return T;
+}
+
+// ------------------------------------------------------------ chain form
+// Simulation state at the start of a window, two DMA engines.  The DtHs of
+// positions < j are on the chain (entries in the queue); c is the first of
+// them that may still run at t, and its entry is kept in registers.
+template <typename TT>
+struct CLane {
+    using ST = typename Signed<TT>::type;
+    TT t;       // now: end of the previous HtD (0 before the first)
+    TT ck;      // end of the previous kernel
+    ST emax;    // max over placed positions p of (K_p end - sum_{s<p} d_s)
+    TT dpre;    // sum of solo DtH durations of the positions placed so far
+    TT elast;   // end of the last DtH on the chain (0 while it is empty)
+    TT cs, ce;  // start and end of DtH c (when c is on the chain)
+    TT dcross;  // sum of solo DtH durations of the DtHs before c
+    int c;      // chain cursor: every DtH before c ends by t
+    bool run;   // the last window's HtD ended while DtH c ran
+};
+
+template <typename TT>
+__device__ __forceinline__ void lane_reset(CLane<TT> &s) {
+    using ST = typename Signed<TT>::type;
+    s.t = 0; s.ck = 0;
+    s.emax = (ST)(((TT)1) << (8 * sizeof(TT) - 1));  // most negative
+    s.dpre = 0; s.elast = 0; s.cs = 0; s.ce = 0; s.dcross = 0;
+    s.c = 0; s.run = false;
+}
+
+// Window j of the chain form: HtD of task x from s.t, against the DtHs on the
+// chain.  The loop visits only DtHs that end before the HtD: in the busy state
+// the HtD end estimate stays valid while DtHs follow each other without a gap;
+// at a gap the exact remaining work gives the idle estimate, and a DtH that
+// starts before it gives a new busy estimate.  Event order and roundings are
+// those of the event-by-event window (an event at ev is processed when ev is
+// before the current estimate).  PUT = false skips appending DtH j (the last
+// position: no later window reads it).
+template <int DMA = DMA_TWO, bool PUT = true, typename TT, int TS, int QS>
+__device__ __forceinline__ void window(CLane<TT> &s, int j, uint32_t x, const View<TT, TS, QS> &v,
+                                       const Rates &r) {
+    static_assert(DMA == DMA_TWO, "the chain form models two DMA engines");
+    using ST = typename Signed<TT>::type;
+    const Quad<TT> tx = v.task(x);
+    int i = s.c;
+    TT S = s.cs, E = s.ce, dsum = s.dcross;
+    TT rc = s.t;                  // last rate change
+    TT u = tx.h << r.q_log2;      // HtD work left at rc, 1/q solo-ns
+    TT eb;                        // HtD end estimate
+    TT ecmp = E;                  // end of the running DtH; inf once the HtD end is final
+    if (!(i < j)) {
+        eb = s.t + tx.h;          // no DtH on the chain (first position)
+        ecmp = inf_time<TT>();
+    } else if (S < s.t) {
+        eb = s.t + tx.hp;         // DtH c runs at t
+    } else {
+        const TT ei = s.t + tx.h;
+        if (S < ei) {             // DtH c starts inside the window
+            u -= (S - s.t) << r.q_log2;
+            rc = S;
+            eb = S + (TT)ceil_p(u, r.p_h, r.inv_ph, r.c_ph);
+        } else {
+            eb = ei;
+            ecmp = inf_time<TT>();
+        }
+    }
+    // One exit: while the running DtH ends before the estimate, it completes
+    // and the next one on the chain follows, after a gap or without one.
+    while (ecmp < eb) {
+        // its solo time joins the crossed sum (p_dth dp = q d + slack, slack < q)
+        dsum += (TT(r.p_d) * (E - S)) >> r.q_log2;
+        const TT ep = E;
+        ++i;
+        const Span<TT> nx = v.span(i < j ? i : j - 1);  // slot j - 1 exists: i >= 1
+        S = nx.s;
+        E = nx.e;
+        ecmp = E;
+        if (!(i < j) || S != ep) {
+            // the DtH engine goes idle at ep: exact work left, idle estimate;
+            // the next DtH starts from idle if it begins before that estimate
+            u -= TT(r.p_h) * (ep - rc);
+            rc = ep;
+            const TT ei = rc + ceil_q(u, r.q_log2);
+            const bool start = i < j && S < ei;
+            const TT us = u - ((S - rc) << r.q_log2);
+            const TT ebs = S + (TT)ceil_p(us, r.p_h, r.inv_ph, r.c_ph);
+            u = start ? us : u;
+            rc = start ? S : rc;
+            eb = start ? ebs : ei;
+            ecmp = start ? ecmp : inf_time<TT>();
+        }
+    }
+    const TT eh = eb;
+    const bool run = ecmp != inf_time<TT>();
+    s.c = i;
+    s.cs = S;
+    s.ce = E;
+    s.dcross = dsum;
+    s.run = run;
+    s.t = eh;
+    s.ck = tmax(eh, s.ck) + tx.k;
+    const ST e = (ST)s.ck - (ST)s.dpre;
+    s.emax = e > s.emax ? e : s.emax;
+    s.dpre += tx.d;
+    if constexpr (PUT) {
+        // DtH j joins the chain: it starts once the engine and its kernel are done
+        Span<TT> sp;
+        sp.s = tmax(s.elast, s.ck);
+        sp.e = sp.s + v.d(x).dp;
+        v.put_span(j, sp);
+        s.elast = sp.e;
+        if (s.c == j) {
+            s.cs = sp.s;
+            s.ce = sp.e;
+        }
+    }
+}
+
+// Total time of the chain form once the last HtD has ended at s.t: the
+// two-machine recurrence of the event form's tail.  A DtH running at s.t has
+// moved p_dth (s.t - start) of its q d work, so it needs
+// d - floor(p_dth (s.t - start) / q) more ns at full speed, followed by the
+// solo times of the DtHs after it.
+template <int DMA = DMA_TWO, typename TT>
+__device__ __forceinline__ TT tail(const CLane<TT> &s, const Rates &r) {
+    static_assert(DMA == DMA_TWO, "the chain form models two DMA engines");
+    using ST = typename Signed<TT>::type;
+    TT T = (TT)(s.emax + (ST)s.dpre);
+    if (s.run) {
+        const TT dend = s.t + (s.dpre - s.dcross) - ((TT(r.p_d) * (s.t - s.cs)) >> r.q_log2);
         T = tmax(T, dend);
     }
     return T;
