@@ -13,6 +13,7 @@
 // 10!/4! without any host-side schedule.  Per-group results are combined with
 // 64-bit atomics on packed (time, rank) keys, so they do not depend on the
 // order in which tiles finish.
+#include <type_traits>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -145,9 +146,14 @@ __global__ __launch_bounds__(1024) void batch_prepare(const tgo_task *__restrict
     }
 }
 
+// Simulation state of a lane: the chain form with two DMA engines, the
+// event form (windows without DtH events) with one.
+template <typename TT, int DMA>
+using BatchLane = std::conditional_t<DMA == DMA_TWO, CLane<TT>, Lane<TT>>;
+
 template <int M, int DMA>
 __device__ __forceinline__ void run_subtree(const Ctx &c, const View<uint32_t, 1, BT_THREADS> &v,
-                                            const Lane<uint32_t> &st, uint32_t list,
+                                            const BatchLane<uint32_t, DMA> &st, uint32_t list,
                                             Sub<uint32_t> &u) {
     level<uint32_t, M, false, 1, BT_THREADS, DMA>(c, v, st, list, 0u, u);
 }
@@ -223,7 +229,7 @@ __global__ __launch_bounds__(BT_THREADS) __attribute__((amdgpu_waves_per_eu(DMA 
         for (int k = 0; k < cfg.lane_mult; ++k) {
             const uint32_t s = s0 + (uint32_t)k * 64u + (uint32_t)lane;
             if (s < S) {
-                Lane<uint32_t> st;
+                BatchLane<uint32_t, DMA> st;
                 const uint32_t list = (uint32_t)prefix<DMA>(st, s, n, m, v, r);
                 Sub<uint32_t> u;
                 sub_init(u);
@@ -311,7 +317,7 @@ __global__ __launch_bounds__(BT_THREADS) void batch_wide_kernel(const tgo_task *
         p.min_t = ~0ull; p.min_r = ~0ull; p.max_t = 0; p.max_r = ~0ull;
         p.sum_lo = 0; p.sum_hi = 0; p.fp = 0; p.status = 0; p.pad = 0;
         for (uint32_t sb = s0 + (uint32_t)lane; sb < s1; sb += 64u) {
-            Lane<TT> st;
+            BatchLane<TT, DMA> st;
             const uint32_t list = (uint32_t)prefix<DMA>(st, sb, n, m, v, r);
             Sub<TT> u;
             sub_init(u);
