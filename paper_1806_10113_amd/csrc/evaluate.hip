@@ -49,9 +49,7 @@ __global__ __launch_bounds__(EV_THREADS) void evaluate_kernel(const tgo_task *__
             out[i] = TGO_EINVAL;
             continue;
         }
-        Lane<TT> st = lane_init<TT>();
-        for (int j = 0; j < n; ++j) window(st, j, (uint32_t)o[j], v, r);
-        out[i] = (int64_t)tail(st, r);
+        out[i] = (int64_t)simulate_order(n, [o](int j) { return (uint32_t)o[j]; }, v, r);
     }
 }
 

@@ -411,6 +411,23 @@ __device__ __forceinline__ TT tail(const CLane<TT> &s, const Rates &r) {
     return T;
 }
 
+// T of one whole ordering o[0..n) (o(j) gives the task at position j): the
+// chain form with two DMA engines, the event form's windows with one.  The
+// queue needs n - 1 slots.
+template <typename TT, int TS, int QS, typename Order>
+__device__ __forceinline__ TT simulate_order(int n, Order o, const View<TT, TS, QS> &v, const Rates &r) {
+    if (is_one_dma<DMA_RUNTIME>(r)) {
+        Lane<TT> st = lane_init<TT>();
+        for (int j = 0; j < n; ++j) window<DMA_ONE>(st, j, o(j), v, r);
+        return tail<DMA_ONE>(st, r);
+    }
+    CLane<TT> st;
+    lane_reset(st);
+    for (int j = 0; j + 1 < n; ++j) window<DMA_TWO, true>(st, j, o(j), v, r);
+    if (n > 0) window<DMA_TWO, false>(st, n - 1, o(n - 1), v, r);
+    return tail<DMA_TWO>(st, r);
+}
+
 // Host-side validity bound for the 32-bit time path (checked on the device
 // from the task table): every work amount fits 31 bits and every instant of
 // the simulation fits 31 bits.  T never exceeds the sum of each command's

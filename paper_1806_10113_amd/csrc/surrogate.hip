@@ -48,9 +48,7 @@ struct WaveTables {
 
 template <typename TT, int NT>
 __device__ __forceinline__ TT eval_perm(uint64_t perm, int n, const View<TT, 1, NT> &v, const Rates &r) {
-    Lane<TT> st = lane_init<TT>();
-    for (int j = 0; j < n; ++j) window(st, j, (uint32_t)((perm >> (4 * j)) & 15u), v, r);
-    return tail(st, r);
+    return simulate_order(n, [perm](int j) { return (uint32_t)((perm >> (4 * j)) & 15u); }, v, r);
 }
 
 template <typename TT>
