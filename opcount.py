@@ -1,13 +1,16 @@
 """Algorithmic operation count of the exhaustive enumeration (measurement aid).
 
-Counts, on the CPU, the integer operations that the window formulation of the
-model (Section 4.1 simulator, overlap rates of Section 4.2.1) and the
-prefix-sharing walk over the last M positions need per ordering: windows,
-DtH events inside windows, rate changes, tails and the per-ordering
-bookkeeping, each priced at the 32-bit ALU operations its statement needs
-(listed in COSTS).  Lanes are counted on their own: the lockstep of a wave
-(a wave runs as many event iterations as its busiest lane) is reported
-separately, as the ratio of wave-lockstep to lane iterations.
+Counts, on the CPU, the integer operations that the chain form of the model
+(Section 4.1 simulator, overlap rates of Section 4.2.1: every DtH that starts
+before the last HtD ends runs at the overlapped rate, so its start and end are
+appended to a chain once its kernel's end is known) and the prefix-sharing
+walk over the last M positions need per ordering: windows, DtHs crossed
+inside a window, gaps of the DtH engine, starts from idle, chain appends,
+tails and the per-ordering bookkeeping, each priced at the 32-bit ALU
+operations its statement needs (listed in COSTS).  Lanes are counted on their
+own: the lockstep of a wave (a wave runs as many loop iterations as its
+busiest lane) is reported separately, as the ratio of wave-lockstep to lane
+iterations.
 
 The result prices the headline kernel's useful work: algorithmic ops per
 ordering x orderings per second / the ALU peak is the roofline fraction of
@@ -30,14 +33,17 @@ from paper_1806_10113_amd import workloads as W
 
 # ALU operations per statement of the formulation (32-bit integer or select)
 COSTS = {
-    "window_setup": 6,     # idle DtH learns its kernel end (2 compares, select); HtD work, end estimate (select, add)
-    "loop_test": 1,        # next DtH event before the HtD end?
-    "event": 16,           # cursor, slot address, start test (3), rate test, overlapped-work split (3), slack,
-                           # next event (4), DtH solo time
-    "rate_change": 11,     # exact HtD work left (select, sub, mul, sub), two ceilings (3 + 2), new estimate (2)
-    "window_end": 6,       # kernel end (max, add), its lateness against the DtH prefix (sub, max), DtH prefix, slot
-    "tail": 2,             # max(emax + dpre, ...) when the DtH engine is idle at the last HtD end
-    "tail_running": 11,    # running DtH's work left and its end, when busy
+    "window_setup": 6,     # cursor on the chain?, running at t?, idle end estimate, starts inside?, select
+    "start": 6,            # DtH starts inside the window: work left (sub, shift, sub), busy estimate (ceil, add)
+    "loop_test": 1,        # running DtH ends before the estimate?
+    "crossing": 10,        # its solo time (sub, mul, shift, add), cursor, slot index and address, gap test (3)
+    "gap": 18,             # exact work left (sub, mul, sub), idle estimate (3), start test (2), work and
+                           # busy estimate if it starts (3 + 4), four selects
+    "window_end": 6,       # kernel end (max, add), its lateness against the DtH prefix (sub, max), DtH prefix,
+                           # running flag
+    "append": 6,           # chain entry (max, add), slot address, cursor refresh (compare, two selects)
+    "tail": 2,             # emax + dpre when no DtH runs at the last HtD end
+    "tail_running": 7,     # work moved by the running DtH (sub, mul, shift), solo times left (sub, add), max
     "leaf": 12,            # min / max with rank, 64-bit sum, 64-bit rank-weighted sum
     "child": 9,            # next task from the nibble list (2), leaf index (2), remaining list (5)
     "prefix_position": 10,  # factorial digit (div, mul, sub), nibble extract and list splice
@@ -63,15 +69,16 @@ INF = 1 << 62
 
 
 class Lane:
-    __slots__ = ("t", "ck", "dev", "slack", "dpre", "dthru", "emax", "i", "drun")
+    """State at the start of a window; S, E is the chain (shared by copies,
+    like the per-lane queue: entry j is written by the window of position j)."""
+    __slots__ = ("t", "ck", "emax", "dpre", "elast", "cs", "ce", "dcross", "c", "run", "S", "E")
 
-    def __init__(self):
-        self.t = self.ck = 0
-        self.dev = INF
-        self.slack = self.dpre = self.dthru = 0
+    def __init__(self, n):
+        self.t = self.ck = self.dpre = self.elast = self.cs = self.ce = self.dcross = self.c = 0
         self.emax = -INF
-        self.i = 0
-        self.drun = False
+        self.run = False
+        self.S = [0] * n
+        self.E = [0] * n
 
     def copy(self):
         c = Lane.__new__(Lane)
@@ -84,74 +91,82 @@ class Counter:
     def __init__(self):
         self.ops = 0
         self.windows = 0
-        self.events = 0
-        self.rate_changes = 0
+        self.events = 0        # DtHs crossed inside windows
+        self.rate_changes = 0  # gaps of the DtH engine inside windows
 
     def add(self, key, n=1):
         self.ops += COSTS[key] * n
 
 
-def window(s, j, x, H, D, Q, r, put, cnt, iters_out=None):
-    """Window j of the formulation (HtD of task x at position j); returns T
-    only through the lane state, counts operations into cnt."""
+def window(s, j, x, H, D, r, put, cnt, iters_out=None):
+    """Window j (HtD of task x at position j) of the chain form; the lane
+    state advances in place, operations are counted into cnt."""
     q = 1 << r.q_log2
     h, hp, k, d = H[x]
     cnt.add("window_setup")
     cnt.windows += 1
-    if not s.drun and s.i == j - 1:
-        s.dev = s.ck
-    jlast = j - 1 if j > 0 else 0
-    uh = h << r.q_log2
-    th0 = s.t
-    eh = s.t + (hp if s.drun else h)
+    i, S, E, dsum = s.c, s.cs, s.ce, s.dcross
+    rc, u, ecmp = s.t, h << r.q_log2, E
+    if not i < j:
+        eb, ecmp = s.t + h, INF
+    elif S < s.t:
+        eb = s.t + hp
+    else:
+        ei = s.t + h
+        if S < ei:
+            cnt.add("start")
+            u -= (S - s.t) << r.q_log2
+            rc = S
+            eb = S + -(-u // r.p_h)
+        else:
+            eb, ecmp = ei, INF
     it = 0
     while True:
         cnt.add("loop_test")
-        ev = s.dev
-        if not ev < eh:
+        if not ecmp < eb:
             break
         it += 1
-        cnt.add("event")
+        cnt.add("crossing")
         cnt.events += 1
-        inew = s.i + (1 if s.drun else 0)
-        ck_n, dp_n = Q[inew if put else min(inew, jlast)]
-        start = inew < j and ck_n <= ev
-        if start != s.drun:
-            cnt.add("rate_change")
+        dsum += (r.p_d * (E - S)) >> r.q_log2
+        ep = E
+        i += 1
+        S, E = s.S[min(i, j - 1)], s.E[min(i, j - 1)]
+        ecmp = E
+        if i >= j or S != ep:
+            cnt.add("gap")
             cnt.rate_changes += 1
-            uh -= (r.p_h if s.drun else q) * (ev - th0)
-            th0 = ev
-            cp = -(-uh // r.p_h)
-            cq = -(-uh // q)
-            eh = ev + (cp if start else cq)
-        w = r.p_d * dp_n
-        if start:
-            s.dthru += w >> r.q_log2
-            s.slack = w & (q - 1)
-            s.dev = ev + dp_n
-        else:
-            s.dev = ck_n if inew < j else INF
-        s.drun = start
-        s.i = inew
+            u -= r.p_h * (ep - rc)
+            rc = ep
+            ei = rc + -(-u // q)
+            if i < j and S < ei:
+                u -= (S - rc) << r.q_log2
+                rc = S
+                eb = rc + -(-u // r.p_h)
+            else:
+                eb, ecmp = ei, INF
     cnt.add("window_end")
-    s.t = eh
-    s.ck = max(eh, s.ck) + k
+    s.c, s.cs, s.ce, s.dcross, s.run = i, S, E, dsum, ecmp != INF
+    s.t = eb
+    s.ck = max(eb, s.ck) + k
     s.emax = max(s.emax, s.ck - s.dpre)
     s.dpre += d
     if put:
-        Q[j] = (s.ck, D[x])
+        cnt.add("append")
+        sj = max(s.elast, s.ck)
+        s.S[j], s.E[j] = sj, sj + D[x]
+        s.elast = s.E[j]
+        if s.c == j:
+            s.cs, s.ce = s.S[j], s.E[j]
     if iters_out is not None:
         iters_out.append(it)
 
 
 def tail(s, r, cnt):
-    q = 1 << r.q_log2
     T = s.emax + s.dpre
-    if s.drun:
+    if s.run:
         cnt.add("tail_running")
-        pw = r.p_d * (s.dev - s.t)
-        ud = pw - s.slack if pw > s.slack else 0
-        T = max(T, s.t + (-(-ud // q)) + (s.dpre - s.dthru))
+        T = max(T, s.t + (s.dpre - s.dcross) - ((r.p_d * (s.t - s.cs)) >> r.q_log2))
     else:
         cnt.add("tail")
     return T
@@ -160,13 +175,12 @@ def tail(s, r, cnt):
 def walk_subtree(tasks, sub, M, r, cnt, trace=None):
     """The orderings of subtree `sub` (ranks sub*M! ..), as one lane walks
     them; returns their times in rank order.  trace (optional) receives the
-    event-iteration count of every window in walk order."""
+    loop iterations (DtHs crossed) of every window in walk order."""
     n = len(tasks)
     H, D = tables(tasks, r)
-    Q = [(0, 0)] * n
     cnt.add("subtree")
     rest = list(range(n))
-    s = Lane()
+    s = Lane(n)
     plen = n - M
     blk = math.factorial(n - 1) // math.factorial(M)
     rem = sub
@@ -177,7 +191,7 @@ def walk_subtree(tasks, sub, M, r, cnt, trace=None):
         if i + 1 < plen:
             blk //= n - 1 - i
         x = rest.pop(c)
-        window(s, i, x, H, D, Q, r, True, cnt, trace)
+        window(s, i, x, H, D, r, True, cnt, trace)
     out = []
 
     def level(s, L, rest):
@@ -186,7 +200,7 @@ def walk_subtree(tasks, sub, M, r, cnt, trace=None):
             cnt.add("child")
             x = rest[ci]
             s2 = s.copy()
-            window(s2, j, x, H, D, Q, r, L > 1, cnt, trace)
+            window(s2, j, x, H, D, r, L > 1, cnt, trace)
             if L == 1:
                 cnt.add("leaf")
                 out.append(tail(s2, r, cnt))
@@ -229,8 +243,8 @@ def main():
         "M": M, "subtrees": args.subtrees, "orderings": orderings,
         "alg_ops_per_ordering": cnt.ops / orderings,
         "windows_per_ordering": cnt.windows / orderings,
-        "events_per_ordering": cnt.events / orderings,
-        "rate_changes_per_ordering": cnt.rate_changes / orderings,
+        "dth_crossings_per_ordering": cnt.events / orderings,
+        "gaps_per_ordering": cnt.rate_changes / orderings,
         "lockstep_iterations_ratio": float(wave_iters / lane_iters),
         "costs": COSTS,
     }
