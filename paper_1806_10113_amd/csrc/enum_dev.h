@@ -100,6 +100,76 @@ __device__ __forceinline__ uint64_t prefix(LaneT &st, uint32_t s, int n, int m,
     return list;
 }
 
+// Binomial coefficients C(a, b) for a, b <= MAXN.
+struct Binom {
+    uint32_t c[MAXN + 1][MAXN + 1];
+    constexpr Binom() : c() {
+        for (int a = 0; a <= MAXN; ++a) {
+            c[a][0] = 1;
+            for (int b = 1; b <= a; ++b) c[a][b] = c[a - 1][b - 1] + (b <= a - 1 ? c[a - 1][b] : 0u);
+        }
+    }
+};
+__constant__ constexpr Binom BINOM{};
+
+// Set-major order of the subtrees: index s' = c * plen! + p, where c ranks
+// (lexicographically) the set of tasks in the prefix of length plen = n - m
+// and p ranks their order.  Consecutive indices share the set, so the lanes
+// of a wave walk the same remaining tasks in the same order (their walked
+// windows place the same task at every step) and differ only in the order of
+// their prefixes, which makes their DtH work alike.  Decodes s', simulates the
+// prefix windows and returns the remaining tasks (ascending, one per nibble);
+// *lex receives the subtree's lexicographic index (its first rank / m!).
+template <int DMA, typename LaneT, typename TT, int TS, int QS>
+__device__ __forceinline__ uint64_t prefix_by_set(LaneT &st, uint32_t sp, int n, int m,
+                                                  const View<TT, TS, QS> &v, const Rates &r, uint32_t *lex) {
+    lane_reset(st);
+    const int plen = n - m;
+    uint32_t pf = 1;  // plen! < 2^32: n!/m! = C(n, plen) * plen! fits 32 bits
+    for (int i = 2; i <= plen; ++i) pf *= (uint32_t)i;
+    const uint32_t cset = sp / pf;
+    uint32_t p = sp - cset * pf;
+    // the set: the cset-th plen-subset of {0..n-1} in lexicographic order
+    uint64_t sub = 0, rest = 0;  // ascending nibble lists of the set and of the rest
+    int ns = 0, nr = 0;
+    uint32_t cc = cset;
+    int k = plen;
+    for (int x = 0; x < n; ++x) {
+        const uint32_t w = k > 0 ? BINOM.c[n - 1 - x][k - 1] : 0u;  // subsets whose next element is x
+        if (k > 0 && cc < w) {
+            sub |= (uint64_t)x << (4 * ns++);
+            --k;
+        } else {
+            cc -= k > 0 ? w : 0u;
+            rest |= (uint64_t)x << (4 * nr++);
+        }
+    }
+    // the order: factorial digits of p over the set; the lexicographic index
+    // of the prefix counts, at each position, the unused tasks below it
+    uint32_t f = pf / (plen > 0 ? (uint32_t)plen : 1u);  // (plen - 1)!
+    uint32_t blk = 1;  // (n-1-i)!/m! at position i
+    for (int i = m + 1; i <= n - 1; ++i) blk *= (uint32_t)i;
+    uint32_t avail = (1u << n) - 1u;
+    uint32_t s = 0;
+    for (int i = 0; i < plen; ++i) {
+        const uint32_t d = p / f;
+        p -= d * f;
+        const uint32_t x = (uint32_t)(sub >> (4 * d)) & 15u;
+        const uint64_t lo = sub & ((1ull << (4 * d)) - 1ull);
+        const uint64_t hi = (sub >> (4 * d + 4)) << (4 * d);
+        sub = lo | hi;
+        s += (uint32_t)__popc(avail & ((1u << x) - 1u)) * blk;
+        avail &= ~(1u << x);
+        if (i + 1 < plen) {
+            f /= (uint32_t)(plen - 1 - i);
+            blk /= (uint32_t)(n - 1 - i);
+        }
+        window<DMA>(st, i, x, v, r);
+    }
+    *lex = s;
+    return rest;
+}
+
 template <typename T>
 __device__ __forceinline__ T shfl_xor64(T v, int m) {
     const uint64_t u = (uint64_t)v;

@@ -4,9 +4,9 @@
 // Section 5.1 rule out at runtime on a CPU), reduced to the best, worst and
 // average ordering (the quantities plotted in Section 6).
 //
-// Each lane walks subtrees (see enum_dev.h), striding over the grid; a lane
-// meets its ranks in increasing order, and every merge prefers the lower rank,
-// so the reduction keeps the lowest rank on ties.
+// Each lane walks subtrees (see enum_dev.h), striding over the grid in the
+// set-major order of prefix_by_set; every merge prefers the lower rank on
+// equal times, so the reduction keeps the lowest rank on ties.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -43,16 +43,18 @@ __device__ __forceinline__ void acc_init(Acc<TT> &a) {
 }
 
 // Fold a finished subtree (first rank r0) into the lane accumulators.  The
-// lane meets its subtrees in increasing rank order, so strict comparisons
-// keep the lowest rank on ties.  fingerprint: sum of (2r+1) T with
-// r = r0 + l is 2 (r0 sum T + sum l T) + sum T.
+// lane meets its subtrees in set-major order, not in rank order, so ties
+// between subtrees go to the lower rank explicitly (inside a subtree the
+// leaves come in rank order).  fingerprint: sum of (2r+1) T with r = r0 + l
+// is 2 (r0 sum T + sum l T) + sum T.
 // On the 32-bit time path every T is below 2^31 and a group has at most
 // 13! < 2^33 orderings, so even the sum over all of them stays below 2^64:
 // the lane keeps no carry word there (two fewer live registers).
 template <typename TT>
 __device__ __forceinline__ void fold(Acc<TT> &a, const Sub<TT> &u, uint64_t r0) {
-    if (u.min_t < a.min_t) { a.min_t = u.min_t; a.min_r = r0 + u.min_l; }
-    if (u.max_t1 > a.max_t1) { a.max_t1 = u.max_t1; a.max_r = r0 + u.max_l; }
+    const uint64_t rmin = r0 + u.min_l, rmax = r0 + u.max_l;
+    if (u.min_t < a.min_t || (u.min_t == a.min_t && rmin < a.min_r)) { a.min_t = u.min_t; a.min_r = rmin; }
+    if (u.max_t1 > a.max_t1 || (u.max_t1 == a.max_t1 && rmax < a.max_r)) { a.max_t1 = u.max_t1; a.max_r = rmax; }
     const uint64_t lo = a.sum_lo + u.sum;
     if constexpr (sizeof(TT) == 8) a.sum_hi += lo < a.sum_lo ? 1ull : 0ull;
     a.sum_lo = lo;
@@ -176,8 +178,9 @@ void exhaustive_kernel(const tgo_task *__restrict__ tasks, int n, Rates r, uint3
     using LaneT = std::conditional_t<DMA == DMA_TWO, CLane<TT>, Lane<TT>>;
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_sub; s += stride) {
         LaneT st;
-        const uint64_t list = prefix<DMA>(st, s, n, M, v, r);
-        const uint64_t r0 = (uint64_t)s * factorial(M);
+        uint32_t lex;
+        const uint64_t list = prefix_by_set<DMA>(st, s, n, M, v, r, &lex);
+        const uint64_t r0 = (uint64_t)lex * factorial(M);
         if constexpr (STORE) c.out_sub = out + r0;
         Sub<TT> u;
         sub_init(u);

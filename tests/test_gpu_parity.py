@@ -184,6 +184,32 @@ def test_exhaustive_grid_sizes_agree(dev, monkeypatch):
     monkeypatch.delenv("TGO_EXHAUSTIVE_BLOCKS", raising=False)
 
 
+def test_exhaustive_ties_across_subtrees(dev, monkeypatch):
+    """Lanes meet their subtrees out of rank order (set-major), so equal
+    times in different subtrees must still resolve to the lowest rank: groups
+    whose tasks come in identical pairs (every ordering ties with the ones
+    that swap equal tasks) against the oracle, on one block (each lane folds
+    hundreds of subtrees), a few blocks and the default grid."""
+    from paper_1806_10113_amd import tgo
+    rng = np.random.default_rng(21)
+    groups = []
+    for n in (8, 9, 10):
+        base = rng.integers(1, 40, size=((n + 1) // 2, 3))
+        groups.append(np.concatenate([base, base])[:n][rng.permutation(n)].astype(np.int64))
+    models = (M.DEFAULT, M.Model(4, 3, 3, 1))
+    refs = {(i, m): cmodel.exhaustive(g, m) for i, g in enumerate(groups) for m in models}
+    for blocks in (None, "1", "3"):
+        if blocks is None:
+            monkeypatch.delenv("TGO_EXHAUSTIVE_BLOCKS", raising=False)
+        else:
+            monkeypatch.setenv("TGO_EXHAUSTIVE_BLOCKS", blocks)
+        for i, g in enumerate(groups):
+            for m in models:
+                s = tgo.read_summary(tgo.exhaustive(to_dev(g, dev), tmodel(m))[0])
+                check_summary(s, refs[(i, m)], len(g))
+    monkeypatch.delenv("TGO_EXHAUSTIVE_BLOCKS", raising=False)
+
+
 def test_exhaustive_concurrent_streams(dev):
     """Calls in flight on two streams at once do not share scratch memory:
     each gets the oracle's per-ordering times and summary (two groups, both
