@@ -46,8 +46,10 @@ COSTS = {
     "tail_running": 7,     # work moved by the running DtH (sub, mul, shift), solo times left (sub, add), max
     "leaf": 12,            # min / max with rank, 64-bit sum, 64-bit rank-weighted sum
     "child": 9,            # next task from the nibble list (2), leaf index (2), remaining list (5)
-    "prefix_position": 10,  # factorial digit (div, mul, sub), nibble extract and list splice
-    "subtree": 16,         # list init, rank of the subtree, fold into the lane accumulators
+    "prefix_position": 13,  # factorial digit (div, mul, sub), nibble extract and list splice,
+                            # lexicographic digit (mask, popcount, multiply-add)
+    "subtree": 64,         # set-major index split, the prefix's task set (one binomial step per task),
+                           # fold into the lane accumulators with ties to the lower rank
 }
 
 
@@ -211,6 +213,30 @@ def walk_subtree(tasks, sub, M, r, cnt, trace=None):
     return out
 
 
+def set_major_subtree(sp, n, m):
+    """Lexicographic subtree index of set-major index sp (the order in which a
+    wave's 64 lanes take subtrees: consecutive indices share the prefix's set
+    of tasks and differ in its order)."""
+    plen = n - m
+    pf = math.factorial(plen)
+    cset, p = divmod(sp, pf)
+    sub, k = [], plen
+    for x in range(n):
+        w = math.comb(n - 1 - x, k - 1) if k > 0 else 0
+        if k > 0 and cset < w:
+            sub.append(x)
+            k -= 1
+        elif k > 0:
+            cset -= w
+    rest, s = list(range(n)), 0
+    for i in range(plen):
+        d, p = divmod(p, math.factorial(plen - 1 - i))
+        x = sub.pop(d)
+        s = s * (n - i) + rest.index(x)
+        rest.remove(x)
+    return s
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--subtrees", type=int, default=3000)
@@ -226,14 +252,14 @@ def main():
     for sidx in subs:
         walk_subtree(tasks, int(sidx), M, r, cnt)
     orderings = args.subtrees * math.factorial(M)
-    # lockstep of waves: 64 lanes take 64 consecutive subtrees
+    # lockstep of waves: 64 lanes take 64 consecutive set-major subtrees
     lane_iters, wave_iters = 0, 0
-    starts = rng.choice(nsub - 64, size=args.waves, replace=False)
-    for s0 in starts:
+    starts = rng.choice(nsub // 64, size=args.waves, replace=False)
+    for w0 in starts:
         traces = []
         for lane in range(64):
             tr = []
-            walk_subtree(tasks, int(s0) + lane, M, r, Counter(), tr)
+            walk_subtree(tasks, set_major_subtree(64 * int(w0) + lane, n, M), M, r, Counter(), tr)
             traces.append(tr)
         arr = np.array(traces)  # every lane walks the same tree shape
         lane_iters += arr.sum()
