@@ -484,25 +484,51 @@ def serving_extra(dev, sur, seconds: float):
     # below 95 % of offered)
     pool = W.batch_groups(50_000, 4, 16, seed=5, per_task_label=True)
     sweep, capacity, sustained = [], None, None
-    rate = 20_000.0
-    while rate <= 640_000.0:
+    cap_lo, cap_hi = None, None  # offered loads around the capacity point
+
+    def run_at(rate, refine):
+        nonlocal capacity, sustained
         a = W.poisson_stream(rate, 1.5, pool, seed=6)
-        r = {"offered_groups_per_s": rate, **_serve_run(sur, a, 0.5)}
+        r = {"offered_groups_per_s": rate, "refine": refine, **_serve_run(sur, a, 0.5)}
         sweep.append(r)
         keeps_up = r["achieved_groups_per_s"] >= 0.95 * rate and r["bad_status"] == 0
+        if keeps_up:
+            sustained = max(sustained or 0.0, r["achieved_groups_per_s"])
+        ok = keeps_up and r["p99_us"] <= SERVE_P99_TARGET_US
+        if ok:
+            capacity = max(capacity or 0.0, r["achieved_groups_per_s"])
+        return keeps_up, ok
+
+    rate = 20_000.0
+    while rate <= 640_000.0:
+        keeps_up, ok = run_at(rate, False)
+        if ok:
+            cap_lo = rate
+        elif cap_hi is None:
+            cap_hi = rate
         if not keeps_up:
             break
-        sustained = r["achieved_groups_per_s"]
-        if r["p99_us"] <= SERVE_P99_TARGET_US:
-            capacity = r["achieved_groups_per_s"]
         rate *= 2
+    # three bisection steps between the last load that met the p99 target and
+    # the first that did not
+    if cap_lo is not None and cap_hi is not None:
+        for _ in range(3):
+            mid = round(0.5 * (cap_lo + cap_hi), -3)
+            if mid <= cap_lo or mid >= cap_hi:
+                break
+            _, ok = run_at(mid, True)
+            if ok:
+                cap_lo = mid
+            else:
+                cap_hi = mid
     res["capacity_sweep"] = sweep
     res["capacity_groups_per_s"] = capacity
     res["sustained_groups_per_s"] = sustained
     res["capacity_rule"] = (f"offered load doubled from 20,000/s (1.5 s traces, latency over arrivals "
-                            f"after 0.5 s) until the server falls below 95 % of it: capacity = the largest "
-                            f"load served with p99 <= {SERVE_P99_TARGET_US:g} us, sustained = the largest "
-                            f"load served at any latency")
+                            f"after 0.5 s) until the server falls below 95 % of it, then three bisection "
+                            f"steps between the last load served with p99 <= {SERVE_P99_TARGET_US:g} us and "
+                            f"the first that was not: capacity = the largest load served with p99 <= "
+                            f"{SERVE_P99_TARGET_US:g} us, sustained = the largest load served at any latency")
     # a budget that binds: the server's own memory plus 512 task rows
     tight = res["base_bytes"] + 512 * 24
     a = W.poisson_stream(20_000.0, 2.0, pool, seed=8)
