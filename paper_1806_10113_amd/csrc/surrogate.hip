@@ -35,7 +35,7 @@ constexpr int GK = 32;  // K per MFMA instruction (16 x 16 x 32 bf16)
 // ------------------------------------------------------------- exact lanes
 // Exact evaluation of (group, ordering) items, one wave per group tile: the
 // wave loads the group's task table into its own LDS area and each lane
-// evaluates one ordering with the window code.  A group runs the 32-bit time
+// evaluates one ordering with simulate_order.  A group runs the 32-bit time
 // path when its times stay below 2^31 ns (group mode 0) and the 64-bit path
 // otherwise (mode 1); every kernel below exists in both widths and takes the
 // groups of its own mode.
