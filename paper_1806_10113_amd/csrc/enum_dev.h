@@ -58,8 +58,7 @@ template <typename TT, int L, bool STORE, int TS, int QS, int DMA, typename Lane
 __device__ __forceinline__ void level(const Ctx &c, const View<TT, TS, QS> &v, const LaneT &s,
                                       uint32_t list, uint32_t l, Sub<TT> &u) {
     const int j = c.n - L;
-#pragma unroll 1
-    for (int ci = 0; ci < L; ++ci) {
+    auto child = [&](int ci) {
         const uint32_t x = (list >> (4 * ci)) & 15u;
         LaneT s2 = s;
         window<DMA, (L > 1)>(s2, j, x, v, c.r);
@@ -71,6 +70,15 @@ __device__ __forceinline__ void level(const Ctx &c, const View<TT, TS, QS> &v, c
             const uint32_t hi = (list >> (4 * ci + 4)) << (4 * ci);
             level<TT, L - 1, STORE, TS, QS, DMA>(c, v, s2, lo | hi, l2, u);
         }
+    };
+    // the three innermost levels are unrolled (each child's state is then
+    // derived from the parent's registers without loop-carried copies)
+    if constexpr (L <= 3) {
+#pragma unroll
+        for (int ci = 0; ci < L; ++ci) child(ci);
+    } else {
+#pragma unroll 1
+        for (int ci = 0; ci < L; ++ci) child(ci);
     }
 }
 
