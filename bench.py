@@ -34,25 +34,25 @@ SEED = 1
 # of the 2 wave-instructions per CU-clock this implies.
 VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
-# VALU lane-ops per ordering issued by exhaustive_kernel<u32, M=4> on this
+# VALU lane-ops per ordering issued by exhaustive_kernel<u32, M=5> on this
 # workload: SQ_INSTS_VALU per launch x 64 lanes / 12! (rocprofv3 counter run
 # recorded in profiles/exhaustive_n12_counters.txt).
-VALU_LANE_OPS_PER_ORDERING = 207.81
+VALU_LANE_OPS_PER_ORDERING = 175.89
 # Share of lanes active per issued VALU instruction of that kernel on this
 # workload: SQ_THREAD_CYCLES_VALU / (64 x SQ_ACTIVE_INST_VALU) from a counter
 # run (profiles/exhaustive_n12_lane_utilisation.txt).  Issued lane-ops times
 # this share are the lane-ops that did work for some ordering; lanes masked off
 # in a divergent step do none.
-VALU_LANE_UTILISATION = 0.6950
+VALU_LANE_UTILISATION = 0.5805
 # Integer operations the method needs per ordering of that workload, counted
 # by `python opcount.py` (a transcription of the chain form of the windows and
-# the walk over the last four positions, each statement priced at its 32-bit
-# ALU operations, lanes counted on their own: 3.0 windows, 1.38 DtHs crossed
-# and 0.26 gaps of the DtH engine per ordering, the set-major prefix decode).
-ALG_OPS_PER_ORDERING = 121.8
+# the walk over the last five positions, each statement priced at its 32-bit
+# ALU operations, lanes counted on their own: 2.77 windows, 1.32 DtHs crossed
+# and 0.23 gaps of the DtH engine per ordering, the set-major prefix decode).
+ALG_OPS_PER_ORDERING = 110.6
 # HBM bytes per launch: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, each scaled by
 # what the counter reads for a 256 MiB device copy (same profile file).
-TRAFFIC_BYTES_PER_LAUNCH = 18_674_790
+TRAFFIC_BYTES_PER_LAUNCH = 833_346_406
 
 
 def parse():
@@ -699,7 +699,7 @@ def main():
         roof.update({"achieved": None, "frac": None})
     roof["traffic"] = TRAFFIC_BYTES_PER_LAUNCH
     roof["launch_ms"] = avg_launch_ms
-    roof["kernel"] = "exhaustive_kernel<u32, M=4>"
+    roof["kernel"] = "exhaustive_kernel<u32, M=5>"
     roof["launch_ms_note"] = "HIP events around the exhaustive call (time-path classify, main kernel, idle 64-bit twin, finalize)"
     roof["hbm_gbs"] = TRAFFIC_BYTES_PER_LAUNCH / (avg_launch_ms / 1e3) / 1e9
 

@@ -243,7 +243,7 @@ def main():
     ap.add_argument("--waves", type=int, default=40)
     args = ap.parse_args()
     tasks = W.single_group_mixed(12, 1)
-    n, M = 12, 4
+    n, M = 12, 5
     r = Rates()
     nsub = math.factorial(n) // math.factorial(M)
     rng = np.random.default_rng(0)

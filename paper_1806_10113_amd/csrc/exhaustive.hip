@@ -340,11 +340,11 @@ static int choose_m(int n, bool one_dma) {
         const int m = std::atoi(e);
         if (m >= 1 && m <= cap && m <= n) return m;
     }
-    // two engines: 4 levels beat 5 at n = 12 on MI355X (fewer live
-    // snapshots, one more wave per SIMD); deeper walks only pay when
-    // subtrees are scarce.  One engine: a window is a handful of operations,
-    // so the per-subtree prefix decode is worth amortising over 6 levels.
-    const int top = one_dma ? 6 : 4;
+    // two engines: with the three innermost levels unrolled, 5 levels beat 4
+    // at n = 12 on MI355X (1.81 vs 1.99 ms: fewer windows per ordering, 2.77
+    // vs 3.0).  One engine: a window is a handful of operations, so the
+    // per-subtree prefix decode is worth amortising over 6 levels.
+    const int top = one_dma ? 6 : 5;
     int m = 1;
     for (int c = top; c >= 1; --c) {
         if (c > n) continue;

@@ -24,7 +24,7 @@ def test_transcription_times_equal_the_oracle():
 
 
 def test_counts_per_subtree():
-    """Windows per subtree: n - 4 prefix windows and 4 + 12 + 24 + 24 walked."""
+    """Windows per subtree: n - 4 prefix windows and 4 + 12 + 24 + 24 walked (M = 4)."""
     cnt = opcount.Counter()
     opcount.walk_subtree(W.single_group_mixed(12, 1), 12345, 4, opcount.Rates(), cnt)
     assert cnt.windows == 8 + 64
