@@ -259,7 +259,9 @@ void tgo_plan_destroy(tgo_plan *plan);
  * Search and pair generation evaluate orderings exactly with 32-bit time
  * where a group's times stay below 2^31 ns and with 64-bit time otherwise
  * (durations must lie in [0, 2^40): TGO_ERANGE outside).  All buffers below
- * are device memory; the surrogate owns max_rows rows of activations.
+ * are device memory; the surrogate owns max_rows rows of activations for
+ * training and scoring, and the search's keys for max(max_rows, 2^20) rows
+ * (8 bytes each: the search scores that many rows per launch).
  */
 #define TGO_SURROGATE_PARAMS 144385
 

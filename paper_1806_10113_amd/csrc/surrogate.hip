@@ -8,6 +8,7 @@
 // orderings with a counter-based generator, scores them, keeps the best
 // scored per group and re-scores those exactly; the exact model decides the
 // answer, and the heuristic of Section 5.1 is always a candidate too.
+#include <algorithm>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -1368,6 +1369,7 @@ static_assert(TR_LD_PAD >= tgo::TR_ROWS - 64, "the last block's rows lie inside 
 struct tgo_surrogate {
     int device = 0;
     int64_t max_rows = 0;
+    int64_t search_rows = 0;  // rows scored per launch of the search (a multiple of the top-k run)
     int64_t ldt = 0;  // max_rows + TR_LD_PAD
     int64_t step = 0;
     void *mem = nullptr;
@@ -1462,6 +1464,10 @@ int tgo_surrogate_create(int64_t max_rows, int max_groups, tgo_surrogate **out) 
     tgo_surrogate *s = new (std::nothrow) tgo_surrogate();
     if (!s) return fail(TGO_ENOMEM, "surrogate");
     s->max_rows = max_rows;
+    // the search's only per-row buffer is its key array, so it scores in
+    // launches of at least 2^20 rows: a launch of 1,024 blocks of 64 rows
+    // (4 per CU, 3 resident) ends with a round on a third of the CUs
+    s->search_rows = std::max<int64_t>(max_rows, (int64_t)1 << 20) / TK_RUN * TK_RUN;
     s->ldt = max_rows + TR_LD_PAD;
     s->max_groups = max_groups;
     (void)hipGetDevice(&s->device);
@@ -1481,7 +1487,7 @@ int tgo_surrogate_create(int64_t max_rows, int max_groups, tgo_surrogate **out) 
         {(void **)&s->F, 4 * (size_t)max_groups * SG_POS * 3},
         {(void **)&s->status, 4 * (size_t)max_groups}, {(void **)&s->horders, 16 * (size_t)max_groups},
         {(void **)&s->hns, 8 * (size_t)max_groups}, {(void **)&s->best, sizeof(BestPair) * (size_t)max_groups},
-        {(void **)&s->keys, 8 * R},
+        {(void **)&s->keys, 8 * (size_t)s->search_rows},
     };
     size_t total = 0;
     for (auto &pt : parts) total += align256(pt.second);
@@ -1765,8 +1771,7 @@ extern "C" {
 static int search_candidates(tgo_surrogate *s, const Rates &r, const tgo_task *d_tasks, const int32_t *d_offs,
                              const uint32_t *d_keys, int G, int64_t samples, uint64_t seed, hipStream_t st,
                              int *cur_out, int64_t *len_out) {
-    const int64_t chunk = s->max_rows / TK_RUN * TK_RUN;
-    if (chunk < TK_RUN) return fail(TGO_EINVAL, "search needs max_rows >= 1024");
+    const int64_t chunk = s->search_rows;  // a multiple of TK_RUN
     const int64_t spad = (samples + TK_RUN - 1) / TK_RUN * TK_RUN;
     const int64_t runs = spad / TK_RUN;
     int rc = grow_cand(s, sizeof(unsigned long long) * (size_t)G * (size_t)runs * TK_KEEP);
