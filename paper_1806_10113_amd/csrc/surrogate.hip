@@ -260,14 +260,13 @@ __global__ void group_features_kernel(const tgo_task *__restrict__ tasks, const 
     }
 }
 
-// First-layer input of one row as 32 words of packed bf16 pairs (48
-// features + 16 zeros): the ordering is orders[i] (orders != null, group
+// Group, size and ordering of row i: orders[i] (orders != null, group
 // gid[i]) or sample (row mod spad) of group (row div spad) for row = row0 + i
-// (samples >= S are padding: *ok = false, all-zero input).
-__device__ __forceinline__ void row_input(const float *__restrict__ F, const int32_t *__restrict__ offs,
-                                          const uint32_t *__restrict__ gkeys, const uint8_t *__restrict__ orders,
-                                          const int32_t *__restrict__ gid, int64_t i, int64_t row0, int64_t spad,
-                                          int64_t S, uint64_t seed, uint32_t (&w)[SG_K0 / 2], bool *okp) {
+// (samples >= S are padding: *ok = false, and the row's input is all zero).
+__device__ __forceinline__ void row_order(const int32_t *__restrict__ offs, const uint32_t *__restrict__ gkeys,
+                                          const uint8_t *__restrict__ orders, const int32_t *__restrict__ gid,
+                                          int64_t i, int64_t row0, int64_t spad, int64_t S, uint64_t seed,
+                                          int *gp, int *np, uint64_t *permp, bool *okp) {
     int g;
     uint64_t perm;
     int n;
@@ -285,25 +284,9 @@ __device__ __forceinline__ void row_input(const float *__restrict__ F, const int
         ok = s < S && n >= 1 && n <= SG_POS;
         perm = ok ? sample_ordering(n, gkeys ? gkeys[g] : (uint32_t)g, (uint64_t)s, seed) : 0;
     }
-#pragma unroll
-    for (int c = 0; c < SG_K0 / 2; ++c) w[c] = 0;
-    const float *Fg = F + (int64_t)g * SG_POS * 3;
-#pragma unroll
-    for (int p = 0; p < SG_POS; ++p) {
-        if (ok && p < n) {
-            const int t = (int)((perm >> (4 * p)) & 15u);
-            const uint32_t f0 = f2bf(Fg[t * 3]), f1 = f2bf(Fg[t * 3 + 1]), f2 = f2bf(Fg[t * 3 + 2]);
-            // features 3p, 3p+1, 3p+2 -> halves of words (3p)/2 ...
-            const int c0 = 3 * p;
-            if ((c0 & 1) == 0) {
-                w[c0 / 2] = f0 | (f1 << 16);
-                w[c0 / 2 + 1] |= f2;
-            } else {
-                w[c0 / 2] |= f0 << 16;
-                w[c0 / 2 + 1] = f1 | (f2 << 16);
-            }
-        }
-    }
+    *gp = g;
+    *np = n;
+    *permp = perm;
     *okp = ok;
 }
 
@@ -358,6 +341,8 @@ constexpr int FM_LD = SG_H + 8;        // LDS row pitch in bf16
 constexpr int FM_WAVES = 8;            // wave w owns output columns FM_CT * 16 * w ..
 constexpr int FM_CT = SG_H / 16 / FM_WAVES;  // column tiles per wave
 constexpr int FM_THREADS = 64 * FM_WAVES;
+static_assert(2 * FM_WAVES == SG_POS && 4 * FM_WAVES == SG_K0 / 2,
+              "each wave builds two positions (three words) and one padding word of every row's input");
 
 template <int K>
 __device__ __forceinline__ void fm_layer(const uint16_t (*Hs)[FM_LD], const uint16_t *__restrict__ W, int w, int l,
@@ -426,22 +411,52 @@ __global__ __launch_bounds__(FM_THREADS) void mlp_fused_kernel(const float *__re
     __shared__ __align__(16) uint16_t Hs[FM_ROWS][FM_LD];
     __shared__ float part[FM_WAVES][FM_ROWS];
     __shared__ uint8_t okrow[FM_ROWS];
+    __shared__ unsigned long long sperm[FM_ROWS];
+    __shared__ int sgn[FM_ROWS];  // group << 5 | size, or -1: the row has no ordering
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int64_t base = (int64_t)blockIdx.x * FM_ROWS;
+    // inputs: wave 0 draws each row's ordering, then every wave gathers the
+    // features of two positions of each row (16 positions over 8 waves)
     if (tid < FM_ROWS) {
         const int64_t i = base + tid;
-        uint32_t x[SG_K0 / 2];
+        int g = 0, n = 0;
+        uint64_t perm = 0;
         bool ok = false;
-        if (i < rows) {
-            row_input(F, offs, gkeys, orders, gid, i, row0, spad, S, seed, x, &ok);
-        } else {
-#pragma unroll
-            for (int c = 0; c < SG_K0 / 2; ++c) x[c] = 0;
-        }
+        if (i < rows) row_order(offs, gkeys, orders, gid, i, row0, spad, S, seed, &g, &n, &perm, &ok);
         okrow[tid] = ok ? 1 : 0;
-        uint4 *dst = reinterpret_cast<uint4 *>(&Hs[tid][0]);
+        sperm[tid] = perm;
+        sgn[tid] = ok ? (g << 5) | n : -1;
+    }
+    __syncthreads();
+    {
+        const int gn = sgn[l];
+        uint32_t wv[3] = {0u, 0u, 0u};
+        if (gn >= 0) {
+            const int g = gn >> 5, n = gn & 31;
+            const uint64_t perm = sperm[l];
+            const float *Fg = F + (int64_t)g * SG_POS * 3;
+            uint32_t f[6] = {0u, 0u, 0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int c = 0; c < SG_K0 / 8; ++c) dst[c] = uint4{x[4 * c], x[4 * c + 1], x[4 * c + 2], x[4 * c + 3]};
+            for (int h = 0; h < 2; ++h) {
+                const int p = 2 * w + h;
+                if (p < n) {
+                    const int t = (int)((perm >> (4 * p)) & 15u);
+                    f[3 * h] = f2bf(Fg[t * 3]);
+                    f[3 * h + 1] = f2bf(Fg[t * 3 + 1]);
+                    f[3 * h + 2] = f2bf(Fg[t * 3 + 2]);
+                }
+            }
+            wv[0] = f[0] | (f[1] << 16);
+            wv[1] = f[2] | (f[3] << 16);
+            wv[2] = f[4] | (f[5] << 16);
+        }
+        // features 6w .. 6w + 5 are words 3w .. 3w + 2 of the row; word 24 + w
+        // is padding (48 features in a 64-wide first layer)
+        uint32_t *row = reinterpret_cast<uint32_t *>(&Hs[l][0]);
+        row[3 * w] = wv[0];
+        row[3 * w + 1] = wv[1];
+        row[3 * w + 2] = wv[2];
+        row[SG_K0 / 2 - FM_WAVES + w] = 0u;
     }
     __syncthreads();
     f32x4 acc[4][FM_CT];
