@@ -336,19 +336,23 @@ __device__ __forceinline__ unsigned long long wave_merge_low64(unsigned long lon
 // 8 waves computes 32 output columns of each layer for all 64 rows as 4 x 2
 // MFMA tiles; weights (bf16 [out][in]) come from global memory, where every
 // block reads the same 282 KB.
-constexpr int FM_ROWS = 64;
+constexpr int FM_ROWS = 128;
+constexpr int FM_RT = FM_ROWS / 16;    // row tiles per block
 constexpr int FM_LD = SG_H + 8;        // LDS row pitch in bf16
 constexpr int FM_WAVES = 8;            // wave w owns output columns FM_CT * 16 * w ..
 constexpr int FM_CT = SG_H / 16 / FM_WAVES;  // column tiles per wave
 constexpr int FM_THREADS = 64 * FM_WAVES;
-static_assert(2 * FM_WAVES == SG_POS && 4 * FM_WAVES == SG_K0 / 2,
-              "each wave builds two positions (three words) and one padding word of every row's input");
+constexpr int FM_TPR = FM_THREADS / FM_ROWS;  // threads building one row's input
+constexpr int FM_PPT = SG_POS / FM_TPR;       // positions per thread (3 features each)
+static_assert(FM_TPR * FM_ROWS == FM_THREADS && FM_PPT * FM_TPR == SG_POS && FM_PPT % 2 == 0 &&
+                  (SG_K0 / 2 - 3 * SG_POS / 2) % FM_TPR == 0 && FM_ROWS % 64 == 0,
+              "input build: whole positions and padding words per thread, whole waves of rows");
 
 template <int K>
 __device__ __forceinline__ void fm_layer(const uint16_t (*Hs)[FM_LD], const uint16_t *__restrict__ W, int w, int l,
-                                         f32x4 (&acc)[4][FM_CT]) {
+                                         f32x4 (&acc)[FM_RT][FM_CT]) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < FM_RT; ++a)
 #pragma unroll
         for (int b = 0; b < FM_CT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     const uint16_t *wrow = W + (int64_t)(16 * FM_CT * w + (l & 15)) * K + (l >> 4) * 8;
@@ -362,12 +366,12 @@ __device__ __forceinline__ void fm_layer(const uint16_t (*Hs)[FM_LD], const uint
             for (int t = 0; t < FM_CT; ++t)
                 nb[t] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * t * K + k0 + GK);
         }
-        bf16x8 fa[4];
+        bf16x8 fa[FM_RT];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < FM_RT; ++t)
             fa[t] = *reinterpret_cast<const bf16x8 *>(&Hs[16 * t + (l & 15)][k0 + (l >> 4) * 8]);
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < FM_RT; ++a)
 #pragma unroll
             for (int b = 0; b < FM_CT; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
@@ -379,13 +383,13 @@ __device__ __forceinline__ void fm_layer(const uint16_t (*Hs)[FM_LD], const uint
 // relu(acc + bias) as bf16 into Hs (lane l holds rows 16a + 4(l/16) + i of
 // column 16 (FM_CT w + b) + l%16)
 __device__ __forceinline__ void fm_store(uint16_t (*Hs)[FM_LD], const float *__restrict__ bias, int w, int l,
-                                         const f32x4 (&acc)[4][FM_CT]) {
+                                         const f32x4 (&acc)[FM_RT][FM_CT]) {
 #pragma unroll
     for (int b = 0; b < FM_CT; ++b) {
         const int col = 16 * (FM_CT * w + b) + (l & 15);
         const float bb = bias[col];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < FM_RT; ++a)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float v = acc[a][b][i] + bb;
@@ -415,8 +419,8 @@ __global__ __launch_bounds__(FM_THREADS) void mlp_fused_kernel(const float *__re
     __shared__ int sgn[FM_ROWS];  // group << 5 | size, or -1: the row has no ordering
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int64_t base = (int64_t)blockIdx.x * FM_ROWS;
-    // inputs: wave 0 draws each row's ordering, then every wave gathers the
-    // features of two positions of each row (16 positions over 8 waves)
+    // inputs: the first FM_ROWS threads draw each row's ordering, then
+    // FM_TPR threads per row gather the features of FM_PPT positions each
     if (tid < FM_ROWS) {
         const int64_t i = base + tid;
         int g = 0, n = 0;
@@ -429,16 +433,18 @@ __global__ __launch_bounds__(FM_THREADS) void mlp_fused_kernel(const float *__re
     }
     __syncthreads();
     {
-        const int gn = sgn[l];
-        uint32_t wv[3] = {0u, 0u, 0u};
+        const int r = tid % FM_ROWS, q = tid / FM_ROWS;
+        const int gn = sgn[r];
+        uint32_t f[3 * FM_PPT];
+#pragma unroll
+        for (int c = 0; c < 3 * FM_PPT; ++c) f[c] = 0u;
         if (gn >= 0) {
             const int g = gn >> 5, n = gn & 31;
-            const uint64_t perm = sperm[l];
+            const uint64_t perm = sperm[r];
             const float *Fg = F + (int64_t)g * SG_POS * 3;
-            uint32_t f[6] = {0u, 0u, 0u, 0u, 0u, 0u};
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int p = 2 * w + h;
+            for (int h = 0; h < FM_PPT; ++h) {
+                const int p = FM_PPT * q + h;
                 if (p < n) {
                     const int t = (int)((perm >> (4 * p)) & 15u);
                     f[3 * h] = f2bf(Fg[t * 3]);
@@ -446,20 +452,18 @@ __global__ __launch_bounds__(FM_THREADS) void mlp_fused_kernel(const float *__re
                     f[3 * h + 2] = f2bf(Fg[t * 3 + 2]);
                 }
             }
-            wv[0] = f[0] | (f[1] << 16);
-            wv[1] = f[2] | (f[3] << 16);
-            wv[2] = f[4] | (f[5] << 16);
         }
-        // features 6w .. 6w + 5 are words 3w .. 3w + 2 of the row; word 24 + w
-        // is padding (48 features in a 64-wide first layer)
-        uint32_t *row = reinterpret_cast<uint32_t *>(&Hs[l][0]);
-        row[3 * w] = wv[0];
-        row[3 * w + 1] = wv[1];
-        row[3 * w + 2] = wv[2];
-        row[SG_K0 / 2 - FM_WAVES + w] = 0u;
+        // features 3 FM_PPT q .. are words 3 FM_PPT q / 2 .. of the row; the
+        // words after the 48 features are padding (a 64-wide first layer)
+        uint32_t *row = reinterpret_cast<uint32_t *>(&Hs[r][0]);
+#pragma unroll
+        for (int c = 0; c < 3 * FM_PPT / 2; ++c) row[3 * FM_PPT / 2 * q + c] = f[2 * c] | (f[2 * c + 1] << 16);
+        constexpr int PAD = (SG_K0 / 2 - 3 * SG_POS / 2) / FM_TPR;
+#pragma unroll
+        for (int c = 0; c < PAD; ++c) row[3 * SG_POS / 2 + PAD * q + c] = 0u;
     }
     __syncthreads();
-    f32x4 acc[4][FM_CT];
+    f32x4 acc[FM_RT][FM_CT];
     fm_layer<SG_K0>(Hs, W1, w, l, acc);
     __syncthreads();
     fm_store(Hs, p + SG_OFF_B1, w, l, acc);
@@ -471,9 +475,9 @@ __global__ __launch_bounds__(FM_THREADS) void mlp_fused_kernel(const float *__re
     fm_layer<SG_H>(Hs, W3, w, l, acc);
     // head on the bf16-rounded third layer: per-row partial sums over this
     // wave's columns, reduced across the 16 lanes that share rows
-    float sum[4][4];
+    float sum[FM_RT][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < FM_RT; ++a)
 #pragma unroll
         for (int i = 0; i < 4; ++i) sum[a][i] = 0.f;
 #pragma unroll
@@ -481,7 +485,7 @@ __global__ __launch_bounds__(FM_THREADS) void mlp_fused_kernel(const float *__re
         const int col = 16 * (FM_CT * w + b) + (l & 15);
         const float bb = p[SG_OFF_B3 + col], w4 = p[SG_OFF_W4 + col];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < FM_RT; ++a)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float v = acc[a][b][i] + bb;
@@ -489,7 +493,7 @@ __global__ __launch_bounds__(FM_THREADS) void mlp_fused_kernel(const float *__re
             }
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < FM_RT; ++a)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             float v = sum[a][i];
@@ -497,18 +501,18 @@ __global__ __launch_bounds__(FM_THREADS) void mlp_fused_kernel(const float *__re
             if ((l & 15) == 0) part[w][16 * a + 4 * (l >> 4) + i] = v;
         }
     __syncthreads();
-    if (tid < FM_ROWS) {  // wave 0, one row per lane
+    if (tid < FM_ROWS) {  // one row per lane
         const int64_t i = base + tid;
         float sc = p[SG_OFF_B4];
 #pragma unroll
         for (int v = 0; v < FM_WAVES; ++v) sc += part[v][tid];
         if (keys) {
-            // the block's 64 keys, sorted: the top-k passes take every 64
+            // each wave's 64 keys, sorted: the top-k passes take every 64
             // consecutive keys as an ascending list (rows past the end are
             // ~0, so the valid keys come first)
             unsigned long long key = ~0ull;
             if (i < rows && okrow[tid]) key = ((unsigned long long)orderable(sc) << 32) | (uint64_t)((row0 + i) % spad);
-            key = wave_sort64(key, tid);
+            key = wave_sort64(key, l);
             if (i < rows) keys[i] = key;
         } else if (i < rows) {
             score[i] = okrow[tid] ? sc : INFINITY;
