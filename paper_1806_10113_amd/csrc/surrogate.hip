@@ -329,13 +329,16 @@ __device__ __forceinline__ unsigned long long wave_merge_low64(unsigned long lon
     return v;
 }
 
-// One block scores 64 rows end to end: it builds their first-layer inputs in
-// LDS, runs the three hidden layers on MFMA with the activations kept in LDS
-// (rounded to bf16, as the layer-by-layer path stores them) and applies the
-// head, so only the 64 scores (or top-k keys) leave the block.  Each of the
-// 8 waves computes 32 output columns of each layer for all 64 rows as 4 x 2
-// MFMA tiles; weights (bf16 [out][in]) come from global memory, where every
-// block reads the same 282 KB.
+// One block scores FM_ROWS rows end to end: it builds their first-layer
+// inputs in LDS, runs the three hidden layers on MFMA with the activations
+// kept in LDS (rounded to bf16, as the layer-by-layer path stores them) and
+// applies the head, so only the scores (or top-k keys) leave the block.  Each
+// of the 8 waves computes 32 output columns of each layer for all rows as
+// FM_RT x FM_CT MFMA tiles; weights (bf16 [out][in]) come from global memory,
+// where every block reads the same 282 KB.  The tiles are computed transposed
+// (weights as the A operand, activations as B), so a lane's accumulator holds
+// four consecutive output columns of one row: a layer's outputs leave in
+// 8-byte LDS stores and the head reduces over four lanes per row.
 constexpr int FM_ROWS = 128;
 constexpr int FM_RT = FM_ROWS / 16;    // row tiles per block
 constexpr int FM_LD = SG_H + 8;        // LDS row pitch in bf16
@@ -374,27 +377,32 @@ __device__ __forceinline__ void fm_layer(const uint16_t (*Hs)[FM_LD], const uint
         for (int a = 0; a < FM_RT; ++a)
 #pragma unroll
             for (int b = 0; b < FM_CT; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[b], fa[a], acc[a][b], 0, 0, 0);
 #pragma unroll
         for (int t = 0; t < FM_CT; ++t) fb[t] = nb[t];
     }
 }
 
-// relu(acc + bias) as bf16 into Hs (lane l holds rows 16a + 4(l/16) + i of
-// column 16 (FM_CT w + b) + l%16)
+// relu(acc + bias) as bf16 into Hs (lane l holds columns
+// 16 (FM_CT w + b) + 4(l/16) + i of row 16a + l%16)
 __device__ __forceinline__ void fm_store(uint16_t (*Hs)[FM_LD], const float *__restrict__ bias, int w, int l,
                                          const f32x4 (&acc)[FM_RT][FM_CT]) {
 #pragma unroll
     for (int b = 0; b < FM_CT; ++b) {
-        const int col = 16 * (FM_CT * w + b) + (l & 15);
-        const float bb = bias[col];
+        const int c0 = 16 * (FM_CT * w + b) + 4 * (l >> 4);
+        float bb[4];
 #pragma unroll
-        for (int a = 0; a < FM_RT; ++a)
+        for (int i = 0; i < 4; ++i) bb[i] = bias[c0 + i];
+#pragma unroll
+        for (int a = 0; a < FM_RT; ++a) {
+            uint32_t h[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float v = acc[a][b][i] + bb;
-                Hs[16 * a + 4 * (l >> 4) + i][col] = f2bf(v > 0.f ? v : 0.f);
+                const float v = acc[a][b][i] + bb[i];
+                h[i] = f2bf(v > 0.f ? v : 0.f);
             }
+            *reinterpret_cast<uint2 *>(&Hs[16 * a + (l & 15)][c0]) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+        }
     }
 }
 
@@ -474,32 +482,34 @@ __global__ __launch_bounds__(FM_THREADS) void mlp_fused_kernel(const float *__re
     __syncthreads();
     fm_layer<SG_H>(Hs, W3, w, l, acc);
     // head on the bf16-rounded third layer: per-row partial sums over this
-    // wave's columns, reduced across the 16 lanes that share rows
-    float sum[FM_RT][4];
+    // wave's columns, reduced across the 4 lanes that share a row
+    float sum[FM_RT];
 #pragma unroll
-    for (int a = 0; a < FM_RT; ++a)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) sum[a][i] = 0.f;
+    for (int a = 0; a < FM_RT; ++a) sum[a] = 0.f;
 #pragma unroll
     for (int b = 0; b < FM_CT; ++b) {
-        const int col = 16 * (FM_CT * w + b) + (l & 15);
-        const float bb = p[SG_OFF_B3 + col], w4 = p[SG_OFF_W4 + col];
+        const int c0 = 16 * (FM_CT * w + b) + 4 * (l >> 4);
+        float bb[4], w4[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            bb[i] = p[SG_OFF_B3 + c0 + i];
+            w4[i] = p[SG_OFF_W4 + c0 + i];
+        }
 #pragma unroll
         for (int a = 0; a < FM_RT; ++a)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float v = acc[a][b][i] + bb;
-                sum[a][i] += bf2f(f2bf(v > 0.f ? v : 0.f)) * w4;
+                const float v = acc[a][b][i] + bb[i];
+                sum[a] += bf2f(f2bf(v > 0.f ? v : 0.f)) * w4[i];
             }
     }
 #pragma unroll
-    for (int a = 0; a < FM_RT; ++a)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            float v = sum[a][i];
-            for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m);
-            if ((l & 15) == 0) part[w][16 * a + 4 * (l >> 4) + i] = v;
-        }
+    for (int a = 0; a < FM_RT; ++a) {
+        float v = sum[a];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (l < 16) part[w][16 * a + l] = v;
+    }
     __syncthreads();
     if (tid < FM_ROWS) {  // one row per lane
         const int64_t i = base + tid;
