@@ -334,8 +334,9 @@ __device__ __forceinline__ unsigned long long wave_merge_low64(unsigned long lon
 // kept in LDS (rounded to bf16, as the layer-by-layer path stores them) and
 // applies the head, so only the scores (or top-k keys) leave the block.  Each
 // of the 8 waves computes 32 output columns of each layer for all rows as
-// FM_RT x FM_CT MFMA tiles; weights (bf16 [out][in]) come from global memory,
-// where every block reads the same 282 KB.  The tiles are computed transposed
+// FM_RT x FM_CT MFMA tiles; weights (bf16, in the fragment order that
+// pack_frag_kernel writes) come from global memory, where every block reads
+// the same 282 KB.  The tiles are computed transposed
 // (weights as the A operand, activations as B), so a lane's accumulator holds
 // four consecutive output columns of one row: a layer's outputs leave in
 // 8-byte LDS stores and the head reduces over four lanes per row.
@@ -358,16 +359,19 @@ __device__ __forceinline__ void fm_layer(const uint16_t (*Hs)[FM_LD], const uint
     for (int a = 0; a < FM_RT; ++a)
 #pragma unroll
         for (int b = 0; b < FM_CT; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const uint16_t *wrow = W + (int64_t)(16 * FM_CT * w + (l & 15)) * K + (l >> 4) * 8;
+    // W in fragment order (pack_frag_kernel): fragment (column tile
+    // FM_CT w + t, K step ks) of this lane at wf + (t KS + ks) 512
+    constexpr int KS = K / GK;
+    const uint16_t *wf = W + ((int64_t)FM_CT * w * KS * 64 + l) * 8;
     bf16x8 fb[FM_CT], nb[FM_CT];
 #pragma unroll
-    for (int t = 0; t < FM_CT; ++t) fb[t] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * t * K);
+    for (int t = 0; t < FM_CT; ++t) fb[t] = *reinterpret_cast<const bf16x8 *>(wf + (int64_t)t * KS * 512);
 #pragma unroll 1
     for (int k0 = 0; k0 < K; k0 += GK) {
         if (k0 + GK < K) {
 #pragma unroll
             for (int t = 0; t < FM_CT; ++t)
-                nb[t] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * t * K + k0 + GK);
+                nb[t] = *reinterpret_cast<const bf16x8 *>(wf + ((int64_t)t * KS + (k0 + GK) / GK) * 512);
         }
         bf16x8 fa[FM_RT];
 #pragma unroll
@@ -404,6 +408,33 @@ __device__ __forceinline__ void fm_store(uint16_t (*Hs)[FM_LD], const float *__r
             *reinterpret_cast<uint2 *>(&Hs[16 * a + (l & 15)][c0]) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
         }
     }
+}
+
+// The three layers' bf16 weights ([out][in], W1 padded to SG_K0 inputs) in
+// the fragment order mlp_fused_kernel reads: the B fragment of column tile ct
+// and K step ks (16 output columns x GK inputs) is 64 lanes x 8 bf16 at
+// ((ct K/GK + ks) 64 + lane) 8, lane l holding W[16 ct + l%16][GK ks +
+// 8 (l/16) ..], so each of a wave's fragment loads reads 1 KB contiguously.
+// Layers at 0, FM_WF1 and FM_WF1 + SG_H^2 of Wf.
+constexpr int FM_WF1 = SG_H * SG_K0;
+constexpr int FM_WF = FM_WF1 + 2 * SG_H * SG_H;
+__global__ void pack_frag_kernel(const uint16_t *__restrict__ W1, const uint16_t *__restrict__ W2,
+                                 const uint16_t *__restrict__ W3, uint16_t *__restrict__ Wf) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= FM_WF) return;
+    const uint16_t *W = W3;
+    int K = SG_H, q = e - FM_WF1 - SG_H * SG_H;
+    if (e < FM_WF1) {
+        W = W1;
+        K = SG_K0;
+        q = e;
+    } else if (e < FM_WF1 + SG_H * SG_H) {
+        W = W2;
+        q = e - FM_WF1;
+    }
+    const int j = q & 7, lane = (q >> 3) & 63, frag = q >> 9;
+    const int ks = frag % (K / GK), ct = frag / (K / GK);
+    Wf[e] = W[(16 * ct + (lane & 15)) * K + GK * ks + 8 * (lane >> 4) + j];
 }
 
 // Rows are chosen as in features_kernel.  Output: score[i] (keys == null) or
@@ -1406,6 +1437,7 @@ struct tgo_surrogate {
     // W [out][in] (W1 padded to 64 inputs) and, for back-propagation, W^T
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
     uint16_t *W1 = nullptr, *W2 = nullptr, *W2t = nullptr, *W3 = nullptr, *W3t = nullptr;
+    uint16_t *Wf = nullptr;  // W1, W2, W3 in the fused inference kernel's fragment order
     // training batch, transposed [feature][row] with row pitch max_rows
     uint16_t *Xt = nullptr, *H1t = nullptr, *H2t = nullptr, *G1t = nullptr, *G2t = nullptr, *G3t = nullptr;
     // kept by tgo_surrogate_grad for inspection: h3 [row][256] and scores
@@ -1506,7 +1538,7 @@ int tgo_surrogate_create(int64_t max_rows, int max_groups, tgo_surrogate **out) 
         {(void **)&s->p, 4 * SG_NPARAM}, {(void **)&s->g, 4 * SG_NPARAM}, {(void **)&s->m, 4 * SG_NPARAM},
         {(void **)&s->v, 4 * SG_NPARAM},
         {(void **)&s->W1, 2 * SG_H * SG_K0}, {(void **)&s->W2, 2 * SG_H * SG_H}, {(void **)&s->W2t, 2 * SG_H * SG_H},
-        {(void **)&s->W3, 2 * SG_H * SG_H}, {(void **)&s->W3t, 2 * SG_H * SG_H},
+        {(void **)&s->W3, 2 * SG_H * SG_H}, {(void **)&s->W3t, 2 * SG_H * SG_H}, {(void **)&s->Wf, 2 * (size_t)FM_WF},
         {(void **)&s->Xt, 2 * LT * SG_K0}, {(void **)&s->H1t, 2 * LT * SG_H}, {(void **)&s->H2t, 2 * LT * SG_H},
         {(void **)&s->G1t, 2 * LT * SG_H}, {(void **)&s->G2t, 2 * LT * SG_H}, {(void **)&s->G3t, 2 * LT * SG_H},
         {(void **)&s->H3, 2 * R * SG_H}, {(void **)&s->score, 4 * R},
@@ -1662,9 +1694,11 @@ int tgo_surrogate_score(tgo_surrogate *s, const tgo_task *d_tasks, const int32_t
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(group_features_kernel, dim3((G * SG_POS + 255) / 256), dim3(256), 0, st, d_tasks, d_offs,
                        G, s->F);
+    hipLaunchKernelGGL(pack_frag_kernel, dim3((FM_WF + 255) / 256), dim3(256), 0, st, s->W1, s->W2, s->W3, s->Wf);
     hipLaunchKernelGGL(mlp_fused_kernel, dim3((unsigned)((rows + FM_ROWS - 1) / FM_ROWS)), dim3(FM_THREADS), 0, st, s->F,
                        d_offs, (const uint32_t *)nullptr, d_orders, d_gid, (int64_t)0, rows, (int64_t)1, (int64_t)1,
-                       (uint64_t)0, s->W1, s->W2, s->W3, s->p, d_scores, (unsigned long long *)nullptr);
+                       (uint64_t)0, s->Wf, s->Wf + FM_WF1, s->Wf + FM_WF1 + SG_H * SG_H, s->p, d_scores,
+                       (unsigned long long *)nullptr);
     TGO_HIP(hipGetLastError());
     return TGO_OK;
 }
@@ -1809,13 +1843,14 @@ static int search_candidates(tgo_surrogate *s, const Rates &r, const tgo_task *d
                        s->status, (int32_t *)nullptr);
     hipLaunchKernelGGL(group_features_kernel, dim3((G * SG_POS + 255) / 256), dim3(256), 0, st, d_tasks, d_offs,
                        G, s->F);
+    hipLaunchKernelGGL(pack_frag_kernel, dim3((FM_WF + 255) / 256), dim3(256), 0, st, s->W1, s->W2, s->W3, s->Wf);
     const int64_t total = (int64_t)G * spad;
     for (int64_t row0 = 0; row0 < total; row0 += chunk) {
         const int64_t rows = std::min(chunk, total - row0);
         // rows is a multiple of TK_RUN, hence of FM_ROWS
         hipLaunchKernelGGL(mlp_fused_kernel, dim3((unsigned)(rows / FM_ROWS)), dim3(FM_THREADS), 0, st, s->F, d_offs, d_keys,
-                           (const uint8_t *)nullptr, (const int32_t *)nullptr, row0, rows, spad, samples, seed, s->W1,
-                           s->W2, s->W3, s->p, (float *)nullptr, s->keys);
+                           (const uint8_t *)nullptr, (const int32_t *)nullptr, row0, rows, spad, samples, seed, s->Wf,
+                           s->Wf + FM_WF1, s->Wf + FM_WF1 + SG_H * SG_H, s->p, (float *)nullptr, s->keys);
         const int nrun = (int)(rows / TK_RUN);
         hipLaunchKernelGGL(topk_pass_kernel, dim3(nrun, 1), dim3(TK_THREADS), 0, st, s->keys, (int64_t)0, rows, nrun,
                            s->cand[0] + (row0 / TK_RUN) * TK_KEEP, (int64_t)0);
